@@ -1,0 +1,39 @@
+"""Solver parameters of the oracle (values the paper gives, or the stated readings
+of what it leaves open).
+
+Paper values: dense pair view-angle limit 60 deg (Sec. 4.3); the distance and
+normal pruning thresholds are not given for the dense energy, so the dense
+verification values tau_d = 0.15 m and tau_n = 0.9 (Sec. 4.1.1) are used.
+The weights w_sparse, w_dense, w_geo, w_photo are not given; w_dense is ramped
+linearly over the Gauss-Newton iterations (Sec. 4.3 says it is linearly
+increased): w_d(k) = w_dense * (k+1) / n_gn.
+"""
+from dataclasses import dataclass
+
+# Photometric weight: chosen once so that the geometric and photometric energies
+# are equal at ground truth on the 11-frame chunk workload, then frozen.
+DEFAULT_W_PHOTO = 1.178
+
+
+@dataclass
+class Params:
+    w_sparse: float = 1.0
+    w_dense: float = 1.0
+    w_geo: float = 1.0
+    w_photo: float = DEFAULT_W_PHOTO
+    dense_ramp: bool = True
+    tau_dist: float = 0.15
+    tau_normal: float = 0.9
+    max_angle_deg: float = 60.0
+    depth_min: float = 0.1
+    depth_max: float = 10.0
+    num_gn: int = 5
+    num_pcg: int = 10
+    use_dense: bool = True
+    use_sparse: bool = True
+
+    def dense_weight(self, k):
+        """w_d for Gauss-Newton iteration k (0-based)."""
+        if self.dense_ramp:
+            return self.w_dense * (k + 1) / self.num_gn
+        return self.w_dense

@@ -1,0 +1,169 @@
+"""Pins of the oracle's linear solvers and Gauss-Newton loop: library solves, the
+Kabsch/Umeyama closed form, an independent least-squares minimiser with
+finite-difference Jacobians, descent and quadratic convergence."""
+import numpy as np
+import pytest
+import scipy.optimize
+
+from oracle import Params
+from oracle.gn import Setup, build_system, solve
+from oracle.se3 import exp_se3, rotation_angle
+from oracle.system import reduce_system, solve_cholesky, solve_pcg
+from oracle.terms import dense_terms, sparse_terms
+from synth import make_chunk
+
+
+def _spd(n, rng, cond=1e3):
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    return Q @ np.diag(np.geomspace(1.0, cond, n)) @ Q.T
+
+
+def test_cholesky_matches_library_solve():
+    rng = np.random.default_rng(0)
+    H = _spd(30, rng)
+    g = rng.normal(size=30)
+    assert np.allclose(solve_cholesky(H, g), np.linalg.solve(H, -g), rtol=1e-12, atol=1e-14)
+
+
+def test_pcg_full_dimension_equals_cholesky():
+    rng = np.random.default_rng(1)
+    H = _spd(36, rng, cond=50.0)
+    g = rng.normal(size=36)
+    x, st = solve_pcg(H, g, 3 * 36)   # n steps suffice in exact arithmetic; allow for rounding
+    ref = solve_cholesky(H, g)
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_pcg_block_diagonal_one_iteration():
+    rng = np.random.default_rng(2)
+    H = np.zeros((24, 24))
+    for k in range(4):
+        H[6 * k:6 * k + 6, 6 * k:6 * k + 6] = _spd(6, rng)
+    g = rng.normal(size=24)
+    x, st = solve_pcg(H, g, 1)
+    assert st["iters"] == 1
+    assert np.allclose(x, solve_cholesky(H, g), rtol=1e-10, atol=1e-12)
+
+
+def _sparse_only_solve(p, q, init, iters, linear="cholesky"):
+    F = len(init)
+    depth = np.zeros((F, 60, 80), np.float32)
+    prm = Params(use_dense=False, num_gn=iters, num_pcg=12, dense_ramp=False)
+    n = len(p)
+    ci = np.zeros(n, np.int32)
+    cj = np.ones(n, np.int32)
+    return solve(depth, depth, (72.0, 72.0, 40.0, 30.0, 80, 60), ci, cj, p, q, init, prm, linear=linear)
+
+
+def test_two_frame_sparse_equals_kabsch():
+    """Sparse-only, two frames: the Gauss-Newton fixed point is the closed-form rigid
+    least-squares fit (Kabsch / Umeyama without scale) of sum |p - T_1 q|^2."""
+    rng = np.random.default_rng(3)
+    T1 = exp_se3([0.1, -0.2, 0.05, 0.3, 0.1, -0.2])
+    q = rng.uniform(-2, 2, size=(60, 3))
+    p = q @ T1[:3, :3].T + T1[:3, 3] + 0.01 * rng.normal(size=(60, 3))
+    init = np.stack([np.eye(4), T1 @ exp_se3([0.03, 0.02, -0.02, 0.05, -0.05, 0.02])])
+    res = _sparse_only_solve(p, q, init, 12)
+    mp, mq = p.mean(0), q.mean(0)
+    S = (p - mp).T @ (q - mq)
+    U, _, Vt = np.linalg.svd(S)
+    D = np.diag([1.0, 1.0, np.sign(np.linalg.det(U) * np.linalg.det(Vt))])
+    R = U @ D @ Vt
+    t = mp - R @ mq
+    assert np.abs(res["poses"][1][:3, :3] - R).max() < 1e-10
+    assert np.abs(res["poses"][1][:3, 3] - t).max() < 1e-10
+    assert np.array_equal(res["poses"][0], init[0])
+
+
+def test_quadratic_convergence_noise_free_sparse():
+    rng = np.random.default_rng(4)
+    T1 = exp_se3([0.2, 0.1, -0.1, 0.5, -0.3, 0.2])
+    q = rng.uniform(-2, 2, size=(40, 3))
+    p = q @ T1[:3, :3].T + T1[:3, 3]
+    init = np.stack([np.eye(4), T1 @ exp_se3([0.1, -0.08, 0.05, 0.1, 0.1, -0.1])])
+    res = _sparse_only_solve(p, q, init, 6)
+    steps = [np.linalg.norm(s["dx"]) for s in res["steps"]]
+    for a, b in zip(steps, steps[1:]):
+        if a > 1e-6:
+            assert b <= 10.0 * a * a, steps
+    assert steps[-1] < 1e-12
+
+
+def _frozen_residuals(setup, poses, assoc, prm):
+    out = []
+    for e, (i, j) in enumerate(setup.edges):
+        s = setup.edge_sparse[e]
+        if s >= 0:
+            lo, hi = setup.sptr[s], setup.sptr[s + 1]
+            r = sparse_terms(poses[i], poses[j], setup.pa[lo:hi], setup.qb[lo:hi])[0]
+            out.append(np.sqrt(prm.w_sparse) * r.ravel())
+        if setup.edge_dense[e] >= 0:
+            t = dense_terms(setup.frames[i], setup.frames[j], poses[i], poses[j], setup.intr, prm, assoc=assoc[e])
+            out.append(np.sqrt(prm.w_geo) * t["rg"])
+            out.append(np.sqrt(prm.w_photo) * t["rp"])
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("nframes", [2, 3])
+def test_gn_minimum_matches_least_squares(nframes):
+    """All terms, association frozen at the converged poses: an independent
+    trust-region least-squares minimiser with finite-difference Jacobians, started
+    from several random perturbations, finds the same minimum as Gauss-Newton."""
+    prob = make_chunk(num_frames=nframes, noise=True, config=0, seed_offset=20 + nframes)
+    prm = Params(num_gn=40, dense_ramp=False)
+    res = solve(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p,
+                prob.corr_q, prob.init_poses, prm, freeze_association=True)
+    X = res["poses"]
+    assert np.linalg.norm(res["steps"][-1]["dx"]) < 1e-10
+    setup = res["setup"]
+    assoc = res["assoc"]
+    free = list(setup.free)
+
+    def fun(z):
+        P = X.copy()
+        for n, f in enumerate(free):
+            P[f] = X[f] @ exp_se3(z[6 * n:6 * n + 6])
+        return _frozen_residuals(setup, P, assoc, prm)
+
+    rng = np.random.default_rng(nframes)
+    for start in range(3):
+        z0 = rng.normal(size=6 * len(free)) * np.tile([0.01, 0.01, 0.01, 0.02, 0.02, 0.02], len(free))
+        ls = scipy.optimize.least_squares(fun, z0, jac="3-point", method="trf", xtol=1e-15, ftol=1e-15,
+                                          gtol=1e-15, max_nfev=200)
+        for n, f in enumerate(free):
+            T = X[f] @ exp_se3(ls.x[6 * n:6 * n + 6])
+            assert rotation_angle(T[:3, :3].T @ X[f][:3, :3]) < 1e-7
+            assert np.linalg.norm(T[:3, 3] - X[f][:3, 3]) < 1e-7
+
+
+@pytest.mark.parametrize("noise", [False, True])
+def test_monotone_descent(noise):
+    """Association held fixed, ramp off, init within 3 cm / 2 deg: every Gauss-Newton
+    step lowers the energy.  With re-association at every step the first steps (which
+    carry almost all of the decrease) descend too; later ones may move by the energy
+    of a few pixels entering or leaving the association."""
+    prob = make_chunk(num_frames=6, noise=noise, config=0, seed_offset=30)
+    prm = Params(num_gn=6, dense_ramp=False)
+    args = (prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p,
+            prob.corr_q, prob.init_poses, prm)
+    res = solve(*args, freeze_association=True)
+    E = [t["total"] for t in res["trace"]] + [res["energy"]["total"]]
+    for a, b in zip(E, E[1:]):
+        assert b <= a * (1 + 1e-12), E
+    assert np.array_equal(res["poses"][0], prob.init_poses[0])
+    res = solve(*args)
+    E = [t["total"] for t in res["trace"]]
+    assert E[1] < E[0] and E[2] < E[1]
+    assert min(E) < E[0] and abs(E[-1] - min(E)) < 1e-3 * min(E)
+
+
+def test_pcg_mode_approaches_cholesky_on_chunk():
+    prob = make_chunk(num_frames=5, noise=True, config=0, seed_offset=40)
+    prm = Params(num_gn=3, num_pcg=24, dense_ramp=False)
+    s = Setup(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p,
+              prob.corr_q, prob.init_poses, prm)
+    H, g, _, _ = build_system(s, prob.init_poses, 1.0)
+    Hr, gr, _ = reduce_system(H, g, s.free)
+    x, st = solve_pcg(Hr, gr, 3 * Hr.shape[0])
+    ref = solve_cholesky(Hr, gr)
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
