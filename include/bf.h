@@ -1,0 +1,230 @@
+/*
+ * bf.h -- C ABI of the MI355X global pose alignment library (libbf.so).
+ *
+ * The library solves the global alignment problem of Dai et al., "BundleFusion"
+ * (arXiv:1604.01093), Sec. 4.3-4.4: given RGB-D frames, sparse 3D point
+ * correspondences between frame pairs and initial camera poses, it minimises
+ *
+ *   E_align = w_sparse E_sparse + w_d (w_geo E_geo + w_photo E_photo)
+ *
+ * over the camera-to-world poses T_f (T_0 fixed) by Gauss-Newton with a
+ * block-Jacobi preconditioned conjugate gradient solve of J^T J dX = -J^T F
+ * (Sec. 4.4) and the SE(3) exponential update (Sec. 4.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers are DEVICE pointers owned by the caller unless the comment says
+ *   "host".  Device buffers must stay valid until the call has completed on the
+ *   context's stream.  Calls are ordered on that stream.  A call that writes a
+ *   host output synchronises the stream before returning; the others return after
+ *   enqueueing their work (bf_prepare_frames only).
+ * - Images are row-major [num_frames][height][width] float32.  Depth is in metres;
+ *   0, non-finite or outside [depth_min, depth_max] means "no depth".  Intensity
+ *   is used directly as luminance.  Pixel (x, y) has its centre at u = x, v = y.
+ * - Poses are row-major 4x4 float64 camera-to-world matrices, [num_frames][4][4].
+ *   A pose update is T_f <- T_f Exp(xi_f), xi_f = (omega_f, v_f), and increments
+ *   are returned in that order, 6 per frame.
+ * - Correspondence points are float32 [count][3] in the camera frame of their own
+ *   frame, metres.  frame_i != frame_j; either order is accepted.
+ * - Dense pairs are int32 [count][2] with ij[k][0] < ij[k][1], strictly
+ *   increasing in (i, j).  The lower index is the source frame of the pair job.
+ * - On any error the outputs are left unwritten and the message of the last error
+ *   is available from bf_last_error().
+ * - A context is not thread safe; use one context per stream.  Its workspace is
+ *   allocated on first use, grown on demand, never inside a Gauss-Newton loop,
+ *   and freed by bf_destroy().
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bf_status {
+  BF_OK = 0,
+  BF_ERR_INVALID_ARG = 1,    /* bad sizes, null pointers, indices out of range, unsorted pairs */
+  BF_ERR_OUT_OF_MEMORY = 2,  /* device workspace could not be allocated */
+  BF_ERR_DEVICE = 3,         /* a HIP runtime call failed */
+  BF_ERR_NOT_PD = 4,         /* a 6x6 diagonal block of J^T J is not positive definite */
+  BF_ERR_NONFINITE = 5,      /* non-finite correspondence point or pose */
+  BF_ERR_UNSUPPORTED = 6     /* a parameter combination this build does not implement */
+} bf_status;
+
+typedef struct bf_context bf_context;
+
+/* Camera intrinsics of the (downsampled) frames, Sec. 4.1.1 / 4.3. */
+typedef struct bf_intrinsics {
+  double fx, fy, cx, cy;
+  int32_t width, height;
+} bf_intrinsics;
+
+/* RGB-D frames S = {f_i} (Sec. 4): depth and intensity, [F][H][W] float32 device. */
+typedef struct bf_frames {
+  int32_t num_frames;
+  const float* depth;
+  const float* intensity;
+} bf_frames;
+
+/* Sparse correspondences C(i,j) of E_sparse (Sec. 4.3). */
+typedef struct bf_corrs {
+  int64_t count;
+  const int32_t* frame_i;   /* [count] */
+  const int32_t* frame_j;   /* [count] */
+  const float* p_i;         /* [count][3], point in camera frame_i */
+  const float* p_j;         /* [count][3], point in camera frame_j */
+} bf_corrs;
+
+/* Dense frame-pair set E (Sec. 4.3). */
+typedef struct bf_pairs {
+  int64_t count;
+  const int32_t* ij;        /* [count][2] */
+} bf_pairs;
+
+/* Solver parameters.  Values the paper gives: 60 degree pair angle (Sec. 4.3).
+ * The paper gives no weights, pruning thresholds or iteration counts for the
+ * dense energy; bf_params_default() fills the readings documented there. */
+typedef struct bf_params {
+  double w_sparse, w_dense, w_geo, w_photo;
+  int32_t dense_ramp;       /* 1: w_d(k) = w_dense (k+1)/num_gn (Sec. 4.3 "linearly increased") */
+  int32_t use_sparse;       /* 0 drops E_sparse */
+  int32_t use_dense;        /* 0 drops E_geo and E_photo */
+  int32_t num_gn;           /* Gauss-Newton iterations */
+  int32_t num_pcg;          /* PCG iterations per Gauss-Newton iteration (early exit if r^T z <= 1e-30) */
+  int32_t accumulate;       /* per-pixel J^T J accumulation: 0 = FP32, 1 = compensated (two-sum) FP32 */
+  int32_t pcg_storage;      /* PCG matrix and vectors: 0 = FP32 (dots and alpha/beta in FP64), 1 = FP64 */
+  int32_t timing;           /* 1: record HIP events per phase for bf_last_timings() */
+  double tau_dist;          /* dense association: |c - q| < tau_dist (metres) */
+  double tau_normal;        /* dense association: normal dot product > tau_normal */
+  double max_angle_deg;     /* dense pair test: viewing directions within this angle */
+  double depth_min, depth_max;
+} bf_params;
+
+void bf_params_default(bf_params* out);
+
+bf_status bf_create(bf_context** out, void* hip_stream);   /* stream owned by the caller; NULL = default */
+void bf_destroy(bf_context* ctx);
+const char* bf_status_string(bf_status s);
+const char* bf_last_error(const bf_context* ctx);
+
+/*
+ * Per-frame preprocessing (Sec. 4.1.1: camera-space positions and normals of the
+ * low-resolution depth are cached per frame; Sec. 4.3: the photometric term uses
+ * the gradient of the luminance).
+ *   out_normal_depth: [F][H][W][4] float32 (nx, ny, nz, depth); the normal is NaN
+ *                     where it is invalid (image border, centre or a 4-neighbour
+ *                     without depth, vanishing cross product).  May be NULL.
+ *   out_grad:         [F][H][W] float32 central-difference gradient magnitude of the
+ *                     intensity, NaN on the border or next to non-finite intensity.
+ *                     May be NULL.
+ * The normal at (x,y) is the normalised cross product (P(x+1,y)-P(x-1,y)) x
+ * (P(x,y+1)-P(x,y-1)) oriented towards the camera.  Does not synchronise.
+ */
+bf_status bf_prepare_frames(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                            const bf_params* params, float* out_normal_depth, float* out_grad);
+
+/*
+ * Dense pair set E (Sec. 4.3): pairs i < j whose viewing directions are within
+ * max_angle_deg and where at least one pixel of a fixed 8x6 grid of frame i with
+ * valid depth projects in front of camera j and inside its image, evaluated at
+ * `poses`.  out_ij: [capacity][2] int32, sorted; *out_count (host) receives the
+ * number of pairs found (also when it exceeds capacity: then BF_ERR_INVALID_ARG).
+ */
+bf_status bf_build_pairs(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                         const double* poses, const bf_params* params,
+                         int32_t* out_ij, int64_t capacity, int64_t* out_count);
+
+/* Problem structure exported for inspection (all device, caller-allocated, each may be NULL). */
+typedef struct bf_structure {
+  int64_t num_pairs;        /* host out: dense pair jobs */
+  int64_t num_sparse_pairs; /* host out: distinct unordered frame pairs with correspondences */
+  int64_t num_edges;        /* host out: union of the two pair sets */
+  int64_t num_free;         /* host out: frames that are variables (not frame 0, at least one edge) */
+  int32_t* pairs_ij;        /* [num_pairs][2] */
+  int32_t* sparse_ij;       /* [num_sparse_pairs][2] */
+  int64_t* sparse_ptr;      /* [num_sparse_pairs+1] CSR into the sorted correspondences */
+  int64_t* corr_perm;       /* [corr count] stable sort of correspondences by (min, max) frame */
+  int32_t* edges_ij;        /* [num_edges][2] */
+  int32_t* free_frames;     /* [num_free] */
+} bf_structure;
+
+/*
+ * Build the per-solve structure (prepared frames, dense pairs -- computed from
+ * `poses` when pairs == NULL --, correspondence grouping, edge union, free frames)
+ * and export it into `out`.  The capacities of the out arrays are the caller's
+ * responsibility: call once with all pointers NULL to obtain the counts.
+ */
+bf_status bf_build_structure(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                             const bf_corrs* corrs, const bf_pairs* pairs, const double* poses,
+                             const bf_params* params, bf_structure* out);
+
+/*
+ * Residual evaluation at fixed poses (Sec. 4.3-4.4): the energy terms with the
+ * dense weight of Gauss-Newton iteration `gn_iter`.
+ *   out_energy (host) [4]: total, sparse, geometric, photometric (weighted, no 1/2).
+ *   out_counts (host) [3]: sparse correspondences, geometric and photometric
+ *                          residuals that were associated.
+ *   out_pair_records (device, may be NULL) [num_pairs][32] float64: per dense pair job
+ *     the upper triangle of sum w J_j^T J_j (21, row-major), sum w J_j^T r (6), the
+ *     weighted geometric and photometric energies and the two residual counts, where
+ *     J_j is the Jacobian with respect to the target frame's perturbation.
+ */
+bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                            const bf_corrs* corrs, const bf_pairs* pairs, const double* poses,
+                            const bf_params* params, int32_t gn_iter, double* out_energy,
+                            int64_t* out_counts, double* out_pair_records);
+
+/*
+ * Normal equations at fixed poses (Sec. 4.4): J^T J and J^T F of E_align with the
+ * dense weight of iteration `gn_iter`, kept in the context for bf_pcg_solve().
+ *   out_H (device, may be NULL): dense [6F][6F] float64 (for small problems / tests).
+ *   out_g (device, may be NULL): [6F] float64.
+ *   out_edge_blocks (device, may be NULL): [num_edges][128] float64 per edge (i,j):
+ *     H_ii (36), H_jj (36), H_ij (36), g_i (6), g_j (6), sparse, geometric and
+ *     photometric energy, and the three residual counts.
+ *   out_energy (host, may be NULL) [4] as for bf_eval_residuals.
+ */
+bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                                    const bf_corrs* corrs, const bf_pairs* pairs, const double* poses,
+                                    const bf_params* params, int32_t gn_iter, double* out_H,
+                                    double* out_g, double* out_edge_blocks, double* out_energy);
+
+/*
+ * Block-Jacobi PCG (Sec. 4.4) on the system of the last bf_build_normal_equations()
+ * call in this context: solves H' dx = -g' over the free frames from dx = 0 with
+ * `num_iters` iterations.  out_delta (device) [6F] float64 receives dx in frame
+ * order with zeros for frame 0 and frames that are not variables.
+ * out_stats (host, may be NULL) [3]: r^T z at the start, at the end, iterations run.
+ * BF_ERR_NOT_PD if a diagonal block cannot be factorised.
+ */
+bf_status bf_pcg_solve(bf_context* ctx, int32_t num_iters, double* out_delta, double* out_stats);
+
+/*
+ * The full solve (Sec. 4.3-4.4): params->num_gn Gauss-Newton iterations from
+ * init_poses, each evaluating residuals and Jacobians, reducing them into 6x6
+ * blocks, running params->num_pcg block-Jacobi PCG iterations and applying
+ * T_f <- T_f Exp(dx_f).  The dense pair set is computed from init_poses when
+ * pairs == NULL.  Frame 0 and frames without any constraint keep their pose
+ * bit for bit.
+ *   out_poses (device) [F][4][4] float64; may alias init_poses.
+ *   out_energy (host) [4]: energy at the returned poses with the last iteration's w_d.
+ *   out_trace (host, may be NULL) [num_gn][4]: energy at the start of each iteration.
+ */
+bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                          const bf_corrs* corrs, const bf_pairs* pairs, const double* init_poses,
+                          const bf_params* params, double* out_poses, double* out_energy,
+                          double* out_trace);
+
+/* Microseconds spent in each phase of the last bf_gauss_newton() call run with
+ * params->timing = 1, measured with HIP events on the context's stream (host out,
+ * [8]): setup, dense pair jobs (sum over iterations), edge blocks, assembly,
+ * PCG + update, final energy, total, and the number of dense pair-job launches. */
+bf_status bf_last_timings(const bf_context* ctx, double* out_us);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BF_H */

@@ -1,0 +1,512 @@
+// C entry points of libbf (declared and documented in include/bf.h).
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+struct bf_context : bf::Context {
+  std::vector<hipEvent_t> pool;
+};
+
+namespace bf {
+
+void fail(bf_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) fail(BF_ERR_OUT_OF_MEMORY, std::string(what) + ": out of device memory");
+    fail(BF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+void ensure(Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return;
+  if (b.p) {
+    check_hip(hipFree(b.p), "hipFree");
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t cap = bytes + bytes / 4;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, cap);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(BF_ERR_OUT_OF_MEMORY, "workspace allocation of " + std::to_string(cap) + " bytes failed");
+  }
+  b.p = p;
+  b.cap = cap;
+}
+
+namespace {
+
+__global__ void k_check_poses(const double* __restrict__ poses, int F, int* __restrict__ flags) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < F * 16 && !isfinite(poses[k])) raise_flag(flags, kFlagNonFinite);
+}
+
+__global__ void k_copy_if_ok(const double* __restrict__ src, double* __restrict__ dst, int n,
+                             const int* __restrict__ flags) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && flags[0] == 0) dst[k] = src[k];
+}
+
+void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_params* prm) {
+  if (!ctx) fail(BF_ERR_INVALID_ARG, "null context");
+  if (!fr || !in || !prm) fail(BF_ERR_INVALID_ARG, "null frames, intrinsics or params");
+  if (fr->num_frames < 1) fail(BF_ERR_INVALID_ARG, "num_frames must be >= 1");
+  if (fr->num_frames > 16384) fail(BF_ERR_UNSUPPORTED, "more than 16384 frames");
+  if (!fr->depth || !fr->intensity) fail(BF_ERR_INVALID_ARG, "null depth or intensity");
+  if (in->width < 3 || in->height < 3 || in->width > 4096 || in->height > 4096)
+    fail(BF_ERR_INVALID_ARG, "image size must be within [3, 4096]");
+  if (!(in->fx > 0) || !(in->fy > 0) || !isfinite(in->fx) || !isfinite(in->fy) || !isfinite(in->cx) ||
+      !isfinite(in->cy))
+    fail(BF_ERR_INVALID_ARG, "bad intrinsics");
+  if ((int64_t)in->width * in->height * fr->num_frames > (int64_t)1 << 34) fail(BF_ERR_UNSUPPORTED, "frames too large");
+  if (prm->num_gn < 0 || prm->num_gn > 1000 || prm->num_pcg < 0 || prm->num_pcg > 100000)
+    fail(BF_ERR_INVALID_ARG, "iteration counts out of range");
+  if (!(prm->w_sparse >= 0) || !(prm->w_dense >= 0) || !(prm->w_geo >= 0) || !(prm->w_photo >= 0) ||
+      !isfinite(prm->w_sparse) || !isfinite(prm->w_dense) || !isfinite(prm->w_geo) || !isfinite(prm->w_photo))
+    fail(BF_ERR_INVALID_ARG, "weights must be finite and >= 0");
+  if (prm->accumulate != 0 && prm->accumulate != 1) fail(BF_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+  if (prm->pcg_storage != 0 && prm->pcg_storage != 1) fail(BF_ERR_INVALID_ARG, "pcg_storage must be 0 or 1");
+  if (!(prm->tau_dist > 0) || !isfinite(prm->tau_normal) || !(prm->depth_max > prm->depth_min) ||
+      !isfinite(prm->max_angle_deg))
+    fail(BF_ERR_INVALID_ARG, "bad thresholds");
+}
+
+void validate_problem(const bf_corrs* co, const bf_pairs* pairs, const double* poses) {
+  if (!poses) fail(BF_ERR_INVALID_ARG, "null poses");
+  if (co) {
+    if (co->count < 0) fail(BF_ERR_INVALID_ARG, "negative correspondence count");
+    if (co->count > 0 && (!co->frame_i || !co->frame_j || !co->p_i || !co->p_j))
+      fail(BF_ERR_INVALID_ARG, "null correspondence arrays");
+    if (co->count > ((int64_t)1 << 31) - 2) fail(BF_ERR_UNSUPPORTED, "too many correspondences");
+  }
+  if (pairs) {
+    if (pairs->count < 0) fail(BF_ERR_INVALID_ARG, "negative pair count");
+    if (pairs->count > 0 && !pairs->ij) fail(BF_ERR_INVALID_ARG, "null pair array");
+  }
+}
+
+double dense_weight(const bf_params& p, int k) {
+  if (!p.dense_ramp || p.num_gn <= 0) return p.w_dense;
+  return p.w_dense * (double)(k + 1) / (double)p.num_gn;
+}
+
+void check_poses(Context& c, const double* poses, int F) {
+  ensure(c.flags, sizeof(int));
+  hipLaunchKernelGGL(k_check_poses, dim3((F * 16 + 255) / 256), dim3(256), 0, c.stream, poses, F, c.flags.as<int>());
+}
+
+// Structure + per-iteration buffers for the current shape.
+void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co, const bf_pairs* pairs,
+           const double* poses, const bf_params* prm) {
+  Context& c = *ctx;
+  c.pcg_storage = prm->pcg_storage;
+  c.have_system = false;
+  ensure(c.counts, 8 * sizeof(long long));
+  ensure(c.flags, sizeof(int));
+  build_structure(c, *fr, *in, co, pairs, poses, *prm);
+  const Shape& s = c.shape;
+  ensure(c.records, sizeof(double) * kRecWords * (s.P + 1));
+  ensure(c.eblocks, sizeof(double) * kEdgeWords * (s.E + 1));
+  if (c.pcg_storage == 1) {
+    ensure(c.hij64, sizeof(double) * 36 * (s.E + 1));
+    ensure(c.diag64, sizeof(double) * 36 * (s.nfree + 1));
+    ensure(c.minv64, sizeof(double) * 36 * (s.nfree + 1));
+    ensure(c.rhs, sizeof(double) * 6 * (s.nfree + 1));
+    ensure(c.pcg_vec, sizeof(double) * 5 * 6 * (s.nfree + 1));
+  } else {
+    ensure(c.hij32, sizeof(float) * 36 * (s.E + 1));
+    ensure(c.diag32, sizeof(float) * 36 * (s.nfree + 1));
+    ensure(c.minv32, sizeof(float) * 36 * (s.nfree + 1));
+    ensure(c.rhs, sizeof(float) * 6 * (s.nfree + 1));
+    ensure(c.pcg_vec, sizeof(float) * 5 * 6 * (s.nfree + 1));
+  }
+  ensure(c.energy, sizeof(double) * 8);
+  ensure(c.stats, sizeof(double) * 4);
+}
+
+void sync_and_flags(Context& c, int* hf) {
+  check_hip(hipMemcpyAsync(hf, c.flags.p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy flags");
+  check_hip(hipStreamSynchronize(c.stream), "synchronise");
+}
+
+void raise_flags(int fl) {
+  if (fl & kFlagBadIndex) fail(BF_ERR_INVALID_ARG, "index out of range");
+  if (fl & kFlagUnsorted) fail(BF_ERR_INVALID_ARG, "dense pairs are not strictly increasing");
+  if (fl & kFlagNonFinite) fail(BF_ERR_NONFINITE, "non-finite input");
+  if (fl & kFlagNotPD) fail(BF_ERR_NOT_PD, "a diagonal block of J^T J is not positive definite");
+}
+
+struct Timer {
+  bf_context* ctx;
+  bool on;
+  std::vector<std::pair<int, int>> spans[6];
+  int used = 0;
+  Timer(bf_context* c, bool enable) : ctx(c), on(enable) {}
+  int mark() {
+    if (!on) return -1;
+    if (used >= (int)ctx->pool.size()) {
+      hipEvent_t e;
+      check_hip(hipEventCreate(&e), "hipEventCreate");
+      ctx->pool.push_back(e);
+    }
+    check_hip(hipEventRecord(ctx->pool[used], ctx->stream), "hipEventRecord");
+    return used++;
+  }
+  void span(int slot, int a, int b) {
+    if (on) spans[slot].push_back({a, b});
+  }
+  void finish(double* out) {
+    for (int k = 0; k < 8; ++k) out[k] = 0.0;
+    if (!on) return;
+    for (int s = 0; s < 6; ++s)
+      for (auto& ab : spans[s]) {
+        float ms = 0.f;
+        check_hip(hipEventElapsedTime(&ms, ctx->pool[ab.first], ctx->pool[ab.second]), "hipEventElapsedTime");
+        out[s] += 1000.0 * ms;
+      }
+    out[7] = (double)spans[1].size();
+  }
+};
+
+template <class Fn>
+bf_status guarded(bf_context* ctx, Fn fn) {
+  try {
+    fn();
+    if (ctx) ctx->last_error.clear();
+    return BF_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->last_error = "host allocation failed";
+    return BF_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    if (ctx) ctx->last_error = "unexpected exception";
+    return BF_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+}  // namespace bf
+
+using namespace bf;
+
+extern "C" {
+
+void bf_params_default(bf_params* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->w_sparse = 1.0;
+  o->w_dense = 1.0;
+  o->w_geo = 1.0;
+  o->w_photo = 1.178;
+  o->dense_ramp = 1;
+  o->use_sparse = 1;
+  o->use_dense = 1;
+  o->num_gn = 5;
+  o->num_pcg = 10;
+  o->accumulate = 0;
+  o->pcg_storage = 0;
+  o->timing = 0;
+  o->tau_dist = 0.15;
+  o->tau_normal = 0.9;
+  o->max_angle_deg = 60.0;
+  o->depth_min = 0.1;
+  o->depth_max = 10.0;
+}
+
+bf_status bf_create(bf_context** out, void* hip_stream) {
+  if (!out) return BF_ERR_INVALID_ARG;
+  *out = nullptr;
+  bf_context* c = new (std::nothrow) bf_context();
+  if (!c) return BF_ERR_OUT_OF_MEMORY;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return BF_ERR_DEVICE;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+    delete c;
+    return BF_ERR_DEVICE;
+  }
+  c->num_cus = cus;
+  *out = c;
+  return BF_OK;
+}
+
+void bf_destroy(bf_context* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  Buf* bufs[] = {&c->nd, &c->grad, &c->kx, &c->ky, &c->pair_flags, &c->row_count, &c->row_off, &c->pairs,
+                 &c->pair_keys, &c->corr_key, &c->corr_idx, &c->corr_key_sorted, &c->corr_perm, &c->corr_head,
+                 &c->corr_group, &c->sparse_ij, &c->sparse_keys, &c->sparse_ptr, &c->moments, &c->in_b,
+                 &c->common_scan, &c->edge_ij, &c->edge_keys, &c->edge_dense, &c->edge_sparse, &c->ej_key,
+                 &c->ej_idx, &c->ej_key_sorted, &c->ej_sorted, &c->iptr, &c->jptr, &c->free_flag, &c->var_of,
+                 &c->frame_of_var, &c->records, &c->eblocks, &c->hij32, &c->hij64, &c->diag32, &c->diag64,
+                 &c->minv32, &c->minv64, &c->rhs, &c->poses_work, &c->pcg_vec, &c->stats, &c->trace,
+                 &c->cub_tmp, &c->counts, &c->flags, &c->host_pinned, &c->energy};
+  for (Buf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* bf_status_string(bf_status s) {
+  switch (s) {
+    case BF_OK: return "ok";
+    case BF_ERR_INVALID_ARG: return "invalid argument";
+    case BF_ERR_OUT_OF_MEMORY: return "out of memory";
+    case BF_ERR_DEVICE: return "device error";
+    case BF_ERR_NOT_PD: return "matrix not positive definite";
+    case BF_ERR_NONFINITE: return "non-finite input";
+    case BF_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* bf_last_error(const bf_context* c) { return c ? c->last_error.c_str() : "null context"; }
+
+bf_status bf_prepare_frames(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_params* prm,
+                            float* out_nd, float* out_grad) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    Context& c = *ctx;
+    size_t HW = (size_t)in->width * in->height;
+    ensure(c.nd, sizeof(float4) * HW * fr->num_frames);
+    ensure(c.grad, sizeof(float) * HW * fr->num_frames);
+    ensure(c.kx, sizeof(float) * in->width);
+    ensure(c.ky, sizeof(float) * in->height);
+    launch_prepare(c, *fr, *in, *prm);
+    if (out_nd)
+      check_hip(hipMemcpyAsync(out_nd, c.nd.p, sizeof(float4) * HW * fr->num_frames, hipMemcpyDeviceToDevice,
+                               c.stream), "copy normals");
+    if (out_grad)
+      check_hip(hipMemcpyAsync(out_grad, c.grad.p, sizeof(float) * HW * fr->num_frames, hipMemcpyDeviceToDevice,
+                               c.stream), "copy gradients");
+  });
+}
+
+bf_status bf_build_pairs(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const double* poses,
+                         const bf_params* prm, int32_t* out_ij, int64_t capacity, int64_t* out_count) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(nullptr, nullptr, poses);
+    if (!out_count) fail(BF_ERR_INVALID_ARG, "null out_count");
+    Context& c = *ctx;
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
+    check_poses(c, poses, fr->num_frames);
+    int64_t P = launch_pair_search(c, *fr, *in, poses, *prm);
+    int hf = 0;
+    sync_and_flags(c, &hf);
+    raise_flags(hf);
+    *out_count = P;
+    if (P > capacity) fail(BF_ERR_INVALID_ARG, "pair capacity too small");
+    if (P > 0) {
+      if (!out_ij) fail(BF_ERR_INVALID_ARG, "null out_ij");
+      check_hip(hipMemcpyAsync(out_ij, c.pairs.p, sizeof(int) * 2 * P, hipMemcpyDeviceToDevice, c.stream), "copy");
+      check_hip(hipStreamSynchronize(c.stream), "synchronise");
+    }
+  });
+}
+
+bf_status bf_build_structure(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
+                             const bf_pairs* pairs, const double* poses, const bf_params* prm, bf_structure* out) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(co, pairs, poses);
+    if (!out) fail(BF_ERR_INVALID_ARG, "null out");
+    Context& c = *ctx;
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
+    check_poses(c, poses, fr->num_frames);
+    setup(ctx, fr, in, co, pairs, poses, prm);
+    const Shape& s = c.shape;
+    out->num_pairs = s.P;
+    out->num_sparse_pairs = s.S;
+    out->num_edges = s.E;
+    out->num_free = s.nfree;
+    auto cp = [&](void* dst, const Buf& src, size_t bytes) {
+      if (dst && bytes) check_hip(hipMemcpyAsync(dst, src.p, bytes, hipMemcpyDeviceToDevice, c.stream), "copy");
+    };
+    cp(out->pairs_ij, c.pairs, sizeof(int) * 2 * s.P);
+    cp(out->sparse_ij, c.sparse_ij, sizeof(int) * 2 * s.S);
+    if (s.S > 0) cp(out->sparse_ptr, c.sparse_ptr, sizeof(long long) * (s.S + 1));
+    cp(out->corr_perm, c.corr_perm, sizeof(long long) * s.M);
+    cp(out->edges_ij, c.edge_ij, sizeof(int) * 2 * s.E);
+    cp(out->free_frames, c.frame_of_var, sizeof(int) * s.nfree);
+    check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  });
+}
+
+bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
+                            const bf_pairs* pairs, const double* poses, const bf_params* prm, int32_t gn_iter,
+                            double* out_energy, int64_t* out_counts, double* out_records) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(co, pairs, poses);
+    if (!out_energy) fail(BF_ERR_INVALID_ARG, "null out_energy");
+    Context& c = *ctx;
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
+    check_poses(c, poses, fr->num_frames);
+    setup(ctx, fr, in, co, pairs, poses, prm);
+    double wd = dense_weight(*prm, gn_iter);
+    bool jac = out_records != nullptr;
+    launch_dense(c, *in, poses, *prm, wd, jac);
+    launch_edge_blocks(c, poses, *prm, false);
+    launch_energy(c, c.energy.as<double>());
+    if (out_records && c.shape.P > 0)
+      check_hip(hipMemcpyAsync(out_records, c.records.p, sizeof(double) * kRecWords * c.shape.P,
+                               hipMemcpyDeviceToDevice, c.stream), "copy records");
+    double e8[8];
+    int hf = 0;
+    check_hip(hipMemcpyAsync(e8, c.energy.p, sizeof(e8), hipMemcpyDeviceToHost, c.stream), "copy energy");
+    sync_and_flags(c, &hf);
+    raise_flags(hf);
+    for (int k = 0; k < 4; ++k) out_energy[k] = e8[k];
+    if (out_counts)
+      for (int k = 0; k < 3; ++k) out_counts[k] = (int64_t)llround(e8[4 + k]);
+  });
+}
+
+bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in,
+                                    const bf_corrs* co, const bf_pairs* pairs, const double* poses,
+                                    const bf_params* prm, int32_t gn_iter, double* out_H, double* out_g,
+                                    double* out_edge_blocks, double* out_energy) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(co, pairs, poses);
+    Context& c = *ctx;
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
+    check_poses(c, poses, fr->num_frames);
+    setup(ctx, fr, in, co, pairs, poses, prm);
+    double wd = dense_weight(*prm, gn_iter);
+    launch_dense(c, *in, poses, *prm, wd, true);
+    launch_edge_blocks(c, poses, *prm, true);
+    launch_energy(c, c.energy.as<double>());
+    launch_assemble(c);
+    if (out_H || out_g) launch_export_dense(c, out_H, out_g);
+    if (out_edge_blocks && c.shape.E > 0)
+      check_hip(hipMemcpyAsync(out_edge_blocks, c.eblocks.p, sizeof(double) * kEdgeWords * c.shape.E,
+                               hipMemcpyDeviceToDevice, c.stream), "copy edge blocks");
+    double e8[8];
+    int hf = 0;
+    check_hip(hipMemcpyAsync(e8, c.energy.p, sizeof(e8), hipMemcpyDeviceToHost, c.stream), "copy energy");
+    sync_and_flags(c, &hf);
+    c.have_system = true;
+    raise_flags(hf & ~kFlagNotPD);
+    if (out_energy)
+      for (int k = 0; k < 4; ++k) out_energy[k] = e8[k];
+  });
+}
+
+bf_status bf_pcg_solve(bf_context* ctx, int32_t num_iters, double* out_delta, double* out_stats) {
+  return guarded(ctx, [&] {
+    if (!ctx) fail(BF_ERR_INVALID_ARG, "null context");
+    Context& c = *ctx;
+    if (!c.have_system) fail(BF_ERR_INVALID_ARG, "no system: call bf_build_normal_equations first");
+    if (num_iters < 0) fail(BF_ERR_INVALID_ARG, "negative iteration count");
+    if (!out_delta) fail(BF_ERR_INVALID_ARG, "null out_delta");
+    if (c.shape.nfree == 0) {
+      check_hip(hipMemsetAsync(out_delta, 0, sizeof(double) * 6 * c.shape.F, c.stream), "memset");
+    } else {
+      launch_pcg(c, num_iters, out_delta, nullptr, c.stats.as<double>(), false);
+    }
+    double st[4] = {0, 0, 0, 0};
+    int hf = 0;
+    if (c.shape.nfree > 0)
+      check_hip(hipMemcpyAsync(st, c.stats.p, sizeof(double) * 3, hipMemcpyDeviceToHost, c.stream), "copy stats");
+    sync_and_flags(c, &hf);
+    raise_flags(hf);
+    if (out_stats)
+      for (int k = 0; k < 3; ++k) out_stats[k] = st[k];
+  });
+}
+
+bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
+                          const bf_pairs* pairs, const double* init_poses, const bf_params* prm, double* out_poses,
+                          double* out_energy, double* out_trace) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(co, pairs, init_poses);
+    if (!out_poses || !out_energy) fail(BF_ERR_INVALID_ARG, "null out_poses or out_energy");
+    Context& c = *ctx;
+    Timer tm(ctx, prm->timing != 0);
+    const int F = fr->num_frames;
+    int t_start = tm.mark();
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
+    check_poses(c, init_poses, F);
+    setup(ctx, fr, in, co, pairs, init_poses, prm);
+    ensure(c.poses_work, sizeof(double) * 16 * F);
+    ensure(c.trace, sizeof(double) * 8 * (prm->num_gn + 1));
+    double* poses = c.poses_work.as<double>();
+    check_hip(hipMemcpyAsync(poses, init_poses, sizeof(double) * 16 * F, hipMemcpyDeviceToDevice, c.stream),
+              "copy poses");
+    int t_setup = tm.mark();
+    tm.span(0, t_start, t_setup);
+    for (int k = 0; k < prm->num_gn; ++k) {
+      double wd = dense_weight(*prm, k);
+      int a = tm.mark();
+      launch_dense(c, *in, poses, *prm, wd, true);
+      int b = tm.mark();
+      launch_edge_blocks(c, poses, *prm, true);
+      launch_energy(c, c.trace.as<double>() + 8 * k);
+      int d = tm.mark();
+      launch_assemble(c);
+      int e = tm.mark();
+      if (c.shape.nfree > 0) launch_pcg(c, prm->num_pcg, nullptr, poses, nullptr, true);
+      int f = tm.mark();
+      tm.span(1, a, b);
+      tm.span(2, b, d);
+      tm.span(3, d, e);
+      tm.span(4, e, f);
+    }
+    int g0 = tm.mark();
+    double wd = dense_weight(*prm, prm->num_gn > 0 ? prm->num_gn - 1 : 0);
+    launch_dense(c, *in, poses, *prm, wd, false);
+    launch_edge_blocks(c, poses, *prm, false);
+    launch_energy(c, c.energy.as<double>());
+    hipLaunchKernelGGL(k_copy_if_ok, dim3((16 * F + 255) / 256), dim3(256), 0, c.stream, poses, out_poses, 16 * F,
+                       c.flags.as<int>());
+    int g1 = tm.mark();
+    tm.span(5, g0, g1);
+    double e8[8];
+    int hf = 0;
+    std::vector<double> tr(8 * (size_t)(prm->num_gn + 1));
+    check_hip(hipMemcpyAsync(e8, c.energy.p, sizeof(e8), hipMemcpyDeviceToHost, c.stream), "copy energy");
+    if (out_trace && prm->num_gn > 0)
+      check_hip(hipMemcpyAsync(tr.data(), c.trace.p, sizeof(double) * 8 * prm->num_gn, hipMemcpyDeviceToHost,
+                               c.stream), "copy trace");
+    sync_and_flags(c, &hf);
+    raise_flags(hf);
+    for (int k = 0; k < 4; ++k) out_energy[k] = e8[k];
+    if (out_trace)
+      for (int k = 0; k < prm->num_gn; ++k)
+        for (int l = 0; l < 4; ++l) out_trace[4 * k + l] = tr[8 * k + l];
+    tm.finish(c.timings);
+    if (tm.on) {
+      float ms = 0.f;
+      check_hip(hipEventElapsedTime(&ms, ctx->pool[t_start], ctx->pool[g1]), "hipEventElapsedTime");
+      c.timings[6] = 1000.0 * ms;
+    }
+  });
+}
+
+bf_status bf_last_timings(const bf_context* ctx, double* out_us) {
+  if (!ctx || !out_us) return BF_ERR_INVALID_ARG;
+  for (int k = 0; k < 8; ++k) out_us[k] = ctx->timings[k];
+  return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Host-side context, workspace and launch declarations of libbf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace bf {
+
+// A device buffer that only grows.
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct Error {
+  bf_status status;
+  std::string msg;
+};
+
+// Per-solve structure sizes (host copies of the device-side counts).
+struct Shape {
+  int F = 0, W = 0, H = 0;
+  int64_t M = 0;            // correspondences
+  int64_t P = 0;            // dense pair jobs
+  int64_t S = 0;            // sparse pairs (distinct unordered frame pairs with correspondences)
+  int64_t E = 0;            // edges (union)
+  int64_t nfree = 0;        // free frames
+};
+
+struct Context {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cus = 0;
+  std::string last_error;
+  Shape shape;
+  bool have_system = false;
+  int pcg_storage = 0;
+  double timings[8] = {0};
+
+  // frames
+  Buf nd, grad, kx, ky;
+  // pairs
+  Buf pair_flags, row_count, row_off, pairs, pair_keys;
+  // correspondences
+  Buf corr_key, corr_idx, corr_key_sorted, corr_perm, corr_head, corr_group, sparse_ij, sparse_keys, sparse_ptr,
+      moments;
+  // edges and incidence
+  Buf in_b, common_scan, edge_ij, edge_keys, edge_dense, edge_sparse, ej_key, ej_idx, ej_key_sorted, ej_sorted,
+      iptr, jptr, free_flag, var_of, frame_of_var;
+  // per-iteration data
+  Buf records, eblocks, hij32, hij64, diag32, diag64, minv32, minv64, rhs, poses_work, pcg_vec, stats, trace;
+  // scratch
+  Buf cub_tmp, counts, flags, host_pinned, energy;
+
+  hipEvent_t ev[16] = {};
+  bool events_ready = false;
+};
+
+// Error helpers: throw an Error from host code; the C entry points catch it.
+[[noreturn]] void fail(bf_status s, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+void ensure(Buf& b, size_t bytes);
+
+// prep.hip
+void launch_prepare(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_params& prm);
+
+// structure.hip
+void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_corrs* co,
+                     const bf_pairs* pairs, const double* poses, const bf_params& prm);
+int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics& in, const double* poses,
+                           const bf_params& prm);
+
+// dense.hip
+void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
+                  bool with_jacobians);
+
+// solve.hip
+void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, bool with_jacobians);
+void launch_assemble(Context& c);
+void launch_pcg(Context& c, int iters, double* delta_out, double* poses_inout, double* stats, bool update_poses);
+void launch_energy(Context& c, double* dst8);
+void launch_export_dense(Context& c, double* H, double* g);
+
+}  // namespace bf

@@ -1,0 +1,91 @@
+// Per-frame preparation (paper Sec. 4.1.1: positions and normals of the
+// low-resolution depth are computed once and cached per frame; Sec. 4.3: the
+// photometric term reads the gradient of the luminance).
+//
+// Output per pixel: float4 (nx, ny, nz, depth) with a NaN normal where it is not
+// valid, and the central-difference gradient magnitude G (NaN where invalid).
+// Positions are not stored: P = (kx[x] D, ky[y] D, D) is recomputed from the depth
+// with kx[x] = fl32((x - cx) / fx), 4 bytes per pixel instead of 12.
+#include "internal.h"
+
+namespace bf {
+
+__device__ __forceinline__ bool depth_ok(float d, float dmin, float dmax) {
+  return (d == d) && d >= dmin && d <= dmax && d != __builtin_inff();
+}
+
+__global__ void __launch_bounds__(256) k_ray_tables(double fx, double fy, double cx, double cy, int W, int H,
+                                                    float* __restrict__ kx, float* __restrict__ ky) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < W) kx[t] = (float)(((double)t - cx) / fx);
+  if (t < H) ky[t] = (float)(((double)t - cy) / fy);
+}
+
+// One thread per pixel, grid (ceil(W*H/256), F).
+__global__ void __launch_bounds__(256) k_prepare(const float* __restrict__ depth, const float* __restrict__ inten,
+                                                 const float* __restrict__ kx, const float* __restrict__ ky, int W,
+                                                 int H, float dmin, float dmax, float4* __restrict__ nd,
+                                                 float* __restrict__ grad) {
+  const int HW = W * H;
+  const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pix >= HW) return;
+  const size_t base = (size_t)blockIdx.y * HW;
+  const int x = pix % W, y = pix / W;
+  const float* D = depth + base;
+  const float* L = inten + base;
+  const float nan = __builtin_nanf("");
+  float d = D[pix];
+  float4 out = make_float4(nan, nan, nan, d);
+  float g = nan;
+  bool inner = x > 0 && x < W - 1 && y > 0 && y < H - 1;
+  if (inner) {
+    float dl = D[pix - 1], dr = D[pix + 1], du = D[pix - W], dd = D[pix + W];
+    if (depth_ok(d, dmin, dmax) && depth_ok(dl, dmin, dmax) && depth_ok(dr, dmin, dmax) &&
+        depth_ok(du, dmin, dmax) && depth_ok(dd, dmin, dmax)) {
+#pragma clang fp contract(off)
+      float kxl = kx[x - 1], kxr = kx[x + 1], kxc = kx[x];
+      float kyu = ky[y - 1], kyd = ky[y + 1], kyc = ky[y];
+      // d1 = P(x+1,y) - P(x-1,y), d2 = P(x,y+1) - P(x,y-1)
+      float d1x = kxr * dr - kxl * dl, d1y = kyc * dr - kyc * dl, d1z = dr - dl;
+      float d2x = kxc * dd - kxc * du, d2y = kyd * dd - kyu * du, d2z = dd - du;
+      float cx_ = d1y * d2z - d1z * d2y;
+      float cy_ = d1z * d2x - d1x * d2z;
+      float cz_ = d1x * d2y - d1y * d2x;
+      float l2 = (cx_ * cx_ + cy_ * cy_) + cz_ * cz_;
+      if (l2 > 0.0f) {
+        float nrm = sqrtf(l2);
+        float nx = cx_ / nrm, ny = cy_ / nrm, nz = cz_ / nrm;
+        float px = kxc * d, py = kyc * d;
+        float s = (nx * px + ny * py) + nz * d;
+        if (s > 0.0f) {
+          nx = -nx;
+          ny = -ny;
+          nz = -nz;
+        }
+        out.x = nx;
+        out.y = ny;
+        out.z = nz;
+      }
+    }
+    float lc = L[pix], ll = L[pix - 1], lr = L[pix + 1], lu = L[pix - W], ld = L[pix + W];
+    if (isfinite(lc) && isfinite(ll) && isfinite(lr) && isfinite(lu) && isfinite(ld)) {
+      float gx = (lr - ll) * 0.5f, gy = (ld - lu) * 0.5f;
+      g = sqrtf(gx * gx + gy * gy);
+    }
+  }
+  nd[base + pix] = out;
+  grad[base + pix] = g;
+}
+
+void launch_prepare(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_params& prm) {
+  const int W = in.width, H = in.height;
+  int n = W > H ? W : H;
+  hipLaunchKernelGGL(k_ray_tables, dim3((n + 255) / 256), dim3(256), 0, c.stream, in.fx, in.fy, in.cx, in.cy, W, H,
+                     c.kx.as<float>(), c.ky.as<float>());
+  dim3 grid((W * H + 255) / 256, fr.num_frames);
+  hipLaunchKernelGGL(k_prepare, grid, dim3(256), 0, c.stream, fr.depth, fr.intensity, c.kx.as<float>(),
+                     c.ky.as<float>(), W, H, (float)prm.depth_min, (float)prm.depth_max, c.nd.as<float4>(),
+                     c.grad.as<float>());
+}
+
+}  // namespace bf

@@ -1,0 +1,545 @@
+// Per-solve structure of the energy.
+//
+// * Dense pair set E (paper Sec. 4.3: viewing directions within 60 degrees and
+//   non-zero overlap).  Overlap is tested on a fixed 8x6 pixel grid of the lower
+//   frame: at least one grid pixel with valid depth must land in front of the
+//   other camera and inside its image.  FP64, fixed operation order, no
+//   contraction, so the set is reproducible bit for bit.
+// * Sparse correspondences (Sec. 4.3, E_sparse) grouped by unordered frame pair
+//   with a stable radix sort, and reduced once per solve to FP64 moments
+//   (count, sums of p and q, and of p p^T, q q^T, p q^T).  The sparse residual
+//   is affine in p and q, so its J^T J blocks, J^T r and energy at any poses are
+//   functions of these moments (evaluated per edge in solve.hip).
+// * Edges: the sorted union of dense pairs and sparse pairs; per-frame incidence
+//   (edges where the frame is the lower index are contiguous; the others come
+//   from a stable sort by the upper index); free frames (not frame 0, at least
+//   one edge) numbered in frame order.
+#include <hipcub/hipcub.hpp>
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace bf {
+
+namespace {
+
+template <class Fn>
+void cub_call(Context& c, Fn fn) {
+  size_t bytes = 0;
+  check_hip(fn(nullptr, bytes), "hipcub size query");
+  ensure(c.cub_tmp, bytes + 256);
+  check_hip(fn(c.cub_tmp.p, bytes), "hipcub call");
+}
+
+int bits_for(uint64_t v) {
+  int b = 1;
+  while (b < 63 && (1ull << b) <= v) ++b;
+  return b;
+}
+
+__device__ __forceinline__ bool depth_valid(float d, float dmin, float dmax) {
+  return (d == d) && d >= dmin && d <= dmax && d != __builtin_inff();
+}
+
+// ---------------------------------------------------------------- dense pair test
+
+// Does grid point p of frame i land in front of camera j and inside its image?
+__device__ __forceinline__ bool grid_point_hits(const double* R, const double* t, double p0, double p1, double p2,
+                                                double fx, double fy, double cx, double cy, int W, int H) {
+#pragma clang fp contract(off)
+  double c0 = ((R[0] * p0 + R[1] * p1) + R[2] * p2) + t[0];
+  double c1 = ((R[3] * p0 + R[4] * p1) + R[5] * p2) + t[1];
+  double c2 = ((R[6] * p0 + R[7] * p1) + R[8] * p2) + t[2];
+  if (!(c2 > 0.0)) return false;
+  double u = ((fx * c0) / c2) + cx;
+  double v = ((fy * c1) / c2) + cy;
+  return u >= 0.0 && u <= (double)(W - 1) && v >= 0.0 && v <= (double)(H - 1);
+}
+
+// One workgroup per source frame i; thread per candidate j > i.
+__global__ void __launch_bounds__(256) k_pair_rows(const float* __restrict__ depth, const double* __restrict__ poses,
+                                                   int F, int W, int H, double fx, double fy, double cx, double cy,
+                                                   float dmin, float dmax, double cos_lim,
+                                                   uint8_t* __restrict__ flags, long long* __restrict__ row_count) {
+  const int i = blockIdx.x;
+  __shared__ double gp[48][3];
+  __shared__ int gvalid[48];
+  __shared__ double Ti[16];
+  __shared__ int red[256];
+  const int tid = threadIdx.x;
+  const int s = W / 80 > 0 ? W / 80 : 1;
+  if (tid < 48) {
+    int a = tid % 8, b = tid / 8;
+    int x = s * (5 + 10 * a), y = s * (5 + 10 * b);
+    int ok = 0;
+    double p0 = 0, p1 = 0, p2 = 0;
+    if (x < W && y < H) {
+      float d = depth[(size_t)i * W * H + (size_t)y * W + x];
+      if (depth_valid(d, dmin, dmax)) {
+#pragma clang fp contract(off)
+        double D = (double)d;
+        p0 = (((double)x - cx) / fx) * D;
+        p1 = (((double)y - cy) / fy) * D;
+        p2 = D;
+        ok = 1;
+      }
+    }
+    gp[tid][0] = p0;
+    gp[tid][1] = p1;
+    gp[tid][2] = p2;
+    gvalid[tid] = ok;
+  }
+  if (tid < 16) Ti[tid] = poses[(size_t)i * 16 + tid];
+  __syncthreads();
+  int cnt = 0;
+  for (int j = i + 1 + tid; j < F; j += blockDim.x) {
+    const double* Tj = poses + (size_t)j * 16;
+    bool hit = false;
+    double dot;
+    {
+#pragma clang fp contract(off)
+      dot = (Ti[2] * Tj[2] + Ti[6] * Tj[6]) + Ti[10] * Tj[10];
+    }
+    if (dot > cos_lim) {
+      double R[9], t[3];
+      relative_pose_nc(Ti, Tj, R, t);
+      for (int k = 0; k < 48 && !hit; ++k)
+        if (gvalid[k]) hit = grid_point_hits(R, t, gp[k][0], gp[k][1], gp[k][2], fx, fy, cx, cy, W, H);
+    }
+    flags[(size_t)i * F + j] = hit ? 1 : 0;
+    cnt += hit ? 1 : 0;
+  }
+  red[tid] = cnt;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) row_count[i] = red[0];
+}
+
+// One workgroup per row: block-scan the row's flags and write the pairs in order.
+__global__ void __launch_bounds__(256) k_pair_compact(const uint8_t* __restrict__ flags,
+                                                      const long long* __restrict__ row_off, int F,
+                                                      int* __restrict__ pairs, long long* __restrict__ keys) {
+  const int i = blockIdx.x;
+  __shared__ int sc[256];
+  const int tid = threadIdx.x;
+  long long base = row_off[i];
+  for (int j0 = i + 1; j0 < F; j0 += 256) {
+    int j = j0 + tid;
+    int f = (j < F) ? flags[(size_t)i * F + j] : 0;
+    sc[tid] = f;
+    __syncthreads();
+    // inclusive Hillis-Steele scan
+    for (int o = 1; o < 256; o <<= 1) {
+      int v = (tid >= o) ? sc[tid - o] : 0;
+      __syncthreads();
+      sc[tid] += v;
+      __syncthreads();
+    }
+    if (f) {
+      long long r = base + sc[tid] - 1;
+      pairs[2 * r] = i;
+      pairs[2 * r + 1] = j;
+      keys[r] = (long long)i * F + j;
+    }
+    base += sc[255];
+    __syncthreads();
+  }
+}
+
+// Caller-given pairs: range / order validation and keys.
+__global__ void k_pairs_check(const int* __restrict__ ij, long long P, int F, int* __restrict__ pairs_out,
+                              long long* __restrict__ keys, int* __restrict__ flags) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  int i = ij[2 * k], j = ij[2 * k + 1];
+  bool ok = i >= 0 && j < F && i < j;
+  if (!ok) raise_flag(flags, kFlagBadIndex);
+  if (k > 0) {
+    int pi = ij[2 * k - 2], pj = ij[2 * k - 1];
+    if (!(pi < i || (pi == i && pj < j))) raise_flag(flags, kFlagUnsorted);
+  }
+  pairs_out[2 * k] = ok ? i : 0;
+  pairs_out[2 * k + 1] = ok ? j : 1;
+  keys[k] = ok ? (long long)i * F + j : 1;
+}
+
+// ---------------------------------------------------------------- correspondences
+
+__global__ void k_corr_keys(const int* __restrict__ fi, const int* __restrict__ fj, const float* __restrict__ pi,
+                            const float* __restrict__ pj, long long M, int F, long long* __restrict__ key,
+                            long long* __restrict__ idx, int* __restrict__ flags) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M) return;
+  int a = fi[c], b = fj[c];
+  bool ok = a >= 0 && a < F && b >= 0 && b < F && a != b;
+  if (!ok) raise_flag(flags, kFlagBadIndex);
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(pi[3 * c + k]) || !isfinite(pj[3 * c + k])) raise_flag(flags, kFlagNonFinite);
+  int lo = a < b ? a : b, hi = a < b ? b : a;
+  key[c] = ok ? (long long)lo * F + hi : 1;
+  idx[c] = c;
+}
+
+__global__ void k_corr_heads(const long long* __restrict__ ks, long long M, long long* __restrict__ head) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M) return;
+  head[c] = (c == 0 || ks[c] != ks[c - 1]) ? 1 : 0;
+}
+
+__global__ void k_corr_groups(const long long* __restrict__ ks, const long long* __restrict__ grp, long long M, int F,
+                              int* __restrict__ sparse_ij, long long* __restrict__ sparse_keys,
+                              long long* __restrict__ sparse_ptr, long long* __restrict__ counts) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M) return;
+  bool head = (c == 0 || ks[c] != ks[c - 1]);
+  if (head) {
+    long long g = grp[c] - 1;
+    long long k = ks[c];
+    sparse_keys[g] = k;
+    sparse_ij[2 * g] = (int)(k / F);
+    sparse_ij[2 * g + 1] = (int)(k % F);
+    sparse_ptr[g] = c;
+  }
+  if (c == M - 1) {
+    sparse_ptr[grp[c]] = M;
+    counts[1] = grp[c];
+  }
+}
+
+// One wavefront per sparse pair: FP64 moments of its correspondences in sorted order,
+// with the lower frame's point as p.  Fixed reduction tree, read from lane 0.
+__global__ void __launch_bounds__(64) k_moments(const int* __restrict__ fi, const int* __restrict__ fj,
+                                                const float* __restrict__ pi, const float* __restrict__ pj,
+                                                const long long* __restrict__ perm,
+                                                const long long* __restrict__ ptr, long long S,
+                                                double* __restrict__ mom) {
+  long long g = blockIdx.x;
+  if (g >= S) return;
+  const int lane = threadIdx.x;
+  double acc[kMomWords - 2];
+  for (int k = 0; k < kMomWords - 2; ++k) acc[k] = 0.0;
+  for (long long k = ptr[g] + lane; k < ptr[g + 1]; k += 64) {
+    long long c = perm[k];
+    bool sw = fi[c] > fj[c];
+    const float* P = sw ? pj : pi;
+    const float* Q = sw ? pi : pj;
+    double p[3] = {P[3 * c], P[3 * c + 1], P[3 * c + 2]};
+    double q[3] = {Q[3 * c], Q[3 * c + 1], Q[3 * c + 2]};
+    acc[kMN] += 1.0;
+    for (int a = 0; a < 3; ++a) {
+      acc[kMP + a] += p[a];
+      acc[kMQ + a] += q[a];
+      for (int b = 0; b < 3; ++b) {
+        acc[kMPP + 3 * a + b] += p[a] * p[b];
+        acc[kMQQ + 3 * a + b] += q[a] * q[b];
+        acc[kMPQ + 3 * a + b] += p[a] * q[b];
+      }
+    }
+  }
+  for (int k = 0; k < kMomWords - 2; ++k) {
+    double v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    acc[k] = v;
+  }
+  if (lane == 0) {
+    for (int k = 0; k < kMomWords - 2; ++k) mom[g * kMomWords + k] = acc[k];
+    mom[g * kMomWords + kMomWords - 2] = 0.0;
+    mom[g * kMomWords + kMomWords - 1] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- edges
+
+__device__ __forceinline__ long long lower_bound_ll(const long long* a, long long n, long long key) {
+  long long lo = 0, hi = n;
+  while (lo < hi) {
+    long long mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ long long lower_bound_i(const int* a, long long n, int key) {
+  long long lo = 0, hi = n;
+  while (lo < hi) {
+    long long mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_union_inb(const long long* __restrict__ A, long long nA, const long long* __restrict__ B,
+                            long long nB, long long* __restrict__ inb) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > nA) return;
+  if (k == nA) {
+    inb[k] = 0;
+    return;
+  }
+  long long pos = lower_bound_ll(B, nB, A[k]);
+  inb[k] = (pos < nB && B[pos] == A[k]) ? 1 : 0;
+}
+
+// rank of a in the union = (#A < a) + (#B < a) - (#common < a); cA = exclusive scan of inb.
+__global__ void k_union_write(const long long* __restrict__ A, long long nA, const long long* __restrict__ B,
+                              long long nB, const long long* __restrict__ cA, int F, long long* __restrict__ ekeys,
+                              int* __restrict__ eij, long long* __restrict__ edense, long long* __restrict__ esparse,
+                              long long* __restrict__ counts) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) counts[2] = nA + nB - cA[nA];
+  if (k < nA) {
+    long long key = A[k];
+    long long pos = lower_bound_ll(B, nB, key);
+    bool found = pos < nB && B[pos] == key;
+    long long r = k + pos - cA[k];
+    ekeys[r] = key;
+    eij[2 * r] = (int)(key / F);
+    eij[2 * r + 1] = (int)(key % F);
+    edense[r] = k;
+    esparse[r] = found ? pos : -1;
+  } else if (k < nA + nB) {
+    long long ib = k - nA;
+    long long key = B[ib];
+    long long pos = lower_bound_ll(A, nA, key);
+    if (pos < nA && A[pos] == key) return;
+    long long r = ib + pos - cA[pos];
+    ekeys[r] = key;
+    eij[2 * r] = (int)(key / F);
+    eij[2 * r + 1] = (int)(key % F);
+    edense[r] = -1;
+    esparse[r] = ib;
+  }
+}
+
+__global__ void k_ej_keys(const int* __restrict__ eij, long long cap, const long long* __restrict__ counts, int F,
+                          int* __restrict__ kj, long long* __restrict__ idx) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cap) return;
+  long long E = counts[2];
+  kj[e] = e < E ? eij[2 * e + 1] : F;
+  idx[e] = e;
+}
+
+__global__ void k_incidence(const long long* __restrict__ ekeys, const int* __restrict__ kj_sorted,
+                            const long long* __restrict__ counts, int F, long long* __restrict__ iptr,
+                            long long* __restrict__ jptr, long long* __restrict__ free_flag) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f > F) return;
+  long long E = counts[2];
+  iptr[f] = lower_bound_ll(ekeys, E, (long long)f * F);
+  jptr[f] = lower_bound_i(kj_sorted, E, f);
+  if (f == F) {
+    free_flag[F] = 0;
+    return;
+  }
+  long long ihi = lower_bound_ll(ekeys, E, (long long)(f + 1) * F);
+  long long jhi = lower_bound_i(kj_sorted, E, f + 1);
+  long long deg = (ihi - iptr[f]) + (jhi - jptr[f]);
+  free_flag[f] = (f != 0 && deg > 0) ? 1 : 0;
+}
+
+__global__ void k_free_write(const long long* __restrict__ free_flag, const long long* __restrict__ scan, int F,
+                             int* __restrict__ var_of, int* __restrict__ frame_of_var, long long* __restrict__ counts) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f > F) return;
+  if (f == F) {
+    counts[3] = scan[F];
+    return;
+  }
+  if (free_flag[f]) {
+    var_of[f] = (int)scan[f];
+    frame_of_var[scan[f]] = f;
+  } else {
+    var_of[f] = -1;
+  }
+}
+
+inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+void read_counts(Context& c, long long* host_counts, int* host_flags) {
+  check_hip(hipMemcpyAsync(host_counts, c.counts.p, 8 * sizeof(long long), hipMemcpyDeviceToHost, c.stream),
+            "copy counts");
+  check_hip(hipMemcpyAsync(host_flags, c.flags.p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy flags");
+  check_hip(hipStreamSynchronize(c.stream), "synchronise");
+}
+
+void raise_device_flags(int fl) {
+  if (fl & kFlagBadIndex) fail(BF_ERR_INVALID_ARG, "frame index out of range, equal frames or i >= j");
+  if (fl & kFlagUnsorted) fail(BF_ERR_INVALID_ARG, "dense pairs are not strictly increasing");
+  if (fl & kFlagNonFinite) fail(BF_ERR_NONFINITE, "non-finite correspondence point");
+}
+
+}  // namespace
+
+int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics& in, const double* poses,
+                           const bf_params& prm) {
+  const int F = fr.num_frames;
+  ensure(c.pair_flags, (size_t)F * F);
+  ensure(c.row_count, sizeof(long long) * (F + 1));
+  ensure(c.row_off, sizeof(long long) * (F + 1));
+  double cos_lim = cos(prm.max_angle_deg * (M_PI / 180.0));
+  hipLaunchKernelGGL(k_pair_rows, dim3(F), dim3(256), 0, c.stream, fr.depth, poses, F, in.width, in.height, in.fx,
+                     in.fy, in.cx, in.cy, (float)prm.depth_min, (float)prm.depth_max, cos_lim,
+                     c.pair_flags.as<uint8_t>(), c.row_count.as<long long>());
+  check_hip(hipMemsetAsync(c.row_count.as<long long>() + F, 0, sizeof(long long), c.stream), "memset");
+  long long* rc = c.row_count.as<long long>();
+  long long* ro = c.row_off.as<long long>();
+  cub_call(c, [&](void* t, size_t& b) {
+    return hipcub::DeviceScan::ExclusiveSum(t, b, rc, ro, F + 1, c.stream);
+  });
+  long long P = 0;
+  check_hip(hipMemcpyAsync(&P, ro + F, sizeof(long long), hipMemcpyDeviceToHost, c.stream), "copy pair count");
+  check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  ensure(c.pairs, sizeof(int) * 2 * (P + 1));
+  ensure(c.pair_keys, sizeof(long long) * (P + 1));
+  hipLaunchKernelGGL(k_pair_compact, dim3(F), dim3(256), 0, c.stream, c.pair_flags.as<uint8_t>(), ro, F,
+                     c.pairs.as<int>(), c.pair_keys.as<long long>());
+  return P;
+}
+
+void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_corrs* co,
+                     const bf_pairs* pairs, const double* poses, const bf_params& prm) {
+  const int F = fr.num_frames;
+  Shape sh;
+  sh.F = F;
+  sh.W = in.width;
+  sh.H = in.height;
+  ensure(c.counts, 8 * sizeof(long long));
+  ensure(c.flags, sizeof(int));
+  check_hip(hipMemsetAsync(c.counts.p, 0, 8 * sizeof(long long), c.stream), "memset counts");
+
+  // a1: frames
+  size_t HW = (size_t)in.width * in.height;
+  ensure(c.nd, sizeof(float4) * HW * F);
+  ensure(c.grad, sizeof(float) * HW * F);
+  ensure(c.kx, sizeof(float) * in.width);
+  ensure(c.ky, sizeof(float) * in.height);
+  launch_prepare(c, fr, in, prm);
+
+  // a2: dense pairs
+  if (!prm.use_dense) {
+    sh.P = 0;
+    ensure(c.pairs, 8);
+    ensure(c.pair_keys, 8);
+  } else if (pairs) {
+    sh.P = pairs->count;
+    ensure(c.pairs, sizeof(int) * 2 * (sh.P + 1));
+    ensure(c.pair_keys, sizeof(long long) * (sh.P + 1));
+    if (sh.P > 0)
+      hipLaunchKernelGGL(k_pairs_check, dim3(blocks_for(sh.P)), dim3(256), 0, c.stream, pairs->ij, (long long)sh.P, F,
+                         c.pairs.as<int>(), c.pair_keys.as<long long>(), c.flags.as<int>());
+  } else {
+    sh.P = launch_pair_search(c, fr, in, poses, prm);
+  }
+
+  // correspondences: keys, stable sort, groups
+  const long long M = (prm.use_sparse && co) ? co->count : 0;
+  sh.M = M;
+  ensure(c.corr_key, sizeof(long long) * (M + 1));
+  ensure(c.corr_idx, sizeof(long long) * (M + 1));
+  ensure(c.corr_key_sorted, sizeof(long long) * (M + 1));
+  ensure(c.corr_perm, sizeof(long long) * (M + 1));
+  ensure(c.corr_head, sizeof(long long) * (M + 1));
+  ensure(c.corr_group, sizeof(long long) * (M + 1));
+  ensure(c.sparse_ij, sizeof(int) * 2 * (M + 1));
+  ensure(c.sparse_keys, sizeof(long long) * (M + 1));
+  ensure(c.sparse_ptr, sizeof(long long) * (M + 2));
+  if (M > 0) {
+    hipLaunchKernelGGL(k_corr_keys, dim3(blocks_for(M)), dim3(256), 0, c.stream, co->frame_i, co->frame_j, co->p_i,
+                       co->p_j, M, F, c.corr_key.as<long long>(), c.corr_idx.as<long long>(), c.flags.as<int>());
+    int endbit = bits_for((uint64_t)F * (uint64_t)F);
+    long long* k_in = c.corr_key.as<long long>();
+    long long* k_out = c.corr_key_sorted.as<long long>();
+    long long* v_in = c.corr_idx.as<long long>();
+    long long* v_out = c.corr_perm.as<long long>();
+    cub_call(c, [&](void* t, size_t& b) {
+      return hipcub::DeviceRadixSort::SortPairs(t, b, k_in, k_out, v_in, v_out, (int)M, 0, endbit, c.stream);
+    });
+    hipLaunchKernelGGL(k_corr_heads, dim3(blocks_for(M)), dim3(256), 0, c.stream, k_out, M,
+                       c.corr_head.as<long long>());
+    long long* hd = c.corr_head.as<long long>();
+    long long* gp = c.corr_group.as<long long>();
+    cub_call(c, [&](void* t, size_t& b) { return hipcub::DeviceScan::InclusiveSum(t, b, hd, gp, (int)M, c.stream); });
+    hipLaunchKernelGGL(k_corr_groups, dim3(blocks_for(M)), dim3(256), 0, c.stream, k_out, gp, M, F,
+                       c.sparse_ij.as<int>(), c.sparse_keys.as<long long>(), c.sparse_ptr.as<long long>(),
+                       c.counts.as<long long>());
+  }
+
+  long long hc[8];
+  int hf = 0;
+  read_counts(c, hc, &hf);
+  raise_device_flags(hf);
+  sh.S = M > 0 ? hc[1] : 0;
+
+  ensure(c.moments, sizeof(double) * kMomWords * (sh.S + 1));
+  if (sh.S > 0)
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)sh.S), dim3(64), 0, c.stream, co->frame_i, co->frame_j, co->p_i,
+                       co->p_j, c.corr_perm.as<long long>(), c.sparse_ptr.as<long long>(), (long long)sh.S,
+                       c.moments.as<double>());
+
+  // edges = union(dense pairs, sparse pairs)
+  const long long cap = sh.P + sh.S;
+  ensure(c.in_b, sizeof(long long) * (sh.P + 1));
+  ensure(c.common_scan, sizeof(long long) * (sh.P + 1));
+  ensure(c.edge_keys, sizeof(long long) * (cap + 1));
+  ensure(c.edge_ij, sizeof(int) * 2 * (cap + 1));
+  ensure(c.edge_dense, sizeof(long long) * (cap + 1));
+  ensure(c.edge_sparse, sizeof(long long) * (cap + 1));
+  long long* A = c.pair_keys.as<long long>();
+  long long* B = c.sparse_keys.as<long long>();
+  hipLaunchKernelGGL(k_union_inb, dim3(blocks_for(sh.P + 1)), dim3(256), 0, c.stream, A, (long long)sh.P, B,
+                     (long long)sh.S, c.in_b.as<long long>());
+  long long* ib = c.in_b.as<long long>();
+  long long* cs = c.common_scan.as<long long>();
+  cub_call(c, [&](void* t, size_t& b) {
+    return hipcub::DeviceScan::ExclusiveSum(t, b, ib, cs, (int)(sh.P + 1), c.stream);
+  });
+  hipLaunchKernelGGL(k_union_write, dim3(blocks_for(cap > 0 ? cap : 1)), dim3(256), 0, c.stream, A, (long long)sh.P, B,
+                     (long long)sh.S, cs, F, c.edge_keys.as<long long>(), c.edge_ij.as<int>(),
+                     c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.counts.as<long long>());
+
+  // incidence: edges sorted by the upper frame (stable), per-frame ranges
+  ensure(c.ej_key, sizeof(int) * (cap + 1));
+  ensure(c.ej_idx, sizeof(long long) * (cap + 1));
+  ensure(c.ej_key_sorted, sizeof(int) * (cap + 1));
+  ensure(c.ej_sorted, sizeof(long long) * (cap + 1));
+  ensure(c.iptr, sizeof(long long) * (F + 1));
+  ensure(c.jptr, sizeof(long long) * (F + 1));
+  ensure(c.free_flag, sizeof(long long) * (F + 1));
+  ensure(c.var_of, sizeof(int) * (F + 1));
+  ensure(c.frame_of_var, sizeof(int) * (F + 1));
+  if (cap > 0) {
+    hipLaunchKernelGGL(k_ej_keys, dim3(blocks_for(cap)), dim3(256), 0, c.stream, c.edge_ij.as<int>(), (long long)cap,
+                       c.counts.as<long long>(), F, c.ej_key.as<int>(), c.ej_idx.as<long long>());
+    int* kin = c.ej_key.as<int>();
+    int* kout = c.ej_key_sorted.as<int>();
+    long long* vin = c.ej_idx.as<long long>();
+    long long* vout = c.ej_sorted.as<long long>();
+    int endbit = bits_for((uint64_t)F + 1);
+    cub_call(c, [&](void* t, size_t& b) {
+      return hipcub::DeviceRadixSort::SortPairs(t, b, kin, kout, vin, vout, (int)cap, 0, endbit, c.stream);
+    });
+  }
+  hipLaunchKernelGGL(k_incidence, dim3(blocks_for(F + 1)), dim3(256), 0, c.stream, c.edge_keys.as<long long>(),
+                     c.ej_key_sorted.as<int>(), c.counts.as<long long>(), F, c.iptr.as<long long>(),
+                     c.jptr.as<long long>(), c.free_flag.as<long long>());
+  long long* ff = c.free_flag.as<long long>();
+  ensure(c.row_off, sizeof(long long) * (F + 1));
+  long long* fs = c.row_off.as<long long>();
+  cub_call(c, [&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, ff, fs, F + 1, c.stream); });
+  hipLaunchKernelGGL(k_free_write, dim3(blocks_for(F + 1)), dim3(256), 0, c.stream, ff, fs, F, c.var_of.as<int>(),
+                     c.frame_of_var.as<int>(), c.counts.as<long long>());
+  read_counts(c, hc, &hf);
+  raise_device_flags(hf);
+  sh.E = hc[2];
+  sh.nfree = hc[3];
+  c.shape = sh;
+}
+
+}  // namespace bf
