@@ -1,0 +1,163 @@
+"""Benchmark: Gauss-Newton iterations per second of the full pose solve on the
+200-keyframe global workload (80x60 frames, ~3700 dense pair jobs, ~300k
+sparse correspondences, 8 GN x 20 PCG), one MI355X.
+
+One step = one bf_gauss_newton() call: per-frame preparation, pair test,
+correspondence grouping and moments, then 8 iterations of dense pair jobs +
+edge blocks + assembly + 20 PCG iterations + SE(3) update, then the final
+energy.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SOURCE_PIXEL = 40  # depth+normal+gradient of the source pixel and of its target footprint
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, n_gn, n_pcg):
+    """The FP64 oracle on a bounded sample: per-solve setup + one Gauss-Newton iteration."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Params
+    from oracle.gn import Setup, build_system
+    from oracle.se3 import exp_se3
+    from oracle.system import reduce_system, solve_pcg
+
+    prm = Params(num_gn=n_gn, num_pcg=n_pcg)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        s = Setup(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p, prob.corr_q,
+                  prob.init_poses, prm)
+        t1 = time.perf_counter()
+        H, g, _, _ = build_system(s, prob.init_poses, prm.dense_weight(0))
+        Hr, gr, _ = reduce_system(H, g, s.free)
+        dx, _ = solve_pcg(Hr, gr, n_pcg)
+        poses = prob.init_poses.copy()
+        for n, f in enumerate(s.free):
+            poses[f] = poses[f] @ exp_se3(dx[6 * n:6 * n + 6])
+        t2 = time.perf_counter()
+    return {"value": 1.0 / (t2 - t1), "unit": "GN iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 of {n_gn} Gauss-Newton iterations ({n_pcg} PCG) of the same workload, single thread; "
+                      f"per-solve setup took {t1 - t0:.1f} s and is excluded",
+            "seconds": round(t2 - t1, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pcg-storage", type=int, default=0)
+    ap.add_argument("--accumulate", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the solve is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1604_01093_amd import bf
+    from synth import make_problem
+
+    log("generating the 200-keyframe workload")
+    t0 = time.perf_counter()
+    prob = make_problem(1)
+    log(f"generated in {time.perf_counter() - t0:.1f} s: {prob.num_frames} frames, {len(prob.corr_i)} correspondences")
+
+    ctx = bf.Context()
+    dp = bf.DeviceProblem.from_numpy(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j,
+                                     prob.corr_p, prob.corr_q)
+    init = torch.as_tensor(prob.init_poses).cuda()
+    out = torch.empty_like(init)
+    params = bf.bf_params_default(num_gn=prob.n_gn, num_pcg=prob.n_pcg, pcg_storage=args.pcg_storage,
+                                  accumulate=args.accumulate, timing=1)
+    st = bf.bf_build_structure(ctx, dp, init, params)
+    P = st["pairs"].shape[0]
+    log(f"structure: {P} dense pair jobs, {st['sparse_ij'].shape[0]} sparse pairs, {st['edges'].shape[0]} edges")
+
+    for k in range(args.warmup):
+        bf.bf_gauss_newton(ctx, dp, init, params, out_poses=out)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    dense_us = 0.0
+    dense_launches = 0
+    phase = np.zeros(8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = t0
+    for k in range(args.steps):
+        res = bf.bf_gauss_newton(ctx, dp, init, params, out_poses=out)
+        tm = ctx.last_timings()
+        dense_us += tm["dense_us"]
+        dense_launches += int(tm["dense_launches"])
+        phase += np.array([tm[key] for key in ("setup_us", "dense_us", "edges_us", "assemble_us", "pcg_us",
+                                               "final_us", "total_us", "dense_launches")])
+        if time.perf_counter() - last > 20:
+            log(f"step {k + 1}/{args.steps}")
+            last = time.perf_counter()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = prob.n_gn * args.steps / elapsed
+
+    avg_dense_s = dense_us / max(dense_launches, 1) * 1e-6
+    alg_bytes = BYTES_PER_SOURCE_PIXEL * prob.width * prob.height * P
+    achieved = alg_bytes / avg_dense_s / 1e9
+    phase /= args.steps
+    log("per step (us): " + ", ".join(f"{n}={v:.1f}" for n, v in zip(
+        ["setup", "dense", "edges", "assemble", "pcg", "final", "total", "dense_launches"], phase)))
+    log(f"energy {res['energy']}")
+
+    line = {
+        "metric": "GN iters/sec (JᵀJ build+PCG) at 200 keyframes",
+        "value": round(value, 3),
+        "unit": "GN iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "global200: 200 keyframes, 80x60, 3-room apartment loop, "
+                               f"{P} dense pair jobs, {len(prob.corr_i)} sparse correspondences, "
+                               f"{prob.n_gn} GN x {prob.n_pcg} PCG",
+                   "frames": prob.num_frames, "width": prob.width, "height": prob.height,
+                   "dense_pairs": int(P), "correspondences": int(len(prob.corr_i)),
+                   "gn_iters": prob.n_gn, "pcg_iters": prob.n_pcg,
+                   "pcg_storage": "fp64" if args.pcg_storage else "fp32",
+                   "accumulate": "two-sum" if args.accumulate else "fp32"},
+        "roofline": {"bound": "hbm", "kernel": "k_dense<jacobians>", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_us": round(avg_dense_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": int(alg_bytes)},
+        "phase_us_per_step": {n: round(v, 1) for n, v in zip(
+            ["setup", "dense", "edges", "assemble", "pcg", "final", "total"], phase[:7])},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(prob, prob.n_gn, prob.n_pcg)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,9 @@ typedef struct bf_params {
   int32_t accumulate;       /* per-pixel J^T J accumulation: 0 = FP32, 1 = compensated (two-sum) FP32 */
   int32_t pcg_storage;      /* PCG matrix and vectors: 0 = FP32 (dots and alpha/beta in FP64), 1 = FP64 */
   int32_t timing;           /* 1: record HIP events per phase for bf_last_timings() */
+  int32_t solve_kernel;     /* PCG kernel: 0 = automatic, 1 = single workgroup (vectors in LDS),
+                               2 = cooperative grid (any size) */
+  int32_t reserved0;        /* must be 0 */
   double tau_dist;          /* dense association: |c - q| < tau_dist (metres) */
   double tau_normal;        /* dense association: normal dot product > tau_normal */
   double max_angle_deg;     /* dense pair test: viewing directions within this angle */

@@ -50,6 +50,7 @@ class bf_params(ctypes.Structure):
     _fields_ = [("w_sparse", c_double), ("w_dense", c_double), ("w_geo", c_double), ("w_photo", c_double),
                 ("dense_ramp", c_int32), ("use_sparse", c_int32), ("use_dense", c_int32), ("num_gn", c_int32),
                 ("num_pcg", c_int32), ("accumulate", c_int32), ("pcg_storage", c_int32), ("timing", c_int32),
+                ("solve_kernel", c_int32), ("reserved0", c_int32),
                 ("tau_dist", c_double), ("tau_normal", c_double), ("max_angle_deg", c_double),
                 ("depth_min", c_double), ("depth_max", c_double)]
 

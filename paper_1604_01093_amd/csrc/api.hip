@@ -73,6 +73,7 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
     fail(BF_ERR_INVALID_ARG, "weights must be finite and >= 0");
   if (prm->accumulate != 0 && prm->accumulate != 1) fail(BF_ERR_INVALID_ARG, "accumulate must be 0 or 1");
   if (prm->pcg_storage != 0 && prm->pcg_storage != 1) fail(BF_ERR_INVALID_ARG, "pcg_storage must be 0 or 1");
+  if (prm->solve_kernel < 0 || prm->solve_kernel > 2) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0, 1 or 2");
   if (!(prm->tau_dist > 0) || !isfinite(prm->tau_normal) || !(prm->depth_max > prm->depth_min) ||
       !isfinite(prm->max_angle_deg))
     fail(BF_ERR_INVALID_ARG, "bad thresholds");
@@ -107,6 +108,7 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
            const double* poses, const bf_params* prm) {
   Context& c = *ctx;
   c.pcg_storage = prm->pcg_storage;
+  c.solve_mode = prm->solve_kernel;
   c.have_system = false;
   ensure(c.counts, 8 * sizeof(long long));
   ensure(c.flags, sizeof(int));
@@ -119,13 +121,13 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
     ensure(c.diag64, sizeof(double) * 36 * (s.nfree + 1));
     ensure(c.minv64, sizeof(double) * 36 * (s.nfree + 1));
     ensure(c.rhs, sizeof(double) * 6 * (s.nfree + 1));
-    ensure(c.pcg_vec, sizeof(double) * 5 * 6 * (s.nfree + 1));
+    ensure(c.pcg_vec, sizeof(double) * 6 * 6 * (s.nfree + 1));
   } else {
     ensure(c.hij32, sizeof(float) * 36 * (s.E + 1));
     ensure(c.diag32, sizeof(float) * 36 * (s.nfree + 1));
     ensure(c.minv32, sizeof(float) * 36 * (s.nfree + 1));
     ensure(c.rhs, sizeof(float) * 6 * (s.nfree + 1));
-    ensure(c.pcg_vec, sizeof(float) * 5 * 6 * (s.nfree + 1));
+    ensure(c.pcg_vec, sizeof(float) * 6 * 6 * (s.nfree + 1));
   }
   ensure(c.energy, sizeof(double) * 8);
   ensure(c.stats, sizeof(double) * 4);
@@ -141,6 +143,7 @@ void raise_flags(int fl) {
   if (fl & kFlagUnsorted) fail(BF_ERR_INVALID_ARG, "dense pairs are not strictly increasing");
   if (fl & kFlagNonFinite) fail(BF_ERR_NONFINITE, "non-finite input");
   if (fl & kFlagNotPD) fail(BF_ERR_NOT_PD, "a diagonal block of J^T J is not positive definite");
+  if (fl & kFlagTimeout) fail(BF_ERR_DEVICE, "grid barrier of the PCG kernel did not complete");
 }
 
 struct Timer {
@@ -394,7 +397,6 @@ bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* fr, const 
     launch_dense(c, *in, poses, *prm, wd, true);
     launch_edge_blocks(c, poses, *prm, true);
     launch_energy(c, c.energy.as<double>());
-    launch_assemble(c);
     if (out_H || out_g) launch_export_dense(c, out_H, out_g);
     if (out_edge_blocks && c.shape.E > 0)
       check_hip(hipMemcpyAsync(out_edge_blocks, c.eblocks.p, sizeof(double) * kEdgeWords * c.shape.E,
@@ -420,7 +422,7 @@ bf_status bf_pcg_solve(bf_context* ctx, int32_t num_iters, double* out_delta, do
     if (c.shape.nfree == 0) {
       check_hip(hipMemsetAsync(out_delta, 0, sizeof(double) * 6 * c.shape.F, c.stream), "memset");
     } else {
-      launch_pcg(c, num_iters, out_delta, nullptr, c.stats.as<double>(), false);
+      launch_solve(c, num_iters, nullptr, out_delta, nullptr, c.stats.as<double>(), false);
     }
     double st[4] = {0, 0, 0, 0};
     int hf = 0;
@@ -461,16 +463,13 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* fr, const bf_intrins
       launch_dense(c, *in, poses, *prm, wd, true);
       int b = tm.mark();
       launch_edge_blocks(c, poses, *prm, true);
-      launch_energy(c, c.trace.as<double>() + 8 * k);
       int d = tm.mark();
-      launch_assemble(c);
-      int e = tm.mark();
-      if (c.shape.nfree > 0) launch_pcg(c, prm->num_pcg, nullptr, poses, nullptr, true);
+      if (c.shape.nfree > 0) launch_solve(c, prm->num_pcg, c.trace.as<double>() + 8 * k, nullptr, poses, nullptr, true);
+      else launch_energy(c, c.trace.as<double>() + 8 * k);
       int f = tm.mark();
       tm.span(1, a, b);
       tm.span(2, b, d);
-      tm.span(3, d, e);
-      tm.span(4, e, f);
+      tm.span(4, d, f);
     }
     int g0 = tm.mark();
     double wd = dense_weight(*prm, prm->num_gn > 0 ? prm->num_gn - 1 : 0);

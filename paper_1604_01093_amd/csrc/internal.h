@@ -55,11 +55,13 @@ struct Context {
       moments;
   // edges and incidence
   Buf in_b, common_scan, edge_ij, edge_keys, edge_dense, edge_sparse, ej_key, ej_idx, ej_key_sorted, ej_sorted,
-      iptr, jptr, free_flag, var_of, frame_of_var;
+      iptr, jptr, free_flag, var_of, frame_of_var, row_cnt, row_ptr, row_entries;
   // per-iteration data
   Buf records, eblocks, hij32, hij64, diag32, diag64, minv32, minv64, rhs, poses_work, pcg_vec, stats, trace;
   // scratch
-  Buf cub_tmp, counts, flags, host_pinned, energy;
+  Buf cub_tmp, counts, flags, host_pinned, energy, pcg_partials, pcg_barrier;
+  int pcg_grid = 0;       // workgroups of the cooperative PCG kernel (0 = not yet chosen)
+  int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative
 
   hipEvent_t ev[16] = {};
   bool events_ready = false;
@@ -85,8 +87,8 @@ void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, cons
 
 // solve.hip
 void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, bool with_jacobians);
-void launch_assemble(Context& c);
-void launch_pcg(Context& c, int iters, double* delta_out, double* poses_inout, double* stats, bool update_poses);
+void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
+                  bool update_poses);
 void launch_energy(Context& c, double* dst8);
 void launch_export_dense(Context& c, double* H, double* g);
 

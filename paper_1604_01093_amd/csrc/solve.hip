@@ -13,6 +13,8 @@
 // PCG: x0 = 0, fixed iteration count, early exit when r^T z <= 1e-30, FP64 dot
 // products and alpha/beta; matrix and vectors in FP32 (default) or FP64.
 // Update: T_f <- T_f Exp(x_f) in FP64 (Sec. 4.3 exponential map).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace bf {
@@ -250,43 +252,6 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
   out[kENp] = np;
 }
 
-// One wavefront per free frame: diagonal block and gradient from the incident edges
-// (lower-index edges first, in edge order, then upper-index edges in edge order).
-template <class T>
-__global__ void __launch_bounds__(64) k_assemble(const double* __restrict__ eb, const long long* __restrict__ iptr,
-                                                 const long long* __restrict__ jptr,
-                                                 const long long* __restrict__ ej_sorted,
-                                                 const int* __restrict__ frame_of_var, long long nfree,
-                                                 T* __restrict__ diag, T* __restrict__ minv, T* __restrict__ rhs,
-                                                 int* __restrict__ flags) {
-  long long v = blockIdx.x;
-  if (v >= nfree) return;
-  const int lane = threadIdx.x;
-  const int f = frame_of_var[v];
-  __shared__ double blk[48];
-  if (lane < 42) {
-    const int offH = lane < 36 ? kEHii + lane : kEGi + (lane - 36);
-    const int offHj = lane < 36 ? kEHjj + lane : kEGj + (lane - 36);
-    double s = 0.0;
-    for (long long k = iptr[f]; k < iptr[f + 1]; ++k) s += eb[(size_t)k * kEdgeWords + offH];
-    for (long long k = jptr[f]; k < jptr[f + 1]; ++k) s += eb[(size_t)ej_sorted[k] * kEdgeWords + offHj];
-    blk[lane] = s;
-  }
-  __syncthreads();
-  if (lane < 36) diag[(size_t)v * 36 + lane] = (T)blk[lane];
-  if (lane < 6) rhs[(size_t)v * 6 + lane] = (T)(-blk[36 + lane]);
-  if (lane == 0) {
-    double A[36];
-    for (int k = 0; k < 36; ++k) A[k] = blk[k];
-    bool ok = spd_inverse6(A);
-    if (!ok) {
-      raise_flag(flags, kFlagNotPD);
-      for (int k = 0; k < 36; ++k) A[k] = (k % 7 == 0) ? 1.0 : 0.0;
-    }
-    for (int k = 0; k < 36; ++k) minv[(size_t)v * 36 + k] = (T)A[k];
-  }
-}
-
 // Deterministic block reduction of one double per thread (blockDim.x = 1024).
 __device__ double block_sum(double v, double* sh) {
   const int tid = threadIdx.x;
@@ -301,65 +266,469 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Single-workgroup PCG over all free frames (1024 threads), then the pose update.
+// ---------------------------------------------------------------- persistent solve
+
+constexpr unsigned kSpinLimit = 1u << 26;   // ~2 s of polling: a barrier that never completes raises an error
+constexpr int kSolveThreads = 1024;          // 16 wavefronts, one matrix row per wavefront at a time
+constexpr int kSolveWaves = kSolveThreads / 64;
+constexpr int kParts = 8;                     // doubles per workgroup in a grid reduction
+
+// Data shared between workgroups is written and read with agent-scope relaxed
+// atomics (coherent across the XCDs without L2 write-back fences); a barrier
+// waits for the wavefront's memory operations to complete, then arrives.
 template <class T>
-__global__ void __launch_bounds__(1024) k_pcg_single(
-    long long nfree, int F, int iters, const T* __restrict__ diag, const T* __restrict__ minv,
-    const T* __restrict__ rhs, const T* __restrict__ hij, const int* __restrict__ eij,
-    const long long* __restrict__ iptr, const long long* __restrict__ jptr, const long long* __restrict__ ej_sorted,
-    const int* __restrict__ frame_of_var, const int* __restrict__ var_of, T* __restrict__ x, T* __restrict__ r,
-    T* __restrict__ z, T* __restrict__ p, T* __restrict__ Ap, double* __restrict__ delta_out,
-    double* __restrict__ poses, int update, double* __restrict__ stats, const int* __restrict__ flags) {
-  __shared__ double sh[1024];
-  const int tid = threadIdx.x;
-  const long long n = 6 * nfree;
-  const bool bad = flags[0] & kFlagNotPD;
-  // x = 0, r = b, z = M^-1 r, p = z
-  for (long long o = tid; o < n; o += 1024) {
-    x[o] = (T)0;
-    r[o] = rhs[o];
+__device__ __forceinline__ T ld_shared(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_shared(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns false if the spin limit was hit (then every later barrier is skipped).
+__device__ __forceinline__ bool grid_sync(unsigned* ctr, unsigned target, int* flags, int* sh_ok) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = *sh_ok;
+    if (ok) {
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned spins = 0;
+      while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          atomicOr(flags, kFlagTimeout);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    *sh_ok = ok;
   }
   __syncthreads();
+  return *sh_ok != 0;
+}
+
+// Grid-wide sums of K <= kParts doubles per thread, identical in every workgroup
+// (fixed trees: lanes, then wavefronts in order, then workgroups in order).
+template <int K>
+__device__ void grid_sums(double (&v)[K], double* parts, unsigned* bar, unsigned& nbar, int* flags, double* sh,
+                          int* sh_ok) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = v[k];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) sh[wave * kParts + k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double t = 0.0;
+    for (int w = 0; w < kSolveWaves; ++w) t += sh[w * kParts + threadIdx.x];
+    st_shared(&parts[blockIdx.x * kParts + threadIdx.x], t);
+  }
+  ++nbar;
+  grid_sync(bar, nbar * gridDim.x, flags, sh_ok);
+  if (wave == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double t = 0.0;
+      for (int g = lane; g < (int)gridDim.x; g += 64) t += ld_shared(&parts[g * kParts + k]);
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+      if (lane == 0) sh[kSolveWaves * kParts + k] = t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = sh[kSolveWaves * kParts + k];
+  __syncthreads();
+}
+
+// Assembly + block-Jacobi PCG + pose update in one cooperative launch.
+//  prologue: each wavefront assembles the diagonal block and gradient of its rows
+//            from the incident edges (fixed order), inverts the diagonal block
+//            (6x6 Cholesky, FP64), sets x = 0, r = -g, z = M^-1 r, p = z; the
+//            energy over all edges is reduced alongside r.z.
+//  per iteration, two barriers:
+//   A: p_v = z_v + beta p_v(prev) for own rows (into the other p buffer), and
+//      Ap_v = D_v p_v + sum_w H_vw p_w with partners' p_w formed on the fly from
+//      their z_w and previous p_w;  barrier (p.Ap)
+//   B: x += alpha p, r -= alpha Ap, z = M^-1 r for own rows;  barrier (r.z)
+//  epilogue: owners write dx and/or apply T_f <- T_f Exp(x_f).
+template <class T>
+__global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
+    long long nfree, int F, long long E, int iters, const double* __restrict__ eb, const T* __restrict__ hij,
+    const long long* __restrict__ iptr, const long long* __restrict__ jptr, const long long* __restrict__ ej_sorted,
+    const long long* __restrict__ row_ptr, const int2* __restrict__ entries, const int* __restrict__ frame_of_var,
+    const int* __restrict__ var_of, T* __restrict__ diag, T* __restrict__ minv, T* __restrict__ x,
+    T* __restrict__ r, T* __restrict__ Ap, T* z, T* pb0, T* pb1, double* parts, unsigned* bar,
+    double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
+    double* __restrict__ stats, int* flags) {
+  __shared__ double sh[(kSolveWaves + 1) * kParts];
+  __shared__ double red[kSolveWaves][64];
+  __shared__ double blk[kSolveWaves][48];
+  __shared__ int sh_ok;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long gw = (long long)blockIdx.x * kSolveWaves + wave, nw = (long long)gridDim.x * kSolveWaves;
+  const int grp = lane / 6, a = lane % 6;
+  unsigned nbar = 0;
+  if (threadIdx.x == 0) sh_ok = 1;
+  __syncthreads();
+
+  // ---- prologue: assembly, preconditioner, initial residual
+  double pro[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // r.z, not-PD count, Es, Eg, Ep, ns, ng, np
+  for (long long v = gw; v < nfree; v += nw) {
+    const int f = frame_of_var[v];
+    if (lane < 42) {
+      const int offI = lane < 36 ? kEHii + lane : kEGi + (lane - 36);
+      const int offJ = lane < 36 ? kEHjj + lane : kEGj + (lane - 36);
+      double s0 = 0.0, s1 = 0.0;
+      const long long i0 = iptr[f], i1 = iptr[f + 1];
+      long long k = i0;
+      for (; k + 1 < i1; k += 2) {
+        s0 += eb[(size_t)k * kEdgeWords + offI];
+        s1 += eb[(size_t)(k + 1) * kEdgeWords + offI];
+      }
+      if (k < i1) s0 += eb[(size_t)k * kEdgeWords + offI];
+      const long long j0 = jptr[f], j1 = jptr[f + 1];
+      for (k = j0; k + 1 < j1; k += 2) {
+        s0 += eb[(size_t)ej_sorted[k] * kEdgeWords + offJ];
+        s1 += eb[(size_t)ej_sorted[k + 1] * kEdgeWords + offJ];
+      }
+      if (k < j1) s0 += eb[(size_t)ej_sorted[k] * kEdgeWords + offJ];
+      blk[wave][lane] = s0 + s1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 36) diag[v * 36 + lane] = (T)blk[wave][lane];
+    if (lane == 0) {
+      double A[36];
+      for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
+      bool ok = spd_inverse6(A);
+      if (!ok) {
+        pro[1] += 1.0;
+        for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
+      }
+      for (int q = 0; q < 36; ++q) minv[v * 36 + q] = (T)A[q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (lane < 6) {
+      const T rv = (T)(-blk[wave][36 + a]);
+      double s = 0.0;
+      for (int b = 0; b < 6; ++b) s += (double)minv[v * 36 + 6 * a + b] * (double)(T)(-blk[wave][36 + b]);
+      const T zt = (T)s;
+      x[6 * v + a] = (T)0;
+      r[6 * v + a] = rv;
+      st_shared(&z[6 * v + a], zt);
+      st_shared(&pb0[6 * v + a], zt);
+      pro[0] += (double)rv * (double)zt;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (trace_slot) {
+    for (long long e = (long long)blockIdx.x * kSolveThreads + threadIdx.x; e < E;
+         e += (long long)gridDim.x * kSolveThreads)
+      for (int q = 0; q < 6; ++q) pro[2 + q] += eb[(size_t)e * kEdgeWords + kEEs + q];
+  }
+  grid_sums<8>(pro, parts, bar, nbar, flags, sh, &sh_ok);
+  double rz = pro[0];
+  const bool bad = pro[1] > 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bad) atomicOr(flags, kFlagNotPD);
+    if (trace_slot) {
+      trace_slot[0] = pro[2] + pro[3] + pro[4];
+      for (int q = 0; q < 6; ++q) trace_slot[1 + q] = pro[2 + q];
+      trace_slot[7] = 0.0;
+    }
+  }
+  const double rz0 = rz;
+  double beta = 0.0;
+  int done = 0;
+  for (int k = 0; k < iters && !bad && sh_ok; ++k) {
+    if (rz <= 1e-30) break;
+    T* pold = (k & 1) ? pb0 : pb1;  // p^{k-1}
+    T* pnew = (k & 1) ? pb1 : pb0;  // p^k (for k = 0 it already holds z^0)
+    const T tb = (T)beta;
+    double part[1] = {0.0};
+    for (long long v = gw; v < nfree; v += nw) {
+      double acc = 0.0;
+      if (grp < 10) {
+        if (grp == 0) {
+          for (int b = 0; b < 6; ++b) {
+            const T pv = (k == 0) ? ld_shared(&pnew[6 * v + b])
+                                  : (T)(ld_shared(&z[6 * v + b]) + tb * ld_shared(&pold[6 * v + b]));
+            acc += (double)(diag[v * 36 + 6 * a + b] * pv);
+          }
+        }
+        const long long q1 = row_ptr[v + 1];
+#pragma unroll 2
+        for (long long q = row_ptr[v] + grp; q < q1; q += 10) {
+          const int2 en = entries[q];
+          const long long w = en.x;
+          const T* B = hij + (size_t)(en.y >> 1) * 36;
+          const bool tr = en.y & 1;
+          T sacc = (T)0;
+          for (int b = 0; b < 6; ++b) {
+            const T pw = (k == 0) ? ld_shared(&pnew[6 * w + b])
+                                  : (T)(ld_shared(&z[6 * w + b]) + tb * ld_shared(&pold[6 * w + b]));
+            sacc += (tr ? B[6 * b + a] : B[6 * a + b]) * pw;
+          }
+          acc += (double)sacc;
+        }
+      }
+      red[wave][lane] = acc;
+      __builtin_amdgcn_wave_barrier();
+      if (lane < 6) {
+        double t = 0.0;
+        for (int g = 0; g < 10; ++g) t += red[wave][a + 6 * g];
+        const T apv = (T)t;
+        Ap[6 * v + a] = apv;
+        const T pv = (k == 0) ? ld_shared(&pnew[6 * v + a])
+                              : (T)(ld_shared(&z[6 * v + a]) + tb * ld_shared(&pold[6 * v + a]));
+        if (k > 0) st_shared(&pnew[6 * v + a], pv);
+        part[0] += (double)pv * (double)apv;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    grid_sums<1>(part, parts, bar, nbar, flags, sh, &sh_ok);
+    const double alpha = rz / part[0];
+    double part2[1] = {0.0};
+    for (long long v = gw; v < nfree; v += nw) {
+      double rv = 0.0;
+      if (lane < 6) {
+        const T pv = ld_shared(&pnew[6 * v + a]);
+        x[6 * v + a] = (T)((double)x[6 * v + a] + alpha * (double)pv);
+        rv = (double)(T)((double)r[6 * v + a] - alpha * (double)Ap[6 * v + a]);
+        r[6 * v + a] = (T)rv;
+      }
+      double s = 0.0;
+      for (int b = 0; b < 6; ++b) {
+        const double rb = __shfl(rv, b);
+        if (lane < 6) s += (double)minv[v * 36 + 6 * a + b] * rb;
+      }
+      if (lane < 6) {
+        const T zt = (T)s;
+        st_shared(&z[6 * v + a], zt);
+        part2[0] += rv * (double)zt;
+      }
+    }
+    grid_sums<1>(part2, parts, bar, nbar, flags, sh, &sh_ok);
+    beta = part2[0] / rz;
+    rz = part2[0];
+    ++done;
+  }
+  if (delta_out) {
+    // owners write their own rows (x never crosses workgroups); frames that are not
+    // variables get zeros
+    for (long long v = gw; v < nfree; v += nw)
+      if (lane < 6) delta_out[6LL * frame_of_var[v] + a] = bad ? 0.0 : (double)x[6 * v + a];
+    for (long long o = (long long)blockIdx.x * kSolveThreads + threadIdx.x; o < 6LL * F;
+         o += (long long)gridDim.x * kSolveThreads)
+      if (var_of[o / 6] < 0) delta_out[o] = 0.0;
+  }
+  if (update && !bad && sh_ok) {
+    for (long long v = gw; v < nfree; v += nw) {
+      if (lane != 0) continue;
+      const int f = frame_of_var[v];
+      double xi[6];
+      for (int q = 0; q < 6; ++q) xi[q] = (double)x[6 * v + q];
+      double dR[9], dt[3];
+      exp_se3(xi, dR, dt);
+      double* T4 = poses + (size_t)f * 16;
+      double Rn[9], tn[3];
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+          Rn[3 * i + j] = T4[4 * i] * dR[j] + T4[4 * i + 1] * dR[3 + j] + T4[4 * i + 2] * dR[6 + j];
+        tn[i] = T4[4 * i] * dt[0] + T4[4 * i + 1] * dt[1] + T4[4 * i + 2] * dt[2] + T4[4 * i + 3];
+      }
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) T4[4 * i + j] = Rn[3 * i + j];
+        T4[4 * i + 3] = tn[i];
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && stats) {
+    stats[0] = rz0;
+    stats[1] = rz;
+    stats[2] = done;
+  }
+}
+
+// Deterministic sum over a 1024-thread workgroup (fixed tree through LDS).
+__device__ double block_sum1024(double v, double* red1024) {
+  const int tid = threadIdx.x;
+  red1024[tid] = v;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o) red1024[tid] += red1024[tid + o];
+    __syncthreads();
+  }
+  const double r = red1024[0];
+  __syncthreads();
+  return r;
+}
+
+// y = B p (or B^T p) for one 6x6 block, 16-byte loads, FP32 or FP64 arithmetic.
+template <class T>
+__device__ __forceinline__ void block_mv(const T* __restrict__ B, const T* pw, bool tr, T y[6]) {
+  T m[36];
+#pragma unroll
+  for (int q = 0; q < 36; ++q) m[q] = B[q];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T s = (T)0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s += (tr ? m[6 * j + i] : m[6 * i + j]) * pw[j];
+    y[i] = s;
+  }
+}
+
+// Assembly + block-Jacobi PCG + pose update for problems whose PCG vectors fit in
+// one workgroup's LDS: no grid barriers.  LDS holds x, r, z, p, Ap (and M^-1 when
+// it fits); the off-diagonal blocks are streamed from L2 every iteration, one
+// block per lane.  Same arithmetic and reduction orders as the cooperative kernel
+// where they matter for determinism (every sum has a fixed order).
+template <class T>
+__global__ void __launch_bounds__(1024) k_solve_single(
+    long long nfree, int F, long long E, int iters, const double* __restrict__ eb, const T* __restrict__ hij,
+    const long long* __restrict__ iptr, const long long* __restrict__ jptr, const long long* __restrict__ ej_sorted,
+    const long long* __restrict__ row_ptr, const int2* __restrict__ entries, const int* __restrict__ frame_of_var,
+    const int* __restrict__ var_of, T* __restrict__ diag_g, T* __restrict__ minv_g, int minv_in_lds,
+    double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
+    double* __restrict__ stats, int* __restrict__ flags) {
+  extern __shared__ double dyn[];
+  __shared__ double red1024[1024];
+  __shared__ double blk[16][48];
+  __shared__ int bad_sh;
+  const long long n = 6 * nfree;
+  T* x = reinterpret_cast<T*>(dyn);
+  T* r = x + n;
+  T* z = r + n;
+  T* p = z + n;
+  T* Ap = p + n;
+  T* minv = minv_in_lds ? Ap + n : minv_g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) bad_sh = 0;
+  __syncthreads();
+
+  // prologue: per-row assembly and preconditioner (one wavefront per row)
+  for (long long v = wave; v < nfree; v += 16) {
+    const int f = frame_of_var[v];
+    if (lane < 42) {
+      const int offI = lane < 36 ? kEHii + lane : kEGi + (lane - 36);
+      const int offJ = lane < 36 ? kEHjj + lane : kEGj + (lane - 36);
+      double s0 = 0.0, s1 = 0.0;
+      const long long i0 = iptr[f], i1 = iptr[f + 1];
+      long long k = i0;
+      for (; k + 1 < i1; k += 2) {
+        s0 += eb[(size_t)k * kEdgeWords + offI];
+        s1 += eb[(size_t)(k + 1) * kEdgeWords + offI];
+      }
+      if (k < i1) s0 += eb[(size_t)k * kEdgeWords + offI];
+      const long long j0 = jptr[f], j1 = jptr[f + 1];
+      for (k = j0; k + 1 < j1; k += 2) {
+        s0 += eb[(size_t)ej_sorted[k] * kEdgeWords + offJ];
+        s1 += eb[(size_t)ej_sorted[k + 1] * kEdgeWords + offJ];
+      }
+      if (k < j1) s0 += eb[(size_t)ej_sorted[k] * kEdgeWords + offJ];
+      blk[wave][lane] = s0 + s1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 36) diag_g[v * 36 + lane] = (T)blk[wave][lane];
+    if (lane == 0) {
+      double A[36];
+      for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
+      if (!spd_inverse6(A)) {
+        bad_sh = 1;
+        for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
+      }
+      for (int q = 0; q < 36; ++q) blk[wave][q] = A[q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 36) minv[v * 36 + lane] = (T)blk[wave][lane];
+    if (lane < 6) {
+      x[6 * v + lane] = (T)0;
+      r[6 * v + lane] = (T)(-blk[wave][36 + lane]);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // energy over all edges
+  double en[6] = {0, 0, 0, 0, 0, 0};
+  if (trace_slot)
+    for (long long e = tid; e < E; e += 1024)
+      for (int q = 0; q < 6; ++q) en[q] += eb[(size_t)e * kEdgeWords + kEEs + q];
+  __syncthreads();
+  if (trace_slot) {
+    double tot[6];
+    for (int q = 0; q < 6; ++q) tot[q] = block_sum1024(en[q], red1024);
+    if (tid == 0) {
+      trace_slot[0] = tot[0] + tot[1] + tot[2];
+      for (int q = 0; q < 6; ++q) trace_slot[1 + q] = tot[q];
+      trace_slot[7] = 0.0;
+    }
+  }
+  const bool bad = bad_sh != 0;
+  if (bad && tid == 0) atomicOr(flags, kFlagNotPD);
+  // z = M^-1 r, p = z
   double part = 0.0;
   for (long long o = tid; o < n; o += 1024) {
-    long long v = o / 6;
-    int a = (int)(o % 6);
+    const long long v = o / 6;
+    const int a = (int)(o % 6);
     double s = 0.0;
     for (int b = 0; b < 6; ++b) s += (double)minv[v * 36 + 6 * a + b] * (double)r[6 * v + b];
     z[o] = (T)s;
     p[o] = (T)s;
     part += (double)r[o] * (double)(T)s;
   }
-  double rz = block_sum(part, sh);
+  double rz = block_sum1024(part, red1024);
   const double rz0 = rz;
   int done = 0;
   for (int it = 0; it < iters && !bad; ++it) {
     if (rz <= 1e-30) break;
+    // Ap = H p: one wavefront per row, one block per lane
     part = 0.0;
-    for (long long o = tid; o < n; o += 1024) {
-      long long v = o / 6;
-      int a = (int)(o % 6);
-      int f = frame_of_var[v];
-      T s = (T)0;
-      for (int b = 0; b < 6; ++b) s += diag[v * 36 + 6 * a + b] * p[6 * v + b];
-      for (long long k = iptr[f]; k < iptr[f + 1]; ++k) {
-        int w = var_of[eij[2 * k + 1]];
-        if (w < 0) continue;
-        const T* B = hij + (size_t)k * 36 + 6 * a;
-        for (int b = 0; b < 6; ++b) s += B[b] * p[6 * (long long)w + b];
+    for (long long v = wave; v < nfree; v += 16) {
+      const long long q0 = row_ptr[v], q1 = row_ptr[v + 1];
+      T acc[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+      for (long long qb = q0; qb < q1; qb += 64) {
+        const long long q = qb + lane;
+        if (q < q1) {
+          const int2 en2 = entries[q];
+          T pw[6], y[6];
+#pragma unroll
+          for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)en2.x + b];
+          block_mv<T>(hij + (size_t)(en2.y >> 1) * 36, pw, en2.y & 1, y);
+#pragma unroll
+          for (int b = 0; b < 6; ++b) acc[b] += y[b];
+        }
       }
-      for (long long k = jptr[f]; k < jptr[f + 1]; ++k) {
-        long long e = ej_sorted[k];
-        int w = var_of[eij[2 * e]];
-        if (w < 0) continue;
-        const T* B = hij + (size_t)e * 36 + a;
-        for (int b = 0; b < 6; ++b) s += B[6 * b] * p[6 * (long long)w + b];
+      if (lane == 63) {
+        T pv[6], y[6];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) pv[b] = p[6 * v + b];
+        block_mv<T>(diag_g + v * 36, pv, false, y);
+#pragma unroll
+        for (int b = 0; b < 6; ++b) acc[b] += y[b];
       }
-      Ap[o] = s;
-      part += (double)p[o] * (double)s;
+      // fixed butterfly over the 64 lanes (lane 0 holds the result)
+      double tot[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        double t = (double)acc[b];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        tot[b] = t;
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+          const T apv = (T)tot[b];
+          Ap[6 * v + b] = apv;
+          part += (double)p[6 * v + b] * (double)apv;
+        }
+      }
     }
-    double pAp = block_sum(part, sh);
-    double alpha = rz / pAp;
+    const double pAp = block_sum1024(part, red1024);
+    const double alpha = rz / pAp;
     for (long long o = tid; o < n; o += 1024) {
       x[o] = (T)((double)x[o] + alpha * (double)p[o]);
       r[o] = (T)((double)r[o] - alpha * (double)Ap[o]);
@@ -367,53 +736,52 @@ __global__ void __launch_bounds__(1024) k_pcg_single(
     __syncthreads();
     part = 0.0;
     for (long long o = tid; o < n; o += 1024) {
-      long long v = o / 6;
-      int a = (int)(o % 6);
+      const long long v = o / 6;
+      const int a = (int)(o % 6);
       double s = 0.0;
       for (int b = 0; b < 6; ++b) s += (double)minv[v * 36 + 6 * a + b] * (double)r[6 * v + b];
       z[o] = (T)s;
       part += (double)r[o] * (double)(T)s;
     }
-    double rz_new = block_sum(part, sh);
-    ++done;
-    double beta = rz_new / rz;
+    const double rz_new = block_sum1024(part, red1024);
+    const double beta = rz_new / rz;
     rz = rz_new;
+    ++done;
     for (long long o = tid; o < n; o += 1024) p[o] = (T)((double)z[o] + beta * (double)p[o]);
     __syncthreads();
   }
-  if (delta_out) {
+  if (delta_out)
     for (long long o = tid; o < 6LL * F; o += 1024) {
-      int f = (int)(o / 6);
-      int w = var_of[f];
+      const int w = var_of[o / 6];
       delta_out[o] = (w >= 0 && !bad) ? (double)x[6LL * w + (o % 6)] : 0.0;
     }
-  }
-  if (update && !bad) {
+  if (update && !bad)
     for (long long v = tid; v < nfree; v += 1024) {
-      int f = frame_of_var[v];
+      const int f = frame_of_var[v];
       double xi[6];
-      for (int k = 0; k < 6; ++k) xi[k] = (double)x[6 * v + k];
+      for (int q = 0; q < 6; ++q) xi[q] = (double)x[6 * v + q];
       double dR[9], dt[3];
       exp_se3(xi, dR, dt);
       double* T4 = poses + (size_t)f * 16;
       double Rn[9], tn[3];
-      for (int a = 0; a < 3; ++a) {
-        for (int b = 0; b < 3; ++b)
-          Rn[3 * a + b] = T4[4 * a] * dR[b] + T4[4 * a + 1] * dR[3 + b] + T4[4 * a + 2] * dR[6 + b];
-        tn[a] = T4[4 * a] * dt[0] + T4[4 * a + 1] * dt[1] + T4[4 * a + 2] * dt[2] + T4[4 * a + 3];
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+          Rn[3 * i + j] = T4[4 * i] * dR[j] + T4[4 * i + 1] * dR[3 + j] + T4[4 * i + 2] * dR[6 + j];
+        tn[i] = T4[4 * i] * dt[0] + T4[4 * i + 1] * dt[1] + T4[4 * i + 2] * dt[2] + T4[4 * i + 3];
       }
-      for (int a = 0; a < 3; ++a) {
-        for (int b = 0; b < 3; ++b) T4[4 * a + b] = Rn[3 * a + b];
-        T4[4 * a + 3] = tn[a];
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) T4[4 * i + j] = Rn[3 * i + j];
+        T4[4 * i + 3] = tn[i];
       }
     }
-  }
   if (tid == 0 && stats) {
     stats[0] = rz0;
     stats[1] = rz;
     stats[2] = done;
   }
 }
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
 // Energy and counts over all edges, fixed order (one workgroup of 1024).
 __global__ void __launch_bounds__(1024) k_energy(const double* __restrict__ eb, long long E, double* __restrict__ dst) {
@@ -487,39 +855,97 @@ void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, b
                        c.eblocks.as<double>(), c.hij32.as<float>());
 }
 
-void launch_assemble(Context& c) {
-  const long long nf = c.shape.nfree;
-  if (nf == 0) return;
-  if (c.pcg_storage == 1)
-    hipLaunchKernelGGL(k_assemble<double>, dim3((unsigned)nf), dim3(64), 0, c.stream, c.eblocks.as<double>(),
-                       c.iptr.as<long long>(), c.jptr.as<long long>(), c.ej_sorted.as<long long>(),
-                       c.frame_of_var.as<int>(), nf, c.diag64.as<double>(), c.minv64.as<double>(),
-                       c.rhs.as<double>(), c.flags.as<int>());
-  else
-    hipLaunchKernelGGL(k_assemble<float>, dim3((unsigned)nf), dim3(64), 0, c.stream, c.eblocks.as<double>(),
-                       c.iptr.as<long long>(), c.jptr.as<long long>(), c.ej_sorted.as<long long>(),
-                       c.frame_of_var.as<int>(), nf, c.diag32.as<float>(), c.minv32.as<float>(),
-                       c.rhs.as<float>(), c.flags.as<int>());
+template <class T>
+void launch_solve_coop(Context& c, int iters, double* trace_slot, double* delta_out, double* poses, double* stats,
+                       bool update, T* diag, T* minv, T* hij, T* vec) {
+  long long nf = c.shape.nfree;
+  long long n = 6 * nf;
+  long long E = c.shape.E;
+  auto kern = k_solve_coop<T>;
+  if (c.pcg_grid == 0) {
+    int per_cu = 0;
+    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                           kSolveThreads, 0),
+              "occupancy query");
+    c.pcg_grid = std::max(1, per_cu) * c.num_cus;
+  }
+  int G = (int)std::min<long long>((nf + kSolveWaves - 1) / kSolveWaves, std::min(c.pcg_grid, 512));
+  if (G < 1) G = 1;
+  ensure(c.pcg_partials, sizeof(double) * kParts * 512);
+  ensure(c.pcg_barrier, sizeof(unsigned) * 4);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c.stream, c.pcg_barrier.as<unsigned>());
+  T* x = vec;
+  T* r = vec + n;
+  T* z = vec + 2 * n;
+  T* pb0 = vec + 3 * n;
+  T* pb1 = vec + 4 * n;
+  T* Ap = vec + 5 * n;
+  double* parts = c.pcg_partials.as<double>();
+  unsigned* bar = c.pcg_barrier.as<unsigned>();
+  int F = c.shape.F;
+  int upd = update ? 1 : 0;
+  const double* eb = c.eblocks.as<double>();
+  const long long* ip = c.iptr.as<long long>();
+  const long long* jp = c.jptr.as<long long>();
+  const long long* ejs = c.ej_sorted.as<long long>();
+  const long long* rp = c.row_ptr.as<long long>();
+  const int2* en = c.row_entries.as<int2>();
+  const int* fov = c.frame_of_var.as<int>();
+  const int* vof = c.var_of.as<int>();
+  int* fl = c.flags.as<int>();
+  void* args[] = {&nf, &F, &E, &iters, &eb, &hij, &ip, &jp, &ejs, &rp, &en, &fov, &vof, &diag, &minv, &x, &r,
+                  &Ap, &z, &pb0, &pb1, &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl};
+  check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kSolveThreads), args, 0,
+                                       c.stream),
+            "cooperative solve launch");
 }
 
-void launch_pcg(Context& c, int iters, double* delta_out, double* poses_inout, double* stats, bool update_poses) {
+// LDS budget of the single-workgroup solve (dynamic part).
+constexpr size_t kSingleLdsMax = 64 * 1024;
+
+template <class T>
+bool launch_solve_single(Context& c, int iters, double* trace_slot, double* delta_out, double* poses, double* stats,
+                         bool update, T* diag, T* minv, T* hij) {
   const long long nf = c.shape.nfree;
-  const long long n = 6 * nf;
-  if (c.pcg_storage == 1) {
-    double* v = c.pcg_vec.as<double>();
-    hipLaunchKernelGGL(k_pcg_single<double>, dim3(1), dim3(1024), 0, c.stream, nf, c.shape.F, iters,
-                       c.diag64.as<double>(), c.minv64.as<double>(), c.rhs.as<double>(), c.hij64.as<double>(),
-                       c.edge_ij.as<int>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
-                       c.ej_sorted.as<long long>(), c.frame_of_var.as<int>(), c.var_of.as<int>(), v, v + n, v + 2 * n,
-                       v + 3 * n, v + 4 * n, delta_out, poses_inout, update_poses ? 1 : 0, stats, c.flags.as<int>());
-  } else {
-    float* v = c.pcg_vec.as<float>();
-    hipLaunchKernelGGL(k_pcg_single<float>, dim3(1), dim3(1024), 0, c.stream, nf, c.shape.F, iters,
-                       c.diag32.as<float>(), c.minv32.as<float>(), c.rhs.as<float>(), c.hij32.as<float>(),
-                       c.edge_ij.as<int>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
-                       c.ej_sorted.as<long long>(), c.frame_of_var.as<int>(), c.var_of.as<int>(), v, v + n, v + 2 * n,
-                       v + 3 * n, v + 4 * n, delta_out, poses_inout, update_poses ? 1 : 0, stats, c.flags.as<int>());
+  const size_t vec_bytes = sizeof(T) * 5 * 6 * (size_t)nf;
+  const size_t minv_bytes = sizeof(T) * 36 * (size_t)nf;
+  if (vec_bytes > kSingleLdsMax) return false;
+  const int minv_lds = (vec_bytes + minv_bytes <= kSingleLdsMax) ? 1 : 0;
+  const size_t lds = vec_bytes + (minv_lds ? minv_bytes : 0);
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[sizeof(T) == 8]) {
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve_single<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSingleLdsMax),
+              "set LDS limit");
+    attr_set[sizeof(T) == 8] = true;
   }
+  hipLaunchKernelGGL(k_solve_single<T>, dim3(1), dim3(1024), lds, c.stream, nf, c.shape.F, (long long)c.shape.E, iters,
+                     c.eblocks.as<double>(), hij, c.iptr.as<long long>(), c.jptr.as<long long>(),
+                     c.ej_sorted.as<long long>(), c.row_ptr.as<long long>(), c.row_entries.as<int2>(),
+                     c.frame_of_var.as<int>(), c.var_of.as<int>(), diag, minv, minv_lds, trace_slot, delta_out, poses,
+                     update ? 1 : 0, stats, c.flags.as<int>());
+  return true;
+}
+
+void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
+                  bool update_poses) {
+  if (c.shape.nfree == 0) return;
+  if (c.solve_mode != 2) {
+    bool ok = c.pcg_storage == 1
+                  ? launch_solve_single<double>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
+                                                c.diag64.as<double>(), c.minv64.as<double>(), c.hij64.as<double>())
+                  : launch_solve_single<float>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
+                                               c.diag32.as<float>(), c.minv32.as<float>(), c.hij32.as<float>());
+    if (ok) return;
+    if (c.solve_mode == 1) fail(BF_ERR_UNSUPPORTED, "PCG vectors do not fit in one workgroup's LDS");
+  }
+  if (c.pcg_storage == 1)
+    launch_solve_coop<double>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
+                              c.diag64.as<double>(), c.minv64.as<double>(), c.hij64.as<double>(),
+                              c.pcg_vec.as<double>());
+  else
+    launch_solve_coop<float>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses, c.diag32.as<float>(),
+                             c.minv32.as<float>(), c.hij32.as<float>(), c.pcg_vec.as<float>());
 }
 
 void launch_energy(Context& c, double* dst8) {

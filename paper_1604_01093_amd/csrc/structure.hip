@@ -360,6 +360,44 @@ __global__ void k_free_write(const long long* __restrict__ free_flag, const long
   }
 }
 
+// Per free frame (PCG row): number of incident edges whose other frame is free.
+__global__ void k_row_count(const long long* __restrict__ iptr, const long long* __restrict__ jptr,
+                            const long long* __restrict__ ej_sorted, const int* __restrict__ eij,
+                            const int* __restrict__ var_of, const int* __restrict__ frame_of_var, long long nfree,
+                            long long* __restrict__ cnt) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > nfree) return;
+  if (v == nfree) {
+    cnt[v] = 0;
+    return;
+  }
+  int f = frame_of_var[v];
+  long long n = 0;
+  for (long long k = iptr[f]; k < iptr[f + 1]; ++k) n += var_of[eij[2 * k + 1]] >= 0 ? 1 : 0;
+  for (long long k = jptr[f]; k < jptr[f + 1]; ++k) n += var_of[eij[2 * ej_sorted[k]]] >= 0 ? 1 : 0;
+  cnt[v] = n;
+}
+
+// Row entries (partner variable, 2*edge + transposed) in incidence order.
+__global__ void k_row_fill(const long long* __restrict__ iptr, const long long* __restrict__ jptr,
+                           const long long* __restrict__ ej_sorted, const int* __restrict__ eij,
+                           const int* __restrict__ var_of, const int* __restrict__ frame_of_var, long long nfree,
+                           const long long* __restrict__ row_ptr, int2* __restrict__ entries) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nfree) return;
+  int f = frame_of_var[v];
+  long long o = row_ptr[v];
+  for (long long k = iptr[f]; k < iptr[f + 1]; ++k) {
+    int w = var_of[eij[2 * k + 1]];
+    if (w >= 0) entries[o++] = make_int2(w, (int)(2 * k));
+  }
+  for (long long k = jptr[f]; k < jptr[f + 1]; ++k) {
+    long long e = ej_sorted[k];
+    int w = var_of[eij[2 * e]];
+    if (w >= 0) entries[o++] = make_int2(w, (int)(2 * e + 1));
+  }
+}
+
 inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 void read_counts(Context& c, long long* host_counts, int* host_flags) {
@@ -539,6 +577,23 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
   raise_device_flags(hf);
   sh.E = hc[2];
   sh.nfree = hc[3];
+
+  // PCG rows: (partner variable, edge) lists of every free frame
+  ensure(c.row_cnt, sizeof(long long) * (sh.nfree + 1));
+  ensure(c.row_ptr, sizeof(long long) * (sh.nfree + 1));
+  ensure(c.row_entries, sizeof(int2) * (2 * sh.E + 1));
+  hipLaunchKernelGGL(k_row_count, dim3(blocks_for(sh.nfree + 1)), dim3(256), 0, c.stream, c.iptr.as<long long>(),
+                     c.jptr.as<long long>(), c.ej_sorted.as<long long>(), c.edge_ij.as<int>(), c.var_of.as<int>(),
+                     c.frame_of_var.as<int>(), (long long)sh.nfree, c.row_cnt.as<long long>());
+  long long* rcnt = c.row_cnt.as<long long>();
+  long long* rptr = c.row_ptr.as<long long>();
+  cub_call(c, [&](void* t, size_t& b) {
+    return hipcub::DeviceScan::ExclusiveSum(t, b, rcnt, rptr, (int)(sh.nfree + 1), c.stream);
+  });
+  if (sh.nfree > 0)
+    hipLaunchKernelGGL(k_row_fill, dim3(blocks_for(sh.nfree)), dim3(256), 0, c.stream, c.iptr.as<long long>(),
+                       c.jptr.as<long long>(), c.ej_sorted.as<long long>(), c.edge_ij.as<int>(), c.var_of.as<int>(),
+                       c.frame_of_var.as<int>(), (long long)sh.nfree, rptr, c.row_entries.as<int2>());
   c.shape = sh;
 }
 

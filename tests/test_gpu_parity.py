@@ -168,11 +168,12 @@ def test_normal_equations_and_edge_blocks(ctx, chunk, chunk_setup, pcg_storage):
     assert abs(out["energy"][0] - en["total"]) <= 1e-6 * en["total"]
 
 
-@pytest.mark.parametrize("pcg_storage", [0, 1])
-def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage):
+@pytest.mark.parametrize("pcg_storage,solve_kernel", [(0, 1), (1, 1), (0, 2), (1, 2)])
+def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage, solve_kernel):
     prm = chunk_setup.params
     dp = device_problem(chunk)
-    bf.bf_build_normal_equations(ctx, dp, poses_cuda(chunk.init_poses), bf_params_from(prm, pcg_storage=pcg_storage),
+    bf.bf_build_normal_equations(ctx, dp, poses_cuda(chunk.init_poses),
+                                 bf_params_from(prm, pcg_storage=pcg_storage, solve_kernel=solve_kernel),
                                  gn_iter=0, dense=False)
     delta, st = bf.bf_pcg_solve(ctx, chunk.num_frames, 10)
     delta = delta.cpu().numpy()
@@ -187,18 +188,18 @@ def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage):
     assert (delta[:6] == 0).all()
 
 
-@pytest.mark.parametrize("pcg_storage,accumulate", [(0, 0), (1, 0), (0, 1)])
-def test_gauss_newton_chunk(ctx, chunk, pcg_storage, accumulate):
+@pytest.mark.parametrize("pcg_storage,accumulate,solve_kernel", [(0, 0, 1), (1, 0, 1), (0, 1, 1), (0, 0, 2), (1, 0, 2)])
+def test_gauss_newton_chunk(ctx, chunk, pcg_storage, accumulate, solve_kernel):
     prm = Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg)
     ref = solve(chunk.depth, chunk.intensity, chunk.intrinsics, chunk.corr_i, chunk.corr_j, chunk.corr_p,
                 chunk.corr_q, chunk.init_poses, prm, linear="pcg")
     dp = device_problem(chunk)
     init = poses_cuda(chunk.init_poses)
-    out = bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, pcg_storage=pcg_storage, accumulate=accumulate),
-                             trace=True)
+    kw = dict(pcg_storage=pcg_storage, accumulate=accumulate, solve_kernel=solve_kernel)
+    out = bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, **kw), trace=True)
     P = out["poses"].cpu().numpy()
     rot, tr = pose_errors(P, ref["poses"])
-    print(f"chunk pcg_storage={pcg_storage} accumulate={accumulate}: pose err {rot:.3e} rad {tr:.3e} m, "
+    print(f"chunk {kw}: pose err {rot:.3e} rad {tr:.3e} m, "
           f"energy {out['energy']['total']:.9g} vs {ref['energy']['total']:.9g}")
     assert rot < 1e-5 and tr < 1e-5
     assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
@@ -207,5 +208,5 @@ def test_gauss_newton_chunk(ctx, chunk, pcg_storage, accumulate):
         assert abs(t[0] - ref["trace"][k]["total"]) <= 1e-4 * ref["trace"][k]["total"]
     # inputs untouched, deterministic
     assert np.array_equal(init.cpu().numpy(), chunk.init_poses)
-    again = bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, pcg_storage=pcg_storage, accumulate=accumulate))
+    again = bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, **kw))
     assert torch.equal(again["poses"], out["poses"])
