@@ -62,6 +62,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pcg-storage", type=int, default=0)
     ap.add_argument("--accumulate", type=int, default=0)
+    ap.add_argument("--solve-kernel", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -85,7 +86,7 @@ def main():
     init = torch.as_tensor(prob.init_poses).cuda()
     out = torch.empty_like(init)
     params = bf.bf_params_default(num_gn=prob.n_gn, num_pcg=prob.n_pcg, pcg_storage=args.pcg_storage,
-                                  accumulate=args.accumulate, timing=1)
+                                  accumulate=args.accumulate, solve_kernel=args.solve_kernel, timing=1)
     st = bf.bf_build_structure(ctx, dp, init, params)
     P = st["pairs"].shape[0]
     log(f"structure: {P} dense pair jobs, {st['sparse_ij'].shape[0]} sparse pairs, {st['edges'].shape[0]} edges")
@@ -144,7 +145,8 @@ def main():
                    "dense_pairs": int(P), "correspondences": int(len(prob.corr_i)),
                    "gn_iters": prob.n_gn, "pcg_iters": prob.n_pcg,
                    "pcg_storage": "fp64" if args.pcg_storage else "fp32",
-                   "accumulate": "two-sum" if args.accumulate else "fp32"},
+                   "accumulate": ["fp32", "fp32-two-sum", "fp64"][args.accumulate],
+                   "solve_kernel": ["auto", "single", "coop", "replicated"][args.solve_kernel]},
         "roofline": {"bound": "hbm", "kernel": "k_dense<jacobians>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "avg_launch_us": round(avg_dense_s * 1e6, 2),

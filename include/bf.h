@@ -93,11 +93,15 @@ typedef struct bf_params {
   int32_t use_dense;        /* 0 drops E_geo and E_photo */
   int32_t num_gn;           /* Gauss-Newton iterations */
   int32_t num_pcg;          /* PCG iterations per Gauss-Newton iteration (early exit if r^T z <= 1e-30) */
-  int32_t accumulate;       /* per-pixel J^T J accumulation: 0 = FP32, 1 = compensated (two-sum) FP32 */
+  int32_t accumulate;       /* per-pixel residual/Jacobian values and J^T J lane sums:
+                               0 = FP32, 1 = FP32 with two-sum compensated sums,
+                               2 = FP64 values and sums (association decisions are FP32 in
+                               every mode, so the masks do not depend on this choice) */
   int32_t pcg_storage;      /* PCG matrix and vectors: 0 = FP32 (dots and alpha/beta in FP64), 1 = FP64 */
   int32_t timing;           /* 1: record HIP events per phase for bf_last_timings() */
   int32_t solve_kernel;     /* PCG kernel: 0 = automatic, 1 = single workgroup (vectors in LDS),
-                               2 = cooperative grid (any size) */
+                               2 = cooperative grid with owner-computed vectors (any size),
+                               3 = cooperative grid with replicated vectors (vectors in LDS) */
   int32_t reserved0;        /* must be 0 */
   double tau_dist;          /* dense association: |c - q| < tau_dist (metres) */
   double tau_normal;        /* dense association: normal dot product > tau_normal */

@@ -71,9 +71,9 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
   if (!(prm->w_sparse >= 0) || !(prm->w_dense >= 0) || !(prm->w_geo >= 0) || !(prm->w_photo >= 0) ||
       !isfinite(prm->w_sparse) || !isfinite(prm->w_dense) || !isfinite(prm->w_geo) || !isfinite(prm->w_photo))
     fail(BF_ERR_INVALID_ARG, "weights must be finite and >= 0");
-  if (prm->accumulate != 0 && prm->accumulate != 1) fail(BF_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+  if (prm->accumulate < 0 || prm->accumulate > 2) fail(BF_ERR_INVALID_ARG, "accumulate must be 0, 1 or 2");
   if (prm->pcg_storage != 0 && prm->pcg_storage != 1) fail(BF_ERR_INVALID_ARG, "pcg_storage must be 0 or 1");
-  if (prm->solve_kernel < 0 || prm->solve_kernel > 2) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0, 1 or 2");
+  if (prm->solve_kernel < 0 || prm->solve_kernel > 3) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..3");
   if (!(prm->tau_dist > 0) || !isfinite(prm->tau_normal) || !(prm->depth_max > prm->depth_min) ||
       !isfinite(prm->max_angle_deg))
     fail(BF_ERR_INVALID_ARG, "bad thresholds");
@@ -248,14 +248,15 @@ bf_status bf_create(bf_context** out, void* hip_stream) {
 void bf_destroy(bf_context* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  Buf* bufs[] = {&c->nd, &c->grad, &c->kx, &c->ky, &c->pair_flags, &c->row_count, &c->row_off, &c->pairs,
+  Buf* bufs[] = {&c->nd, &c->grad, &c->kx, &c->ky, &c->kx64, &c->ky64, &c->pair_flags, &c->row_count, &c->row_off, &c->pairs,
                  &c->pair_keys, &c->corr_key, &c->corr_idx, &c->corr_key_sorted, &c->corr_perm, &c->corr_head,
                  &c->corr_group, &c->sparse_ij, &c->sparse_keys, &c->sparse_ptr, &c->moments, &c->in_b,
                  &c->common_scan, &c->edge_ij, &c->edge_keys, &c->edge_dense, &c->edge_sparse, &c->ej_key,
                  &c->ej_idx, &c->ej_key_sorted, &c->ej_sorted, &c->iptr, &c->jptr, &c->free_flag, &c->var_of,
                  &c->frame_of_var, &c->records, &c->eblocks, &c->hij32, &c->hij64, &c->diag32, &c->diag64,
                  &c->minv32, &c->minv64, &c->rhs, &c->poses_work, &c->pcg_vec, &c->stats, &c->trace,
-                 &c->cub_tmp, &c->counts, &c->flags, &c->host_pinned, &c->energy};
+                 &c->cub_tmp, &c->counts, &c->flags, &c->host_pinned, &c->energy,
+                 &c->pcg_partials, &c->pcg_barrier, &c->pcg_tags};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
@@ -287,6 +288,8 @@ bf_status bf_prepare_frames(bf_context* ctx, const bf_frames* fr, const bf_intri
     ensure(c.grad, sizeof(float) * HW * fr->num_frames);
     ensure(c.kx, sizeof(float) * in->width);
     ensure(c.ky, sizeof(float) * in->height);
+    ensure(c.kx64, sizeof(double) * in->width);
+    ensure(c.ky64, sizeof(double) * in->height);
     launch_prepare(c, *fr, *in, *prm);
     if (out_nd)
       check_hip(hipMemcpyAsync(out_nd, c.nd.p, sizeof(float4) * HW * fr->num_frames, hipMemcpyDeviceToDevice,

@@ -3,9 +3,9 @@
 //
 // One workgroup per pair job (i -> j, source = lower index), one source pixel per
 // lane per step.  For each pixel with a valid normal:
-//   d = P_i(x,y), c = T_ji d, m = R_ji n                       (FP32, fixed order)
+//   d = P_i(x,y), c = T_ji d, m = R_ji n
 //   nearest pixel (floor(u+1/2), floor(v+1/2)) of pi(c) in frame j with a valid
-//   normal, |c - q|^2 < tau_d^2 and m.N_j > tau_n               (FP32, fixed order)
+//   normal, |c - q|^2 < tau_d^2 and m.N_j > tau_n
 //   r_g = m.(c - q),            J_g = [(m x q)^T, -m^T]
 //   r_p = G_i(x,y) - G_j(pi(c)) (bilinear, photometric only where the geometric
 //   association holds and the four taps and G_i are valid),
@@ -13,51 +13,54 @@
 // where J_g, J_p are the Jacobians with respect to the right perturbation of
 // frame j.  The frame-i blocks follow per pair in FP64 from the adjoint
 // (J_i = -J_j Ad(T_ji)), so each pixel feeds one 6x6 block: 21 + 6 + 4 values.
-// Lane sums are FP32 (optionally two-sum compensated), combined across the
-// workgroup in FP64 in a fixed order: the record is deterministic.
+//
+// The association decisions are always taken in FP32 with a fixed operation
+// order and no contraction (reproducible bit for bit).  The residual/Jacobian
+// values and their accumulation come in three precisions:
+//   mode 0: FP32 values, FP32 lane sums;
+//   mode 1: FP32 values, two-sum compensated FP32 lane sums;
+//   mode 2: FP64 values (c, q, r, pi(c), Jacobians) and FP64 lane sums -- on
+//           MI355X FP64 FMAs issue at the rate of unpacked FP32 FMAs.
+// Lane sums are combined across the workgroup in FP64 in a fixed order: the
+// record is deterministic.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace bf {
 
 namespace {
 
-struct Acc31 {
-  float v[31];
-};
-
-__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+__device__ __forceinline__ void two_sum_add(float& s, float& c, float x) {
   float y = x - c;
   float t = s + y;
   c = (t - s) - y;
   s = t;
 }
 
-template <bool JAC, bool KAHAN>
+template <int MODE, int N>
 struct LaneAcc {
-  static constexpr int N = JAC ? 31 : 4;
-  float s[N];
-  float c[KAHAN ? N : 1];
+  using V = typename std::conditional<MODE == 2, double, float>::type;
+  V s[N];
+  V c[MODE == 1 ? N : 1];
   __device__ __forceinline__ void zero() {
 #pragma unroll
-    for (int k = 0; k < N; ++k) s[k] = 0.0f;
+    for (int k = 0; k < N; ++k) s[k] = (V)0;
 #pragma unroll
-    for (int k = 0; k < (KAHAN ? N : 1); ++k) c[k] = 0.0f;
+    for (int k = 0; k < (MODE == 1 ? N : 1); ++k) c[k] = (V)0;
   }
-  __device__ __forceinline__ void add(int k, float x) {
-    if constexpr (KAHAN) kahan_add(s[k], c[k], x);
+  __device__ __forceinline__ void add(int k, V x) {
+    if constexpr (MODE == 1) two_sum_add(s[k], c[k], x);
     else s[k] += x;
   }
   __device__ __forceinline__ double value(int k) const {
-    if constexpr (KAHAN) return (double)s[k] - (double)c[k];
+    if constexpr (MODE == 1) return (double)s[k] - (double)c[k];
     else return (double)s[k];
   }
 };
 
-// Accumulate the outer products of the geometric and photometric Jacobians (both
-// already scaled by the square root of their weights).
-template <bool KAHAN>
-__device__ __forceinline__ void accumulate_jac(LaneAcc<true, KAHAN>& A, const float* jg, float rg, const float* jp,
-                                               float rp, float ph) {
+template <int MODE, class V>
+__device__ __forceinline__ void accumulate_jac(LaneAcc<MODE, 31>& A, const V* jg, V rg, const V* jp, V rp, V ph) {
   int k = 0;
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
@@ -71,16 +74,29 @@ __device__ __forceinline__ void accumulate_jac(LaneAcc<true, KAHAN>& A, const fl
   for (int a = 0; a < 6; ++a) A.add(21 + a, jg[a] * rg + jp[a] * rp);
   A.add(27, rg * rg);
   A.add(28, rp * rp);
-  A.add(29, 1.0f);
+  A.add(29, (V)1);
   A.add(30, ph);
 }
 
-template <bool JAC, bool KAHAN>
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int MODE, bool JAC>
 __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, long long P,
                                                const float4* __restrict__ nd, const float* __restrict__ grad,
                                                const float* __restrict__ kx, const float* __restrict__ ky,
-                                               const double* __restrict__ poses, Intr32 in, float tau_d2,
-                                               float tau_n, float swg, float swp, double* __restrict__ records) {
+                                               const double* __restrict__ kx64, const double* __restrict__ ky64,
+                                               const double* __restrict__ poses, Intr32 in, double fx64, double fy64,
+                                               double cx64, double cy64, float tau_d2, float tau_n, double swg,
+                                               double swp, double* __restrict__ records) {
   // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs, so give
   // each XCD a contiguous block of pair jobs (neighbouring jobs share frames and
   // stay in that XCD's L2).  The grid is a multiple of 8.
@@ -91,14 +107,19 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
   const int i = pairs[2 * p], j = pairs[2 * p + 1];
   const int W = in.W, H = in.H, HW = W * H;
 
+  // relative pose: FP64 (fixed order), FP32 copy for the decisions; wave-uniform
   float R[9], t[3];
-  {
-    double Rd[9], td[3];
-    relative_pose_nc(poses + (size_t)i * 16, poses + (size_t)j * 16, Rd, td);
+  double Rd[9], td[3];
+  relative_pose_nc(poses + (size_t)i * 16, poses + (size_t)j * 16, Rd, td);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) R[k] = (float)Rd[k];
+  for (int k = 0; k < 9; ++k) {
+    R[k] = uniform_f((float)Rd[k]);
+    Rd[k] = uniform_d(Rd[k]);
+  }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) t[k] = (float)td[k];
+  for (int k = 0; k < 3; ++k) {
+    t[k] = uniform_f((float)td[k]);
+    td[k] = uniform_d(td[k]);
   }
   const float4* __restrict__ ndi = nd + (size_t)i * HW;
   const float4* __restrict__ ndj = nd + (size_t)j * HW;
@@ -106,8 +127,10 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
   const float* __restrict__ gj = grad + (size_t)j * HW;
   const float fWm1 = (float)(W - 1), fHm1 = (float)(H - 1), fWm2 = (float)(W - 2), fHm2 = (float)(H - 2);
 
-  LaneAcc<JAC, KAHAN> A;
+  constexpr int NV = JAC ? 31 : 4;
+  LaneAcc<MODE, NV> A;
   A.zero();
+  using V = typename LaneAcc<MODE, NV>::V;
 
   int x = tid % W, y = tid / W;
   const int sx = blockDim.x % W, sy = blockDim.x / W;
@@ -119,6 +142,7 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
       x -= W;
       y += 1;
     }
+    // ---- FP32 association decisions (fixed operation order)
     const float4 s = ndi[pix];
     if (is_nan(s.x)) continue;
     const float D = s.w;
@@ -139,10 +163,6 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
     const float3 n = make_float3(s.x, s.y, s.z);
     const float3 m = rotate_nc(R, n);
     if (!(dot_nc(m, make_float3(tq.x, tq.y, tq.z)) > tau_n)) continue;
-
-    // geometric term
-    const float rg = (m.x * e.x + m.y * e.y + m.z * e.z) * swg;
-    // photometric term
     const float x0f = floorf(u), y0f = floorf(v);
     bool ph = x0f >= 0.0f && x0f <= fWm2 && y0f >= 0.0f && y0f <= fHm2;
     const float Gi = gi[pix];
@@ -156,28 +176,80 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
       g11 = gj[t0 + W + 1];
       ph = !(is_nan(g00) || is_nan(g10) || is_nan(g01) || is_nan(g11));
     }
-    float rp = 0.0f;
-    float ax = 0.f, ay = 0.f, az = 0.f;
-    if (ph) {
-      const float al = u - x0f, be = v - y0f;
-      const float Gj = (1.0f - al) * ((1.0f - be) * g00 + be * g01) + al * ((1.0f - be) * g10 + be * g11);
-      const float gu = ((1.0f - be) * (g10 - g00) + be * (g11 - g01)) * swp;
-      const float gv = ((1.0f - al) * (g01 - g00) + al * (g11 - g10)) * swp;
-      rp = (Gi - Gj) * swp;
-      ax = gu * in.fx * iz;
-      ay = gv * in.fy * iz;
-      az = -(ax * c.x + ay * c.y) * iz;
+
+    // ---- residuals and Jacobians w.r.t. frame j
+    V rg, rp = (V)0, jg[6], jp[6] = {(V)0, (V)0, (V)0, (V)0, (V)0, (V)0};
+    if constexpr (MODE == 2) {
+      const double D64 = (double)D, Dj = (double)tq.w;
+      const double dx = kx64[px] * D64, dy = ky64[py] * D64;
+      const double cx_ = Rd[0] * dx + Rd[1] * dy + Rd[2] * D64 + td[0];
+      const double cy_ = Rd[3] * dx + Rd[4] * dy + Rd[5] * D64 + td[1];
+      const double cz_ = Rd[6] * dx + Rd[7] * dy + Rd[8] * D64 + td[2];
+      const double qx = kx64[xh] * Dj, qy = ky64[yh] * Dj, qz = Dj;
+      const double nx = n.x, ny = n.y, nz = n.z;
+      const double mx = Rd[0] * nx + Rd[1] * ny + Rd[2] * nz;
+      const double my = Rd[3] * nx + Rd[4] * ny + Rd[5] * nz;
+      const double mz = Rd[6] * nx + Rd[7] * ny + Rd[8] * nz;
+      rg = (mx * (cx_ - qx) + my * (cy_ - qy) + mz * (cz_ - qz)) * swg;
+      const double sx_ = mx * swg, sy_ = my * swg, sz_ = mz * swg;
+      jg[0] = sy_ * qz - sz_ * qy;
+      jg[1] = sz_ * qx - sx_ * qz;
+      jg[2] = sx_ * qy - sy_ * qx;
+      jg[3] = -sx_;
+      jg[4] = -sy_;
+      jg[5] = -sz_;
+      if (ph) {
+        const double iz64 = 1.0 / cz_;
+        const double u64 = fx64 * cx_ * iz64 + cx64;
+        const double v64 = fy64 * cy_ * iz64 + cy64;
+        const double al = u64 - (double)x0f, be = v64 - (double)y0f;
+        const double G00 = g00, G10 = g10, G01 = g01, G11 = g11;
+        const double Gj = (1.0 - al) * ((1.0 - be) * G00 + be * G01) + al * ((1.0 - be) * G10 + be * G11);
+        const double gu = ((1.0 - be) * (G10 - G00) + be * (G11 - G01)) * swp;
+        const double gv = ((1.0 - al) * (G01 - G00) + al * (G11 - G10)) * swp;
+        rp = ((double)Gi - Gj) * swp;
+        const double ax = gu * fx64 * iz64, ay = gv * fy64 * iz64;
+        const double az = -(ax * cx_ + ay * cy_) * iz64;
+        jp[0] = cy_ * az - cz_ * ay;
+        jp[1] = cz_ * ax - cx_ * az;
+        jp[2] = cx_ * ay - cy_ * ax;
+        jp[3] = ax;
+        jp[4] = ay;
+        jp[5] = az;
+      }
+    } else {
+      const float fswg = (float)swg, fswp = (float)swp;
+      rg = (m.x * e.x + m.y * e.y + m.z * e.z) * fswg;
+      const float mx = m.x * fswg, my = m.y * fswg, mz = m.z * fswg;
+      jg[0] = my * q.z - mz * q.y;
+      jg[1] = mz * q.x - mx * q.z;
+      jg[2] = mx * q.y - my * q.x;
+      jg[3] = -mx;
+      jg[4] = -my;
+      jg[5] = -mz;
+      if (ph) {
+        const float al = u - x0f, be = v - y0f;
+        const float Gj = (1.0f - al) * ((1.0f - be) * g00 + be * g01) + al * ((1.0f - be) * g10 + be * g11);
+        const float gu = ((1.0f - be) * (g10 - g00) + be * (g11 - g01)) * fswp;
+        const float gv = ((1.0f - al) * (g01 - g00) + al * (g11 - g10)) * fswp;
+        rp = (Gi - Gj) * fswp;
+        const float ax = gu * in.fx * iz, ay = gv * in.fy * iz;
+        const float az = -(ax * c.x + ay * c.y) * iz;
+        jp[0] = c.y * az - c.z * ay;
+        jp[1] = c.z * ax - c.x * az;
+        jp[2] = c.x * ay - c.y * ax;
+        jp[3] = ax;
+        jp[4] = ay;
+        jp[5] = az;
+      }
     }
     if constexpr (JAC) {
-      const float mx = m.x * swg, my = m.y * swg, mz = m.z * swg;
-      const float jg[6] = {my * q.z - mz * q.y, mz * q.x - mx * q.z, mx * q.y - my * q.x, -mx, -my, -mz};
-      const float jp[6] = {c.y * az - c.z * ay, c.z * ax - c.x * az, c.x * ay - c.y * ax, ax, ay, az};
-      accumulate_jac<KAHAN>(A, jg, rg, jp, rp, ph ? 1.0f : 0.0f);
+      accumulate_jac<MODE, V>(A, jg, rg, jp, rp, ph ? (V)1 : (V)0);
     } else {
       A.add(0, rg * rg);
       A.add(1, rp * rp);
-      A.add(2, 1.0f);
-      A.add(3, ph ? 1.0f : 0.0f);
+      A.add(2, (V)1);
+      A.add(3, ph ? (V)1 : (V)0);
     }
   }
 
@@ -185,7 +257,6 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
   __shared__ double red[16][256];
   __shared__ double part[16][16];
   __shared__ double out[32];
-  constexpr int NV = LaneAcc<JAC, KAHAN>::N;
 #pragma unroll
   for (int base = 0; base < 32; base += 16) {
     if (base < NV) {
@@ -221,34 +292,34 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
   }
 }
 
+template <int MODE, bool JAC>
+void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd) {
+  const long long P = c.shape.P;
+  Intr32 i32{(float)in.fx, (float)in.fy, (float)in.cx, (float)in.cy, in.width, in.height};
+  float tau_d2 = (float)(prm.tau_dist * prm.tau_dist);
+  float tau_n = (float)prm.tau_normal;
+  double swg = sqrt(wd * prm.w_geo);
+  double swp = sqrt(wd * prm.w_photo);
+  unsigned grid = (unsigned)(8 * ((P + 7) / 8));
+  hipLaunchKernelGGL((k_dense<MODE, JAC>), dim3(grid), dim3(256), 0, c.stream, c.pairs.as<int>(), P,
+                     c.nd.as<float4>(), c.grad.as<float>(), c.kx.as<float>(), c.ky.as<float>(), c.kx64.as<double>(),
+                     c.ky64.as<double>(), poses, i32, in.fx, in.fy, in.cx, in.cy, tau_d2, tau_n, swg, swp,
+                     c.records.as<double>());
+}
+
 }  // namespace
 
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
                   bool with_jacobians) {
-  const long long P = c.shape.P;
-  if (P == 0) return;
-  Intr32 i32{(float)in.fx, (float)in.fy, (float)in.cx, (float)in.cy, in.width, in.height};
-  float tau_d2 = (float)(prm.tau_dist * prm.tau_dist);
-  float tau_n = (float)prm.tau_normal;
-  float swg = (float)sqrt(wd * prm.w_geo);
-  float swp = (float)sqrt(wd * prm.w_photo);
-  unsigned grid = (unsigned)(8 * ((P + 7) / 8));
-  const int* pr = c.pairs.as<int>();
-  const float4* nd = c.nd.as<float4>();
-  const float* g = c.grad.as<float>();
-  double* rec = c.records.as<double>();
-  const float* kx = c.kx.as<float>();
-  const float* ky = c.ky.as<float>();
+  if (c.shape.P == 0) return;
+  const int mode = prm.accumulate;
   if (with_jacobians) {
-    if (prm.accumulate == 1)
-      hipLaunchKernelGGL((k_dense<true, true>), dim3(grid), dim3(256), 0, c.stream, pr, P, nd, g, kx, ky, poses, i32,
-                         tau_d2, tau_n, swg, swp, rec);
-    else
-      hipLaunchKernelGGL((k_dense<true, false>), dim3(grid), dim3(256), 0, c.stream, pr, P, nd, g, kx, ky, poses, i32,
-                         tau_d2, tau_n, swg, swp, rec);
+    if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd);
+    else if (mode == 1) launch_mode<1, true>(c, in, poses, prm, wd);
+    else launch_mode<0, true>(c, in, poses, prm, wd);
   } else {
-    hipLaunchKernelGGL((k_dense<false, false>), dim3(grid), dim3(256), 0, c.stream, pr, P, nd, g, kx, ky, poses, i32,
-                       tau_d2, tau_n, swg, swp, rec);
+    if (mode == 2) launch_mode<2, false>(c, in, poses, prm, wd);
+    else launch_mode<0, false>(c, in, poses, prm, wd);
   }
 }
 

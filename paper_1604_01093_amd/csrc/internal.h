@@ -47,7 +47,7 @@ struct Context {
   double timings[8] = {0};
 
   // frames
-  Buf nd, grad, kx, ky;
+  Buf nd, grad, kx, ky, kx64, ky64;
   // pairs
   Buf pair_flags, row_count, row_off, pairs, pair_keys;
   // correspondences
@@ -59,9 +59,9 @@ struct Context {
   // per-iteration data
   Buf records, eblocks, hij32, hij64, diag32, diag64, minv32, minv64, rhs, poses_work, pcg_vec, stats, trace;
   // scratch
-  Buf cub_tmp, counts, flags, host_pinned, energy, pcg_partials, pcg_barrier;
+  Buf cub_tmp, counts, flags, host_pinned, energy, pcg_partials, pcg_barrier, pcg_tags;
   int pcg_grid = 0;       // workgroups of the cooperative PCG kernel (0 = not yet chosen)
-  int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative
+  int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative, 3 = replicated vectors
 
   hipEvent_t ev[16] = {};
   bool events_ready = false;

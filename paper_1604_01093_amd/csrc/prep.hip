@@ -14,11 +14,21 @@ __device__ __forceinline__ bool depth_ok(float d, float dmin, float dmax) {
   return (d == d) && d >= dmin && d <= dmax && d != __builtin_inff();
 }
 
+// Ray coefficients (x - cx) / fx and (y - cy) / fy: FP64, and rounded to FP32.
 __global__ void __launch_bounds__(256) k_ray_tables(double fx, double fy, double cx, double cy, int W, int H,
-                                                    float* __restrict__ kx, float* __restrict__ ky) {
+                                                    float* __restrict__ kx, float* __restrict__ ky,
+                                                    double* __restrict__ kx64, double* __restrict__ ky64) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < W) kx[t] = (float)(((double)t - cx) / fx);
-  if (t < H) ky[t] = (float)(((double)t - cy) / fy);
+  if (t < W) {
+    double k = ((double)t - cx) / fx;
+    kx64[t] = k;
+    kx[t] = (float)k;
+  }
+  if (t < H) {
+    double k = ((double)t - cy) / fy;
+    ky64[t] = k;
+    ky[t] = (float)k;
+  }
 }
 
 // One thread per pixel, grid (ceil(W*H/256), F).
@@ -81,7 +91,7 @@ void launch_prepare(Context& c, const bf_frames& fr, const bf_intrinsics& in, co
   const int W = in.width, H = in.height;
   int n = W > H ? W : H;
   hipLaunchKernelGGL(k_ray_tables, dim3((n + 255) / 256), dim3(256), 0, c.stream, in.fx, in.fy, in.cx, in.cy, W, H,
-                     c.kx.as<float>(), c.ky.as<float>());
+                     c.kx.as<float>(), c.ky.as<float>(), c.kx64.as<double>(), c.ky64.as<double>());
   dim3 grid((W * H + 255) / 256, fr.num_frames);
   hipLaunchKernelGGL(k_prepare, grid, dim3(256), 0, c.stream, fr.depth, fr.intensity, c.kx.as<float>(),
                      c.ky.as<float>(), W, H, (float)prm.depth_min, (float)prm.depth_max, c.nd.as<float4>(),

@@ -272,6 +272,7 @@ constexpr unsigned kSpinLimit = 1u << 26;   // ~2 s of polling: a barrier that n
 constexpr int kSolveThreads = 1024;          // 16 wavefronts, one matrix row per wavefront at a time
 constexpr int kSolveWaves = kSolveThreads / 64;
 constexpr int kParts = 8;                     // doubles per workgroup in a grid reduction
+constexpr int kMaxSolveGroups = 512;          // workgroups of a cooperative solve
 
 // Data shared between workgroups is written and read with agent-scope relaxed
 // atomics (coherent across the XCDs without L2 write-back fences); a barrier
@@ -311,7 +312,7 @@ __device__ __forceinline__ bool grid_sync(unsigned* ctr, unsigned target, int* f
 
 // Grid-wide sums of K <= kParts doubles per thread, identical in every workgroup
 // (fixed trees: lanes, then wavefronts in order, then workgroups in order).
-template <int K>
+template <int K, int NW = kSolveWaves>
 __device__ void grid_sums(double (&v)[K], double* parts, unsigned* bar, unsigned& nbar, int* flags, double* sh,
                           int* sh_ok) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -322,10 +323,14 @@ __device__ void grid_sums(double (&v)[K], double* parts, unsigned* bar, unsigned
     if (lane == 0) sh[wave * kParts + k] = t;
   }
   __syncthreads();
+  // two partial buffers alternating with the barrier count: a workgroup can only
+  // overwrite a buffer after every workgroup has passed the next barrier, i.e.
+  // after all of them have read it
+  double* pb = parts + (size_t)(nbar & 1) * kParts * kMaxSolveGroups;
   if (threadIdx.x < K) {
     double t = 0.0;
-    for (int w = 0; w < kSolveWaves; ++w) t += sh[w * kParts + threadIdx.x];
-    st_shared(&parts[blockIdx.x * kParts + threadIdx.x], t);
+    for (int w = 0; w < NW; ++w) t += sh[w * kParts + threadIdx.x];
+    st_shared(&pb[blockIdx.x * kParts + threadIdx.x], t);
   }
   ++nbar;
   grid_sync(bar, nbar * gridDim.x, flags, sh_ok);
@@ -333,14 +338,14 @@ __device__ void grid_sums(double (&v)[K], double* parts, unsigned* bar, unsigned
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double t = 0.0;
-      for (int g = lane; g < (int)gridDim.x; g += 64) t += ld_shared(&parts[g * kParts + k]);
+      for (int g = lane; g < (int)gridDim.x; g += 64) t += ld_shared(&pb[g * kParts + k]);
       for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-      if (lane == 0) sh[kSolveWaves * kParts + k] = t;
+      if (lane == 0) sh[NW * kParts + k] = t;
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = sh[kSolveWaves * kParts + k];
+  for (int k = 0; k < K; ++k) v[k] = sh[NW * kParts + k];
   __syncthreads();
 }
 
@@ -554,18 +559,35 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
   }
 }
 
-// Deterministic sum over a 1024-thread workgroup (fixed tree through LDS).
-__device__ double block_sum1024(double v, double* red1024) {
+// Deterministic sum over a workgroup of NT threads (fixed tree through LDS).
+template <int NT>
+__device__ double block_sum(double v, double* red) {
   const int tid = threadIdx.x;
-  red1024[tid] = v;
+  red[tid] = v;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if (tid < o) red1024[tid] += red1024[tid + o];
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  const double r = red1024[0];
+  const double r = red[0];
   __syncthreads();
   return r;
+}
+
+__device__ __forceinline__ double block_sum1024(double v, double* red1024) { return block_sum<1024>(v, red1024); }
+
+// Deterministic workgroup sum: fixed butterfly per wavefront (lane 0's result),
+// then the NW wavefront sums in order; every thread returns the same value.
+template <int NW>
+__device__ __forceinline__ double block_sum_w(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < NW; ++w) t += sh[w];
+  __syncthreads();
+  return t;
 }
 
 // y = B p (or B^T p) for one 6x6 block, 16-byte loads, FP32 or FP64 arithmetic.
@@ -781,7 +803,299 @@ __global__ void __launch_bounds__(1024) k_solve_single(
   }
 }
 
+// Replicated-vector PCG in one cooperative launch, one grid barrier per iteration.
+// Every workgroup keeps the full r, z, p vectors and all block-Jacobi inverses in
+// LDS and updates them redundantly, in the same fixed order, so all copies stay
+// bit-identical; each wavefront owns one matrix row and keeps that row's blocks
+// in registers (one block per lane) for the whole solve.  Per iteration the owners
+// publish (A p)_v; after the barrier every workgroup reads all of A p and
+// performs the vector updates locally.
+constexpr int kRepThreads = 512;
+constexpr int kRepWaves = kRepThreads / 64;
+
+template <class T>
+__global__ void __launch_bounds__(kRepThreads) k_solve_rep(
+    long long nfree, int F, long long E, int iters, const double* __restrict__ eb, const T* __restrict__ hij,
+    const long long* __restrict__ iptr, const long long* __restrict__ jptr, const long long* __restrict__ ej_sorted,
+    const long long* __restrict__ row_ptr, const int2* __restrict__ entries, const int* __restrict__ frame_of_var,
+    const int* __restrict__ var_of, T* minv_sh, T* r0_sh, unsigned long long* ap_words, double* parts, unsigned* bar,
+    double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
+    double* __restrict__ stats, int* flags) {
+  extern __shared__ double lds_dyn[];
+  __shared__ double sh[(kRepWaves + 1) * kParts];
+  __shared__ double red1024[kRepThreads];
+  __shared__ double blk[kRepWaves][48];
+  __shared__ int sh_ok;
+  const long long n = 6 * nfree;
+  T* r = reinterpret_cast<T*>(lds_dyn);
+  T* z = r + n;
+  T* p = z + n;
+  T* ap = p + n;
+  T* minv = ap + n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long v = (long long)blockIdx.x * kRepWaves + wave;  // owned row (if < nfree)
+  const bool owner = v < nfree;
+  unsigned nbar = 0;
+  if (tid == 0) sh_ok = 1;
+  __syncthreads();
+
+  // ---- prologue: owners assemble their row, invert the diagonal block, publish
+  double pro[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // -, not-PD count, Es, Eg, Ep, ns, ng, np
+  T blockreg[36];
+  int partner = -1;
+  bool tr = false;
+  long long ne = 0;
+  if (owner) {
+    const int f = frame_of_var[v];
+    if (lane < 42) {
+      const int offI = lane < 36 ? kEHii + lane : kEGi + (lane - 36);
+      const int offJ = lane < 36 ? kEHjj + lane : kEGj + (lane - 36);
+      double s0 = 0.0, s1 = 0.0;
+      const long long i0 = iptr[f], i1 = iptr[f + 1];
+      long long k = i0;
+      for (; k + 1 < i1; k += 2) {
+        s0 += eb[(size_t)k * kEdgeWords + offI];
+        s1 += eb[(size_t)(k + 1) * kEdgeWords + offI];
+      }
+      if (k < i1) s0 += eb[(size_t)k * kEdgeWords + offI];
+      const long long j0 = jptr[f], j1 = jptr[f + 1];
+      for (k = j0; k + 1 < j1; k += 2) {
+        s0 += eb[(size_t)ej_sorted[k] * kEdgeWords + offJ];
+        s1 += eb[(size_t)ej_sorted[k + 1] * kEdgeWords + offJ];
+      }
+      if (k < j1) s0 += eb[(size_t)ej_sorted[k] * kEdgeWords + offJ];
+      blk[wave][lane] = s0 + s1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 6) st_shared(&r0_sh[6 * v + lane], (T)(-blk[wave][36 + lane]));
+    // row blocks into registers: lanes < ne hold the off-diagonal entries, lane ne the diagonal
+    ne = row_ptr[v + 1] - row_ptr[v];
+    if (lane < ne) {
+      const int2 en = entries[row_ptr[v] + lane];
+      partner = en.x;
+      tr = en.y & 1;
+      const T* B = hij + (size_t)(en.y >> 1) * 36;
+#pragma unroll
+      for (int q = 0; q < 36; ++q) blockreg[q] = B[q];
+    } else if (lane == ne) {
+      partner = (int)v;
+#pragma unroll
+      for (int q = 0; q < 36; ++q) blockreg[q] = (T)blk[wave][q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      double A[36];
+      for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
+      if (!spd_inverse6(A)) {
+        pro[1] += 1.0;
+        for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
+      }
+      for (int q = 0; q < 36; ++q) st_shared(&minv_sh[v * 36 + q], (T)A[q]);
+    }
+  }
+  if (trace_slot)
+    for (long long e = (long long)blockIdx.x * kRepThreads + tid; e < E; e += (long long)gridDim.x * kRepThreads)
+      for (int q = 0; q < 6; ++q) pro[2 + q] += eb[(size_t)e * kEdgeWords + kEEs + q];
+  grid_sums<8, kRepWaves>(pro, parts, bar, nbar, flags, sh, &sh_ok);
+  const bool bad = pro[1] > 0.0;
+  if (blockIdx.x == 0 && tid == 0) {
+    if (bad) atomicOr(flags, kFlagNotPD);
+    if (trace_slot) {
+      trace_slot[0] = pro[2] + pro[3] + pro[4];
+      for (int q = 0; q < 6; ++q) trace_slot[1 + q] = pro[2 + q];
+      trace_slot[7] = 0.0;
+    }
+  }
+  // every workgroup: full r and M^-1 into LDS, z = M^-1 r, p = z
+  for (long long o = tid; o < n; o += kRepThreads) r[o] = ld_shared(&r0_sh[o]);
+  for (long long o = tid; o < 36 * nfree; o += kRepThreads) minv[o] = ld_shared(&minv_sh[o]);
+  __syncthreads();
+  double part = 0.0;
+  for (long long o = tid; o < n; o += kRepThreads) {
+    const long long w = o / 6;
+    const int a = (int)(o % 6);
+    double s = 0.0;
+    for (int b = 0; b < 6; ++b) s += (double)minv[w * 36 + 6 * a + b] * (double)r[6 * w + b];
+    z[o] = (T)s;
+    p[o] = (T)s;
+    part += (double)r[o] * (double)(T)s;
+  }
+  double rz = block_sum<kRepThreads>(part, red1024);
+  const double rz0 = rz;
+  T xo = (T)0;  // owner lanes 0..5: x of the owned row
+  int done = 0;
+  for (int k = 0; k < iters && !bad && sh_ok; ++k) {
+    if (rz <= 1e-30) break;
+    const unsigned tag = (unsigned)k + 1u;
+    constexpr int WPV = sizeof(T) / 4;  // 32-bit halves per value, each published with the tag
+    unsigned long long* apw = ap_words + (size_t)(k & 1) * n * WPV;
+    // A: owners compute (A p)_v from register blocks and the LDS copy of p, publish it
+    if (owner) {
+      T acc[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+      if (partner >= 0) {
+        T pw[6];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)partner + b];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          T s2 = (T)0;
+#pragma unroll
+          for (int j = 0; j < 6; ++j) s2 += (tr ? blockreg[6 * j + i] : blockreg[6 * i + j]) * pw[j];
+          acc[i] = s2;
+        }
+      }
+      // virtual entries 0..ne-1 are the off-diagonal blocks, ne the diagonal; lanes
+      // hold 0..63, rows with more entries take the rest from memory
+      for (long long q = 64 + lane; q <= ne; q += 64) {
+        T pw[6], y[6];
+        if (q < ne) {
+          const int2 en = entries[row_ptr[v] + q];
+#pragma unroll
+          for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)en.x + b];
+          block_mv<T>(hij + (size_t)(en.y >> 1) * 36, pw, en.y & 1, y);
+        } else {
+          T dg[36];
+#pragma unroll
+          for (int q2 = 0; q2 < 36; ++q2) dg[q2] = (T)blk[wave][q2];
+#pragma unroll
+          for (int b = 0; b < 6; ++b) pw[b] = p[6 * v + b];
+          block_mv<T>(dg, pw, false, y);
+        }
+#pragma unroll
+        for (int b = 0; b < 6; ++b) acc[b] += y[b];
+      }
+      double tot[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        double t = (double)acc[b];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        tot[b] = t;
+      }
+      if (lane < 6 * WPV) {
+        // lane b*WPV + h publishes half h of value b: (tag << 32) | bits
+        const int b = lane / WPV, h = lane % WPV;
+        double tb = tot[0];
+#pragma unroll
+        for (int q = 1; q < 6; ++q)
+          if (b == q) tb = tot[q];
+        unsigned bits;
+        if constexpr (WPV == 1) {
+          bits = __float_as_uint((float)tb);
+        } else {
+          const unsigned long long d = (unsigned long long)__double_as_longlong(tb);
+          bits = h ? (unsigned)(d >> 32) : (unsigned)(d & 0xffffffffull);
+        }
+        st_shared(&apw[(6 * v + b) * WPV + h], ((unsigned long long)tag << 32) | bits);
+      }
+    }
+    // B: every workgroup gathers all of A p (polling the tagged words), then updates its copy
+    double part = 0.0;
+    {
+      constexpr int kMaxPer = 8;                 // values per thread gathered at once
+      const long long nw = n * WPV;
+      for (long long o0 = tid; o0 < nw; o0 += (long long)kRepThreads * kMaxPer) {
+        unsigned long long wv[kMaxPer];
+        bool ready = false;
+        unsigned spins = 0;
+        while (!ready) {
+          ready = true;
+#pragma unroll
+          for (int q = 0; q < kMaxPer; ++q) {
+            const long long o = o0 + (long long)q * kRepThreads;
+            if (o < nw) {
+              wv[q] = ld_shared(&apw[o]);
+              ready = ready && (unsigned)(wv[q] >> 32) == tag;
+            }
+          }
+          if (!ready) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+              atomicOr(flags, kFlagTimeout);
+              sh_ok = 0;
+              break;
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxPer; ++q) {
+          const long long o = o0 + (long long)q * kRepThreads;
+          if (o < nw) reinterpret_cast<unsigned*>(ap)[o] = (unsigned)(wv[q] & 0xffffffffull);
+        }
+      }
+      __syncthreads();
+      for (long long o = tid; o < n; o += kRepThreads) part += (double)p[o] * (double)ap[o];
+    }
+    const double pAp = block_sum_w<kRepWaves>(part, sh);
+    if (!sh_ok) break;
+    const double alpha = rz / pAp;
+    if (owner && lane < 6) xo = (T)((double)xo + alpha * (double)p[6 * v + lane]);
+    part = 0.0;
+    for (long long w = tid; w < nfree; w += kRepThreads) {
+      double rw[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        rw[b] = (double)(T)((double)r[6 * w + b] - alpha * (double)ap[6 * w + b]);
+        r[6 * w + b] = (T)rw[b];
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) s2 += (double)minv[w * 36 + 6 * a + b] * rw[b];
+        const T zt = (T)s2;
+        z[6 * w + a] = zt;
+        part += rw[a] * (double)zt;
+      }
+    }
+    const double rz_new = block_sum_w<kRepWaves>(part, sh);
+    const double beta = rz_new / rz;
+    rz = rz_new;
+    ++done;
+    for (long long w = tid; w < nfree; w += kRepThreads)
+#pragma unroll
+      for (int b = 0; b < 6; ++b) p[6 * w + b] = (T)((double)z[6 * w + b] + beta * (double)p[6 * w + b]);
+    __syncthreads();
+  }
+  // epilogue: owners publish dx and update their poses
+  if (owner && lane < 6 && delta_out) delta_out[6LL * frame_of_var[v] + lane] = bad ? 0.0 : (double)xo;
+  if (delta_out)
+    for (long long o = (long long)blockIdx.x * kRepThreads + tid; o < 6LL * F;
+         o += (long long)gridDim.x * kRepThreads)
+      if (var_of[o / 6] < 0) delta_out[o] = 0.0;
+  if (owner && update && !bad && sh_ok) {
+    double xi[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) xi[q] = (double)__shfl(xo, q);
+    if (lane == 0) {
+      double dR[9], dt[3];
+      exp_se3(xi, dR, dt);
+      double* T4 = poses + (size_t)frame_of_var[v] * 16;
+      double Rn[9], tn[3];
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+          Rn[3 * i + j] = T4[4 * i] * dR[j] + T4[4 * i + 1] * dR[3 + j] + T4[4 * i + 2] * dR[6 + j];
+        tn[i] = T4[4 * i] * dt[0] + T4[4 * i + 1] * dt[1] + T4[4 * i + 2] * dt[2] + T4[4 * i + 3];
+      }
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) T4[4 * i + j] = Rn[3 * i + j];
+        T4[4 * i + 3] = tn[i];
+      }
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0 && stats) {
+    stats[0] = rz0;
+    stats[1] = rz;
+    stats[2] = done;
+  }
+}
+
 __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+__global__ void k_zero_tags(unsigned long long* tags, long long n, unsigned* bar) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) tags[k] = 0ull;
+  if (k == 0) *bar = 0u;
+}
 
 // Energy and counts over all edges, fixed order (one workgroup of 1024).
 __global__ void __launch_bounds__(1024) k_energy(const double* __restrict__ eb, long long E, double* __restrict__ dst) {
@@ -869,9 +1183,9 @@ void launch_solve_coop(Context& c, int iters, double* trace_slot, double* delta_
               "occupancy query");
     c.pcg_grid = std::max(1, per_cu) * c.num_cus;
   }
-  int G = (int)std::min<long long>((nf + kSolveWaves - 1) / kSolveWaves, std::min(c.pcg_grid, 512));
+  int G = (int)std::min<long long>((nf + kSolveWaves - 1) / kSolveWaves, std::min(c.pcg_grid, kMaxSolveGroups));
   if (G < 1) G = 1;
-  ensure(c.pcg_partials, sizeof(double) * kParts * 512);
+  ensure(c.pcg_partials, sizeof(double) * 2 * kParts * kMaxSolveGroups);
   ensure(c.pcg_barrier, sizeof(unsigned) * 4);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c.stream, c.pcg_barrier.as<unsigned>());
   T* x = vec;
@@ -927,10 +1241,73 @@ bool launch_solve_single(Context& c, int iters, double* trace_slot, double* delt
   return true;
 }
 
+// LDS budget of the replicated-vector solve (dynamic part).
+constexpr size_t kRepLdsMax = 128 * 1024;
+
+template <class T>
+bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_out, double* poses, double* stats,
+                      bool update, T* minv_sh, T* hij, T* vec) {
+  long long nf = c.shape.nfree;
+  long long n = 6 * nf;
+  long long E = c.shape.E;
+  const size_t lds = sizeof(T) * (4 * (size_t)n + 36 * (size_t)nf);
+  if (lds > kRepLdsMax) return false;
+  auto kern = k_solve_rep<T>;
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[sizeof(T) == 8]) {
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kRepLdsMax),
+              "set LDS limit");
+    attr_set[sizeof(T) == 8] = true;
+  }
+  int per_cu = 0;
+  check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kRepThreads,
+                                                         lds),
+            "occupancy query");
+  const long long G = (nf + kRepWaves - 1) / kRepWaves;   // one row per wavefront
+  if (per_cu < 1 || G > (long long)per_cu * c.num_cus || G > kMaxSolveGroups) return false;
+  ensure(c.pcg_partials, sizeof(double) * 2 * kParts * kMaxSolveGroups);
+  ensure(c.pcg_barrier, sizeof(unsigned) * 4);
+  const long long nwords = 2 * n * (long long)(sizeof(T) / 4);
+  ensure(c.pcg_tags, sizeof(unsigned long long) * (size_t)(nwords + 1));
+  unsigned long long* tags = c.pcg_tags.as<unsigned long long>();
+  hipLaunchKernelGGL(k_zero_tags, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, c.stream, tags, nwords,
+                     c.pcg_barrier.as<unsigned>());
+  T* r0 = vec;
+  double* parts = c.pcg_partials.as<double>();
+  unsigned* bar = c.pcg_barrier.as<unsigned>();
+  int F = c.shape.F;
+  int upd = update ? 1 : 0;
+  const double* eb = c.eblocks.as<double>();
+  const long long* ip = c.iptr.as<long long>();
+  const long long* jp = c.jptr.as<long long>();
+  const long long* ejs = c.ej_sorted.as<long long>();
+  const long long* rp = c.row_ptr.as<long long>();
+  const int2* en = c.row_entries.as<int2>();
+  const int* fov = c.frame_of_var.as<int>();
+  const int* vof = c.var_of.as<int>();
+  int* fl = c.flags.as<int>();
+  void* args[] = {&nf, &F, &E, &iters, &eb, &hij, &ip, &jp, &ejs, &rp, &en, &fov, &vof, &minv_sh, &r0, &tags,
+                  &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl};
+  check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)G), dim3(kRepThreads),
+                                       args, (unsigned)lds, c.stream),
+            "cooperative solve launch");
+  return true;
+}
+
 void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
                   bool update_poses) {
   if (c.shape.nfree == 0) return;
-  if (c.solve_mode != 2) {
+  if (c.solve_mode == 0 || c.solve_mode == 3) {
+    bool ok = c.pcg_storage == 1
+                  ? launch_solve_rep<double>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
+                                             c.minv64.as<double>(), c.hij64.as<double>(), c.pcg_vec.as<double>())
+                  : launch_solve_rep<float>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
+                                            c.minv32.as<float>(), c.hij32.as<float>(), c.pcg_vec.as<float>());
+    if (ok) return;
+    if (c.solve_mode == 3) fail(BF_ERR_UNSUPPORTED, "replicated-vector solve does not fit");
+  }
+  if (c.solve_mode == 1) {
     bool ok = c.pcg_storage == 1
                   ? launch_solve_single<double>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
                                                 c.diag64.as<double>(), c.minv64.as<double>(), c.hij64.as<double>())

@@ -458,6 +458,8 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
   ensure(c.grad, sizeof(float) * HW * F);
   ensure(c.kx, sizeof(float) * in.width);
   ensure(c.ky, sizeof(float) * in.height);
+  ensure(c.kx64, sizeof(double) * in.width);
+  ensure(c.ky64, sizeof(double) * in.height);
   launch_prepare(c, fr, in, prm);
 
   // a2: dense pairs

@@ -31,10 +31,19 @@ def global200():
     prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
     res = solve_problem(prob, prm, linear="pcg")
     s = res["setup"]
+    # trajectory X_0..X_n and the per-iteration increments (reduced, free frames in order)
+    from oracle.se3 import exp_se3
+    traj = [prob.init_poses.copy()]
+    X = prob.init_poses.copy()
+    for st in res["steps"]:
+        for n, f in enumerate(s.free):
+            X[f] = X[f] @ exp_se3(st["dx"][6 * n:6 * n + 6])
+        traj.append(X.copy())
     np.savez_compressed(
         os.path.join(HERE, "global200_oracle.npz"),
         digest=np.array(input_digest(prob)),
         poses=res["poses"], pairs=s.pairs, edges=s.edges, free=s.free,
+        traj=np.array(traj), steps=np.array([st["dx"] for st in res["steps"]]),
         energy=np.array([res["energy"][k] for k in ("total", "sparse", "geo", "photo")]),
         counts=np.array([res["energy"][k] for k in ("n_sparse", "n_geo", "n_photo")]),
         trace=np.array([[t[k] for k in ("total", "sparse", "geo", "photo")] for t in res["trace"]]),

@@ -168,7 +168,7 @@ def test_normal_equations_and_edge_blocks(ctx, chunk, chunk_setup, pcg_storage):
     assert abs(out["energy"][0] - en["total"]) <= 1e-6 * en["total"]
 
 
-@pytest.mark.parametrize("pcg_storage,solve_kernel", [(0, 1), (1, 1), (0, 2), (1, 2)])
+@pytest.mark.parametrize("pcg_storage,solve_kernel", [(0, 1), (1, 1), (0, 2), (1, 2), (0, 3), (1, 3)])
 def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage, solve_kernel):
     prm = chunk_setup.params
     dp = device_problem(chunk)
@@ -188,7 +188,8 @@ def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage, solve_kern
     assert (delta[:6] == 0).all()
 
 
-@pytest.mark.parametrize("pcg_storage,accumulate,solve_kernel", [(0, 0, 1), (1, 0, 1), (0, 1, 1), (0, 0, 2), (1, 0, 2)])
+@pytest.mark.parametrize("pcg_storage,accumulate,solve_kernel",
+                         [(0, 0, 1), (1, 0, 1), (0, 1, 1), (0, 2, 1), (0, 0, 2), (1, 0, 2), (0, 0, 3), (1, 2, 3)])
 def test_gauss_newton_chunk(ctx, chunk, pcg_storage, accumulate, solve_kernel):
     prm = Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg)
     ref = solve(chunk.depth, chunk.intensity, chunk.intrinsics, chunk.corr_i, chunk.corr_j, chunk.corr_p,
