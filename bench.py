@@ -20,10 +20,52 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SOURCE_PIXEL = 40  # depth+normal+gradient of the source pixel and of its target footprint
+DENSE_SOURCE = os.path.join(ROOT, "paper_1604_01093_amd", "csrc", "dense.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_dense_global200_traffic.md")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per dense launch from the committed FETCH_SIZE/WRITE_SIZE summary,
+    or None when the summary is absent or the dense kernel's source has changed since."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for ln in f:
+            if ln.startswith("- ") and ":" in ln:
+                k, v = ln[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("dense.hip sha256") != source_digest(DENSE_SOURCE):
+        return None
+    try:
+        return int(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """A plain device copy of known size (read mib MiB, write mib MiB) for scaling the
+    FETCH_SIZE/WRITE_SIZE counters; only run when asked for, under the profiler."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 x {mib} MiB read + {mib} MiB written")
+    del src, dst
 
 
 def cpu_baseline(prob, n_gn, n_pcg):
@@ -63,6 +105,8 @@ def main():
     ap.add_argument("--pcg-storage", type=int, default=0)
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--solve-kernel", type=int, default=0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain copy of this size first (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -75,6 +119,8 @@ def main():
     from paper_1604_01093_amd import bf
     from synth import make_problem
 
+    if args.copy_calibration_mib > 0:
+        copy_calibration(args.copy_calibration_mib)
     log("generating the 200-keyframe workload")
     t0 = time.perf_counter()
     prob = make_problem(1)
@@ -149,7 +195,7 @@ def main():
                    "solve_kernel": ["auto", "single", "coop", "replicated"][args.solve_kernel]},
         "roofline": {"bound": "hbm", "kernel": "k_dense<jacobians>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(avg_dense_s * 1e6, 2),
+                     "traffic": measured_traffic(), "avg_launch_us": round(avg_dense_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": int(alg_bytes)},
         "phase_us_per_step": {n: round(v, 1) for n, v in zip(
             ["setup", "dense", "edges", "assemble", "pcg", "final", "total"], phase[:7])},
