@@ -7,7 +7,13 @@ correspondence grouping and moments, then 8 iterations of dense pair jobs +
 edge blocks + assembly + 20 PCG iterations + SE(3) update, then the final
 energy.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line (see the design doc for the fields).
+Beside it (field "batched"), the batched intra-chunk workload: 256 independent
+chunk problems of 4-11 frames at 160x120, solved (5 GN x 10 PCG each) by one
+bf_gauss_newton_batch call per step, against the same 256 problems solved one
+after another by bf_gauss_newton; problems per second for both, and the largest
+pose difference between the two forms.
+
+Prints one JSON line.
 """
 import argparse
 import json
@@ -105,6 +111,8 @@ def main():
     ap.add_argument("--pcg-storage", type=int, default=0)
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--solve-kernel", type=int, default=0)
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain copy of this size first (for scaling HBM counters)")
     args = ap.parse_args()
@@ -117,14 +125,21 @@ def main():
     import torch
 
     from paper_1604_01093_amd import bf
-    from synth import make_problem
+    from synth import make_batch_chunks, make_problem
 
-    if args.copy_calibration_mib > 0:
-        copy_calibration(args.copy_calibration_mib)
+    # inputs are generated before anything touches the GPU (the batch generator forks)
     log("generating the 200-keyframe workload")
     t0 = time.perf_counter()
     prob = make_problem(1)
     log(f"generated in {time.perf_counter() - t0:.1f} s: {prob.num_frames} frames, {len(prob.corr_i)} correspondences")
+    chunks = None
+    if not args.skip_batched:
+        t0 = time.perf_counter()
+        chunks = make_batch_chunks()
+        log(f"generated 256 chunk problems in {time.perf_counter() - t0:.1f} s "
+            f"({sum(c.num_frames for c in chunks)} frames)")
+    if args.copy_calibration_mib > 0:
+        copy_calibration(args.copy_calibration_mib)
 
     ctx = bf.Context()
     dp = bf.DeviceProblem.from_numpy(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j,
@@ -200,11 +215,61 @@ def main():
         "phase_us_per_step": {n: round(v, 1) for n, v in zip(
             ["setup", "dense", "edges", "assemble", "pcg", "final", "total"], phase[:7])},
     }
+    if chunks is not None:
+        line["batched"] = batched(bf, ctx, chunks, args.batched_steps)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(prob, prob.n_gn, prob.n_pcg)
     ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def batched(bf, ctx, chunks, steps):
+    """256 chunk problems: one batched call per step vs one plain call per problem."""
+    import numpy as np
+    import torch
+
+    n_gn, n_pcg = chunks[0].n_gn, chunks[0].n_pcg
+    params = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0)
+    dp, offs, init = bf.device_batch(chunks)
+    out = torch.empty_like(init)
+    singles = [(bf.DeviceProblem.from_numpy(c.depth, c.intensity, c.intrinsics, c.corr_i, c.corr_j, c.corr_p,
+                                            c.corr_q), torch.as_tensor(c.init_poses).cuda()) for c in chunks]
+    singles_out = [torch.empty_like(i) for _, i in singles]
+    torch.cuda.synchronize()
+    log("batched: warm-up (first calls time the dense workgroup sizes)")
+    for _ in range(2):
+        res = bf.bf_gauss_newton_batch(ctx, dp, offs, init, params, out_poses=out)
+    for (d, i), o in zip(singles, singles_out):
+        bf.bf_gauss_newton(ctx, d, i, params, out_poses=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = bf.bf_gauss_newton_batch(ctx, dp, offs, init, params, out_poses=out)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for (d, i), o in zip(singles, singles_out):
+        bf.bf_gauss_newton(ctx, d, i, params, out_poses=o)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    P = out.cpu().numpy()
+    worst_r = worst_t = 0.0
+    for b, o in enumerate(singles_out):
+        A, B = P[offs[b]:offs[b + 1]], o.cpu().numpy()
+        for f in range(A.shape[0]):
+            c = np.clip((np.trace(A[f, :3, :3].T @ B[f, :3, :3]) - 1.0) / 2.0, -1.0, 1.0)
+            worst_r = max(worst_r, float(np.arccos(c)))
+            worst_t = max(worst_t, float(np.linalg.norm(A[f, :3, 3] - B[f, :3, 3])))
+    nb = len(chunks)
+    log(f"batched: {nb / t_batch:.1f} problems/s ({1e3 * t_batch:.2f} ms per batch); "
+        f"one at a time: {nb / t_seq:.1f} problems/s ({1e3 * t_seq:.1f} ms)")
+    return {"metric": "batched solves/sec", "value": round(nb / t_batch, 2), "unit": "solves/s",
+            "sequential_value": round(nb / t_seq, 2), "speedup": round(t_seq / t_batch, 2),
+            "ms_per_batch": round(1e3 * t_batch, 3), "steps": steps,
+            "max_pose_diff_vs_sequential": {"rad": worst_r, "m": worst_t},
+            "config": {"workload": f"{nb} chunk problems, 4-11 frames (sum {offs[-1]}), 160x120, "
+                                   f"{n_gn} GN x {n_pcg} PCG, dense workgroup size timed per shape"}}
 
 
 if __name__ == "__main__":

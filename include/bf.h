@@ -101,8 +101,14 @@ typedef struct bf_params {
   int32_t timing;           /* 1: record HIP events per phase for bf_last_timings() */
   int32_t solve_kernel;     /* PCG kernel: 0 = automatic, 1 = single workgroup (vectors in LDS),
                                2 = cooperative grid with owner-computed vectors (any size),
-                               3 = cooperative grid with replicated vectors (vectors in LDS) */
-  int32_t reserved0;        /* must be 0 */
+                               3 = cooperative grid with replicated vectors (vectors in LDS),
+                               4 = one workgroup per problem (the kernel of bf_gauss_newton_batch;
+                                   chosen automatically for problems of at most 64 free frames) */
+  int32_t dense_threads;    /* threads per dense pair job: 64, 128, 256 (default) or 512; 0 = the
+                               fastest, timed once per image size, mode and job-count range in
+                               this context (the first call of a shape synchronises once).  The
+                               lane sums of a job are combined in an order fixed by this value,
+                               so results are bitwise reproducible for a fixed value. */
   double tau_dist;          /* dense association: |c - q| < tau_dist (metres) */
   double tau_normal;        /* dense association: normal dot product > tau_normal */
   double max_angle_deg;     /* dense pair test: viewing directions within this angle */
@@ -223,6 +229,28 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* frames, const bf_int
                           const bf_corrs* corrs, const bf_pairs* pairs, const double* init_poses,
                           const bf_params* params, double* out_poses, double* out_energy,
                           double* out_trace);
+
+/*
+ * Many independent problems in one call (Sec. 4.1: every chunk's intra-chunk
+ * alignment is its own solve of the same energy).  Problem b owns the consecutive
+ * frames [frame_offsets[b], frame_offsets[b+1]) of `frames`; its first frame is
+ * its fixed gauge frame.  Correspondences and caller-given pairs use indices into
+ * the concatenated frames and must not connect two problems (BF_ERR_INVALID_ARG).
+ * All problems share the intrinsics and params; every kernel launch covers all
+ * problems (dense pair jobs of all problems in one grid, one PCG workgroup per
+ * problem), and each problem's result is the result it gets alone up to rounding
+ * (bitwise the same with a fixed params->dense_threads).
+ *   frame_offsets (host) [num_problems + 1], 0 = first, strictly increasing, last =
+ *                 frames->num_frames.
+ *   out_poses (device) [F][4][4]; out_energy (host) [num_problems][4];
+ *   out_trace (host, may be NULL) [num_problems][num_gn][4].
+ * params->solve_kernel must be 0 or 4.
+ */
+bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                                const bf_corrs* corrs, const bf_pairs* pairs, int32_t num_problems,
+                                const int32_t* frame_offsets, const double* init_poses,
+                                const bf_params* params, double* out_poses, double* out_energy,
+                                double* out_trace);
 
 /* Microseconds spent in each phase of the last bf_gauss_newton() call run with
  * params->timing = 1, measured with HIP events on the context's stream (host out,

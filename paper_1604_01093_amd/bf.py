@@ -50,7 +50,7 @@ class bf_params(ctypes.Structure):
     _fields_ = [("w_sparse", c_double), ("w_dense", c_double), ("w_geo", c_double), ("w_photo", c_double),
                 ("dense_ramp", c_int32), ("use_sparse", c_int32), ("use_dense", c_int32), ("num_gn", c_int32),
                 ("num_pcg", c_int32), ("accumulate", c_int32), ("pcg_storage", c_int32), ("timing", c_int32),
-                ("solve_kernel", c_int32), ("reserved0", c_int32),
+                ("solve_kernel", c_int32), ("dense_threads", c_int32),
                 ("tau_dist", c_double), ("tau_normal", c_double), ("max_angle_deg", c_double),
                 ("depth_min", c_double), ("depth_max", c_double)]
 
@@ -83,6 +83,9 @@ _SIGS = {
     "bf_gauss_newton": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                 POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_void_p, POINTER(c_double),
                                 POINTER(c_double)]),
+    "bf_gauss_newton_batch": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
+                                      POINTER(bf_pairs), c_int32, POINTER(c_int32), c_void_p, POINTER(bf_params),
+                                      c_void_p, POINTER(c_double), POINTER(c_double)]),
     "bf_last_timings": (c_int, [c_void_p, POINTER(c_double)]),
 }
 
@@ -325,3 +328,61 @@ def bf_gauss_newton(ctx, prob, init_poses, params, out_poses=None, trace=False):
     if trace:
         res["trace"] = [list(tr[4 * k:4 * k + 4]) for k in range(params.num_gn)]
     return res
+
+
+def bf_gauss_newton_batch(ctx, prob, frame_offsets, init_poses, params, out_poses=None, trace=False):
+    """Independent problems over consecutive frame ranges of one DeviceProblem.
+    frame_offsets: sequence of num_problems + 1 ints (host)."""
+    _poses_check(init_poses, prob.num_frames)
+    offs = [int(v) for v in frame_offsets]
+    B = len(offs) - 1
+    if out_poses is None:
+        out_poses = torch.empty_like(init_poses)
+    off_arr = (c_int32 * len(offs))(*offs)
+    e = (c_double * (4 * max(B, 1)))()
+    tr = (c_double * (4 * max(B, 1) * max(params.num_gn, 1)))() if trace else None
+    ctx._check(ctx.lib.bf_gauss_newton_batch(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr),
+                                             ctypes.byref(prob.corrs), prob._pairs_ref(), B, off_arr,
+                                             _ptr(init_poses), ctypes.byref(params), _ptr(out_poses), e, tr))
+    res = {"poses": out_poses,
+           "energy": [{"total": e[4 * b], "sparse": e[4 * b + 1], "geo": e[4 * b + 2], "photo": e[4 * b + 3]}
+                      for b in range(B)]}
+    if trace:
+        G = params.num_gn
+        res["trace"] = [[list(tr[(b * G + k) * 4:(b * G + k) * 4 + 4]) for k in range(G)] for b in range(B)]
+    return res
+
+
+def concat_problems(problems):
+    """Host-side concatenation of independent problems for bf_gauss_newton_batch:
+    frames stacked in order, correspondence frame indices shifted by each problem's
+    first frame.  Each problem provides depth, intensity, intrinsics, corr_i, corr_j,
+    corr_p, corr_q and init_poses (numpy arrays); all must share the intrinsics."""
+    import numpy as np
+    intr = tuple(problems[0].intrinsics)
+    offs = [0]
+    for pr in problems:
+        if tuple(pr.intrinsics) != intr:
+            raise ValueError("all problems of a batch must share the intrinsics")
+        offs.append(offs[-1] + pr.depth.shape[0])
+    cat = lambda xs, dt: np.ascontiguousarray(np.concatenate(xs), dtype=dt)
+    return {
+        "depth": cat([pr.depth for pr in problems], np.float32),
+        "intensity": cat([pr.intensity for pr in problems], np.float32),
+        "intrinsics": intr,
+        "corr_i": cat([np.asarray(pr.corr_i, np.int64) + o for pr, o in zip(problems, offs)], np.int32),
+        "corr_j": cat([np.asarray(pr.corr_j, np.int64) + o for pr, o in zip(problems, offs)], np.int32),
+        "corr_p": cat([np.asarray(pr.corr_p).reshape(-1, 3) for pr in problems], np.float32),
+        "corr_q": cat([np.asarray(pr.corr_q).reshape(-1, 3) for pr in problems], np.float32),
+        "init_poses": cat([pr.init_poses for pr in problems], np.float64),
+        "offsets": offs,
+    }
+
+
+def device_batch(problems, device="cuda"):
+    """DeviceProblem, frame offsets and initial poses (device) of a batch of problems."""
+    b = concat_problems(problems)
+    dp = DeviceProblem.from_numpy(b["depth"], b["intensity"], b["intrinsics"], b["corr_i"], b["corr_j"],
+                                  b["corr_p"], b["corr_q"], device=device)
+    init = torch.as_tensor(b["init_poses"]).to(device)
+    return dp, b["offsets"], init

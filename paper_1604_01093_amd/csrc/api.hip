@@ -73,7 +73,10 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
     fail(BF_ERR_INVALID_ARG, "weights must be finite and >= 0");
   if (prm->accumulate < 0 || prm->accumulate > 2) fail(BF_ERR_INVALID_ARG, "accumulate must be 0, 1 or 2");
   if (prm->pcg_storage != 0 && prm->pcg_storage != 1) fail(BF_ERR_INVALID_ARG, "pcg_storage must be 0 or 1");
-  if (prm->solve_kernel < 0 || prm->solve_kernel > 3) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..3");
+  if (prm->solve_kernel < 0 || prm->solve_kernel > 4) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..4");
+  if (prm->dense_threads != 0 && prm->dense_threads != 64 && prm->dense_threads != 128 &&
+      prm->dense_threads != 256 && prm->dense_threads != 512)
+    fail(BF_ERR_INVALID_ARG, "dense_threads must be 0, 64, 128, 256 or 512");
   if (!(prm->tau_dist > 0) || !isfinite(prm->tau_normal) || !(prm->depth_max > prm->depth_min) ||
       !isfinite(prm->max_angle_deg))
     fail(BF_ERR_INVALID_ARG, "bad thresholds");
@@ -103,15 +106,17 @@ void check_poses(Context& c, const double* poses, int F) {
   hipLaunchKernelGGL(k_check_poses, dim3((F * 16 + 255) / 256), dim3(256), 0, c.stream, poses, F, c.flags.as<int>());
 }
 
-// Structure + per-iteration buffers for the current shape.
+// Structure + per-iteration buffers for the current shape (offsets: host frame
+// offsets of nseg independent problems, or nullptr for one problem).
 void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co, const bf_pairs* pairs,
-           const double* poses, const bf_params* prm) {
+           const double* poses, const bf_params* prm, const int32_t* offsets = nullptr, int nseg = 1) {
   Context& c = *ctx;
   c.pcg_storage = prm->pcg_storage;
   c.solve_mode = prm->solve_kernel;
   c.have_system = false;
   ensure(c.counts, 8 * sizeof(long long));
   ensure(c.flags, sizeof(int));
+  set_segments(c, fr->num_frames, offsets, nseg);
   build_structure(c, *fr, *in, co, pairs, poses, *prm);
   const Shape& s = c.shape;
   ensure(c.records, sizeof(double) * kRecWords * (s.P + 1));
@@ -129,8 +134,9 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
     ensure(c.rhs, sizeof(float) * 6 * (s.nfree + 1));
     ensure(c.pcg_vec, sizeof(float) * 6 * 6 * (s.nfree + 1));
   }
-  ensure(c.energy, sizeof(double) * 8);
-  ensure(c.stats, sizeof(double) * 4);
+  ensure(c.energy, sizeof(double) * 8 * s.nseg);
+  ensure(c.stats, sizeof(double) * 4 * s.nseg);
+  ensure(c.trace, sizeof(double) * 8 * s.nseg * (prm->num_gn + 1));
 }
 
 void sync_and_flags(Context& c, int* hf) {
@@ -218,6 +224,8 @@ void bf_params_default(bf_params* o) {
   o->accumulate = 0;
   o->pcg_storage = 0;
   o->timing = 0;
+  o->solve_kernel = 0;
+  o->dense_threads = 0;
   o->tau_dist = 0.15;
   o->tau_normal = 0.9;
   o->max_angle_deg = 60.0;
@@ -256,7 +264,8 @@ void bf_destroy(bf_context* c) {
                  &c->frame_of_var, &c->records, &c->eblocks, &c->hij32, &c->hij64, &c->diag32, &c->diag64,
                  &c->minv32, &c->minv64, &c->rhs, &c->poses_work, &c->pcg_vec, &c->stats, &c->trace,
                  &c->cub_tmp, &c->counts, &c->flags, &c->host_pinned, &c->energy,
-                 &c->pcg_partials, &c->pcg_barrier, &c->pcg_tags};
+                 &c->pcg_partials, &c->pcg_barrier, &c->pcg_tags, &c->seg_start, &c->seg_of,
+                 &c->seg_var_ptr, &c->seg_edge_ptr};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
@@ -310,6 +319,7 @@ bf_status bf_build_pairs(bf_context* ctx, const bf_frames* fr, const bf_intrinsi
     ensure(c.flags, sizeof(int));
     check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
     check_poses(c, poses, fr->num_frames);
+    set_segments(c, fr->num_frames, nullptr, 1);
     int64_t P = launch_pair_search(c, *fr, *in, poses, *prm);
     int hf = 0;
     sync_and_flags(c, &hf);
@@ -438,6 +448,77 @@ bf_status bf_pcg_solve(bf_context* ctx, int32_t num_iters, double* out_delta, do
   });
 }
 
+}  // extern "C"
+
+namespace bf {
+namespace {
+
+// The Gauss-Newton loop over the structure built by setup(): nseg problems solved
+// together; energies (host) [nseg][4], trace (host, may be NULL) [nseg][num_gn][4].
+void run_gauss_newton(bf_context* ctx, const bf_intrinsics* in, const bf_params* prm, const double* init_poses,
+                      double* out_poses, double* out_energy, double* out_trace, Timer& tm, int t_start) {
+  Context& c = *ctx;
+  const int F = c.shape.F;
+  const int nseg = c.shape.nseg;
+  ensure(c.poses_work, sizeof(double) * 16 * F);
+  double* poses = c.poses_work.as<double>();
+  check_hip(hipMemcpyAsync(poses, init_poses, sizeof(double) * 16 * F, hipMemcpyDeviceToDevice, c.stream),
+            "copy poses");
+  int t_setup = tm.mark();
+  tm.span(0, t_start, t_setup);
+  for (int k = 0; k < prm->num_gn; ++k) {
+    double wd = dense_weight(*prm, k);
+    double* slot = c.trace.as<double>() + 8 * (size_t)nseg * k;
+    int a = tm.mark();
+    launch_dense(c, *in, poses, *prm, wd, true);
+    int b = tm.mark();
+    launch_edge_blocks(c, poses, *prm, true);
+    int d = tm.mark();
+    if (c.shape.nfree > 0) launch_solve(c, prm->num_pcg, slot, nullptr, poses, nullptr, true);
+    else launch_energy(c, slot);
+    int f = tm.mark();
+    tm.span(1, a, b);
+    tm.span(2, b, d);
+    tm.span(4, d, f);
+  }
+  int g0 = tm.mark();
+  double wd = dense_weight(*prm, prm->num_gn > 0 ? prm->num_gn - 1 : 0);
+  launch_dense(c, *in, poses, *prm, wd, false);
+  launch_edge_blocks(c, poses, *prm, false);
+  launch_energy(c, c.energy.as<double>());
+  hipLaunchKernelGGL(k_copy_if_ok, dim3((16 * F + 255) / 256), dim3(256), 0, c.stream, poses, out_poses, 16 * F,
+                     c.flags.as<int>());
+  int g1 = tm.mark();
+  tm.span(5, g0, g1);
+  std::vector<double> e8(8 * (size_t)nseg);
+  int hf = 0;
+  std::vector<double> tr(8 * (size_t)nseg * (prm->num_gn + 1));
+  check_hip(hipMemcpyAsync(e8.data(), c.energy.p, sizeof(double) * e8.size(), hipMemcpyDeviceToHost, c.stream),
+            "copy energy");
+  if (out_trace && prm->num_gn > 0)
+    check_hip(hipMemcpyAsync(tr.data(), c.trace.p, sizeof(double) * 8 * nseg * prm->num_gn, hipMemcpyDeviceToHost,
+                             c.stream), "copy trace");
+  sync_and_flags(c, &hf);
+  raise_flags(hf);
+  for (int b = 0; b < nseg; ++b)
+    for (int l = 0; l < 4; ++l) out_energy[4 * b + l] = e8[8 * b + l];
+  if (out_trace)
+    for (int b = 0; b < nseg; ++b)
+      for (int k = 0; k < prm->num_gn; ++k)
+        for (int l = 0; l < 4; ++l) out_trace[((size_t)b * prm->num_gn + k) * 4 + l] = tr[8 * ((size_t)nseg * k + b) + l];
+  tm.finish(c.timings);
+  if (tm.on) {
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, ctx->pool[t_start], ctx->pool[g1]), "hipEventElapsedTime");
+    c.timings[6] = 1000.0 * ms;
+  }
+}
+
+}  // namespace
+}  // namespace bf
+
+extern "C" {
+
 bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
                           const bf_pairs* pairs, const double* init_poses, const bf_params* prm, double* out_poses,
                           double* out_energy, double* out_trace) {
@@ -447,61 +528,34 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* fr, const bf_intrins
     if (!out_poses || !out_energy) fail(BF_ERR_INVALID_ARG, "null out_poses or out_energy");
     Context& c = *ctx;
     Timer tm(ctx, prm->timing != 0);
-    const int F = fr->num_frames;
     int t_start = tm.mark();
     ensure(c.flags, sizeof(int));
     check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
-    check_poses(c, init_poses, F);
+    check_poses(c, init_poses, fr->num_frames);
     setup(ctx, fr, in, co, pairs, init_poses, prm);
-    ensure(c.poses_work, sizeof(double) * 16 * F);
-    ensure(c.trace, sizeof(double) * 8 * (prm->num_gn + 1));
-    double* poses = c.poses_work.as<double>();
-    check_hip(hipMemcpyAsync(poses, init_poses, sizeof(double) * 16 * F, hipMemcpyDeviceToDevice, c.stream),
-              "copy poses");
-    int t_setup = tm.mark();
-    tm.span(0, t_start, t_setup);
-    for (int k = 0; k < prm->num_gn; ++k) {
-      double wd = dense_weight(*prm, k);
-      int a = tm.mark();
-      launch_dense(c, *in, poses, *prm, wd, true);
-      int b = tm.mark();
-      launch_edge_blocks(c, poses, *prm, true);
-      int d = tm.mark();
-      if (c.shape.nfree > 0) launch_solve(c, prm->num_pcg, c.trace.as<double>() + 8 * k, nullptr, poses, nullptr, true);
-      else launch_energy(c, c.trace.as<double>() + 8 * k);
-      int f = tm.mark();
-      tm.span(1, a, b);
-      tm.span(2, b, d);
-      tm.span(4, d, f);
-    }
-    int g0 = tm.mark();
-    double wd = dense_weight(*prm, prm->num_gn > 0 ? prm->num_gn - 1 : 0);
-    launch_dense(c, *in, poses, *prm, wd, false);
-    launch_edge_blocks(c, poses, *prm, false);
-    launch_energy(c, c.energy.as<double>());
-    hipLaunchKernelGGL(k_copy_if_ok, dim3((16 * F + 255) / 256), dim3(256), 0, c.stream, poses, out_poses, 16 * F,
-                       c.flags.as<int>());
-    int g1 = tm.mark();
-    tm.span(5, g0, g1);
-    double e8[8];
-    int hf = 0;
-    std::vector<double> tr(8 * (size_t)(prm->num_gn + 1));
-    check_hip(hipMemcpyAsync(e8, c.energy.p, sizeof(e8), hipMemcpyDeviceToHost, c.stream), "copy energy");
-    if (out_trace && prm->num_gn > 0)
-      check_hip(hipMemcpyAsync(tr.data(), c.trace.p, sizeof(double) * 8 * prm->num_gn, hipMemcpyDeviceToHost,
-                               c.stream), "copy trace");
-    sync_and_flags(c, &hf);
-    raise_flags(hf);
-    for (int k = 0; k < 4; ++k) out_energy[k] = e8[k];
-    if (out_trace)
-      for (int k = 0; k < prm->num_gn; ++k)
-        for (int l = 0; l < 4; ++l) out_trace[4 * k + l] = tr[8 * k + l];
-    tm.finish(c.timings);
-    if (tm.on) {
-      float ms = 0.f;
-      check_hip(hipEventElapsedTime(&ms, ctx->pool[t_start], ctx->pool[g1]), "hipEventElapsedTime");
-      c.timings[6] = 1000.0 * ms;
-    }
+    run_gauss_newton(ctx, in, prm, init_poses, out_poses, out_energy, out_trace, tm, t_start);
+  });
+}
+
+bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
+                                const bf_pairs* pairs, int32_t num_problems, const int32_t* frame_offsets,
+                                const double* init_poses, const bf_params* prm, double* out_poses,
+                                double* out_energy, double* out_trace) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(co, pairs, init_poses);
+    if (num_problems < 1 || !frame_offsets) fail(BF_ERR_INVALID_ARG, "num_problems must be >= 1 with frame offsets");
+    if (!out_poses || !out_energy) fail(BF_ERR_INVALID_ARG, "null out_poses or out_energy");
+    if (prm->solve_kernel != 0 && prm->solve_kernel != 4)
+      fail(BF_ERR_UNSUPPORTED, "a batch is solved by the per-problem kernel (solve_kernel 0 or 4)");
+    Context& c = *ctx;
+    Timer tm(ctx, prm->timing != 0);
+    int t_start = tm.mark();
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
+    check_poses(c, init_poses, fr->num_frames);
+    setup(ctx, fr, in, co, pairs, init_poses, prm, frame_offsets, num_problems);
+    run_gauss_newton(ctx, in, prm, init_poses, out_poses, out_energy, out_trace, tm, t_start);
   });
 }
 

@@ -21,8 +21,10 @@
 //   mode 1: FP32 values, two-sum compensated FP32 lane sums;
 //   mode 2: FP64 values (c, q, r, pi(c), Jacobians) and FP64 lane sums -- on
 //           MI355X FP64 FMAs issue at the rate of unpacked FP32 FMAs.
-// Lane sums are combined across the workgroup in FP64 in a fixed order: the
-// record is deterministic.
+// Lane sums are combined across the workgroup in FP64 in a fixed order through
+// LDS: the record is deterministic for a given workgroup size.  The workgroup size (threads per pair
+// job, 64..512) is a launch parameter; when the caller leaves it open it is chosen
+// by timing the candidates once per image size, precision mode and job-count range.
 #include <type_traits>
 
 #include "internal.h"
@@ -89,8 +91,8 @@ __device__ __forceinline__ double uniform_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-template <int MODE, bool JAC>
-__global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, long long P,
+template <int MODE, bool JAC, int NT>
+__global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, long long P,
                                                const float4* __restrict__ nd, const float* __restrict__ grad,
                                                const float* __restrict__ kx, const float* __restrict__ ky,
                                                const double* __restrict__ kx64, const double* __restrict__ ky64,
@@ -253,29 +255,47 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
     }
   }
 
-  // Workgroup reduction in FP64, fixed order: 16 values at a time through LDS.
-  __shared__ double red[16][256];
-  __shared__ double part[16][16];
+  // Workgroup reduction in FP64, fixed order, 16 values at a time through LDS: with
+  // 512 threads the upper half first adds onto the lower half; then each value's
+  // RL lane sums are added in chunks of 16 lanes, and the chunk sums in order.
+  constexpr int RL = NT < 256 ? NT : 256;
+  constexpr int NCH = RL / 16;
+  __shared__ double red[16][RL];
+  __shared__ double part[16][NCH];
   __shared__ double out[32];
 #pragma unroll
   for (int base = 0; base < 32; base += 16) {
     if (base < NV) {
+      if constexpr (NT > RL) {
+        if (tid >= RL)
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (base + k < NV) red[k][tid] = A.value(base + k);
+          for (int k = 0; k < 16; ++k)
+            if (base + k < NV) red[k][tid - RL] = A.value(base + k);
+        __syncthreads();
+        if (tid < RL)
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            if (base + k < NV) red[k][tid] = A.value(base + k) + red[k][tid];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (base + k < NV) red[k][tid] = A.value(base + k);
+      }
       __syncthreads();
-      const int k = tid >> 4, ch = tid & 15;
-      if (base + k < NV) {
-        double sum = 0.0;
+      if (tid < RL) {
+        const int k = tid / NCH, ch = tid % NCH;
+        if (base + k < NV) {
+          double sum = 0.0;
 #pragma unroll
-        for (int l = 0; l < 16; ++l) sum += red[k][ch * 16 + l];
-        part[k][ch] = sum;
+          for (int l = 0; l < 16; ++l) sum += red[k][ch * 16 + l];
+          part[k][ch] = sum;
+        }
       }
       __syncthreads();
       if (tid < 16 && base + tid < NV) {
         double sum = 0.0;
 #pragma unroll
-        for (int l = 0; l < 16; ++l) sum += part[tid][l];
+        for (int l = 0; l < NCH; ++l) sum += part[tid][l];
         out[base + tid] = sum;
       }
       __syncthreads();
@@ -292,8 +312,8 @@ __global__ void __launch_bounds__(256) k_dense(const int* __restrict__ pairs, lo
   }
 }
 
-template <int MODE, bool JAC>
-void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd) {
+template <int MODE, bool JAC, int NT>
+void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd) {
   const long long P = c.shape.P;
   Intr32 i32{(float)in.fx, (float)in.fy, (float)in.cx, (float)in.cy, in.width, in.height};
   float tau_d2 = (float)(prm.tau_dist * prm.tau_dist);
@@ -301,10 +321,70 @@ void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const
   double swg = sqrt(wd * prm.w_geo);
   double swp = sqrt(wd * prm.w_photo);
   unsigned grid = (unsigned)(8 * ((P + 7) / 8));
-  hipLaunchKernelGGL((k_dense<MODE, JAC>), dim3(grid), dim3(256), 0, c.stream, c.pairs.as<int>(), P,
+  hipLaunchKernelGGL((k_dense<MODE, JAC, NT>), dim3(grid), dim3(NT), 0, c.stream, c.pairs.as<int>(), P,
                      c.nd.as<float4>(), c.grad.as<float>(), c.kx.as<float>(), c.ky.as<float>(), c.kx64.as<double>(),
                      c.ky64.as<double>(), poses, i32, in.fx, in.fy, in.cx, in.cy, tau_d2, tau_n, swg, swp,
                      c.records.as<double>());
+}
+
+template <int MODE, bool JAC>
+void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd, int nt) {
+  switch (nt) {
+    case 64: launch_nt<MODE, JAC, 64>(c, in, poses, prm, wd); break;
+    case 128: launch_nt<MODE, JAC, 128>(c, in, poses, prm, wd); break;
+    case 512: launch_nt<MODE, JAC, 512>(c, in, poses, prm, wd); break;
+    default: launch_nt<MODE, JAC, 256>(c, in, poses, prm, wd); break;
+  }
+}
+
+void launch_any(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
+                bool jac, int nt) {
+  const int mode = prm.accumulate;
+  if (jac) {
+    if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd, nt);
+    else if (mode == 1) launch_mode<1, true>(c, in, poses, prm, wd, nt);
+    else launch_mode<0, true>(c, in, poses, prm, wd, nt);
+  } else {
+    if (mode == 2) launch_mode<2, false>(c, in, poses, prm, wd, nt);
+    else launch_mode<0, false>(c, in, poses, prm, wd, nt);
+  }
+}
+
+// Threads per pair job for this launch: the caller's choice, or the fastest of the
+// candidates, timed once per (pixels per frame, precision mode, Jacobians, range of
+// job counts) in this context.  Timing runs the real launch (it only rewrites the
+// records) and synchronises the stream once.
+int choose_threads(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
+                   bool jac) {
+  if (prm.dense_threads != 0) return prm.dense_threads;
+  int bucket = 0;
+  while (bucket < 40 && (1LL << bucket) < c.shape.P) ++bucket;
+  const long long key = (((long long)in.width * in.height * 4 + prm.accumulate) * 2 + (jac ? 1 : 0)) * 64 + bucket;
+  auto it = c.dense_threads.find(key);
+  if (it != c.dense_threads.end()) return it->second;
+  static const int cand[4] = {64, 128, 256, 512};
+  hipEvent_t e0, e1;
+  check_hip(hipEventCreate(&e0), "hipEventCreate");
+  check_hip(hipEventCreate(&e1), "hipEventCreate");
+  int best = 256;
+  float best_ms = 1e30f;
+  for (int nt : cand) {
+    launch_any(c, in, poses, prm, wd, jac, nt);  // warm-up
+    check_hip(hipEventRecord(e0, c.stream), "hipEventRecord");
+    for (int r = 0; r < 3; ++r) launch_any(c, in, poses, prm, wd, jac, nt);
+    check_hip(hipEventRecord(e1, c.stream), "hipEventRecord");
+    check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = nt;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.dense_threads[key] = best;
+  return best;
 }
 
 }  // namespace
@@ -312,15 +392,8 @@ void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
                   bool with_jacobians) {
   if (c.shape.P == 0) return;
-  const int mode = prm.accumulate;
-  if (with_jacobians) {
-    if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd);
-    else if (mode == 1) launch_mode<1, true>(c, in, poses, prm, wd);
-    else launch_mode<0, true>(c, in, poses, prm, wd);
-  } else {
-    if (mode == 2) launch_mode<2, false>(c, in, poses, prm, wd);
-    else launch_mode<0, false>(c, in, poses, prm, wd);
-  }
+  const int nt = choose_threads(c, in, poses, prm, wd, with_jacobians);
+  launch_any(c, in, poses, prm, wd, with_jacobians, nt);
 }
 
 }  // namespace bf

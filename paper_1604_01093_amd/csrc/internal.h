@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,8 @@ struct Shape {
   int64_t S = 0;            // sparse pairs (distinct unordered frame pairs with correspondences)
   int64_t E = 0;            // edges (union)
   int64_t nfree = 0;        // free frames
+  int nseg = 1;             // independent problems (segments of consecutive frames)
+  int64_t max_seg_free = 0; // most free frames in one segment
 };
 
 struct Context {
@@ -58,8 +61,13 @@ struct Context {
       iptr, jptr, free_flag, var_of, frame_of_var, row_cnt, row_ptr, row_entries;
   // per-iteration data
   Buf records, eblocks, hij32, hij64, diag32, diag64, minv32, minv64, rhs, poses_work, pcg_vec, stats, trace;
+  // independent problems: frame offsets, segment of each frame, variable and edge ranges
+  Buf seg_start, seg_of, seg_var_ptr, seg_edge_ptr;
+  std::vector<int> seg_host;  // offsets currently on the device (seg_start, seg_of)
   // scratch
   Buf cub_tmp, counts, flags, host_pinned, energy, pcg_partials, pcg_barrier, pcg_tags;
+  // threads per dense pair job chosen by timing, per (pixels per frame, precision mode, Jacobians)
+  std::map<long long, int> dense_threads;
   int pcg_grid = 0;       // workgroups of the cooperative PCG kernel (0 = not yet chosen)
   int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative, 3 = replicated vectors
 
@@ -76,6 +84,9 @@ void ensure(Buf& b, size_t bytes);
 void launch_prepare(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_params& prm);
 
 // structure.hip
+// Segments: frames [offsets[b], offsets[b+1]) form independent problem b (host array
+// of nseg + 1 entries; nullptr = one problem of all frames).
+void set_segments(Context& c, int F, const int32_t* offsets, int nseg);
 void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_corrs* co,
                      const bf_pairs* pairs, const double* poses, const bf_params& prm);
 int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics& in, const double* poses,

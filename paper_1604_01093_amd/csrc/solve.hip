@@ -605,37 +605,48 @@ __device__ __forceinline__ void block_mv(const T* __restrict__ B, const T* pw, b
   }
 }
 
-// Assembly + block-Jacobi PCG + pose update for problems whose PCG vectors fit in
-// one workgroup's LDS: no grid barriers.  LDS holds x, r, z, p, Ap (and M^-1 when
-// it fits); the off-diagonal blocks are streamed from L2 every iteration, one
-// block per lane.  Same arithmetic and reduction orders as the cooperative kernel
-// where they matter for determinism (every sum has a fixed order).
-template <class T>
-__global__ void __launch_bounds__(1024) k_solve_single(
-    long long nfree, int F, long long E, int iters, const double* __restrict__ eb, const T* __restrict__ hij,
+// Assembly + block-Jacobi PCG + pose update, one workgroup of NT threads per
+// problem (segment b = blockIdx.x of consecutive frames, variables and edges), no
+// grid barriers.  LDS holds x, r, z, p, Ap of the problem (and M^-1 when it fits);
+// the off-diagonal blocks are streamed from L2 every iteration, one block per
+// lane.  Every sum has a fixed order, so a problem's result does not depend on the
+// other problems launched with it.  trace_slot, stats: 8 and 4 words per problem.
+template <class T, int NT>
+__global__ void __launch_bounds__(NT) k_solve_single(
+    const long long* __restrict__ seg_var_ptr, const long long* __restrict__ seg_edge_ptr,
+    const int* __restrict__ seg_start, int iters, const double* __restrict__ eb, const T* __restrict__ hij,
     const long long* __restrict__ iptr, const long long* __restrict__ jptr, const long long* __restrict__ ej_sorted,
     const long long* __restrict__ row_ptr, const int2* __restrict__ entries, const int* __restrict__ frame_of_var,
-    const int* __restrict__ var_of, T* __restrict__ diag_g, T* __restrict__ minv_g, int minv_in_lds,
-    double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
-    double* __restrict__ stats, int* __restrict__ flags) {
+    const int* __restrict__ var_of, T* __restrict__ diag_all, T* __restrict__ minv_all, int minv_in_lds,
+    double* __restrict__ trace_all, double* __restrict__ delta_out, double* __restrict__ poses, int update,
+    double* __restrict__ stats_all, int* __restrict__ flags) {
+  constexpr int NW = NT / 64;
   extern __shared__ double dyn[];
-  __shared__ double red1024[1024];
-  __shared__ double blk[16][48];
+  __shared__ double red1024[NT];
+  __shared__ double blk[NW][48];
   __shared__ int bad_sh;
+  const int seg = blockIdx.x;
+  const long long v0 = seg_var_ptr[seg];
+  const long long nfree = seg_var_ptr[seg + 1] - v0;
+  const long long E0 = seg_edge_ptr[seg], E = seg_edge_ptr[seg + 1];
+  const int F0 = seg_start[seg], F = seg_start[seg + 1];
+  double* trace_slot = trace_all ? trace_all + 8 * seg : nullptr;
+  double* stats = stats_all ? stats_all + 4 * seg : nullptr;
+  T* diag_g = diag_all + 36 * v0;
   const long long n = 6 * nfree;
   T* x = reinterpret_cast<T*>(dyn);
   T* r = x + n;
   T* z = r + n;
   T* p = z + n;
   T* Ap = p + n;
-  T* minv = minv_in_lds ? Ap + n : minv_g;
+  T* minv = minv_in_lds ? Ap + n : minv_all + 36 * v0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) bad_sh = 0;
   __syncthreads();
 
   // prologue: per-row assembly and preconditioner (one wavefront per row)
-  for (long long v = wave; v < nfree; v += 16) {
-    const int f = frame_of_var[v];
+  for (long long v = wave; v < nfree; v += NW) {
+    const int f = frame_of_var[v0 + v];
     if (lane < 42) {
       const int offI = lane < 36 ? kEHii + lane : kEGi + (lane - 36);
       const int offJ = lane < 36 ? kEHjj + lane : kEGj + (lane - 36);
@@ -674,15 +685,15 @@ __global__ void __launch_bounds__(1024) k_solve_single(
     }
     __builtin_amdgcn_wave_barrier();
   }
-  // energy over all edges
+  // energy over the problem's edges
   double en[6] = {0, 0, 0, 0, 0, 0};
   if (trace_slot)
-    for (long long e = tid; e < E; e += 1024)
+    for (long long e = E0 + tid; e < E; e += NT)
       for (int q = 0; q < 6; ++q) en[q] += eb[(size_t)e * kEdgeWords + kEEs + q];
   __syncthreads();
   if (trace_slot) {
     double tot[6];
-    for (int q = 0; q < 6; ++q) tot[q] = block_sum1024(en[q], red1024);
+    for (int q = 0; q < 6; ++q) tot[q] = block_sum<NT>(en[q], red1024);
     if (tid == 0) {
       trace_slot[0] = tot[0] + tot[1] + tot[2];
       for (int q = 0; q < 6; ++q) trace_slot[1 + q] = tot[q];
@@ -693,7 +704,7 @@ __global__ void __launch_bounds__(1024) k_solve_single(
   if (bad && tid == 0) atomicOr(flags, kFlagNotPD);
   // z = M^-1 r, p = z
   double part = 0.0;
-  for (long long o = tid; o < n; o += 1024) {
+  for (long long o = tid; o < n; o += NT) {
     const long long v = o / 6;
     const int a = (int)(o % 6);
     double s = 0.0;
@@ -702,15 +713,15 @@ __global__ void __launch_bounds__(1024) k_solve_single(
     p[o] = (T)s;
     part += (double)r[o] * (double)(T)s;
   }
-  double rz = block_sum1024(part, red1024);
+  double rz = block_sum<NT>(part, red1024);
   const double rz0 = rz;
   int done = 0;
   for (int it = 0; it < iters && !bad; ++it) {
     if (rz <= 1e-30) break;
     // Ap = H p: one wavefront per row, one block per lane
     part = 0.0;
-    for (long long v = wave; v < nfree; v += 16) {
-      const long long q0 = row_ptr[v], q1 = row_ptr[v + 1];
+    for (long long v = wave; v < nfree; v += NW) {
+      const long long q0 = row_ptr[v0 + v], q1 = row_ptr[v0 + v + 1];
       T acc[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
       for (long long qb = q0; qb < q1; qb += 64) {
         const long long q = qb + lane;
@@ -718,7 +729,7 @@ __global__ void __launch_bounds__(1024) k_solve_single(
           const int2 en2 = entries[q];
           T pw[6], y[6];
 #pragma unroll
-          for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)en2.x + b];
+          for (int b = 0; b < 6; ++b) pw[b] = p[6 * ((long long)en2.x - v0) + b];
           block_mv<T>(hij + (size_t)(en2.y >> 1) * 36, pw, en2.y & 1, y);
 #pragma unroll
           for (int b = 0; b < 6; ++b) acc[b] += y[b];
@@ -749,15 +760,15 @@ __global__ void __launch_bounds__(1024) k_solve_single(
         }
       }
     }
-    const double pAp = block_sum1024(part, red1024);
+    const double pAp = block_sum<NT>(part, red1024);
     const double alpha = rz / pAp;
-    for (long long o = tid; o < n; o += 1024) {
+    for (long long o = tid; o < n; o += NT) {
       x[o] = (T)((double)x[o] + alpha * (double)p[o]);
       r[o] = (T)((double)r[o] - alpha * (double)Ap[o]);
     }
     __syncthreads();
     part = 0.0;
-    for (long long o = tid; o < n; o += 1024) {
+    for (long long o = tid; o < n; o += NT) {
       const long long v = o / 6;
       const int a = (int)(o % 6);
       double s = 0.0;
@@ -765,21 +776,21 @@ __global__ void __launch_bounds__(1024) k_solve_single(
       z[o] = (T)s;
       part += (double)r[o] * (double)(T)s;
     }
-    const double rz_new = block_sum1024(part, red1024);
+    const double rz_new = block_sum<NT>(part, red1024);
     const double beta = rz_new / rz;
     rz = rz_new;
     ++done;
-    for (long long o = tid; o < n; o += 1024) p[o] = (T)((double)z[o] + beta * (double)p[o]);
+    for (long long o = tid; o < n; o += NT) p[o] = (T)((double)z[o] + beta * (double)p[o]);
     __syncthreads();
   }
   if (delta_out)
-    for (long long o = tid; o < 6LL * F; o += 1024) {
+    for (long long o = 6LL * F0 + tid; o < 6LL * F; o += NT) {
       const int w = var_of[o / 6];
-      delta_out[o] = (w >= 0 && !bad) ? (double)x[6LL * w + (o % 6)] : 0.0;
+      delta_out[o] = (w >= 0 && !bad) ? (double)x[6LL * (w - v0) + (o % 6)] : 0.0;
     }
   if (update && !bad)
-    for (long long v = tid; v < nfree; v += 1024) {
-      const int f = frame_of_var[v];
+    for (long long v = tid; v < nfree; v += NT) {
+      const int f = frame_of_var[v0 + v];
       double xi[6];
       for (int q = 0; q < 6; ++q) xi[q] = (double)x[6 * v + q];
       double dR[9], dt[3];
@@ -1097,14 +1108,19 @@ __global__ void k_zero_tags(unsigned long long* tags, long long n, unsigned* bar
   if (k == 0) *bar = 0u;
 }
 
-// Energy and counts over all edges, fixed order (one workgroup of 1024).
-__global__ void __launch_bounds__(1024) k_energy(const double* __restrict__ eb, long long E, double* __restrict__ dst) {
-  __shared__ double sh[1024];
+// Energy and counts over each problem's edges, fixed order (one workgroup of 256
+// per problem; 8 words per problem at dst).
+__global__ void __launch_bounds__(256) k_energy(const double* __restrict__ eb,
+                                                const long long* __restrict__ seg_edge_ptr,
+                                                double* __restrict__ dst_all) {
+  __shared__ double sh[256];
+  const long long E0 = seg_edge_ptr[blockIdx.x], E = seg_edge_ptr[blockIdx.x + 1];
+  double* dst = dst_all + 8 * blockIdx.x;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (long long e = threadIdx.x; e < E; e += 1024)
+  for (long long e = E0 + threadIdx.x; e < E; e += 256)
     for (int k = 0; k < 6; ++k) acc[k] += eb[(size_t)e * kEdgeWords + kEEs + k];
   double tot[6];
-  for (int k = 0; k < 6; ++k) tot[k] = block_sum(acc[k], sh);
+  for (int k = 0; k < 6; ++k) tot[k] = block_sum<256>(acc[k], sh);
   if (threadIdx.x == 0) {
     dst[0] = tot[0] + tot[1] + tot[2];
     dst[1] = tot[0];
@@ -1217,10 +1233,11 @@ void launch_solve_coop(Context& c, int iters, double* trace_slot, double* delta_
 // LDS budget of the single-workgroup solve (dynamic part).
 constexpr size_t kSingleLdsMax = 64 * 1024;
 
-template <class T>
+// One workgroup of NT threads per problem; LDS sized for the largest problem.
+template <class T, int NT>
 bool launch_solve_single(Context& c, int iters, double* trace_slot, double* delta_out, double* poses, double* stats,
                          bool update, T* diag, T* minv, T* hij) {
-  const long long nf = c.shape.nfree;
+  const long long nf = c.shape.max_seg_free;
   const size_t vec_bytes = sizeof(T) * 5 * 6 * (size_t)nf;
   const size_t minv_bytes = sizeof(T) * 36 * (size_t)nf;
   if (vec_bytes > kSingleLdsMax) return false;
@@ -1228,12 +1245,13 @@ bool launch_solve_single(Context& c, int iters, double* trace_slot, double* delt
   const size_t lds = vec_bytes + (minv_lds ? minv_bytes : 0);
   static bool attr_set[2] = {false, false};
   if (!attr_set[sizeof(T) == 8]) {
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve_single<T>),
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve_single<T, NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSingleLdsMax),
               "set LDS limit");
     attr_set[sizeof(T) == 8] = true;
   }
-  hipLaunchKernelGGL(k_solve_single<T>, dim3(1), dim3(1024), lds, c.stream, nf, c.shape.F, (long long)c.shape.E, iters,
+  hipLaunchKernelGGL((k_solve_single<T, NT>), dim3(c.shape.nseg), dim3(NT), lds, c.stream,
+                     c.seg_var_ptr.as<long long>(), c.seg_edge_ptr.as<long long>(), c.seg_start.as<int>(), iters,
                      c.eblocks.as<double>(), hij, c.iptr.as<long long>(), c.jptr.as<long long>(),
                      c.ej_sorted.as<long long>(), c.row_ptr.as<long long>(), c.row_entries.as<int2>(),
                      c.frame_of_var.as<int>(), c.var_of.as<int>(), diag, minv, minv_lds, trace_slot, delta_out, poses,
@@ -1295,9 +1313,27 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   return true;
 }
 
+// Largest problem (free frames) solved by the per-problem workgroup kernel when the
+// kernel is chosen automatically.
+constexpr long long kPerProblemMaxFree = 64;
+
 void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
                   bool update_poses) {
   if (c.shape.nfree == 0) return;
+  const bool many = c.shape.nseg > 1;
+  if (many && c.solve_mode != 0 && c.solve_mode != 4)
+    fail(BF_ERR_UNSUPPORTED, "several problems are solved by the per-problem kernel (solve_kernel 0 or 4)");
+  if (c.solve_mode == 4 || (c.solve_mode == 0 && (many || c.shape.max_seg_free <= kPerProblemMaxFree))) {
+    bool ok = c.pcg_storage == 1
+                  ? launch_solve_single<double, 256>(c, iters, trace_slot, delta_out, poses_inout, stats,
+                                                     update_poses, c.diag64.as<double>(), c.minv64.as<double>(),
+                                                     c.hij64.as<double>())
+                  : launch_solve_single<float, 256>(c, iters, trace_slot, delta_out, poses_inout, stats,
+                                                    update_poses, c.diag32.as<float>(), c.minv32.as<float>(),
+                                                    c.hij32.as<float>());
+    if (ok) return;
+    fail(BF_ERR_UNSUPPORTED, "a problem's PCG vectors do not fit in one workgroup's LDS");
+  }
   if (c.solve_mode == 0 || c.solve_mode == 3) {
     bool ok = c.pcg_storage == 1
                   ? launch_solve_rep<double>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
@@ -1309,10 +1345,12 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
   }
   if (c.solve_mode == 1) {
     bool ok = c.pcg_storage == 1
-                  ? launch_solve_single<double>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
-                                                c.diag64.as<double>(), c.minv64.as<double>(), c.hij64.as<double>())
-                  : launch_solve_single<float>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
-                                               c.diag32.as<float>(), c.minv32.as<float>(), c.hij32.as<float>());
+                  ? launch_solve_single<double, 1024>(c, iters, trace_slot, delta_out, poses_inout, stats,
+                                                      update_poses, c.diag64.as<double>(), c.minv64.as<double>(),
+                                                      c.hij64.as<double>())
+                  : launch_solve_single<float, 1024>(c, iters, trace_slot, delta_out, poses_inout, stats,
+                                                     update_poses, c.diag32.as<float>(), c.minv32.as<float>(),
+                                                     c.hij32.as<float>());
     if (ok) return;
     if (c.solve_mode == 1) fail(BF_ERR_UNSUPPORTED, "PCG vectors do not fit in one workgroup's LDS");
   }
@@ -1326,7 +1364,8 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
 }
 
 void launch_energy(Context& c, double* dst8) {
-  hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, c.stream, c.eblocks.as<double>(), (long long)c.shape.E, dst8);
+  hipLaunchKernelGGL(k_energy, dim3(c.shape.nseg), dim3(256), 0, c.stream, c.eblocks.as<double>(),
+                     c.seg_edge_ptr.as<long long>(), dst8);
 }
 
 void launch_export_dense(Context& c, double* H, double* g) {

@@ -12,11 +12,17 @@
 //   functions of these moments (evaluated per edge in solve.hip).
 // * Edges: the sorted union of dense pairs and sparse pairs; per-frame incidence
 //   (edges where the frame is the lower index are contiguous; the others come
-//   from a stable sort by the upper index); free frames (not frame 0, at least
-//   one edge) numbered in frame order.
+//   from a stable sort by the upper index); free frames (not the first frame of
+//   their problem, at least one edge) numbered in frame order.
+// * Several independent problems can share one structure: problem b owns the
+//   consecutive frames [offsets[b], offsets[b+1]); pairs and correspondences never
+//   cross problems, the first frame of each problem is its gauge (Sec. 4.3 fixes
+//   T_0), and the variables and edges of a problem are contiguous ranges.
 #include <hipcub/hipcub.hpp>
 
 #include <math.h>
+
+#include <algorithm>
 
 #include "internal.h"
 
@@ -57,12 +63,27 @@ __device__ __forceinline__ bool grid_point_hits(const double* R, const double* t
   return u >= 0.0 && u <= (double)(W - 1) && v >= 0.0 && v <= (double)(H - 1);
 }
 
-// One workgroup per source frame i; thread per candidate j > i.
+// Segment of every frame (binary search in the offsets).
+__global__ void k_seg_of(const int* __restrict__ seg_start, int nseg, int F, int* __restrict__ seg_of) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  int lo = 0, hi = nseg;  // seg_start[lo] <= f < seg_start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (seg_start[mid] <= f) lo = mid;
+    else hi = mid;
+  }
+  seg_of[f] = lo;
+}
+
+// One workgroup per source frame i; thread per candidate j > i of the same problem.
 __global__ void __launch_bounds__(256) k_pair_rows(const float* __restrict__ depth, const double* __restrict__ poses,
                                                    int F, int W, int H, double fx, double fy, double cx, double cy,
                                                    float dmin, float dmax, double cos_lim,
+                                                   const int* __restrict__ seg_of, const int* __restrict__ seg_start,
                                                    uint8_t* __restrict__ flags, long long* __restrict__ row_count) {
   const int i = blockIdx.x;
+  const int jend = seg_start[seg_of[i] + 1];
   __shared__ double gp[48][3];
   __shared__ int gvalid[48];
   __shared__ double Ti[16];
@@ -93,7 +114,7 @@ __global__ void __launch_bounds__(256) k_pair_rows(const float* __restrict__ dep
   if (tid < 16) Ti[tid] = poses[(size_t)i * 16 + tid];
   __syncthreads();
   int cnt = 0;
-  for (int j = i + 1 + tid; j < F; j += blockDim.x) {
+  for (int j = i + 1 + tid; j < jend; j += blockDim.x) {
     const double* Tj = poses + (size_t)j * 16;
     bool hit = false;
     double dot;
@@ -122,14 +143,17 @@ __global__ void __launch_bounds__(256) k_pair_rows(const float* __restrict__ dep
 // One workgroup per row: block-scan the row's flags and write the pairs in order.
 __global__ void __launch_bounds__(256) k_pair_compact(const uint8_t* __restrict__ flags,
                                                       const long long* __restrict__ row_off, int F,
-                                                      int* __restrict__ pairs, long long* __restrict__ keys) {
+                                                      const int* __restrict__ seg_of,
+                                                      const int* __restrict__ seg_start, int* __restrict__ pairs,
+                                                      long long* __restrict__ keys) {
   const int i = blockIdx.x;
   __shared__ int sc[256];
   const int tid = threadIdx.x;
+  const int jend = seg_start[seg_of[i] + 1];
   long long base = row_off[i];
-  for (int j0 = i + 1; j0 < F; j0 += 256) {
+  for (int j0 = i + 1; j0 < jend; j0 += 256) {
     int j = j0 + tid;
-    int f = (j < F) ? flags[(size_t)i * F + j] : 0;
+    int f = (j < jend) ? flags[(size_t)i * F + j] : 0;
     sc[tid] = f;
     __syncthreads();
     // inclusive Hillis-Steele scan
@@ -151,12 +175,13 @@ __global__ void __launch_bounds__(256) k_pair_compact(const uint8_t* __restrict_
 }
 
 // Caller-given pairs: range / order validation and keys.
-__global__ void k_pairs_check(const int* __restrict__ ij, long long P, int F, int* __restrict__ pairs_out,
-                              long long* __restrict__ keys, int* __restrict__ flags) {
+__global__ void k_pairs_check(const int* __restrict__ ij, long long P, int F, const int* __restrict__ seg_of,
+                              int* __restrict__ pairs_out, long long* __restrict__ keys, int* __restrict__ flags) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
   int i = ij[2 * k], j = ij[2 * k + 1];
   bool ok = i >= 0 && j < F && i < j;
+  ok = ok && seg_of[i] == seg_of[j];
   if (!ok) raise_flag(flags, kFlagBadIndex);
   if (k > 0) {
     int pi = ij[2 * k - 2], pj = ij[2 * k - 1];
@@ -170,12 +195,13 @@ __global__ void k_pairs_check(const int* __restrict__ ij, long long P, int F, in
 // ---------------------------------------------------------------- correspondences
 
 __global__ void k_corr_keys(const int* __restrict__ fi, const int* __restrict__ fj, const float* __restrict__ pi,
-                            const float* __restrict__ pj, long long M, int F, long long* __restrict__ key,
-                            long long* __restrict__ idx, int* __restrict__ flags) {
+                            const float* __restrict__ pj, long long M, int F, const int* __restrict__ seg_of,
+                            long long* __restrict__ key, long long* __restrict__ idx, int* __restrict__ flags) {
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= M) return;
   int a = fi[c], b = fj[c];
   bool ok = a >= 0 && a < F && b >= 0 && b < F && a != b;
+  ok = ok && seg_of[a] == seg_of[b];
   if (!ok) raise_flag(flags, kFlagBadIndex);
   for (int k = 0; k < 3; ++k)
     if (!isfinite(pi[3 * c + k]) || !isfinite(pj[3 * c + k])) raise_flag(flags, kFlagNonFinite);
@@ -327,7 +353,8 @@ __global__ void k_ej_keys(const int* __restrict__ eij, long long cap, const long
 }
 
 __global__ void k_incidence(const long long* __restrict__ ekeys, const int* __restrict__ kj_sorted,
-                            const long long* __restrict__ counts, int F, long long* __restrict__ iptr,
+                            const long long* __restrict__ counts, int F, const int* __restrict__ seg_of,
+                            const int* __restrict__ seg_start, long long* __restrict__ iptr,
                             long long* __restrict__ jptr, long long* __restrict__ free_flag) {
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f > F) return;
@@ -341,7 +368,20 @@ __global__ void k_incidence(const long long* __restrict__ ekeys, const int* __re
   long long ihi = lower_bound_ll(ekeys, E, (long long)(f + 1) * F);
   long long jhi = lower_bound_i(kj_sorted, E, f + 1);
   long long deg = (ihi - iptr[f]) + (jhi - jptr[f]);
-  free_flag[f] = (f != 0 && deg > 0) ? 1 : 0;
+  free_flag[f] = (f != seg_start[seg_of[f]] && deg > 0) ? 1 : 0;
+}
+
+// Per problem: first variable (exclusive scan of the free flags at its first frame)
+// and first edge (edges are sorted by i*F + j, and a problem's frames are consecutive).
+__global__ void k_seg_ptrs(const int* __restrict__ seg_start, int nseg, const long long* __restrict__ free_scan,
+                           const long long* __restrict__ ekeys, const long long* __restrict__ counts, int F,
+                           long long* __restrict__ seg_var_ptr, long long* __restrict__ seg_edge_ptr) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nseg) return;
+  const long long E = counts[2];
+  const int f = seg_start[b];
+  seg_var_ptr[b] = free_scan[f];
+  seg_edge_ptr[b] = b == nseg ? E : lower_bound_ll(ekeys, E, (long long)f * F);
 }
 
 __global__ void k_free_write(const long long* __restrict__ free_flag, const long long* __restrict__ scan, int F,
@@ -424,7 +464,8 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
   double cos_lim = cos(prm.max_angle_deg * (M_PI / 180.0));
   hipLaunchKernelGGL(k_pair_rows, dim3(F), dim3(256), 0, c.stream, fr.depth, poses, F, in.width, in.height, in.fx,
                      in.fy, in.cx, in.cy, (float)prm.depth_min, (float)prm.depth_max, cos_lim,
-                     c.pair_flags.as<uint8_t>(), c.row_count.as<long long>());
+                     c.seg_of.as<int>(), c.seg_start.as<int>(), c.pair_flags.as<uint8_t>(),
+                     c.row_count.as<long long>());
   check_hip(hipMemsetAsync(c.row_count.as<long long>() + F, 0, sizeof(long long), c.stream), "memset");
   long long* rc = c.row_count.as<long long>();
   long long* ro = c.row_off.as<long long>();
@@ -437,14 +478,44 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
   ensure(c.pairs, sizeof(int) * 2 * (P + 1));
   ensure(c.pair_keys, sizeof(long long) * (P + 1));
   hipLaunchKernelGGL(k_pair_compact, dim3(F), dim3(256), 0, c.stream, c.pair_flags.as<uint8_t>(), ro, F,
-                     c.pairs.as<int>(), c.pair_keys.as<long long>());
+                     c.seg_of.as<int>(), c.seg_start.as<int>(), c.pairs.as<int>(), c.pair_keys.as<long long>());
   return P;
+}
+
+void set_segments(Context& c, int F, const int32_t* offsets, int nseg) {
+  std::vector<int> h;
+  if (offsets) {
+    if (nseg < 1) fail(BF_ERR_INVALID_ARG, "num_problems must be >= 1");
+    if (offsets[0] != 0 || offsets[nseg] != F) fail(BF_ERR_INVALID_ARG, "frame offsets must run from 0 to num_frames");
+    for (int b = 0; b < nseg; ++b)
+      if (offsets[b + 1] <= offsets[b]) fail(BF_ERR_INVALID_ARG, "frame offsets must be strictly increasing");
+    h.assign(offsets, offsets + nseg + 1);
+  } else {
+    nseg = 1;
+    h = {0, F};
+  }
+  if (h == c.seg_host && c.seg_of.cap >= sizeof(int) * F) {  // already on the device
+    c.shape.nseg = nseg;
+    return;
+  }
+  c.seg_host.clear();
+  ensure(c.seg_start, sizeof(int) * (nseg + 1));
+  ensure(c.seg_of, sizeof(int) * F);
+  check_hip(hipMemcpyAsync(c.seg_start.p, h.data(), sizeof(int) * (nseg + 1), hipMemcpyHostToDevice, c.stream),
+            "copy frame offsets");
+  hipLaunchKernelGGL(k_seg_of, dim3(blocks_for(F)), dim3(256), 0, c.stream, c.seg_start.as<int>(), nseg, F,
+                     c.seg_of.as<int>());
+  // the host vector must outlive the copy
+  check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  c.seg_host = h;
+  c.shape.nseg = nseg;
 }
 
 void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_corrs* co,
                      const bf_pairs* pairs, const double* poses, const bf_params& prm) {
   const int F = fr.num_frames;
   Shape sh;
+  sh.nseg = c.shape.nseg;
   sh.F = F;
   sh.W = in.width;
   sh.H = in.height;
@@ -473,7 +544,7 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
     ensure(c.pair_keys, sizeof(long long) * (sh.P + 1));
     if (sh.P > 0)
       hipLaunchKernelGGL(k_pairs_check, dim3(blocks_for(sh.P)), dim3(256), 0, c.stream, pairs->ij, (long long)sh.P, F,
-                         c.pairs.as<int>(), c.pair_keys.as<long long>(), c.flags.as<int>());
+                         c.seg_of.as<int>(), c.pairs.as<int>(), c.pair_keys.as<long long>(), c.flags.as<int>());
   } else {
     sh.P = launch_pair_search(c, fr, in, poses, prm);
   }
@@ -492,7 +563,8 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
   ensure(c.sparse_ptr, sizeof(long long) * (M + 2));
   if (M > 0) {
     hipLaunchKernelGGL(k_corr_keys, dim3(blocks_for(M)), dim3(256), 0, c.stream, co->frame_i, co->frame_j, co->p_i,
-                       co->p_j, M, F, c.corr_key.as<long long>(), c.corr_idx.as<long long>(), c.flags.as<int>());
+                       co->p_j, M, F, c.seg_of.as<int>(), c.corr_key.as<long long>(), c.corr_idx.as<long long>(),
+                       c.flags.as<int>());
     int endbit = bits_for((uint64_t)F * (uint64_t)F);
     long long* k_in = c.corr_key.as<long long>();
     long long* k_out = c.corr_key_sorted.as<long long>();
@@ -567,18 +639,31 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
     });
   }
   hipLaunchKernelGGL(k_incidence, dim3(blocks_for(F + 1)), dim3(256), 0, c.stream, c.edge_keys.as<long long>(),
-                     c.ej_key_sorted.as<int>(), c.counts.as<long long>(), F, c.iptr.as<long long>(),
-                     c.jptr.as<long long>(), c.free_flag.as<long long>());
+                     c.ej_key_sorted.as<int>(), c.counts.as<long long>(), F, c.seg_of.as<int>(),
+                     c.seg_start.as<int>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
+                     c.free_flag.as<long long>());
   long long* ff = c.free_flag.as<long long>();
   ensure(c.row_off, sizeof(long long) * (F + 1));
   long long* fs = c.row_off.as<long long>();
   cub_call(c, [&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, ff, fs, F + 1, c.stream); });
   hipLaunchKernelGGL(k_free_write, dim3(blocks_for(F + 1)), dim3(256), 0, c.stream, ff, fs, F, c.var_of.as<int>(),
                      c.frame_of_var.as<int>(), c.counts.as<long long>());
+  const int nseg = c.shape.nseg;
+  ensure(c.seg_var_ptr, sizeof(long long) * (nseg + 1));
+  ensure(c.seg_edge_ptr, sizeof(long long) * (nseg + 1));
+  hipLaunchKernelGGL(k_seg_ptrs, dim3(blocks_for(nseg + 1)), dim3(256), 0, c.stream, c.seg_start.as<int>(), nseg, fs,
+                     c.edge_keys.as<long long>(), c.counts.as<long long>(), F, c.seg_var_ptr.as<long long>(),
+                     c.seg_edge_ptr.as<long long>());
+  std::vector<long long> svp(nseg + 1);
+  check_hip(hipMemcpyAsync(svp.data(), c.seg_var_ptr.p, sizeof(long long) * (nseg + 1), hipMemcpyDeviceToHost,
+                           c.stream), "copy segment variables");
   read_counts(c, hc, &hf);
   raise_device_flags(hf);
   sh.E = hc[2];
   sh.nfree = hc[3];
+  sh.nseg = nseg;
+  sh.max_seg_free = 0;
+  for (int b = 0; b < nseg; ++b) sh.max_seg_free = std::max<int64_t>(sh.max_seg_free, svp[b + 1] - svp[b]);
 
   // PCG rows: (partner variable, edge) lists of every free frame
   ensure(c.row_cnt, sizeof(long long) * (sh.nfree + 1));

@@ -304,10 +304,33 @@ def make_problem(config, seed_offset=0):
     raise ValueError(f"unknown config {config!r}")
 
 
-def make_batch_chunks(count=256, config=2, min_frames=4, max_frames=11):
-    """`count` independent chunk problems at 160x120 with frame counts U{min..max}."""
+def _batch_member(args):
+    k, n, config = args
+    return make_chunk(num_frames=int(n), W=160, H=120, fx=144.0, fy=144.0, cx=80.0, cy=60.0,
+                      seed_offset=1000 * k, config=config, name=f"batch_chunk{k}")
+
+
+def batch_sizes(count=256, config=2, min_frames=4, max_frames=11):
+    """Frame counts U{min..max} of the members of a chunk batch."""
     rng = np.random.Generator(np.random.PCG64(500 + config))
-    sizes = rng.integers(min_frames, max_frames + 1, size=count)
-    return [make_chunk(num_frames=int(n), W=160, H=120, fx=144.0, fy=144.0, cx=80.0, cy=60.0,
-                       seed_offset=1000 * k, config=config, name=f"batch_chunk{k}")
-            for k, n in enumerate(sizes)]
+    return rng.integers(min_frames, max_frames + 1, size=count)
+
+
+def make_batch_chunks(count=256, config=2, min_frames=4, max_frames=11, workers=None):
+    """`count` independent chunk problems at 160x120 with frame counts U{min..max}.
+    Members depend only on their index, so they are generated in parallel
+    (`workers` processes, default min(16, cpu count); 1 = in this process)."""
+    import os
+    sizes = batch_sizes(count, config, min_frames, max_frames)
+    jobs = [(k, int(n), config) for k, n in enumerate(sizes)]
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    import sys
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        workers = 1  # never fork a process that holds a GPU context
+    if workers <= 1 or count < 8:
+        return [_batch_member(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_batch_member, jobs, chunksize=max(1, count // (4 * workers)))

@@ -85,8 +85,102 @@ class Scene:
         val = 0.5 + 0.55 * (0.75 * n1 + 0.25 * n2)
         return np.clip(val, 0.0, 1.0)
 
+    def _bounds(self):
+        """Per primitive: axis-aligned box (lo [3], hi [3]) and texture offset, quads first."""
+        if getattr(self, "_bounds_cache", None) is None:
+            lo, hi, off = [], [], []
+            for q in self.quads:
+                ax = int(q[0])
+                oa = [k for k in range(3) if k != ax]
+                a = np.zeros(3)
+                b = np.zeros(3)
+                a[ax] = b[ax] = q[1]
+                a[oa[0]], b[oa[0]] = q[2], q[3]
+                a[oa[1]], b[oa[1]] = q[4], q[5]
+                lo.append(a)
+                hi.append(b)
+                off.append(q[6])
+            for c, r, o in zip(self.sphere_c, self.sphere_r, self.sphere_tex):
+                lo.append(np.asarray(c, np.float64) - r)
+                hi.append(np.asarray(c, np.float64) + r)
+                off.append(o)
+            self._bounds_cache = (np.array(lo).reshape(-1, 3), np.array(hi).reshape(-1, 3), np.array(off))
+        return self._bounds_cache
+
     def raycast(self, origin, dirs, tmin=1e-6):
-        """Nearest hit along rays origin + t*dirs.
+        """Nearest hit along rays origin + t*dirs from one origin [3] (dirs [N,3], not
+        necessarily unit).  Returns (t [N] with inf for a miss, intensity [N], hit
+        points [N,3]).
+
+        Primitives are visited nearest first and each is tested only on the rays
+        whose current hit is farther than the primitive's bounding box (with a
+        relative margin far above rounding), so skipped tests could never have won.
+        Among hits at exactly the same t the primitive listed first wins, so the
+        result is bit for bit that of testing every primitive in list order
+        (raycast_all)."""
+        dirs = np.asarray(dirs, np.float64)
+        n = dirs.shape[0]
+        origin = np.asarray(origin, np.float64)
+        if origin.ndim != 1 or n == 0:
+            return self.raycast_all(origin, dirs, tmin)
+        lo, hi, offs = self._bounds()
+        nq = len(self.quads)
+        gap = np.maximum(np.maximum(lo - origin, origin - hi), 0.0)
+        dmin = np.sqrt((gap * gap).sum(axis=1))
+        sc = np.asarray(self.sphere_c, np.float64).reshape(-1, 3)
+        if len(sc):
+            ds = np.sqrt(((sc - origin) ** 2).sum(axis=1)) - np.asarray(self.sphere_r, np.float64)
+            dmin[nq:] = np.maximum(np.maximum(ds, 0.0), dmin[nq:])
+        dlen = np.sqrt((dirs * dirs).sum(axis=1))
+        o = np.broadcast_to(origin, (n, 3))
+        best_t = np.full(n, np.inf)
+        best_p = np.full(n, len(offs), np.int64)
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+            reach = np.inf
+            for i, p in enumerate(np.argsort(dmin, kind="stable")):
+                if i % 16 == 0:
+                    reach = float((best_t * dlen).max()) * (1.0 + 1e-9)
+                if dmin[p] > reach:
+                    break  # every later primitive is farther than every current hit
+                act = np.nonzero(best_t * dlen * (1.0 + 1e-9) >= dmin[p])[0]
+                if act.size == 0:
+                    continue
+                d = dirs[act]
+                oo = o[act]
+                bt = best_t[act]
+                if p < nq:
+                    q = self.quads[p]
+                    ax = int(q[0])
+                    oa = [k for k in range(3) if k != ax]
+                    t = (q[1] - oo[:, ax]) / d[:, ax]
+                    pa = oo[:, oa[0]] + t * d[:, oa[0]]
+                    pb = oo[:, oa[1]] + t * d[:, oa[1]]
+                    geo = (t > tmin) & (pa >= q[2]) & (pa <= q[3]) & (pb >= q[4]) & (pb <= q[5])
+                else:
+                    k = p - nq
+                    c, r = self.sphere_c[k], self.sphere_r[k]
+                    a = np.einsum("ij,ij->i", d, d)
+                    oc = oo - c
+                    b = 2.0 * np.einsum("ij,ij->i", d, oc)
+                    cc = np.einsum("ij,ij->i", oc, oc) - r * r
+                    disc = b * b - 4.0 * a * cc
+                    sq = np.sqrt(np.maximum(disc, 0.0))
+                    t1 = (-b - sq) / (2.0 * a)
+                    t2 = (-b + sq) / (2.0 * a)
+                    t = np.where(t1 > tmin, t1, t2)
+                    geo = (disc >= 0) & (t > tmin)
+                ok = geo & ((t < bt) | ((t == bt) & (p < best_p[act])))
+                sel = act[ok]
+                best_t[sel] = t[ok]
+                best_p[sel] = p
+        best_off = np.where(best_p < len(offs), offs[np.minimum(best_p, len(offs) - 1)], 0.0)
+        hit = o + best_t[:, None] * dirs
+        hit = np.where(np.isfinite(best_t)[:, None], hit, 0.0)
+        inten = np.where(np.isfinite(best_t), self.texture(hit, best_off), 0.0)
+        return best_t, inten, hit
+
+    def raycast_all(self, origin, dirs, tmin=1e-6):
+        """Nearest hit along rays origin + t*dirs, testing every primitive on every ray.
 
         origin: [3] or [N,3]; dirs: [N,3] (not necessarily unit).
         Returns (t [N] with inf for a miss, intensity [N], hit points [N,3]).
