@@ -13,6 +13,14 @@ bf_gauss_newton_batch call per step, against the same 256 problems solved one
 after another by bf_gauss_newton; problems per second for both, and the largest
 pose difference between the two forms.
 
+And (field "serving") the serving workload: a Poisson stream of requests, 80 %
+chunk solves (160x120, 4-11 frames) and 20 % global keyframe solves (80x60, 50-800
+keyframes), served by the two-lane continuous-batching server
+(paper_1604_01093_amd.serve) at 0.5x and 0.8x of its measured peak rate, against a
+one-at-a-time loop of plain solves on the same arrival stream; p50/p99 latency and
+solves per second, and whether every served result equals the result of the same
+request solved alone.
+
 Prints one JSON line.
 """
 import argparse
@@ -112,6 +120,8 @@ def main():
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--solve-kernel", type=int, default=0)
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain copy of this size first (for scaling HBM counters)")
@@ -138,6 +148,13 @@ def main():
         chunks = make_batch_chunks()
         log(f"generated 256 chunk problems in {time.perf_counter() - t0:.1f} s "
             f"({sum(c.num_frames for c in chunks)} frames)")
+    pool = None
+    if not args.skip_serving:
+        from synth.problems import make_serving_pool
+        t0 = time.perf_counter()
+        pool = make_serving_pool()
+        log(f"generated the serving request pool in {time.perf_counter() - t0:.1f} s: {len(pool[0])} chunks, "
+            f"windows of {[w.num_frames for w in pool[1]]} keyframes")
     if args.copy_calibration_mib > 0:
         copy_calibration(args.copy_calibration_mib)
 
@@ -217,6 +234,8 @@ def main():
     }
     if chunks is not None:
         line["batched"] = batched(bf, ctx, chunks, args.batched_steps)
+    if pool is not None:
+        line["serving"] = serving(bf, ctx, pool, args.serving_requests)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(prob, prob.n_gn, prob.n_pcg)
@@ -270,6 +289,83 @@ def batched(bf, ctx, chunks, steps):
             "max_pose_diff_vs_sequential": {"rad": worst_r, "m": worst_t},
             "config": {"workload": f"{nb} chunk problems, 4-11 frames (sum {offs[-1]}), 160x120, "
                                    f"{n_gn} GN x {n_pcg} PCG, dense workgroup size timed per shape"}}
+
+
+
+def serving(bf, ctx, pool, n_requests):
+    """Poisson request stream through the two-lane server vs one plain solve at a time."""
+    import numpy as np
+    import torch
+
+    from paper_1604_01093_amd import serve
+
+    chunks, wins = pool
+    p_chunk = bf.bf_params_default(num_gn=5, num_pcg=10, dense_threads=256)
+    p_glob = bf.bf_params_default(num_gn=8, num_pcg=20, dense_threads=256)
+    items = []
+    for pr in chunks:
+        items.append(("chunk", pr, p_chunk))
+    for pr in wins:
+        items.append(("global", pr, p_glob))
+    dev = [(bf.DeviceProblem.from_numpy(pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p,
+                                        pr.corr_q), torch.as_tensor(pr.init_poses).cuda()) for _, pr, _ in items]
+    rng = np.random.Generator(np.random.PCG64(7))
+    is_global = rng.uniform(size=n_requests) < 0.2
+    pick = np.where(is_global, len(chunks) + rng.integers(0, len(wins), n_requests),
+                    rng.integers(0, len(chunks), n_requests))
+    gaps = rng.exponential(size=n_requests)  # unit-rate Poisson process, scaled per run
+
+    def make_reqs():
+        return [serve.Request(dev[k][0], dev[k][1], items[k][2], tag=int(k)) for k in pick]
+
+    # reference: each pool item solved alone (also warms up every shape)
+    torch.cuda.synchronize()
+    alone = []
+    for (d, init), (_, pr, prm) in zip(dev, items):
+        alone.append(bf.bf_gauss_newton(ctx, d, init, prm)["poses"])
+    t0 = time.perf_counter()
+    for k in pick:
+        bf.bf_gauss_newton(ctx, dev[k][0], dev[k][1], items[k][2])
+    torch.cuda.synchronize()
+    t_plain_all = time.perf_counter() - t0
+
+    server = serve.Server()
+    try:
+        # warm-up of the server's own contexts
+        serve.run_stream(server, make_reqs()[:32], np.zeros(32))
+        reqs = make_reqs()
+        wall = serve.run_stream(server, reqs, np.zeros(n_requests))
+        peak = n_requests / wall
+        log(f"serving: peak {peak:.1f} solves/s (all requests at t=0); plain solves back to back "
+            f"{n_requests / t_plain_all:.1f} solves/s")
+        out = {"metric": "p99 latency", "unit": "ms", "requests": n_requests,
+               "mix": "80% chunk (160x120, 4-11 frames, 5x10), 20% global window "
+                      f"({min(w.num_frames for w in wins)}-{max(w.num_frames for w in wins)} keyframes, 80x60, 8x20)",
+               "peak_solves_per_s": round(peak, 2), "plain_back_to_back_solves_per_s": round(n_requests / t_plain_all, 2),
+               "rates": []}
+        same = True
+        for frac in (0.5, 0.8):
+            rate = frac * peak
+            arr = np.cumsum(gaps) / rate
+            reqs = make_reqs()
+            wall = serve.run_stream(server, reqs, arr)
+            st = serve.latency_stats(reqs, wall)
+            for r in reqs:
+                same = same and r.error is None and torch.equal(r.poses, alone[r.tag])
+            batches = [n for n, _ in server.batches[-200:]]
+            plain = make_reqs()
+            wall_p = serve.run_one_at_a_time(plain, arr, ctx)
+            stp = serve.latency_stats(plain, wall_p)
+            log(f"serving at {frac:.1f} x peak ({rate:.1f}/s): server p50 {st['p50_ms']} ms p99 {st['p99_ms']} ms, "
+                f"{st['solves_per_s']} solves/s; one at a time p50 {stp['p50_ms']} ms p99 {stp['p99_ms']} ms")
+            out["rates"].append({"fraction_of_peak": frac, "arrival_rate_per_s": round(rate, 2), "server": st,
+                                 "one_at_a_time": stp,
+                                 "mean_batch": round(float(np.mean(batches)), 2) if batches else None})
+        out["value"] = out["rates"][-1]["server"]["p99_ms"]
+        out["results_equal_alone"] = bool(same)
+        return out
+    finally:
+        server.close()
 
 
 if __name__ == "__main__":

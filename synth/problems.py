@@ -68,18 +68,63 @@ class Problem:
         return (self.fx, self.fy, self.cx, self.cy, self.width, self.height)
 
 
+_SHARED = {}
+
+
+def _workers(n_items, workers=None):
+    """Worker processes for n_items independent tasks: min(16, cpu count), and 1
+    (no fork) when torch already holds a GPU context in this process."""
+    import os
+    import sys
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        workers = 1
+    import multiprocessing as mp
+    if mp.current_process().daemon:
+        workers = 1  # already inside a pool worker
+    return workers if n_items >= 2 * workers else 1
+
+
+def _pmap(fn, items, shared, workers=None):
+    """map(fn, items) over forked worker processes; `shared` (read-only, e.g. the
+    scene) is inherited by the workers through a module global instead of being
+    pickled per task.  Results are returned in item order."""
+    items = list(items)
+    _SHARED.clear()
+    _SHARED.update(shared)
+    w = _workers(len(items), workers)
+    try:
+        if w <= 1:
+            return [fn(x) for x in items]
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(w) as pool:
+            return pool.map(fn, items, chunksize=max(1, len(items) // (8 * w)))
+    finally:
+        _SHARED.clear()
+
+
 def _pixel_rays(W, H, fx, fy, cx, cy):
     ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
     return np.stack([(xs - cx) / fx, (ys - cy) / fy, np.ones_like(xs)], axis=-1).reshape(-1, 3)
 
 
+def _render_one(T):
+    scene, rays = _SHARED["scene"], _SHARED["rays"]
+    t, val, _ = scene.raycast(T[:3, 3], rays @ T[:3, :3].T)
+    return t, val
+
+
 def render_frames(scene, abs_poses, W, H, fx, fy, cx, cy, rng_noise, noise=True, dropout=0.01):
+    """Noise-free renders in parallel (deterministic), then depth noise and dropout
+    drawn frame by frame in order from rng_noise."""
     rays = _pixel_rays(W, H, fx, fy, cx, cy)
     F = len(abs_poses)
     depth = np.zeros((F, H, W), np.float32)
     inten = np.zeros((F, H, W), np.float32)
-    for f, T in enumerate(abs_poses):
-        t, val, _ = scene.raycast(T[:3, 3], rays @ T[:3, :3].T)
+    clean = _pmap(_render_one, list(abs_poses), {"scene": scene, "rays": rays})
+    for f, (t, val) in enumerate(clean):
         z = np.where(np.isfinite(t), t, 0.0)
         if noise:
             z = np.where(z > 0, z + rng_noise.normal(size=z.shape) * 0.0012 * z * z, 0.0)
@@ -179,49 +224,76 @@ def pair_correspondences(rng, scene, Ti, Tj, sensor, k, outlier_rate, noise=True
     return p, q, outl
 
 
+def _covisible_row(i):
+    sh = _SHARED
+    scene, abs_poses, sensor, samp = sh["scene"], sh["poses"], sh["sensor"], sh["samp"]
+    max_dist, cos_max, need = sh["max_dist"], sh["cos_max"], sh["need"]
+    F = len(abs_poses)
+    pos = abs_poses[:, :3, 3]
+    fwd = abs_poses[:, :3, 2]
+    pairs = []
+    js = np.arange(i + 1, F)
+    js = js[(np.linalg.norm(pos[js] - pos[i], axis=1) <= max_dist) & (fwd[js] @ fwd[i] >= cos_max)]
+    if len(js) == 0:
+        return pairs
+    X = samp[i]
+    Xj = np.einsum("nk,jkl->jnl", X, abs_poses[js, :3, :3]) - np.einsum("jk,jkl->jl", pos[js], abs_poses[js, :3, :3])[:, None, :]
+    z = Xj[..., 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = sensor.fx * Xj[..., 0] / z + sensor.cx
+        v = sensor.fy * Xj[..., 1] / z + sensor.cy
+    ok = (z > 0.1) & sensor.in_image(u, v)
+    for jj in np.nonzero(ok.sum(axis=1) >= need)[0]:
+        vis = _visible_from(scene, abs_poses[js[jj]], X[ok[jj]])
+        if vis.sum() >= need:
+            pairs.append((i, int(js[jj])))
+    return pairs
+
+
 def covisible_pairs(rng, scene, abs_poses, sensor, max_dist=8.0, max_angle_deg=75.0,
                     samples=48, min_frac=0.25):
     """Frame pairs i<j that see a common part of the scene (ground truth): at least
-    `min_frac` of `samples` surface points seen by i are in j's view and unoccluded."""
+    `min_frac` of `samples` surface points seen by i are in j's view and unoccluded.
+    The samples are drawn in frame order; the rows are tested in parallel."""
     F = len(abs_poses)
     samp = [_surface_samples(scene, T, sensor, samples, rng)[2] for T in abs_poses]
-    pos = abs_poses[:, :3, 3]
-    fwd = abs_poses[:, :3, 2]
-    cos_max = np.cos(np.deg2rad(max_angle_deg))
-    need = min_frac * samples
-    pairs = []
-    for i in range(F - 1):
-        js = np.arange(i + 1, F)
-        js = js[(np.linalg.norm(pos[js] - pos[i], axis=1) <= max_dist) & (fwd[js] @ fwd[i] >= cos_max)]
-        if len(js) == 0:
-            continue
-        X = samp[i]
-        Xj = np.einsum("nk,jkl->jnl", X, abs_poses[js, :3, :3]) - np.einsum("jk,jkl->jl", pos[js], abs_poses[js, :3, :3])[:, None, :]
-        z = Xj[..., 2]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            u = sensor.fx * Xj[..., 0] / z + sensor.cx
-            v = sensor.fy * Xj[..., 1] / z + sensor.cy
-        ok = (z > 0.1) & sensor.in_image(u, v)
-        for jj in np.nonzero(ok.sum(axis=1) >= need)[0]:
-            vis = _visible_from(scene, abs_poses[js[jj]], X[ok[jj]])
-            if vis.sum() >= need:
-                pairs.append((i, int(js[jj])))
-    return pairs
+    shared = {"scene": scene, "poses": abs_poses, "sensor": sensor, "samp": samp, "max_dist": max_dist,
+              "cos_max": np.cos(np.deg2rad(max_angle_deg)), "need": min_frac * samples}
+    rows = _pmap(_covisible_row, range(F - 1), shared)
+    return [p for row in rows for p in row]
+
+
+def _pair_job(args):
+    n, i, j, k = args
+    sh = _SHARED
+    rng = np.random.Generator(np.random.PCG64([sh["seed"], n]))
+    return pair_correspondences(rng, sh["scene"], sh["poses"][i], sh["poses"][j], sh["sensor"], k,
+                                sh["outlier_rate"], noise=sh["noise"])
 
 
 def _assemble(name, scene, abs_poses, W, H, fx, fy, cx, cy, seeds, sparse_pairs, k_of_pair,
               outlier_rate, init_mode, n_gn, n_pcg, noise=True, init_rot=2.0, init_trans=0.03,
-              drift_rot=0.5, drift_trans=0.01):
+              drift_rot=0.5, drift_trans=0.01, per_pair_streams=False):
+    """per_pair_streams: pair n draws its correspondences from its own stream
+    PCG64([corr seed, n]) (so pairs run in parallel); otherwise one stream in pair order."""
     rng_noise = np.random.Generator(np.random.PCG64(seeds["noise"]))
     rng_corr = np.random.Generator(np.random.PCG64(seeds["corr"]))
     depth, inten = render_frames(scene, abs_poses, W, H, fx, fy, cx, cy, rng_noise, noise=noise,
                                  dropout=0.01 if noise else 0.0)
     sensor = _Sensor(W, fx, fy, cx, cy)
     ci, cj, cp, cq, co = [], [], [], [], []
-    for (i, j) in sparse_pairs:
-        k = k_of_pair(rng_corr)
-        p, q, outl = pair_correspondences(rng_corr, scene, abs_poses[i], abs_poses[j], sensor, k,
-                                          outlier_rate, noise=noise)
+    if per_pair_streams:
+        jobs = [(n, i, j, k_of_pair(rng_corr)) for n, (i, j) in enumerate(sparse_pairs)]
+        shared = {"seed": seeds["corr"], "scene": scene, "poses": abs_poses, "sensor": sensor,
+                  "outlier_rate": outlier_rate, "noise": noise}
+        results = _pmap(_pair_job, jobs, shared)
+    else:
+        results = []
+        for (i, j) in sparse_pairs:
+            k = k_of_pair(rng_corr)
+            results.append(pair_correspondences(rng_corr, scene, abs_poses[i], abs_poses[j], sensor, k,
+                                                outlier_rate, noise=noise))
+    for (i, j), (p, q, outl) in zip(sparse_pairs, results):
         ci.append(np.full(len(p), i, np.int32)); cj.append(np.full(len(p), j, np.int32))
         cp.append(p); cq.append(q); co.append(outl)
     base_inv = rigid_inv(abs_poses[0])
@@ -270,7 +342,7 @@ def make_chunk(num_frames=11, W=80, H=60, fx=72.0, fy=72.0, cx=40.0, cy=30.0, se
 
 
 def make_global(num_frames=200, layout="apartment", seed_offset=0, config=1, outlier_rate=0.05,
-                corr_range=(100, 300), n_gn=8, n_pcg=20, noise=True, name="global200"):
+                corr_range=(100, 300), n_gn=8, n_pcg=20, noise=True, name="global200", per_pair_streams=False):
     """A global keyframe problem along a closed path through a multi-room floor."""
     seeds = _seeds(config, seed_offset)
     rng_scene = np.random.Generator(np.random.PCG64(seeds["scene"]))
@@ -278,6 +350,9 @@ def make_global(num_frames=200, layout="apartment", seed_offset=0, config=1, out
     if layout == "apartment":
         pts, length = apartment_loop(num_frames)
         nx, ny = 3, 1
+    elif layout == "floor3":
+        pts, length = floor_lawnmower(num_frames, nx=3, ny=3)
+        nx, ny = 3, 3
     else:
         pts, length = floor_lawnmower(num_frames)
         nx, ny = 5, 5
@@ -287,7 +362,8 @@ def make_global(num_frames=200, layout="apartment", seed_offset=0, config=1, out
     pairs = covisible_pairs(rng_pairs, scene, abs_poses, sensor)
     lo, hi = corr_range
     prob = _assemble(name, scene, abs_poses, 80, 60, 72.0, 72.0, 40.0, 30.0, seeds, pairs,
-                     lambda r: int(r.integers(lo, hi + 1)), outlier_rate, "drift", n_gn, n_pcg, noise=noise)
+                     lambda r: int(r.integers(lo, hi + 1)), outlier_rate, "drift", n_gn, n_pcg, noise=noise,
+                     per_pair_streams=per_pair_streams)
     prob.info["path_length_m"] = float(length)
     return prob
 
@@ -300,7 +376,7 @@ def make_problem(config, seed_offset=0):
         return make_global(200, "apartment", config=1, seed_offset=seed_offset)
     if config in (4, "global2000"):
         return make_global(2000, "floor", config=4, seed_offset=seed_offset, outlier_rate=0.10,
-                           corr_range=(200, 200), name="global2000")
+                           corr_range=(200, 200), name="global2000", per_pair_streams=True)
     raise ValueError(f"unknown config {config!r}")
 
 
@@ -334,3 +410,40 @@ def make_batch_chunks(count=256, config=2, min_frames=4, max_frames=11, workers=
     import multiprocessing as mp
     with mp.get_context("fork").Pool(workers) as pool:
         return pool.map(_batch_member, jobs, chunksize=max(1, count // (4 * workers)))
+
+
+def window(prob, start, count, name=None):
+    """The sub-problem of frames [start, start+count) of a global problem: its
+    frames, the correspondences between two of them (indices re-based), and its
+    poses (frame `start` becomes the window's fixed first frame)."""
+    end = start + count
+    keep = (prob.corr_i >= start) & (prob.corr_i < end) & (prob.corr_j >= start) & (prob.corr_j < end)
+    return Problem(name=name or f"{prob.name}[{start}:{end}]", width=prob.width, height=prob.height,
+                   fx=prob.fx, fy=prob.fy, cx=prob.cx, cy=prob.cy,
+                   depth=np.ascontiguousarray(prob.depth[start:end]),
+                   intensity=np.ascontiguousarray(prob.intensity[start:end]),
+                   corr_i=(prob.corr_i[keep] - start).astype(np.int32),
+                   corr_j=(prob.corr_j[keep] - start).astype(np.int32),
+                   corr_p=np.ascontiguousarray(prob.corr_p[keep]), corr_q=np.ascontiguousarray(prob.corr_q[keep]),
+                   gt_poses=np.ascontiguousarray(prob.gt_poses[start:end]),
+                   init_poses=np.ascontiguousarray(prob.init_poses[start:end]),
+                   n_gn=prob.n_gn, n_pcg=prob.n_pcg,
+                   outlier=None if prob.outlier is None else prob.outlier[keep],
+                   info={"window_of": prob.name, "start": start, "count": count})
+
+
+def make_serving_pool(num_chunks=64, global_frames=800, global_windows=6, seed=7):
+    """Request pool of the serving workload: `num_chunks` chunk problems (160x120,
+    4-11 frames) and `global_windows` keyframe windows of 50..global_frames frames
+    (geometrically spaced sizes, seeded start frames) cut from one `global_frames`-keyframe problem on a 3x3-room floor at 80x60 (the
+    keyframe spacing of the 2000-keyframe floor)."""
+    chunks = make_batch_chunks(count=num_chunks, config=3)
+    g = make_global(global_frames, "floor3", config=3, outlier_rate=0.10, corr_range=(200, 200),
+                    name=f"global{global_frames}", per_pair_streams=True)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.unique(np.round(np.geomspace(50, global_frames, global_windows)).astype(int))
+    wins = []
+    for n in sizes:
+        s = int(rng.integers(0, global_frames - n + 1))
+        wins.append(window(g, s, int(n)))
+    return chunks, wins

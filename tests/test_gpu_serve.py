@@ -1,0 +1,93 @@
+"""The serving loop (paper_1604_01093_amd.serve): small requests batched on one
+lane while large ones run on the other, admission by device-memory footprint.
+
+Each served result must equal, bit for bit, the result of the same request solved
+alone by bf_gauss_newton (fixed dense workgroup size): batching and overlap change
+when work runs, never what it computes.  Also: a budget that admits one request at
+a time still completes every request with the same results, and a request larger
+than the budget is refused with BF_ERR_OUT_OF_MEMORY."""
+import numpy as np
+import pytest
+import torch
+
+from synth.problems import make_batch_chunks, make_global, window
+
+pytestmark = pytest.mark.gpu
+bf = pytest.importorskip("paper_1604_01093_amd.bf")
+serve = pytest.importorskip("paper_1604_01093_amd.serve")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = bf.Context()
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def pool(ctx):
+    chunks = make_batch_chunks(count=10, config=3)
+    g = make_global(120, "floor3", config=3, outlier_rate=0.10, corr_range=(200, 200), name="g120",
+                    per_pair_streams=True)
+    wins = [window(g, 5, 40), window(g, 20, 90)]
+    p_chunk = bf.bf_params_default(num_gn=5, num_pcg=10, dense_threads=256)
+    p_glob = bf.bf_params_default(num_gn=4, num_pcg=20, dense_threads=256)
+    items = [(pr, p_chunk) for pr in chunks] + [(pr, p_glob) for pr in wins]
+    dev = [(bf.DeviceProblem.from_numpy(pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p,
+                                        pr.corr_q), torch.as_tensor(pr.init_poses).cuda(), prm) for pr, prm in items]
+    alone = [bf.bf_gauss_newton(ctx, d, i, prm) for d, i, prm in dev]
+    return dev, alone
+
+
+def _requests(dev, picks):
+    return [serve.Request(dev[k][0], dev[k][1], dev[k][2], tag=k) for k in picks]
+
+
+def _check(reqs, alone):
+    for r in reqs:
+        assert r.error is None, r.error
+        assert torch.equal(r.poses, alone[r.tag]["poses"]), r.tag
+        assert r.energy == alone[r.tag]["energy"], r.tag
+
+
+def test_mix_equals_alone(pool):
+    dev, alone = pool
+    rng = np.random.Generator(np.random.PCG64(3))
+    picks = [int(k) for k in rng.integers(0, len(dev), 40)] + list(range(len(dev)))
+    server = serve.Server()
+    try:
+        reqs = _requests(dev, picks)
+        serve.run_stream(server, reqs, np.zeros(len(reqs)))       # all at once: large batches
+        _check(reqs, alone)
+        assert max(r.batch_size for r in reqs if r.lane == "batch") > 1
+        assert {r.lane for r in reqs} == {"batch", "large"}
+        reqs = _requests(dev, picks)
+        arrivals = np.cumsum(rng.exponential(0.002, len(reqs)))    # a Poisson stream
+        serve.run_stream(server, reqs, arrivals)
+        _check(reqs, alone)
+        assert all(r.t_done >= r.t_arrival for r in reqs)
+    finally:
+        server.close()
+
+
+def test_admission_budget(pool):
+    dev, alone = pool
+    biggest = max(serve.Request(d, i, p).footprint for d, i, p in dev)
+    server = serve.Server(max_inflight_bytes=biggest)
+    try:
+        reqs = _requests(dev, list(range(len(dev))) * 2)
+        serve.run_stream(server, reqs, np.zeros(len(reqs)))
+        _check(reqs, alone)
+    finally:
+        server.close()
+    server = serve.Server(max_inflight_bytes=biggest - 1)
+    try:
+        big = [k for k in range(len(dev)) if serve.Request(*dev[k]).footprint == biggest][0]
+        reqs = _requests(dev, [big, 0])
+        serve.run_stream(server, reqs, np.zeros(2))
+        assert reqs[0].error is not None and reqs[0].error.status == bf.BF_ERR_OUT_OF_MEMORY
+        _check(reqs[1:], alone)
+    finally:
+        server.close()
