@@ -3,8 +3,9 @@
 E_align = w_sparse E_sparse + w_d (w_geo E_geo + w_photo E_photo), written as
 a sum of squared residuals (no factor 1/2).  Each iteration k linearises the
 residuals at the current poses, assembles J^T J and J^T F, removes the fixed
-reference frame and unconstrained frames, solves for the increment and applies
-it by T_f <- T_f Exp(dx_f) (``se3``).  w_d is ramped linearly over the
+reference frame and unconstrained frames (and holds frames that no residual
+touches at these poses), solves for the increment and applies it by
+T_f <- T_f Exp(dx_f) (``se3``).  w_d is ramped linearly over the
 iterations.  The dense pair set is computed once from the initial poses.  The
 returned energy is evaluated at the returned poses with the last iteration's
 w_d.  There is no damping (the paper's solver is plain Gauss-Newton).
@@ -17,7 +18,7 @@ from .frames import prepare_frames
 from .pairs import dense_pairs, edge_list, group_correspondences
 from .params import Params
 from .se3 import exp_se3
-from .system import (assemble, dense_pair_blocks, free_frames, reduce_system, solve_cholesky,
+from .system import (assemble, dense_pair_blocks, free_frames, inert_frames, reduce_system, solve_cholesky,
                      solve_pcg, sparse_pair_blocks)
 
 
@@ -118,12 +119,16 @@ def solve(depth, intensity, intr, corr_i, corr_j, p, q, init_poses, params=None,
         H, g, blocks, en = build_system(setup, poses, wd, assoc)
         if freeze_association and assoc is None:
             assoc = {e: b["dense"]["terms"] for e, b in enumerate(blocks) if b["dense"] is not None}
-        Hr, gr, _ = reduce_system(H, g, setup.free)
+        inert = inert_frames(H, setup.free)
+        active = setup.free[~inert]
+        Hr, gr, _ = reduce_system(H, g, active)
         if linear == "cholesky":
-            dx = solve_cholesky(Hr, gr)
+            dxa = solve_cholesky(Hr, gr)
             st = {}
         else:
-            dx, st = solve_pcg(Hr, gr, params.num_pcg)
+            dxa, st = solve_pcg(Hr, gr, params.num_pcg)
+        dx = np.zeros(6 * len(setup.free))
+        dx.reshape(-1, 6)[~inert] = dxa.reshape(-1, 6)
         trace.append(en)
         steps.append({"dx": dx, **st, **({"H": Hr, "g": gr} if record else {})})
         for n, f in enumerate(setup.free):

@@ -76,6 +76,14 @@ def free_frames(F, edges):
     return np.array([f for f in range(1, F) if deg[f] > 0], np.int64)
 
 
+def inert_frames(H, free):
+    """Mask over `free`: frames whose 6x6 diagonal block of H is identically zero,
+    i.e. no residual touches them at these poses (every pixel association of their
+    pairs failed and they have no correspondence).  Like the unconstrained frames of
+    Sec. 4.4.1 they carry no information in this iteration and are held fixed."""
+    return np.array([not np.any(H[6 * f:6 * f + 6, 6 * f:6 * f + 6]) for f in free], bool)
+
+
 def reduce_system(H, g, free):
     idx = (6 * free[:, None] + np.arange(6)[None, :]).ravel()
     return H[np.ix_(idx, idx)], g[idx], idx

@@ -408,7 +408,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
     if (lane == 0) {
       double A[36];
       for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
-      bool ok = spd_inverse6(A);
+      bool ok = block_jacobi_inverse6(A) >= 0;
       if (!ok) {
         pro[1] += 1.0;
         for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
@@ -671,7 +671,7 @@ __global__ void __launch_bounds__(NT) k_solve_single(
     if (lane == 0) {
       double A[36];
       for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
-      if (!spd_inverse6(A)) {
+      if (block_jacobi_inverse6(A) < 0) {
         bad_sh = 1;
         for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
       }
@@ -897,7 +897,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     if (lane == 0) {
       double A[36];
       for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
-      if (!spd_inverse6(A)) {
+      if (block_jacobi_inverse6(A) < 0) {
         pro[1] += 1.0;
         for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
       }

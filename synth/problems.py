@@ -243,39 +243,120 @@ def _covisible_row(i):
         u = sensor.fx * Xj[..., 0] / z + sensor.cx
         v = sensor.fy * Xj[..., 1] / z + sensor.cy
     ok = (z > 0.1) & sensor.in_image(u, v)
+    maps = sh.get("maps")
     for jj in np.nonzero(ok.sum(axis=1) >= need)[0]:
-        vis = _visible_from(scene, abs_poses[js[jj]], X[ok[jj]])
+        if maps is None:
+            vis = _visible_from(scene, abs_poses[js[jj]], X[ok[jj]])
+        else:
+            vis = _map_visible(maps[js[jj]][1], u[jj][ok[jj]], v[jj][ok[jj]], z[jj][ok[jj]])
         if vis.sum() >= need:
             pairs.append((i, int(js[jj])))
     return pairs
 
 
+def _map_visible(zmap, u, v, z):
+    """Depth-map visibility at sensor pixels (u, v) of points at camera depth z: the
+    nearest grid point of the frame's surface map is not more than 2 cm (or 1 % of
+    the depth) in front of the point."""
+    gw, gh = SENSOR_W // _MAP_STEP, SENSOR_H // _MAP_STEP
+    gx = np.clip(np.floor(u / _MAP_STEP), 0, gw - 1).astype(np.int64)
+    gy = np.clip(np.floor(v / _MAP_STEP), 0, gh - 1).astype(np.int64)
+    zb = zmap[gy * gw + gx]
+    return (zb > 0) & (zb >= z - np.maximum(0.02, 0.01 * z))
+
+
 def covisible_pairs(rng, scene, abs_poses, sensor, max_dist=8.0, max_angle_deg=75.0,
-                    samples=48, min_frac=0.25):
+                    samples=48, min_frac=0.25, maps=None):
     """Frame pairs i<j that see a common part of the scene (ground truth): at least
     `min_frac` of `samples` surface points seen by i are in j's view and unoccluded.
     The samples are drawn in frame order; the rows are tested in parallel."""
     F = len(abs_poses)
     samp = [_surface_samples(scene, T, sensor, samples, rng)[2] for T in abs_poses]
     shared = {"scene": scene, "poses": abs_poses, "sensor": sensor, "samp": samp, "max_dist": max_dist,
-              "cos_max": np.cos(np.deg2rad(max_angle_deg)), "need": min_frac * samples}
+              "cos_max": np.cos(np.deg2rad(max_angle_deg)), "need": min_frac * samples, "maps": maps}
     rows = _pmap(_covisible_row, range(F - 1), shared)
     return [p for row in rows for p in row]
 
 
+# Sample grid of the per-frame surface maps used by the parallel correspondence
+# generator: every 4th sensor pixel in each direction (160x120 of 640x480).
+_MAP_STEP = 4
+
+
+def _surface_map_one(T):
+    """Surface points (world, float32) and camera depths (0 = no hit) of the sample
+    grid of one frame."""
+    scene, rays = _SHARED["scene"], _SHARED["grid_rays"]
+    t, _, X = scene.raycast(T[:3, 3], rays @ T[:3, :3].T)
+    ok = np.isfinite(t)
+    return X.astype(np.float32), np.where(ok, t, 0.0).astype(np.float32)
+
+
+def surface_maps(scene, abs_poses, sensor):
+    """Per frame: surface points and depths of the sample grid (in parallel)."""
+    gw, gh = SENSOR_W // _MAP_STEP, SENSOR_H // _MAP_STEP
+    gy, gx = np.mgrid[0:gh, 0:gw].astype(np.float64)
+    grid_rays = sensor.rays((gx * _MAP_STEP + 0.5 * (_MAP_STEP - 1)).ravel(),
+                            (gy * _MAP_STEP + 0.5 * (_MAP_STEP - 1)).ravel())
+    return _pmap(_surface_map_one, list(abs_poses), {"scene": scene, "grid_rays": grid_rays})
+
+
 def _pair_job(args):
+    """Correspondences of pair n from its own random stream, using the frames'
+    surface maps: samples are grid points of frame i, visibility in frame j is a
+    depth-map test at the nearest grid point (2 cm or 1 % of the depth)."""
     n, i, j, k = args
     sh = _SHARED
     rng = np.random.Generator(np.random.PCG64([sh["seed"], n]))
-    return pair_correspondences(rng, sh["scene"], sh["poses"][i], sh["poses"][j], sh["sensor"], k,
-                                sh["outlier_rate"], noise=sh["noise"])
+    sensor, Ti, Tj = sh["sensor"], sh["poses"][i], sh["poses"][j]
+    Xi_map, zi = sh["maps"][i]
+    _, zj = sh["maps"][j]
+    gw, gh = SENSOR_W // _MAP_STEP, SENSOR_H // _MAP_STEP
+    valid_i = np.nonzero(zi > 0)[0]
+    got, need = [], k
+    for _ in range(6):
+        if need <= 0 or len(valid_i) == 0:
+            break
+        idx = valid_i[rng.integers(0, len(valid_i), max(4 * need, 64))]
+        X = Xi_map[idx].astype(np.float64)
+        Xj = _cam_coords(Tj, X)
+        front = Xj[:, 2] > 0.1
+        uj, vj = np.full(len(X), -1.0), np.full(len(X), -1.0)
+        uj[front], vj[front] = sensor.project(Xj[front])
+        ok = front & sensor.in_image(uj, vj)
+        ok &= _map_visible(zj, uj, vj, Xj[:, 2])
+        sel = idx[np.nonzero(ok)[0][:need]]
+        got.append(sel)
+        need -= len(sel)
+    sel = np.concatenate(got) if got else np.zeros(0, np.int64)
+    if len(sel) == 0:
+        return np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, bool)
+    X = Xi_map[sel].astype(np.float64)
+    u = (sel % gw) * _MAP_STEP + 0.5 * (_MAP_STEP - 1)
+    v = (sel // gw) * _MAP_STEP + 0.5 * (_MAP_STEP - 1)
+    Xi = _cam_coords(Ti, X)
+    Xj = _cam_coords(Tj, X)
+    p = _observe(rng, sensor, Xi, u, v, sh["noise"])
+    uj, vj = sensor.project(Xj)
+    q = _observe(rng, sensor, Xj, uj, vj, sh["noise"])
+    outl = rng.uniform(size=len(X)) < sh["outlier_rate"]
+    n_out = int(outl.sum())
+    Xj_map, _ = sh["maps"][j]
+    valid_j = np.nonzero(zj > 0)[0]
+    if n_out and len(valid_j):
+        oi = valid_j[rng.integers(0, len(valid_j), n_out)]
+        q[outl] = _cam_coords(Tj, Xj_map[oi].astype(np.float64))
+    elif n_out:
+        outl[:] = False
+    return p, q, outl
 
 
 def _assemble(name, scene, abs_poses, W, H, fx, fy, cx, cy, seeds, sparse_pairs, k_of_pair,
               outlier_rate, init_mode, n_gn, n_pcg, noise=True, init_rot=2.0, init_trans=0.03,
-              drift_rot=0.5, drift_trans=0.01, per_pair_streams=False):
+              drift_rot=0.5, drift_trans=0.01, per_pair_streams=False, maps=None):
     """per_pair_streams: pair n draws its correspondences from its own stream
-    PCG64([corr seed, n]) (so pairs run in parallel); otherwise one stream in pair order."""
+    PCG64([corr seed, n]) against per-frame surface maps (pairs run in parallel);
+    otherwise one stream in pair order with exact ray casts."""
     rng_noise = np.random.Generator(np.random.PCG64(seeds["noise"]))
     rng_corr = np.random.Generator(np.random.PCG64(seeds["corr"]))
     depth, inten = render_frames(scene, abs_poses, W, H, fx, fy, cx, cy, rng_noise, noise=noise,
@@ -284,7 +365,9 @@ def _assemble(name, scene, abs_poses, W, H, fx, fy, cx, cy, seeds, sparse_pairs,
     ci, cj, cp, cq, co = [], [], [], [], []
     if per_pair_streams:
         jobs = [(n, i, j, k_of_pair(rng_corr)) for n, (i, j) in enumerate(sparse_pairs)]
-        shared = {"seed": seeds["corr"], "scene": scene, "poses": abs_poses, "sensor": sensor,
+        if maps is None:
+            maps = surface_maps(scene, abs_poses, sensor)
+        shared = {"seed": seeds["corr"], "poses": abs_poses, "sensor": sensor, "maps": maps,
                   "outlier_rate": outlier_rate, "noise": noise}
         results = _pmap(_pair_job, jobs, shared)
     else:
@@ -359,11 +442,12 @@ def make_global(num_frames=200, layout="apartment", seed_offset=0, config=1, out
     abs_poses = path_poses(pts)
     scene = make_scene(rng_scene, nx, ny, abs_poses[:, :3, 3], doors=True, spheres=True)
     sensor = _Sensor(80, 72.0, 72.0, 40.0, 30.0)
-    pairs = covisible_pairs(rng_pairs, scene, abs_poses, sensor)
+    maps = surface_maps(scene, abs_poses, sensor) if per_pair_streams else None
+    pairs = covisible_pairs(rng_pairs, scene, abs_poses, sensor, maps=maps)
     lo, hi = corr_range
     prob = _assemble(name, scene, abs_poses, 80, 60, 72.0, 72.0, 40.0, 30.0, seeds, pairs,
                      lambda r: int(r.integers(lo, hi + 1)), outlier_rate, "drift", n_gn, n_pcg, noise=noise,
-                     per_pair_streams=per_pair_streams)
+                     per_pair_streams=per_pair_streams, maps=maps)
     prob.info["path_length_m"] = float(length)
     return prob
 

@@ -211,3 +211,27 @@ def test_gauss_newton_chunk(ctx, chunk, pcg_storage, accumulate, solve_kernel):
     assert np.array_equal(init.cpu().numpy(), chunk.init_poses)
     again = bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, **kw))
     assert torch.equal(again["poses"], out["poses"])
+
+
+@pytest.mark.parametrize("solve_kernel", [0, 1, 2, 3])
+def test_frame_without_residuals_is_held(ctx, solve_kernel):
+    """A variable frame that no residual touches (no valid depth, no
+    correspondences, but dense pairs from lower frames) keeps its pose; the rest
+    matches the oracle, which holds such frames in the same way."""
+    pr = make_chunk(num_frames=6)
+    f = 3
+    pr.depth = pr.depth.copy()
+    pr.depth[f] = 0.0
+    keep = (pr.corr_i != f) & (pr.corr_j != f)
+    pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q = pr.corr_i[keep], pr.corr_j[keep], pr.corr_p[keep], pr.corr_q[keep]
+    prm = Params(num_gn=3, num_pcg=10)
+    ref = solve(pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q, pr.init_poses,
+                prm, linear="pcg")
+    assert f in ref["setup"].free
+    out = bf.bf_gauss_newton(ctx, device_problem(pr), poses_cuda(pr.init_poses),
+                             bf_params_from(prm, solve_kernel=solve_kernel))
+    P = out["poses"].cpu().numpy()
+    assert np.array_equal(P[f], pr.init_poses[f])
+    rot, tr = pose_errors(P, ref["poses"])
+    assert rot < 1e-5 and tr < 1e-5
+    assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]

@@ -167,3 +167,52 @@ def test_pcg_mode_approaches_cholesky_on_chunk():
     x, st = solve_pcg(Hr, gr, 3 * Hr.shape[0])
     ref = solve_cholesky(Hr, gr)
     assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def _drop_frame_data(pr, f):
+    """Frame f with no valid depth and no correspondences: it is still a variable
+    (lower frames' grid points fall in its view, so it has dense pairs), but no
+    residual ever touches it."""
+    import copy
+    q = copy.copy(pr)
+    q.depth = pr.depth.copy()
+    q.depth[f] = 0.0
+    keep = (pr.corr_i != f) & (pr.corr_j != f)
+    q.corr_i, q.corr_j = pr.corr_i[keep], pr.corr_j[keep]
+    q.corr_p, q.corr_q = pr.corr_p[keep], pr.corr_q[keep]
+    return q
+
+
+def _delete_frame(pr, f):
+    import copy
+    q = copy.copy(pr)
+    sel = [k for k in range(pr.num_frames) if k != f]
+    q.depth, q.intensity = pr.depth[sel], pr.intensity[sel]
+    q.init_poses = pr.init_poses[sel]
+    keep = (pr.corr_i != f) & (pr.corr_j != f)
+    q.corr_i = (pr.corr_i[keep] - (pr.corr_i[keep] > f)).astype(np.int32)
+    q.corr_j = (pr.corr_j[keep] - (pr.corr_j[keep] > f)).astype(np.int32)
+    q.corr_p, q.corr_q = pr.corr_p[keep], pr.corr_q[keep]
+    return q
+
+
+@pytest.mark.parametrize("linear", ["cholesky", "pcg"])
+def test_frame_without_residuals_is_held(linear):
+    """A variable frame that no residual touches (its diagonal block is identically
+    zero) keeps its pose, and every other frame moves exactly as in the problem
+    where that frame does not exist."""
+    pr = make_chunk(num_frames=6)
+    f = 3
+    prm = Params(num_gn=3, num_pcg=10)
+    a = _drop_frame_data(pr, f)
+    ra = solve(a.depth, a.intensity, a.intrinsics, a.corr_i, a.corr_j, a.corr_p, a.corr_q, a.init_poses, prm,
+               linear=linear)
+    assert any(f in (i, j) for i, j in ra["setup"].pairs), "frame must keep dense pairs"
+    assert f in ra["setup"].free
+    b = _delete_frame(pr, f)
+    rb = solve(b.depth, b.intensity, b.intrinsics, b.corr_i, b.corr_j, b.corr_p, b.corr_q, b.init_poses, prm,
+               linear=linear)
+    assert np.array_equal(ra["poses"][f], pr.init_poses[f])
+    others = [k for k in range(pr.num_frames) if k != f]
+    assert np.abs(ra["poses"][others] - rb["poses"]).max() < 1e-10
+    assert abs(ra["energy"]["total"] - rb["energy"]["total"]) <= 1e-10 * rb["energy"]["total"]
