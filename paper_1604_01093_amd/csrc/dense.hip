@@ -91,21 +91,127 @@ __device__ __forceinline__ double uniform_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Per-lane accumulation of one associated pixel's residuals and Jacobians.
+template <int MODE, bool JAC, class Acc>
+__device__ __forceinline__ void pixel_terms(Acc& A, const float* w, const float* R, const float* t,
+                                            const double* Rd, const double* td, const double* __restrict__ kx64,
+                                            const double* __restrict__ ky64, const Intr32& in, double fx64,
+                                            double fy64, double cx64, double cy64, double swg, double swp) {
+  using V = typename Acc::V;
+  V rg, rp = (V)0, jg[6], jp[6] = {(V)0, (V)0, (V)0, (V)0, (V)0, (V)0};
+  bool ph;
+  if constexpr (MODE == 2) {
+    // payload: D, Dj, n(3), px, py, xh, yh, x0, y0, Gi, taps(4)
+    const double D64 = (double)w[0], Dj = (double)w[1];
+    const int px = (int)w[5], py = (int)w[6], xh = (int)w[7], yh = (int)w[8];
+    const double x0f = (double)w[9], y0f = (double)w[10];
+    const float Gi = w[11];
+    ph = !is_nan(Gi);
+    const double dx = kx64[px] * D64, dy = ky64[py] * D64;
+    const double cx_ = Rd[0] * dx + Rd[1] * dy + Rd[2] * D64 + td[0];
+    const double cy_ = Rd[3] * dx + Rd[4] * dy + Rd[5] * D64 + td[1];
+    const double cz_ = Rd[6] * dx + Rd[7] * dy + Rd[8] * D64 + td[2];
+    const double qx = kx64[xh] * Dj, qy = ky64[yh] * Dj, qz = Dj;
+    const double nx = w[2], ny = w[3], nz = w[4];
+    const double mx = Rd[0] * nx + Rd[1] * ny + Rd[2] * nz;
+    const double my = Rd[3] * nx + Rd[4] * ny + Rd[5] * nz;
+    const double mz = Rd[6] * nx + Rd[7] * ny + Rd[8] * nz;
+    rg = (mx * (cx_ - qx) + my * (cy_ - qy) + mz * (cz_ - qz)) * swg;
+    const double sx_ = mx * swg, sy_ = my * swg, sz_ = mz * swg;
+    jg[0] = sy_ * qz - sz_ * qy;
+    jg[1] = sz_ * qx - sx_ * qz;
+    jg[2] = sx_ * qy - sy_ * qx;
+    jg[3] = -sx_;
+    jg[4] = -sy_;
+    jg[5] = -sz_;
+    if (ph) {
+      const double iz64 = 1.0 / cz_;
+      const double u64 = fx64 * cx_ * iz64 + cx64;
+      const double v64 = fy64 * cy_ * iz64 + cy64;
+      const double al = u64 - x0f, be = v64 - y0f;
+      const double G00 = w[12], G10 = w[13], G01 = w[14], G11 = w[15];
+      const double Gj = (1.0 - al) * ((1.0 - be) * G00 + be * G01) + al * ((1.0 - be) * G10 + be * G11);
+      const double gu = ((1.0 - be) * (G10 - G00) + be * (G11 - G01)) * swp;
+      const double gv = ((1.0 - al) * (G01 - G00) + al * (G11 - G10)) * swp;
+      rp = ((double)Gi - Gj) * swp;
+      const double ax = gu * fx64 * iz64, ay = gv * fy64 * iz64;
+      const double az = -(ax * cx_ + ay * cy_) * iz64;
+      jp[0] = cy_ * az - cz_ * ay;
+      jp[1] = cz_ * ax - cx_ * az;
+      jp[2] = cx_ * ay - cy_ * ax;
+      jp[3] = ax;
+      jp[4] = ay;
+      jp[5] = az;
+    }
+  } else {
+    // payload: c(3), m(3), q(3), u, v, Gi, taps(4)
+    const float cx = w[0], cy = w[1], cz = w[2], mx0 = w[3], my0 = w[4], mz0 = w[5];
+    const float qx = w[6], qy = w[7], qz = w[8], u = w[9], v = w[10], Gi = w[11];
+    ph = !is_nan(Gi);
+    const float fswg = (float)swg, fswp = (float)swp;
+    rg = (mx0 * (cx - qx) + my0 * (cy - qy) + mz0 * (cz - qz)) * fswg;
+    const float mx = mx0 * fswg, my = my0 * fswg, mz = mz0 * fswg;
+    jg[0] = my * qz - mz * qy;
+    jg[1] = mz * qx - mx * qz;
+    jg[2] = mx * qy - my * qx;
+    jg[3] = -mx;
+    jg[4] = -my;
+    jg[5] = -mz;
+    if (ph) {
+      const float iz = 1.0f / cz;
+      const float al = u - floorf(u), be = v - floorf(v);
+      const float g00 = w[12], g10 = w[13], g01 = w[14], g11 = w[15];
+      const float Gj = (1.0f - al) * ((1.0f - be) * g00 + be * g01) + al * ((1.0f - be) * g10 + be * g11);
+      const float gu = ((1.0f - be) * (g10 - g00) + be * (g11 - g01)) * fswp;
+      const float gv = ((1.0f - al) * (g01 - g00) + al * (g11 - g10)) * fswp;
+      rp = (Gi - Gj) * fswp;
+      const float ax = gu * in.fx * iz, ay = gv * in.fy * iz;
+      const float az = -(ax * cx + ay * cy) * iz;
+      jp[0] = cy * az - cz * ay;
+      jp[1] = cz * ax - cx * az;
+      jp[2] = cx * ay - cy * ax;
+      jp[3] = ax;
+      jp[4] = ay;
+      jp[5] = az;
+    }
+  }
+  if constexpr (JAC) {
+    accumulate_jac<MODE, V>(A, jg, rg, jp, rp, ph ? (V)1 : (V)0);
+  } else {
+    A.add(0, rg * rg);
+    A.add(1, rp * rp);
+    A.add(2, (V)1);
+    A.add(3, ph ? (V)1 : (V)0);
+  }
+}
+
+// Payload words per queued pixel and queue slots per wavefront.
+constexpr int kPayload = 16;
+constexpr int kQueue = 128;
+
 template <int MODE, bool JAC, int NT>
 __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, long long P,
-                                               const float4* __restrict__ nd, const float* __restrict__ grad,
-                                               const float* __restrict__ kx, const float* __restrict__ ky,
-                                               const double* __restrict__ kx64, const double* __restrict__ ky64,
-                                               const double* __restrict__ poses, Intr32 in, double fx64, double fy64,
-                                               double cx64, double cy64, float tau_d2, float tau_n, double swg,
-                                               double swp, double* __restrict__ records) {
+                                              const float4* __restrict__ nd, const float* __restrict__ grad,
+                                              const float* __restrict__ kx, const float* __restrict__ ky,
+                                              const double* __restrict__ kx64, const double* __restrict__ ky64,
+                                              const double* __restrict__ poses, Intr32 in, double fx64, double fy64,
+                                              double cx64, double cy64, float tau_d2, float tau_n, double swg,
+                                              double swp, double* __restrict__ records) {
+  constexpr int NW = NT / 64;
+  constexpr int RL = NT < 256 ? NT : 256;
+  constexpr int NCH = RL / 16;
+  constexpr size_t kQueueBytes = sizeof(float) * NW * kPayload * kQueue;
+  constexpr size_t kRedBytes = sizeof(double) * (16 * RL + 16 * NCH + 32);
+  // the per-wavefront queues and the final reduction share the workgroup's LDS
+  __shared__ double smem[(kQueueBytes > kRedBytes ? kQueueBytes : kRedBytes) / sizeof(double)];
+
   // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs, so give
   // each XCD a contiguous block of pair jobs (neighbouring jobs share frames and
   // stay in that XCD's L2).  The grid is a multiple of 8.
   const long long per = gridDim.x / 8;
   const long long p = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (p >= P) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = pairs[2 * p], j = pairs[2 * p + 1];
   const int W = in.W, H = in.H, HW = W * H;
 
@@ -132,11 +238,22 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
   constexpr int NV = JAC ? 31 : 4;
   LaneAcc<MODE, NV> A;
   A.zero();
-  using V = typename LaneAcc<MODE, NV>::V;
+  float* Q = reinterpret_cast<float*>(smem) + (size_t)wave * kPayload * kQueue;  // Q[k * kQueue + slot]
+  int head = 0, tail = 0;  // wavefront-uniform queue positions
 
+  // Wavefront w takes the pixels w*64 + lane + k*NT: first the FP32 association
+  // decisions for every pixel, then the residual/Jacobian work only for the pixels
+  // that passed, 64 at a time from the wavefront's queue (all lanes busy).  The
+  // decisions are written without branches: every load is issued with clamped,
+  // in-bounds indices (the target gather, the four gradient taps and G_i together,
+  // right after the projection) and the tests only decide validity, so the loads of
+  // a step overlap instead of waiting on each other; the source load of the next
+  // step is issued before the current one is processed.
   int x = tid % W, y = tid / W;
-  const int sx = blockDim.x % W, sy = blockDim.x / W;
-  for (int pix = tid; pix < HW; pix += blockDim.x) {
+  const int sx = NT % W, sy = NT / W;
+  float4 s_next = ndi[tid < HW ? tid : HW - 1];
+  for (int base = wave * 64; base < HW; base += NT) {
+    const int pix = base + lane;
     const int px = x, py = y;
     x += sx;
     y += sy;
@@ -144,125 +261,97 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
       x -= W;
       y += 1;
     }
-    // ---- FP32 association decisions (fixed operation order)
-    const float4 s = ndi[pix];
-    if (is_nan(s.x)) continue;
-    const float D = s.w;
-    const float3 d = make_float3(mul_nc(kx[px], D), mul_nc(ky[py], D), D);
-    const float3 c = xform_nc(R, t, d);
-    if (!(c.z > 0.0f)) continue;
-    const float iz = 1.0f / c.z;
-    const float u = project_nc(in.fx, c.x, iz, in.cx);
-    const float v = project_nc(in.fy, c.y, iz, in.cy);
-    const float xf = floorf(u + 0.5f), yf = floorf(v + 0.5f);
-    if (!(xf >= 0.0f && xf <= fWm1 && yf >= 0.0f && yf <= fHm1)) continue;
-    const int xh = (int)xf, yh = (int)yf;
-    const float4 tq = ndj[yh * W + xh];
-    if (is_nan(tq.x)) continue;
-    const float3 q = make_float3(mul_nc(kx[xh], tq.w), mul_nc(ky[yh], tq.w), tq.w);
-    const float3 e = make_float3(c.x - q.x, c.y - q.y, c.z - q.z);
-    if (!(dot_nc(e, e) < tau_d2)) continue;
-    const float3 n = make_float3(s.x, s.y, s.z);
-    const float3 m = rotate_nc(R, n);
-    if (!(dot_nc(m, make_float3(tq.x, tq.y, tq.z)) > tau_n)) continue;
-    const float x0f = floorf(u), y0f = floorf(v);
-    bool ph = x0f >= 0.0f && x0f <= fWm2 && y0f >= 0.0f && y0f <= fHm2;
-    const float Gi = gi[pix];
-    ph = ph && !is_nan(Gi);
-    float g00 = 0.f, g10 = 0.f, g01 = 0.f, g11 = 0.f;
-    if (ph) {
-      const int t0 = (int)y0f * W + (int)x0f;
-      g00 = gj[t0];
-      g10 = gj[t0 + 1];
-      g01 = gj[t0 + W];
-      g11 = gj[t0 + W + 1];
-      ph = !(is_nan(g00) || is_nan(g10) || is_nan(g01) || is_nan(g11));
+    const float4 s4 = s_next;
+    {
+      const int nxt = pix + NT;
+      s_next = ndi[nxt < HW ? nxt : HW - 1];
     }
-
-    // ---- residuals and Jacobians w.r.t. frame j
-    V rg, rp = (V)0, jg[6], jp[6] = {(V)0, (V)0, (V)0, (V)0, (V)0, (V)0};
-    if constexpr (MODE == 2) {
-      const double D64 = (double)D, Dj = (double)tq.w;
-      const double dx = kx64[px] * D64, dy = ky64[py] * D64;
-      const double cx_ = Rd[0] * dx + Rd[1] * dy + Rd[2] * D64 + td[0];
-      const double cy_ = Rd[3] * dx + Rd[4] * dy + Rd[5] * D64 + td[1];
-      const double cz_ = Rd[6] * dx + Rd[7] * dy + Rd[8] * D64 + td[2];
-      const double qx = kx64[xh] * Dj, qy = ky64[yh] * Dj, qz = Dj;
-      const double nx = n.x, ny = n.y, nz = n.z;
-      const double mx = Rd[0] * nx + Rd[1] * ny + Rd[2] * nz;
-      const double my = Rd[3] * nx + Rd[4] * ny + Rd[5] * nz;
-      const double mz = Rd[6] * nx + Rd[7] * ny + Rd[8] * nz;
-      rg = (mx * (cx_ - qx) + my * (cy_ - qy) + mz * (cz_ - qz)) * swg;
-      const double sx_ = mx * swg, sy_ = my * swg, sz_ = mz * swg;
-      jg[0] = sy_ * qz - sz_ * qy;
-      jg[1] = sz_ * qx - sx_ * qz;
-      jg[2] = sx_ * qy - sy_ * qx;
-      jg[3] = -sx_;
-      jg[4] = -sy_;
-      jg[5] = -sz_;
-      if (ph) {
-        const double iz64 = 1.0 / cz_;
-        const double u64 = fx64 * cx_ * iz64 + cx64;
-        const double v64 = fy64 * cy_ * iz64 + cy64;
-        const double al = u64 - (double)x0f, be = v64 - (double)y0f;
-        const double G00 = g00, G10 = g10, G01 = g01, G11 = g11;
-        const double Gj = (1.0 - al) * ((1.0 - be) * G00 + be * G01) + al * ((1.0 - be) * G10 + be * G11);
-        const double gu = ((1.0 - be) * (G10 - G00) + be * (G11 - G01)) * swp;
-        const double gv = ((1.0 - al) * (G01 - G00) + al * (G11 - G10)) * swp;
-        rp = ((double)Gi - Gj) * swp;
-        const double ax = gu * fx64 * iz64, ay = gv * fy64 * iz64;
-        const double az = -(ax * cx_ + ay * cy_) * iz64;
-        jp[0] = cy_ * az - cz_ * ay;
-        jp[1] = cz_ * ax - cx_ * az;
-        jp[2] = cx_ * ay - cy_ * ax;
-        jp[3] = ax;
-        jp[4] = ay;
-        jp[5] = az;
+    float wv[kPayload];
+    bool valid;
+    {
+      const float D = s4.w;
+      const float3 d = make_float3(mul_nc(kx[px], D), mul_nc(ky[py], D), D);
+      const float3 c = xform_nc(R, t, d);
+      const float iz = 1.0f / c.z;
+      const float u = project_nc(in.fx, c.x, iz, in.cx);
+      const float v = project_nc(in.fy, c.y, iz, in.cy);
+      const float xf = floorf(u + 0.5f), yf = floorf(v + 0.5f);
+      const float x0f = floorf(u), y0f = floorf(v);
+      // clamped copies for addressing (fminf/fmaxf also map NaN to the bound)
+      const int xh = (int)fminf(fmaxf(xf, 0.0f), fWm1), yh = (int)fminf(fmaxf(yf, 0.0f), fHm1);
+      const int xt = (int)fminf(fmaxf(x0f, 0.0f), fWm2), yt = (int)fminf(fmaxf(y0f, 0.0f), fHm2);
+      const float4 tq = ndj[yh * W + xh];
+      const int t0 = yt * W + xt;
+      const float g00 = gj[t0], g10 = gj[t0 + 1], g01 = gj[t0 + W], g11 = gj[t0 + W + 1];
+      float Gi = gi[pix < HW ? pix : HW - 1];
+      const float kxh = kx[xh], kyh = ky[yh];
+      valid = pix < HW && !is_nan(s4.x) && c.z > 0.0f && xf >= 0.0f && xf <= fWm1 && yf >= 0.0f && yf <= fHm1 &&
+              !is_nan(tq.x);
+      const float3 q = make_float3(mul_nc(kxh, tq.w), mul_nc(kyh, tq.w), tq.w);
+      const float3 e = make_float3(c.x - q.x, c.y - q.y, c.z - q.z);
+      const float3 n = make_float3(s4.x, s4.y, s4.z);
+      const float3 m = rotate_nc(R, n);
+      valid = valid && dot_nc(e, e) < tau_d2 && dot_nc(m, make_float3(tq.x, tq.y, tq.z)) > tau_n;
+      const bool ph = x0f >= 0.0f && x0f <= fWm2 && y0f >= 0.0f && y0f <= fHm2 && !is_nan(Gi) &&
+                      !(is_nan(g00) || is_nan(g10) || is_nan(g01) || is_nan(g11));
+      if (!ph) Gi = __builtin_nanf("");
+      if constexpr (MODE == 2) {
+        wv[0] = D; wv[1] = tq.w; wv[2] = n.x; wv[3] = n.y; wv[4] = n.z;
+        wv[5] = (float)px; wv[6] = (float)py; wv[7] = (float)xh; wv[8] = (float)yh;
+        wv[9] = x0f; wv[10] = y0f;
+      } else {
+        wv[0] = c.x; wv[1] = c.y; wv[2] = c.z; wv[3] = m.x; wv[4] = m.y; wv[5] = m.z;
+        wv[6] = q.x; wv[7] = q.y; wv[8] = q.z; wv[9] = u; wv[10] = v;
       }
-    } else {
-      const float fswg = (float)swg, fswp = (float)swp;
-      rg = (m.x * e.x + m.y * e.y + m.z * e.z) * fswg;
-      const float mx = m.x * fswg, my = m.y * fswg, mz = m.z * fswg;
-      jg[0] = my * q.z - mz * q.y;
-      jg[1] = mz * q.x - mx * q.z;
-      jg[2] = mx * q.y - my * q.x;
-      jg[3] = -mx;
-      jg[4] = -my;
-      jg[5] = -mz;
-      if (ph) {
-        const float al = u - x0f, be = v - y0f;
-        const float Gj = (1.0f - al) * ((1.0f - be) * g00 + be * g01) + al * ((1.0f - be) * g10 + be * g11);
-        const float gu = ((1.0f - be) * (g10 - g00) + be * (g11 - g01)) * fswp;
-        const float gv = ((1.0f - al) * (g01 - g00) + al * (g11 - g10)) * fswp;
-        rp = (Gi - Gj) * fswp;
-        const float ax = gu * in.fx * iz, ay = gv * in.fy * iz;
-        const float az = -(ax * c.x + ay * c.y) * iz;
-        jp[0] = c.y * az - c.z * ay;
-        jp[1] = c.z * ax - c.x * az;
-        jp[2] = c.x * ay - c.y * ax;
-        jp[3] = ax;
-        jp[4] = ay;
-        jp[5] = az;
-      }
+      wv[11] = Gi; wv[12] = g00; wv[13] = g10; wv[14] = g01; wv[15] = g11;
     }
-    if constexpr (JAC) {
-      accumulate_jac<MODE, V>(A, jg, rg, jp, rp, ph ? (V)1 : (V)0);
-    } else {
-      A.add(0, rg * rg);
-      A.add(1, rp * rp);
-      A.add(2, (V)1);
-      A.add(3, ph ? (V)1 : (V)0);
+    if constexpr (!JAC) {
+      // energy only: too little work per pixel to be worth the queue
+      if (valid) pixel_terms<MODE, JAC>(A, wv, R, t, Rd, td, kx64, ky64, in, fx64, fy64, cx64, cy64, swg, swp);
+      continue;
+    }
+    // append the passing pixels to the queue in lane order
+    const unsigned long long mask = __ballot(valid);
+    const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+    if (valid) {
+      const int slot = (tail + rank) & (kQueue - 1);
+#pragma unroll
+      for (int k = 0; k < kPayload; ++k) Q[k * kQueue + slot] = wv[k];
+    }
+    tail += __popcll(mask);
+    if (tail - head >= 64) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int slot = (head + lane) & (kQueue - 1);
+      float w[kPayload];
+#pragma unroll
+      for (int k = 0; k < kPayload; ++k) w[k] = Q[k * kQueue + slot];
+      pixel_terms<MODE, JAC>(A, w, R, t, Rd, td, kx64, ky64, in, fx64, fy64, cx64, cy64, swg, swp);
+      head += 64;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
   }
+  // the rest of the queue (fewer than 64)
+  if (tail > head) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < tail - head) {
+      const int slot = (head + lane) & (kQueue - 1);
+      float w[kPayload];
+#pragma unroll
+      for (int k = 0; k < kPayload; ++k) w[k] = Q[k * kQueue + slot];
+      pixel_terms<MODE, JAC>(A, w, R, t, Rd, td, kx64, ky64, in, fx64, fy64, cx64, cy64, swg, swp);
+    }
+  }
+  __syncthreads();  // queues are dead: their LDS becomes the reduction buffer
 
   // Workgroup reduction in FP64, fixed order, 16 values at a time through LDS: with
   // 512 threads the upper half first adds onto the lower half; then each value's
   // RL lane sums are added in chunks of 16 lanes, and the chunk sums in order.
-  constexpr int RL = NT < 256 ? NT : 256;
-  constexpr int NCH = RL / 16;
-  __shared__ double red[16][RL];
-  __shared__ double part[16][NCH];
-  __shared__ double out[32];
+  double (*red)[RL] = reinterpret_cast<double (*)[RL]>(smem);
+  double (*part)[NCH] = reinterpret_cast<double (*)[NCH]>(smem + 16 * RL);
+  double* out = smem + 16 * RL + 16 * NCH;
 #pragma unroll
   for (int base = 0; base < 32; base += 16) {
     if (base < NV) {
