@@ -9,8 +9,10 @@ unknowns), against the oracle's run stored in tests/golden/global2000_oracle.npz
 * per-pair dense records at the initial poses on a sample of 16 pair jobs,
   computed by the oracle one pair at a time;
 * one Gauss-Newton step at the oracle's first two iterates: the increment within
-  1e-5 (rad, m) of the oracle's (at the second iterate one frame receives no
-  residual and is held by both);
+  1e-5 (rad, m) of the oracle's in the mixed-precision configuration of this
+  workload (compensated FP32 lane sums, FP64 PCG storage) and with FP64 values,
+  and within 1e-4 on the all-FP32 path, whose error at this size is printed (at
+  the second iterate one frame receives no residual and is held by both);
 * the full solve: the energies at the start of the first two iterations within
   1e-4 relative of the oracle's.
 
@@ -105,18 +107,24 @@ def test_sampled_pair_records(ctx, prob, golden, dp):
             assert block_rel_err(r[:21], upper21(o["Hjj"])) < 1e-5, (i, j)
 
 
-def test_one_step_parity(ctx, prob, golden, dp):
+# (accumulate, pcg_storage, bound): the FP32 path (FP32 values, lane sums, PCG
+# matrix and vectors; FP64 dots) and the mixed-precision configuration of this
+# workload (compensated FP32 lane sums, FP64 PCG storage), and FP64 values.
+@pytest.mark.parametrize("accumulate,pcg_storage,bound", [(0, 0, 1e-4), (1, 1, 1e-5), (2, 1, 1e-5)])
+def test_one_step_parity(ctx, prob, golden, dp, accumulate, pcg_storage, bound):
     prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
     free = golden["free"]
     idx = (6 * free[:, None] + np.arange(6)[None, :]).ravel()
     dpp = device_problem(prob, pairs=golden["pairs"])
     for k in range(len(golden["steps"])):
-        bf.bf_build_normal_equations(ctx, dpp, poses_cuda(golden["traj"][k]), bf_params_from(prm), gn_iter=k,
-                                     dense=False)
+        bf.bf_build_normal_equations(ctx, dpp, poses_cuda(golden["traj"][k]),
+                                     bf_params_from(prm, accumulate=accumulate, pcg_storage=pcg_storage),
+                                     gn_iter=k, dense=False)
         delta, st = bf.bf_pcg_solve(ctx, prob.num_frames, prob.n_pcg)
         err = float(np.abs(delta.cpu().numpy()[idx] - golden["steps"][k]).max())
-        print(f"global2000 step {k}: max |d increment| {err:.2e}", flush=True)
-        assert err < 1e-5
+        print(f"global2000 accumulate={accumulate} storage={pcg_storage} step {k}: max |d increment| {err:.2e} "
+              f"(max |increment| {np.abs(golden['steps'][k]).max():.3f})", flush=True)
+        assert err < bound
         held = free[golden["inert"][k]]
         assert not delta.cpu().numpy().reshape(-1, 6)[held].any()
 
