@@ -72,8 +72,10 @@ _SHARED = {}
 
 
 def _workers(n_items, workers=None):
-    """Worker processes for n_items independent tasks: min(16, cpu count), and 1
-    (no fork) when torch already holds a GPU context in this process."""
+    """Worker processes for n_items independent tasks: $BF_SYNTH_WORKERS if set,
+    else min(16, cpu count); 1 (no fork) when torch already holds a GPU context in
+    this process.  Set BF_SYNTH_WORKERS=1 when a tool attached to the process may
+    hold one (a profiler)."""
     import os
     import sys
     if workers is None:
@@ -479,16 +481,10 @@ def batch_sizes(count=256, config=2, min_frames=4, max_frames=11):
 def make_batch_chunks(count=256, config=2, min_frames=4, max_frames=11, workers=None):
     """`count` independent chunk problems at 160x120 with frame counts U{min..max}.
     Members depend only on their index, so they are generated in parallel
-    (`workers` processes, default min(16, cpu count); 1 = in this process)."""
-    import os
+    (`workers` processes, see _workers; 1 = in this process)."""
     sizes = batch_sizes(count, config, min_frames, max_frames)
     jobs = [(k, int(n), config) for k, n in enumerate(sizes)]
-    if workers is None:
-        workers = min(16, os.cpu_count() or 1)
-    import sys
-    torch = sys.modules.get("torch")
-    if torch is not None and torch.cuda.is_initialized():
-        workers = 1  # never fork a process that holds a GPU context
+    workers = _workers(count, workers)
     if workers <= 1 or count < 8:
         return [_batch_member(j) for j in jobs]
     import multiprocessing as mp
