@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--solve-kernel", type=int, default=0)
     ap.add_argument("--dense-threads", type=int, default=256, help="threads per dense pair job (0 = timed choice)")
+    ap.add_argument("--preconditioner", type=int, default=0, help="0 = 6x6 block-Jacobi, 1 = scalar Jacobi")
     ap.add_argument("--workload", choices=["global200", "global2000"], default="global200",
                     help="global2000: the 2000-keyframe floor (8 GN x 20 PCG); only the solve is measured")
     ap.add_argument("--skip-batched", action="store_true")
@@ -171,7 +172,7 @@ def main():
     out = torch.empty_like(init)
     params = bf.bf_params_default(num_gn=prob.n_gn, num_pcg=prob.n_pcg, pcg_storage=args.pcg_storage,
                                   accumulate=args.accumulate, solve_kernel=args.solve_kernel, timing=1,
-                                  dense_threads=args.dense_threads)
+                                  dense_threads=args.dense_threads, preconditioner=args.preconditioner)
     st = bf.bf_build_structure(ctx, dp, init, params)
     P = st["pairs"].shape[0]
     log(f"structure: {P} dense pair jobs, {st['sparse_ij'].shape[0]} sparse pairs, {st['edges'].shape[0]} edges")
@@ -234,7 +235,8 @@ def main():
                    "pcg_storage": "fp64" if args.pcg_storage else "fp32",
                    "accumulate": ["fp32", "fp32-two-sum", "fp64"][args.accumulate],
                    "solve_kernel": ["auto", "single", "coop", "replicated", "per-problem"][args.solve_kernel],
-                   "dense_threads": args.dense_threads},
+                   "dense_threads": args.dense_threads,
+                   "preconditioner": ["block-jacobi", "jacobi"][args.preconditioner]},
         "roofline": {"bound": "hbm", "kernel": "k_dense<jacobians>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if big else measured_traffic(), "avg_launch_us": round(avg_dense_s * 1e6, 2),

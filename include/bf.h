@@ -113,6 +113,10 @@ typedef struct bf_params {
   double tau_normal;        /* dense association: normal dot product > tau_normal */
   double max_angle_deg;     /* dense pair test: viewing directions within this angle */
   double depth_min, depth_max;
+  int32_t preconditioner;   /* PCG preconditioner: 0 = 6x6 block-Jacobi (one Cholesky-inverted
+                               block per frame), 1 = Jacobi (the diagonal of J^T J, as in
+                               Sec. 4.4) */
+  int32_t reserved1;        /* must be 0 */
 } bf_params;
 
 void bf_params_default(bf_params* out);
@@ -229,6 +233,20 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* frames, const bf_int
                           const bf_corrs* corrs, const bf_pairs* pairs, const double* init_poses,
                           const bf_params* params, double* out_poses, double* out_energy,
                           double* out_trace);
+
+/*
+ * y = H x with the J^T J matrix of the last bf_build_normal_equations() call (all
+ * frames, 6F, frame 0 included), for comparing representations (Sec. 4.4):
+ *   mode 0: from the assembled per-edge 6x6 blocks (what the PCG kernels use);
+ *   mode 1: the sparse term only, matrix-free as the paper does it: J x per
+ *           correspondence, then J^T per frame over the frame's correspondences.
+ *           `corrs` must be the correspondences the system was built from.  With a
+ *           system built with use_dense = 0 both modes give the same product.
+ * x, y: device [6F] float64.  out_us (host, may be NULL): time of the product's
+ * kernels.  Synchronises the stream.
+ */
+bf_status bf_system_matvec(bf_context* ctx, const bf_corrs* corrs, const double* x, double* y, int32_t mode,
+                           double* out_us);
 
 /*
  * Many independent problems in one call (Sec. 4.1: every chunk's intra-chunk

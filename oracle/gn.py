@@ -126,7 +126,7 @@ def solve(depth, intensity, intr, corr_i, corr_j, p, q, init_poses, params=None,
             dxa = solve_cholesky(Hr, gr)
             st = {}
         else:
-            dxa, st = solve_pcg(Hr, gr, params.num_pcg)
+            dxa, st = solve_pcg(Hr, gr, params.num_pcg, preconditioner=params.preconditioner)
         dx = np.zeros(6 * len(setup.free))
         dx.reshape(-1, 6)[~inert] = dxa.reshape(-1, 6)
         trace.append(en)

@@ -31,6 +31,7 @@ class Params:
     num_pcg: int = 10
     use_dense: bool = True
     use_sparse: bool = True
+    preconditioner: str = "block"   # "block": 6x6 block-Jacobi; "jacobi": the diagonal (Sec. 4.4)
 
     def dense_weight(self, k):
         """w_d for Gauss-Newton iteration k (0-based)."""

@@ -117,9 +117,19 @@ def block_jacobi_inverse(Hr):
     return Minv
 
 
-def solve_pcg(Hr, gr, iters, eps=1e-30):
-    """Block-Jacobi PCG on Hr dx = -gr from dx = 0; returns (dx, stats)."""
-    Minv = block_jacobi_inverse(Hr)
+def jacobi_inverse(Hr):
+    """The paper's Jacobi preconditioner (Sec. 4.4): the inverse of the diagonal of
+    Hr, as 6x6 diagonal blocks."""
+    d = np.diag(Hr).reshape(-1, 6)
+    if np.any(~(d > 0)):
+        raise NotPositiveDefinite("non-positive diagonal entry")
+    return np.einsum("ka,ab->kab", 1.0 / d, np.eye(6))
+
+
+def solve_pcg(Hr, gr, iters, eps=1e-30, preconditioner="block"):
+    """PCG on Hr dx = -gr from dx = 0 with the 6x6 block-Jacobi ("block") or the
+    scalar Jacobi ("jacobi") preconditioner; returns (dx, stats)."""
+    Minv = block_jacobi_inverse(Hr) if preconditioner == "block" else jacobi_inverse(Hr)
     n = Hr.shape[0] // 6
 
     def prec(r):

@@ -52,7 +52,8 @@ class bf_params(ctypes.Structure):
                 ("num_pcg", c_int32), ("accumulate", c_int32), ("pcg_storage", c_int32), ("timing", c_int32),
                 ("solve_kernel", c_int32), ("dense_threads", c_int32),
                 ("tau_dist", c_double), ("tau_normal", c_double), ("max_angle_deg", c_double),
-                ("depth_min", c_double), ("depth_max", c_double)]
+                ("depth_min", c_double), ("depth_max", c_double), ("preconditioner", c_int32),
+                ("reserved1", c_int32)]
 
 
 class bf_structure(ctypes.Structure):
@@ -86,6 +87,7 @@ _SIGS = {
     "bf_gauss_newton_batch": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                       POINTER(bf_pairs), c_int32, POINTER(c_int32), c_void_p, POINTER(bf_params),
                                       c_void_p, POINTER(c_double), POINTER(c_double)]),
+    "bf_system_matvec": (c_int, [c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32, POINTER(c_double)]),
     "bf_last_timings": (c_int, [c_void_p, POINTER(c_double)]),
 }
 
@@ -386,3 +388,13 @@ def device_batch(problems, device="cuda"):
                                   b["corr_p"], b["corr_q"], device=device)
     init = torch.as_tensor(b["init_poses"]).to(device)
     return dp, b["offsets"], init
+
+
+def bf_system_matvec(ctx, prob, x, mode):
+    """y = H x of the last assembled system (mode 0 blocks, mode 1 matrix-free sparse
+    term); returns (y, microseconds)."""
+    _need(x, torch.float64, (6 * prob.num_frames,), "x")
+    y = torch.empty_like(x)
+    us = c_double()
+    ctx._check(ctx.lib.bf_system_matvec(ctx.h, ctypes.byref(prob.corrs), _ptr(x), _ptr(y), mode, ctypes.byref(us)))
+    return y, us.value

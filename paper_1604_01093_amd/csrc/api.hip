@@ -74,6 +74,8 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
   if (prm->accumulate < 0 || prm->accumulate > 2) fail(BF_ERR_INVALID_ARG, "accumulate must be 0, 1 or 2");
   if (prm->pcg_storage != 0 && prm->pcg_storage != 1) fail(BF_ERR_INVALID_ARG, "pcg_storage must be 0 or 1");
   if (prm->solve_kernel < 0 || prm->solve_kernel > 4) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..4");
+  if (prm->preconditioner != 0 && prm->preconditioner != 1) fail(BF_ERR_INVALID_ARG, "preconditioner must be 0 or 1");
+  if (prm->reserved1 != 0) fail(BF_ERR_INVALID_ARG, "reserved1 must be 0");
   if (prm->dense_threads != 0 && prm->dense_threads != 64 && prm->dense_threads != 128 &&
       prm->dense_threads != 256 && prm->dense_threads != 512)
     fail(BF_ERR_INVALID_ARG, "dense_threads must be 0, 64, 128, 256 or 512");
@@ -113,6 +115,7 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
   Context& c = *ctx;
   c.pcg_storage = prm->pcg_storage;
   c.solve_mode = prm->solve_kernel;
+  c.precond = prm->preconditioner;
   c.have_system = false;
   ensure(c.counts, 8 * sizeof(long long));
   ensure(c.flags, sizeof(int));
@@ -265,7 +268,7 @@ void bf_destroy(bf_context* c) {
                  &c->minv32, &c->minv64, &c->rhs, &c->poses_work, &c->pcg_vec, &c->stats, &c->trace,
                  &c->cub_tmp, &c->counts, &c->flags, &c->host_pinned, &c->energy,
                  &c->pcg_partials, &c->pcg_barrier, &c->pcg_tags, &c->seg_start, &c->seg_of,
-                 &c->seg_var_ptr, &c->seg_edge_ptr};
+                 &c->seg_var_ptr, &c->seg_edge_ptr, &c->sys_poses, &c->mf_u};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
@@ -410,6 +413,10 @@ bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* fr, const 
     launch_dense(c, *in, poses, *prm, wd, true);
     launch_edge_blocks(c, poses, *prm, true);
     launch_energy(c, c.energy.as<double>());
+    ensure(c.sys_poses, sizeof(double) * 16 * fr->num_frames);
+    check_hip(hipMemcpyAsync(c.sys_poses.p, poses, sizeof(double) * 16 * fr->num_frames, hipMemcpyDeviceToDevice,
+                             c.stream), "copy poses");
+    c.sys_w_sparse = prm->use_sparse ? prm->w_sparse : 0.0;
     if (out_H || out_g) launch_export_dense(c, out_H, out_g);
     if (out_edge_blocks && c.shape.E > 0)
       check_hip(hipMemcpyAsync(out_edge_blocks, c.eblocks.p, sizeof(double) * kEdgeWords * c.shape.E,
@@ -556,6 +563,31 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* fr, const bf_i
     check_poses(c, init_poses, fr->num_frames);
     setup(ctx, fr, in, co, pairs, init_poses, prm, frame_offsets, num_problems);
     run_gauss_newton(ctx, in, prm, init_poses, out_poses, out_energy, out_trace, tm, t_start);
+  });
+}
+
+bf_status bf_system_matvec(bf_context* ctx, const bf_corrs* co, const double* x, double* y, int32_t mode,
+                           double* out_us) {
+  return guarded(ctx, [&] {
+    if (!ctx) fail(BF_ERR_INVALID_ARG, "null context");
+    Context& c = *ctx;
+    if (!c.have_system) fail(BF_ERR_INVALID_ARG, "no system: call bf_build_normal_equations first");
+    if (!x || !y) fail(BF_ERR_INVALID_ARG, "null x or y");
+    if (mode != 0 && mode != 1) fail(BF_ERR_INVALID_ARG, "mode must be 0 or 1");
+    if (mode == 1 && (!co || co->count != c.shape.M))
+      fail(BF_ERR_INVALID_ARG, "mode 1 needs the correspondences the system was built from");
+    hipEvent_t e0, e1;
+    check_hip(hipEventCreate(&e0), "hipEventCreate");
+    check_hip(hipEventCreate(&e1), "hipEventCreate");
+    check_hip(hipEventRecord(e0, c.stream), "hipEventRecord");
+    launch_matvec(c, co, c.sys_w_sparse, mode, x, y);
+    check_hip(hipEventRecord(e1, c.stream), "hipEventRecord");
+    check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (out_us) *out_us = 1000.0 * ms;
   });
 }
 

@@ -112,15 +112,28 @@ __device__ inline void exp_se3(const double xi[6], double R[9], double tv[3]) {
   for (int a = 0; a < 3; ++a) tv[a] = V[3 * a] * xi[3] + V[3 * a + 1] * xi[4] + V[3 * a + 2] * xi[5];
 }
 
-// Block-Jacobi inverse of a frame's 6x6 diagonal block, in place: 1 = inverted;
+// Preconditioner block of a frame's 6x6 diagonal block, in place: 1 = inverted;
 // 0 = the block is identically zero (no residual touches the frame at these poses),
 // A stays zero so the frame is inert in the PCG (its gradient is zero too, so its
 // increment stays zero); -1 = not positive definite.
+// With `scalar` the preconditioner is the paper's Jacobi one (Sec. 4.4): only the
+// diagonal entries, inverted one by one (a non-positive one is -1).
 __device__ inline bool spd_inverse6(double* A);
-__device__ inline int block_jacobi_inverse6(double* A) {
+__device__ inline int block_jacobi_inverse6(double* A, int scalar) {
   bool zero = true;
   for (int q = 0; q < 36; ++q) zero = zero && A[q] == 0.0;
   if (zero) return 0;
+  if (scalar) {
+    for (int q = 0; q < 36; ++q) {
+      if (q % 7 == 0) {
+        if (!(A[q] > 0.0)) return -1;
+        A[q] = 1.0 / A[q];
+      } else {
+        A[q] = 0.0;
+      }
+    }
+    return 1;
+  }
   return spd_inverse6(A) ? 1 : -1;
 }
 

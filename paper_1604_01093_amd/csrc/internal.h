@@ -47,6 +47,7 @@ struct Context {
   Shape shape;
   bool have_system = false;
   int pcg_storage = 0;
+  int precond = 0;          // 0 = 6x6 block-Jacobi, 1 = scalar Jacobi
   double timings[8] = {0};
 
   // frames
@@ -61,6 +62,9 @@ struct Context {
       iptr, jptr, free_flag, var_of, frame_of_var, row_cnt, row_ptr, row_entries;
   // per-iteration data
   Buf records, eblocks, hij32, hij64, diag32, diag64, minv32, minv64, rhs, poses_work, pcg_vec, stats, trace;
+  // the poses and sparse weight of the last assembled system; matrix-free scratch
+  Buf sys_poses, mf_u;
+  double sys_w_sparse = 0.0;
   // independent problems: frame offsets, segment of each frame, variable and edge ranges
   Buf seg_start, seg_of, seg_var_ptr, seg_edge_ptr;
   std::vector<int> seg_host;  // offsets currently on the device (seg_start, seg_of)
@@ -102,5 +106,9 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
                   bool update_poses);
 void launch_energy(Context& c, double* dst8);
 void launch_export_dense(Context& c, double* H, double* g);
+
+// matvec.hip: y = H x of the last assembled system; mode 0 from the edge blocks,
+// mode 1 the sparse term matrix-free (J^T (J x)) over the correspondences `co`.
+void launch_matvec(Context& c, const bf_corrs* co, double w_sparse, int mode, const double* x, double* y);
 
 }  // namespace bf

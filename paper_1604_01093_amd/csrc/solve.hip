@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
     const int* __restrict__ var_of, T* __restrict__ diag, T* __restrict__ minv, T* __restrict__ x,
     T* __restrict__ r, T* __restrict__ Ap, T* z, T* pb0, T* pb1, double* parts, unsigned* bar,
     double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
-    double* __restrict__ stats, int* flags) {
+    double* __restrict__ stats, int* flags, int precond) {
   __shared__ double sh[(kSolveWaves + 1) * kParts];
   __shared__ double red[kSolveWaves][64];
   __shared__ double blk[kSolveWaves][48];
@@ -408,7 +408,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
     if (lane == 0) {
       double A[36];
       for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
-      bool ok = block_jacobi_inverse6(A) >= 0;
+      bool ok = block_jacobi_inverse6(A, precond) >= 0;
       if (!ok) {
         pro[1] += 1.0;
         for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(NT) k_solve_single(
     const long long* __restrict__ row_ptr, const int2* __restrict__ entries, const int* __restrict__ frame_of_var,
     const int* __restrict__ var_of, T* __restrict__ diag_all, T* __restrict__ minv_all, int minv_in_lds,
     double* __restrict__ trace_all, double* __restrict__ delta_out, double* __restrict__ poses, int update,
-    double* __restrict__ stats_all, int* __restrict__ flags) {
+    double* __restrict__ stats_all, int* __restrict__ flags, int precond) {
   constexpr int NW = NT / 64;
   extern __shared__ double dyn[];
   __shared__ double red1024[NT];
@@ -671,7 +671,7 @@ __global__ void __launch_bounds__(NT) k_solve_single(
     if (lane == 0) {
       double A[36];
       for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
-      if (block_jacobi_inverse6(A) < 0) {
+      if (block_jacobi_inverse6(A, precond) < 0) {
         bad_sh = 1;
         for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
       }
@@ -831,7 +831,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     const long long* __restrict__ row_ptr, const int2* __restrict__ entries, const int* __restrict__ frame_of_var,
     const int* __restrict__ var_of, T* minv_sh, T* r0_sh, unsigned long long* ap_words, double* parts, unsigned* bar,
     double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
-    double* __restrict__ stats, int* flags) {
+    double* __restrict__ stats, int* flags, int precond) {
   extern __shared__ double lds_dyn[];
   __shared__ double sh[(kRepWaves + 1) * kParts];
   __shared__ double red1024[kRepThreads];
@@ -897,7 +897,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     if (lane == 0) {
       double A[36];
       for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
-      if (block_jacobi_inverse6(A) < 0) {
+      if (block_jacobi_inverse6(A, precond) < 0) {
         pro[1] += 1.0;
         for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
       }
@@ -1223,8 +1223,9 @@ void launch_solve_coop(Context& c, int iters, double* trace_slot, double* delta_
   const int* fov = c.frame_of_var.as<int>();
   const int* vof = c.var_of.as<int>();
   int* fl = c.flags.as<int>();
+  int pc = c.precond;
   void* args[] = {&nf, &F, &E, &iters, &eb, &hij, &ip, &jp, &ejs, &rp, &en, &fov, &vof, &diag, &minv, &x, &r,
-                  &Ap, &z, &pb0, &pb1, &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl};
+                  &Ap, &z, &pb0, &pb1, &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl, &pc};
   check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kSolveThreads), args, 0,
                                        c.stream),
             "cooperative solve launch");
@@ -1255,7 +1256,7 @@ bool launch_solve_single(Context& c, int iters, double* trace_slot, double* delt
                      c.eblocks.as<double>(), hij, c.iptr.as<long long>(), c.jptr.as<long long>(),
                      c.ej_sorted.as<long long>(), c.row_ptr.as<long long>(), c.row_entries.as<int2>(),
                      c.frame_of_var.as<int>(), c.var_of.as<int>(), diag, minv, minv_lds, trace_slot, delta_out, poses,
-                     update ? 1 : 0, stats, c.flags.as<int>());
+                     update ? 1 : 0, stats, c.flags.as<int>(), c.precond);
   return true;
 }
 
@@ -1305,8 +1306,9 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   const int* fov = c.frame_of_var.as<int>();
   const int* vof = c.var_of.as<int>();
   int* fl = c.flags.as<int>();
+  int pc = c.precond;
   void* args[] = {&nf, &F, &E, &iters, &eb, &hij, &ip, &jp, &ejs, &rp, &en, &fov, &vof, &minv_sh, &r0, &tags,
-                  &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl};
+                  &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl, &pc};
   check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)G), dim3(kRepThreads),
                                        args, (unsigned)lds, c.stream),
             "cooperative solve launch");

@@ -127,3 +127,26 @@ def test_gauss_newton_global200(ctx, prob, golden, pcg_storage, solve_kernel, ac
     for k, t in enumerate(out["trace"]):
         assert abs(t[0] - golden["trace"][k][0]) <= 1e-4 * golden["trace"][k][0]
     assert rot < 2e-3 and tr < 2e-3
+
+
+def test_one_step_jacobi_preconditioner(ctx, prob, golden):
+    """One step at the initial poses with the scalar Jacobi preconditioner, against
+    the oracle's (computed here: one assembly of the full system)."""
+    from oracle.gn import Setup, build_system
+    from oracle.system import inert_frames, reduce_system, solve_pcg
+    prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg, preconditioner="jacobi")
+    s = Setup(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p, prob.corr_q,
+              prob.init_poses, prm, pairs=golden["pairs"])
+    H, g, _, _ = build_system(s, prob.init_poses, prm.dense_weight(0))
+    assert not inert_frames(H, s.free).any()
+    Hr, gr, _ = reduce_system(H, g, s.free)
+    ref, _ = solve_pcg(Hr, gr, prm.num_pcg, preconditioner="jacobi")
+    dp = device_problem(prob, pairs=golden["pairs"])
+    idx = (6 * s.free[:, None] + np.arange(6)[None, :]).ravel()
+    for storage in (0, 1):
+        bf.bf_build_normal_equations(ctx, dp, poses_cuda(prob.init_poses),
+                                     bf_params_from(prm, pcg_storage=storage), gn_iter=0, dense=False)
+        delta, st = bf.bf_pcg_solve(ctx, prob.num_frames, prob.n_pcg)
+        err = float(np.abs(delta.cpu().numpy()[idx] - ref).max())
+        print(f"global200 jacobi storage={storage}: max |d increment| {err:.2e}", flush=True)
+        assert err < 1e-5

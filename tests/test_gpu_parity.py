@@ -235,3 +235,17 @@ def test_frame_without_residuals_is_held(ctx, solve_kernel):
     rot, tr = pose_errors(P, ref["poses"])
     assert rot < 1e-5 and tr < 1e-5
     assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
+
+
+@pytest.mark.parametrize("solve_kernel,pcg_storage", [(0, 0), (1, 0), (2, 0), (3, 0), (3, 1)])
+def test_gauss_newton_chunk_jacobi_preconditioner(ctx, chunk, solve_kernel, pcg_storage):
+    """The paper's scalar Jacobi preconditioner (Sec. 4.4) in every solve kernel."""
+    prm = Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg, preconditioner="jacobi")
+    ref = solve(chunk.depth, chunk.intensity, chunk.intrinsics, chunk.corr_i, chunk.corr_j, chunk.corr_p,
+                chunk.corr_q, chunk.init_poses, prm, linear="pcg")
+    out = bf.bf_gauss_newton(ctx, device_problem(chunk), poses_cuda(chunk.init_poses),
+                             bf_params_from(prm, solve_kernel=solve_kernel, pcg_storage=pcg_storage))
+    rot, tr = pose_errors(out["poses"].cpu().numpy(), ref["poses"])
+    print(f"chunk jacobi kernel={solve_kernel} storage={pcg_storage}: pose err {rot:.3e} rad {tr:.3e} m", flush=True)
+    assert rot < 1e-5 and tr < 1e-5
+    assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]

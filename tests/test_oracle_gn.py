@@ -45,6 +45,42 @@ def test_pcg_block_diagonal_one_iteration():
     assert np.allclose(x, solve_cholesky(H, g), rtol=1e-10, atol=1e-12)
 
 
+def test_jacobi_pcg_full_dimension_equals_cholesky():
+    rng = np.random.default_rng(3)
+    H = _spd(36, rng, cond=50.0)
+    g = rng.normal(size=36)
+    x, st = solve_pcg(H, g, 4 * 36, preconditioner="jacobi")
+    ref = solve_cholesky(H, g)
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_jacobi_pcg_diagonal_one_iteration():
+    """With H diagonal the Jacobi preconditioner is H^-1: one step is exact; the
+    block-diagonal H of the block-Jacobi pin is not solved in one Jacobi step."""
+    rng = np.random.default_rng(4)
+    H = np.diag(rng.uniform(0.5, 20.0, 24))
+    g = rng.normal(size=24)
+    x, st = solve_pcg(H, g, 1, preconditioner="jacobi")
+    assert st["iters"] == 1
+    assert np.allclose(x, -g / np.diag(H), rtol=1e-14, atol=0)
+    Hb = np.zeros((24, 24))
+    for k in range(4):
+        Hb[6 * k:6 * k + 6, 6 * k:6 * k + 6] = _spd(6, rng)
+    x1, _ = solve_pcg(Hb, g, 1, preconditioner="jacobi")
+    assert np.linalg.norm(x1 - solve_cholesky(Hb, g)) > 1e-3 * np.linalg.norm(x1)
+
+
+def test_gn_with_jacobi_preconditioner_converges_to_same_minimum():
+    """Both preconditioners reach the Cholesky GN result when PCG runs to
+    convergence (association frozen, noise-free chunk)."""
+    pr = make_chunk(num_frames=4, noise=False)
+    args = (pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q, pr.init_poses)
+    ref = solve(*args, Params(num_gn=6, num_pcg=10), linear="cholesky", freeze_association=True)
+    jac = solve(*args, Params(num_gn=6, num_pcg=200, preconditioner="jacobi"), linear="pcg",
+                freeze_association=True)
+    assert np.abs(jac["poses"] - ref["poses"]).max() < 1e-8
+
+
 def _sparse_only_solve(p, q, init, iters, linear="cholesky"):
     F = len(init)
     depth = np.zeros((F, 60, 80), np.float32)
