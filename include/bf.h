@@ -235,6 +235,29 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* frames, const bf_int
                           double* out_trace);
 
 /*
+ * Solve with residual pruning (Sec. 4.4.1): after each full solve (as
+ * bf_gauss_newton), the largest sparse residual |T_i p - T_j q| (metres, FP64)
+ * over the active correspondences is found (per-workgroup candidates, final
+ * maximum on the host; ties go to the smallest correspondence index).  If it
+ * exceeds r_prune, every correspondence between that correspondence's two frames
+ * is deactivated, a frame that had correspondences and has none left is marked
+ * invalid (its dense pairs are dropped, its pose is kept), and the problem is
+ * solved again from the current poses.  Stops when the largest residual is at
+ * most r_prune or after max_rounds removals.  The dense pair set is fixed in the
+ * first round (`pairs`, or the pair test at init_poses).
+ *   out_poses (device) [F][4][4]; out_energy (host) [4] of the last solve;
+ *   out_corr_active (device, may be NULL) [M] uint8: 1 = still active;
+ *   out_frame_valid (device, may be NULL) [F] uint8: 0 = removed by pruning;
+ *   out_rounds (host, may be NULL): removals done; out_rmax (host, may be NULL):
+ *   the largest active residual at the returned poses (-1 if none is active).
+ */
+bf_status bf_gauss_newton_pruned(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                                 const bf_corrs* corrs, const bf_pairs* pairs, const double* init_poses,
+                                 const bf_params* params, double r_prune, int32_t max_rounds, double* out_poses,
+                                 double* out_energy, uint8_t* out_corr_active, uint8_t* out_frame_valid,
+                                 int32_t* out_rounds, double* out_rmax);
+
+/*
  * y = H x with the J^T J matrix of the last bf_build_normal_equations() call (all
  * frames, 6F, frame 0 included), for comparing representations (Sec. 4.4):
  *   mode 0: from the assembled per-edge 6x6 blocks (what the PCG kernels use);

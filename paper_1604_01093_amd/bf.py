@@ -87,6 +87,9 @@ _SIGS = {
     "bf_gauss_newton_batch": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                       POINTER(bf_pairs), c_int32, POINTER(c_int32), c_void_p, POINTER(bf_params),
                                       c_void_p, POINTER(c_double), POINTER(c_double)]),
+    "bf_gauss_newton_pruned": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
+                                       POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_double, c_int32, c_void_p,
+                                       POINTER(c_double), c_void_p, c_void_p, POINTER(c_int32), POINTER(c_double)]),
     "bf_system_matvec": (c_int, [c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32, POINTER(c_double)]),
     "bf_last_timings": (c_int, [c_void_p, POINTER(c_double)]),
 }
@@ -398,3 +401,22 @@ def bf_system_matvec(ctx, prob, x, mode):
     us = c_double()
     ctx._check(ctx.lib.bf_system_matvec(ctx.h, ctypes.byref(prob.corrs), _ptr(x), _ptr(y), mode, ctypes.byref(us)))
     return y, us.value
+
+
+def bf_gauss_newton_pruned(ctx, prob, init_poses, params, r_prune=0.05, max_rounds=100, out_poses=None):
+    """Solve with residual pruning; returns poses, energy, masks, rounds, r_max."""
+    _poses_check(init_poses, prob.num_frames)
+    if out_poses is None:
+        out_poses = torch.empty_like(init_poses)
+    dev = init_poses.device
+    act = torch.empty((max(prob.num_corrs, 1),), dtype=torch.uint8, device=dev)
+    val = torch.empty((prob.num_frames,), dtype=torch.uint8, device=dev)
+    e = (c_double * 4)()
+    rounds = c_int32()
+    rmax = c_double()
+    ctx._check(ctx.lib.bf_gauss_newton_pruned(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr),
+                                              ctypes.byref(prob.corrs), prob._pairs_ref(), _ptr(init_poses),
+                                              ctypes.byref(params), r_prune, max_rounds, _ptr(out_poses), e,
+                                              _ptr(act), _ptr(val), ctypes.byref(rounds), ctypes.byref(rmax)))
+    return {"poses": out_poses, "energy": {"total": e[0], "sparse": e[1], "geo": e[2], "photo": e[3]},
+            "corr_active": act[:prob.num_corrs], "frame_valid": val, "rounds": rounds.value, "rmax": rmax.value}

@@ -268,7 +268,10 @@ void bf_destroy(bf_context* c) {
                  &c->minv32, &c->minv64, &c->rhs, &c->poses_work, &c->pcg_vec, &c->stats, &c->trace,
                  &c->cub_tmp, &c->counts, &c->flags, &c->host_pinned, &c->energy,
                  &c->pcg_partials, &c->pcg_barrier, &c->pcg_tags, &c->seg_start, &c->seg_of,
-                 &c->seg_var_ptr, &c->seg_edge_ptr, &c->sys_poses, &c->mf_u};
+                 &c->seg_var_ptr, &c->seg_edge_ptr, &c->sys_poses, &c->mf_u, &c->pr_active, &c->pr_cnt0,
+                 &c->pr_cnt, &c->pr_valid, &c->pr_flag, &c->pr_pos, &c->pr_fi, &c->pr_fj, &c->pr_pi, &c->pr_pj,
+                 &c->pr_pflag, &c->pr_ppos, &c->pr_pairs, &c->pr_pairs_all, &c->pr_bval, &c->pr_bidx,
+                 &c->pr_poses};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
@@ -563,6 +566,76 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* fr, const bf_i
     check_poses(c, init_poses, fr->num_frames);
     setup(ctx, fr, in, co, pairs, init_poses, prm, frame_offsets, num_problems);
     run_gauss_newton(ctx, in, prm, init_poses, out_poses, out_energy, out_trace, tm, t_start);
+  });
+}
+
+bf_status bf_gauss_newton_pruned(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
+                                 const bf_pairs* pairs, const double* init_poses, const bf_params* prm,
+                                 double r_prune, int32_t max_rounds, double* out_poses, double* out_energy,
+                                 uint8_t* out_corr_active, uint8_t* out_frame_valid, int32_t* out_rounds,
+                                 double* out_rmax) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(co, pairs, init_poses);
+    if (!co) fail(BF_ERR_INVALID_ARG, "null correspondences");
+    if (!out_poses || !out_energy) fail(BF_ERR_INVALID_ARG, "null out_poses or out_energy");
+    if (!(r_prune >= 0.0) || max_rounds < 0) fail(BF_ERR_INVALID_ARG, "bad pruning threshold or round limit");
+    Context& c = *ctx;
+    const int F = fr->num_frames;
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
+    check_poses(c, init_poses, F);
+    prune_init(c, *co, F);
+    ensure(c.pr_poses, sizeof(double) * 16 * F);
+    check_hip(hipMemcpyAsync(c.pr_poses.p, init_poses, sizeof(double) * 16 * F, hipMemcpyDeviceToDevice, c.stream),
+              "copy poses");
+    // the dense pair set is fixed by the first round (given, or found at init_poses)
+    long long P = 0;
+    if (prm->use_dense) {
+      if (pairs) {
+        P = pairs->count;
+        ensure(c.pr_pairs_all, sizeof(int) * 2 * (P + 1));
+        if (P > 0)
+          check_hip(hipMemcpyAsync(c.pr_pairs_all.p, pairs->ij, sizeof(int) * 2 * P, hipMemcpyDeviceToDevice,
+                                   c.stream), "copy pairs");
+      } else {
+        set_segments(c, F, nullptr, 1);
+        P = launch_pair_search(c, *fr, *in, init_poses, *prm);
+        ensure(c.pr_pairs_all, sizeof(int) * 2 * (P + 1));
+        if (P > 0)
+          check_hip(hipMemcpyAsync(c.pr_pairs_all.p, c.pairs.p, sizeof(int) * 2 * P, hipMemcpyDeviceToDevice,
+                                   c.stream), "copy pairs");
+      }
+    }
+    int rounds = 0;
+    double e4[4] = {0, 0, 0, 0};
+    double rmax = -1.0;
+    for (;;) {
+      bf_corrs cc = prune_active_corrs(c, *co);
+      bf_pairs pp = prune_valid_pairs(c, c.pr_pairs_all.as<int>(), P);
+      Timer tm(ctx, false);
+      setup(ctx, fr, in, &cc, &pp, c.pr_poses.as<double>(), prm);
+      run_gauss_newton(ctx, in, prm, c.pr_poses.as<double>(), c.pr_poses.as<double>(), e4, nullptr, tm, -1);
+      long long idx = -1;
+      rmax = prune_max_residual(c, *co, c.pr_poses.as<double>(), &idx);
+      if (idx < 0 || rmax <= r_prune || rounds >= max_rounds) break;
+      int ab[2];
+      check_hip(hipMemcpyAsync(&ab[0], co->frame_i + idx, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy");
+      check_hip(hipMemcpyAsync(&ab[1], co->frame_j + idx, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy");
+      check_hip(hipStreamSynchronize(c.stream), "synchronise");
+      prune_drop(c, *co, F, ab[0], ab[1]);
+      ++rounds;
+    }
+    check_hip(hipMemcpyAsync(out_poses, c.pr_poses.p, sizeof(double) * 16 * F, hipMemcpyDeviceToDevice, c.stream),
+              "copy poses");
+    if (out_corr_active && co->count > 0)
+      check_hip(hipMemcpyAsync(out_corr_active, c.pr_active.p, co->count, hipMemcpyDeviceToDevice, c.stream), "copy");
+    if (out_frame_valid)
+      check_hip(hipMemcpyAsync(out_frame_valid, c.pr_valid.p, F, hipMemcpyDeviceToDevice, c.stream), "copy");
+    check_hip(hipStreamSynchronize(c.stream), "synchronise");
+    for (int k = 0; k < 4; ++k) out_energy[k] = e4[k];
+    if (out_rounds) *out_rounds = rounds;
+    if (out_rmax) *out_rmax = rmax;
   });
 }
 

@@ -62,6 +62,10 @@ struct Context {
       iptr, jptr, free_flag, var_of, frame_of_var, row_cnt, row_ptr, row_entries;
   // per-iteration data
   Buf records, eblocks, hij32, hij64, diag32, diag64, minv32, minv64, rhs, poses_work, pcg_vec, stats, trace;
+  // residual pruning: active correspondences, frame counts and validity, compacted
+  // correspondences and pairs, reduction candidates, the round's poses
+  Buf pr_active, pr_cnt0, pr_cnt, pr_valid, pr_flag, pr_pos, pr_fi, pr_fj, pr_pi, pr_pj, pr_pflag, pr_ppos, pr_pairs,
+      pr_pairs_all, pr_bval, pr_bidx, pr_poses;
   // the poses and sparse weight of the last assembled system; matrix-free scratch
   Buf sys_poses, mf_u;
   double sys_w_sparse = 0.0;
@@ -106,6 +110,13 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
                   bool update_poses);
 void launch_energy(Context& c, double* dst8);
 void launch_export_dense(Context& c, double* H, double* g);
+
+// prune.hip: residual pruning state and steps
+void prune_init(Context& c, const bf_corrs& co, int F);
+bf_corrs prune_active_corrs(Context& c, const bf_corrs& co);
+bf_pairs prune_valid_pairs(Context& c, const int* ij, long long P);
+double prune_max_residual(Context& c, const bf_corrs& co, const double* poses, long long* idx);
+void prune_drop(Context& c, const bf_corrs& co, int F, int a, int b);
 
 // matvec.hip: y = H x of the last assembled system; mode 0 from the edge blocks,
 // mode 1 the sparse term matrix-free (J^T (J x)) over the correspondences `co`.

@@ -252,3 +252,78 @@ def test_frame_without_residuals_is_held(linear):
     others = [k for k in range(pr.num_frames) if k != f]
     assert np.abs(ra["poses"][others] - rb["poses"]).max() < 1e-10
     assert abs(ra["energy"]["total"] - rb["energy"]["total"]) <= 1e-10 * rb["energy"]["total"]
+
+
+def _corrupt_pairs(pr, shifts):
+    """Move the q point of every correspondence of the given pairs by a fixed
+    offset (metres along x of camera j): whole frame pairs of gross outliers."""
+    import copy
+    q = copy.copy(pr)
+    q.corr_q = pr.corr_q.copy()
+    for (a, b), d in shifts.items():
+        m = ((pr.corr_i == a) & (pr.corr_j == b)) | ((pr.corr_i == b) & (pr.corr_j == a))
+        q.corr_q[m, 0] += d
+    return q
+
+
+def test_pruning_removes_exactly_the_corrupted_pairs():
+    """Noise-free chunk with two frame pairs of gross outliers: pruning removes
+    those two pairs and nothing else, the largest remaining residual is tiny, and
+    the poses return to ground truth; without pruning they do not."""
+    from oracle.prune import residual_norms, solve_pruned
+    pr = make_chunk(num_frames=6, noise=False, outlier_rate=0.0)
+    bad = {(1, 3): 0.6, (2, 4): 0.35}
+    c = _corrupt_pairs(pr, bad)
+    prm = Params(num_gn=8, num_pcg=30, use_dense=False, dense_ramp=False)
+    args = (c.depth, c.intensity, c.intrinsics, c.corr_i, c.corr_j, c.corr_p, c.corr_q, c.init_poses, prm)
+    out = solve_pruned(*args, r_prune=0.05, max_rounds=10)
+    assert sorted(out["removed"]) == sorted(bad)
+    assert out["rmax"] < 1e-6
+    assert out["valid"].all()
+    err = np.abs(out["poses"] - pr.gt_poses).max()
+    plain = solve(*args, linear="pcg")
+    assert err < 1e-6 < np.abs(plain["poses"] - pr.gt_poses).max()
+    # the residual helper against a per-correspondence loop
+    r = residual_norms(pr.gt_poses, pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q)
+    k = 17
+    Ti, Tj = pr.gt_poses[pr.corr_i[k]], pr.gt_poses[pr.corr_j[k]]
+    d = (Ti[:3, :3] @ pr.corr_p[k].astype(float) + Ti[:3, 3]) - (Tj[:3, :3] @ pr.corr_q[k].astype(float) + Tj[:3, 3])
+    assert abs(r[k] - np.sqrt(d @ d)) < 1e-15
+
+
+def _scramble_frame(pr, f, scale, seed):
+    """Random offsets (uniform, +-scale metres) on the points of frame f in all its
+    correspondences: no pose of f explains any of its pairs."""
+    import copy
+    q = copy.copy(pr)
+    rng = np.random.default_rng(seed)
+    q.corr_p, q.corr_q = pr.corr_p.copy(), pr.corr_q.copy()
+    mi, mj = pr.corr_i == f, pr.corr_j == f
+    q.corr_p[mi] += rng.uniform(-scale, scale, size=(mi.sum(), 3)).astype(np.float32)
+    q.corr_q[mj] += rng.uniform(-scale, scale, size=(mj.sum(), 3)).astype(np.float32)
+    return q
+
+
+def test_pruning_invalidates_frames_left_without_correspondences():
+    from oracle.prune import solve_pruned
+    pr = make_chunk(num_frames=5, noise=False, outlier_rate=0.0)
+    f = 4
+    bad = {(o, f): None for o in range(4)}
+    c = _scramble_frame(pr, f, 0.5, 8)
+    prm = Params(num_gn=6, num_pcg=30, use_dense=False, dense_ramp=False)
+    out = solve_pruned(c.depth, c.intensity, c.intrinsics, c.corr_i, c.corr_j, c.corr_p, c.corr_q, c.init_poses,
+                       prm, r_prune=0.05, max_rounds=20)
+    assert not out["valid"][f] and out["valid"][:f].all()
+    assert sorted(out["removed"]) == sorted(bad)
+    assert np.abs(out["poses"][:f] - pr.gt_poses[:f]).max() < 1e-6
+
+
+def test_pruning_with_no_rounds_is_the_plain_solve():
+    from oracle.prune import solve_pruned
+    pr = make_chunk(num_frames=4)
+    prm = Params(num_gn=3, num_pcg=10)
+    args = (pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q, pr.init_poses, prm)
+    out = solve_pruned(*args, r_prune=0.05, max_rounds=0)
+    plain = solve(*args, linear="pcg")
+    assert out["removed"] == []
+    assert np.array_equal(out["poses"], plain["poses"])
