@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--preconditioner", type=int, default=0, help="0 = 6x6 block-Jacobi, 1 = scalar Jacobi")
     ap.add_argument("--workload", choices=["global200", "global2000"], default="global200",
                     help="global2000: the 2000-keyframe floor (8 GN x 20 PCG); only the solve is measured")
+    ap.add_argument("--prune-rounds", type=int, default=0,
+                    help="also time one solve with residual pruning (threshold 0.05 m) limited to this many removals")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=300)
@@ -244,6 +246,16 @@ def main():
         "phase_us_per_step": {n: round(v, 1) for n, v in zip(
             ["setup", "dense", "edges", "assemble", "pcg", "final", "total"], phase[:7])},
     }
+    if args.prune_rounds > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr = bf.bf_gauss_newton_pruned(ctx, dp, init, params, r_prune=0.05, max_rounds=args.prune_rounds)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        line["pruning"] = {"rounds": pr["rounds"], "seconds": round(dt, 4),
+                           "ms_per_solve": round(1e3 * dt / (pr["rounds"] + 1), 3), "r_max": pr["rmax"],
+                           "corr_active": int(pr["corr_active"].sum().item())}
+        log(f"pruning: {pr['rounds']} removals in {dt * 1e3:.1f} ms, r_max {pr['rmax']:.4f} m")
     if chunks is not None:
         line["batched"] = batched(bf, ctx, chunks, args.batched_steps)
     if pool is not None:
