@@ -235,6 +235,24 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* frames, const bf_int
                           double* out_trace);
 
 /*
+ * Dense two-sided verification of frame pairs (Sec. 4.1.1, "Dense Verification"),
+ * e.g. of every pair of a chunk after its solve.  For each pair (i, j) and the
+ * relative transform of `poses`, each pixel of i with a valid normal is associated
+ * with the nearest pixel of j as in the dense term (FP32 decisions, tau_dist and
+ * tau_normal of `params`) and must also satisfy |C_i(x,y) - C_j(x',y')| < tau_c
+ * (intensities of `frames`); the re-projection errors |T_ji p - q| of the valid
+ * associations are summed; likewise from j to i.  A pair is valid when in both
+ * directions at least min_frac * W * H associations are valid and their mean
+ * error is at most max_err (the paper: tau_c = 0.1, max_err = 0.075 m, min_frac =
+ * 0.02).  Pairs need not be sorted; i != j, both in range.
+ *   out_stats (device) [P][4] float64: error sum and count of i->j, then of j->i;
+ *   out_valid (device) [P] uint8.  Synchronises the stream.
+ */
+bf_status bf_verify_pairs(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                          const bf_pairs* pairs, const double* poses, const bf_params* params, double tau_c,
+                          double max_err, double min_frac, double* out_stats, uint8_t* out_valid);
+
+/*
  * Solve with residual pruning (Sec. 4.4.1): after each full solve (as
  * bf_gauss_newton), the largest sparse residual |T_i p - T_j q| (metres, FP64)
  * over the active correspondences is found (per-workgroup candidates, final

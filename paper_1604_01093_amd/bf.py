@@ -90,6 +90,8 @@ _SIGS = {
     "bf_gauss_newton_pruned": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                        POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_double, c_int32, c_void_p,
                                        POINTER(c_double), c_void_p, c_void_p, POINTER(c_int32), POINTER(c_double)]),
+    "bf_verify_pairs": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_pairs), c_void_p,
+                                POINTER(bf_params), c_double, c_double, c_double, c_void_p, c_void_p]),
     "bf_system_matvec": (c_int, [c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32, POINTER(c_double)]),
     "bf_last_timings": (c_int, [c_void_p, POINTER(c_double)]),
 }
@@ -420,3 +422,18 @@ def bf_gauss_newton_pruned(ctx, prob, init_poses, params, r_prune=0.05, max_roun
                                               _ptr(act), _ptr(val), ctypes.byref(rounds), ctypes.byref(rmax)))
     return {"poses": out_poses, "energy": {"total": e[0], "sparse": e[1], "geo": e[2], "photo": e[3]},
             "corr_active": act[:prob.num_corrs], "frame_valid": val, "rounds": rounds.value, "rmax": rmax.value}
+
+
+def bf_verify_pairs(ctx, prob, pairs, poses, params, tau_c=0.1, max_err=0.075, min_frac=0.02):
+    """Two-sided dense verification of the pairs [P,2] (device int32); returns
+    (stats [P,4] float64, valid [P] bool)."""
+    _poses_check(poses, prob.num_frames)
+    _need(pairs, torch.int32, name="pairs")
+    P = pairs.shape[0]
+    stats = torch.empty((max(P, 1), 4), dtype=torch.float64, device=poses.device)
+    valid = torch.empty((max(P, 1),), dtype=torch.uint8, device=poses.device)
+    bp = bf_pairs(P, _ptr(pairs) if P else None)
+    ctx._check(ctx.lib.bf_verify_pairs(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr), ctypes.byref(bp),
+                                       _ptr(poses), ctypes.byref(params), tau_c, max_err, min_frac, _ptr(stats),
+                                       _ptr(valid)))
+    return stats[:P], valid[:P].bool()

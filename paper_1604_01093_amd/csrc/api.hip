@@ -48,6 +48,13 @@ __global__ void k_check_poses(const double* __restrict__ poses, int F, int* __re
   if (k < F * 16 && !isfinite(poses[k])) raise_flag(flags, kFlagNonFinite);
 }
 
+__global__ void k_check_pair_range(const int* __restrict__ ij, long long P, int F, int* __restrict__ flags) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  const int i = ij[2 * k], j = ij[2 * k + 1];
+  if (!(i >= 0 && i < F && j >= 0 && j < F && i != j)) raise_flag(flags, kFlagBadIndex);
+}
+
 __global__ void k_copy_if_ok(const double* __restrict__ src, double* __restrict__ dst, int n,
                              const int* __restrict__ flags) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -566,6 +573,39 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* fr, const bf_i
     check_poses(c, init_poses, fr->num_frames);
     setup(ctx, fr, in, co, pairs, init_poses, prm, frame_offsets, num_problems);
     run_gauss_newton(ctx, in, prm, init_poses, out_poses, out_energy, out_trace, tm, t_start);
+  });
+}
+
+bf_status bf_verify_pairs(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_pairs* pairs,
+                          const double* poses, const bf_params* prm, double tau_c, double max_err, double min_frac,
+                          double* out_stats, uint8_t* out_valid) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(nullptr, pairs, poses);
+    if (!pairs) fail(BF_ERR_INVALID_ARG, "null pairs");
+    if (!(tau_c >= 0.0) || !(max_err >= 0.0) || !(min_frac >= 0.0)) fail(BF_ERR_INVALID_ARG, "bad thresholds");
+    if (pairs->count > 0 && (!out_stats || !out_valid)) fail(BF_ERR_INVALID_ARG, "null outputs");
+    Context& c = *ctx;
+    const int F = fr->num_frames;
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
+    check_poses(c, poses, F);
+    if (pairs->count > 0)
+      hipLaunchKernelGGL(k_check_pair_range, dim3((unsigned)((pairs->count + 255) / 256)), dim3(256), 0, c.stream,
+                         pairs->ij, (long long)pairs->count, F, c.flags.as<int>());
+    int hf = 0;
+    sync_and_flags(c, &hf);
+    raise_flags(hf);
+    size_t HW = (size_t)in->width * in->height;
+    ensure(c.nd, sizeof(float4) * HW * F);
+    ensure(c.grad, sizeof(float) * HW * F);
+    ensure(c.kx, sizeof(float) * in->width);
+    ensure(c.ky, sizeof(float) * in->height);
+    ensure(c.kx64, sizeof(double) * in->width);
+    ensure(c.ky64, sizeof(double) * in->height);
+    launch_prepare(c, *fr, *in, *prm);
+    launch_verify(c, *fr, *in, pairs->ij, pairs->count, poses, *prm, tau_c, max_err, min_frac, out_stats, out_valid);
+    check_hip(hipStreamSynchronize(c.stream), "synchronise");
   });
 }
 

@@ -111,6 +111,11 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
 void launch_energy(Context& c, double* dst8);
 void launch_export_dense(Context& c, double* H, double* g);
 
+// verify.hip: two-sided dense verification of frame pairs (frames prepared)
+void launch_verify(Context& c, const bf_frames& fr, const bf_intrinsics& in, const int* pairs, long long P,
+                   const double* poses, const bf_params& prm, double tau_c, double max_err, double min_frac,
+                   double* stats, uint8_t* valid);
+
 // prune.hip: residual pruning state and steps
 void prune_init(Context& c, const bf_corrs& co, int F);
 bf_corrs prune_active_corrs(Context& c, const bf_corrs& co);
