@@ -43,9 +43,9 @@ def test_verify_chunk(ctx):
     pairs = [(i, j) for i in range(F) for j in range(i + 1, F)]
     ok0 = _check(ctx, prob, pairs, prob.gt_poses)
     bad = prob.gt_poses.copy()
-    bad[5, :3, 3] += np.array([0.0, 0.2, 0.0])
+    bad[5, :3, 3] += np.array([0.25, 0.0, 0.25])
     ok1 = _check(ctx, prob, pairs + [(5, 2)], bad)
-    print(f"chunk: {ok0.sum()}/{len(pairs)} valid at ground truth, {ok1.sum()} with frame 5 moved 20 cm", flush=True)
+    print(f"chunk: {ok0.sum()}/{len(pairs)} valid at ground truth, {ok1.sum()} with frame 5 moved 35 cm", flush=True)
     assert ok0.sum() > ok1[:len(pairs)].sum()
 
 
