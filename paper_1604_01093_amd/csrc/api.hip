@@ -152,6 +152,7 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
 void sync_and_flags(Context& c, int* hf) {
   check_hip(hipMemcpyAsync(hf, c.flags.p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy flags");
   check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  if (*hf & kFlagTimeout) c.pcg_tags_dirty = true;  // a solve stopped early: clear its exchange state
 }
 
 void raise_flags(int fl) {

@@ -314,7 +314,7 @@ __device__ __forceinline__ bool grid_sync(unsigned* ctr, unsigned target, int* f
 // (fixed trees: lanes, then wavefronts in order, then workgroups in order).
 template <int K, int NW = kSolveWaves>
 __device__ void grid_sums(double (&v)[K], double* parts, unsigned* bar, unsigned& nbar, int* flags, double* sh,
-                          int* sh_ok) {
+                          int* sh_ok, unsigned bar_base = 0u) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -333,7 +333,7 @@ __device__ void grid_sums(double (&v)[K], double* parts, unsigned* bar, unsigned
     st_shared(&pb[blockIdx.x * kParts + threadIdx.x], t);
   }
   ++nbar;
-  grid_sync(bar, nbar * gridDim.x, flags, sh_ok);
+  grid_sync(bar, bar_base + nbar * gridDim.x, flags, sh_ok);
   if (wave == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -576,8 +576,58 @@ __device__ double block_sum(double v, double* red) {
 
 __device__ __forceinline__ double block_sum1024(double v, double* red1024) { return block_sum<1024>(v, red1024); }
 
+// Sum over the 64 lanes of a wavefront in FP64, returned to every lane: four DPP
+// steps inside each row of 16 lanes (swap neighbours, swap pairs, mirror within
+// 8, mirror within 16; each lane adds the same two values in the other order as
+// its partner, so all lanes agree), then two exchanges across rows.  Fixed order.
+__device__ __forceinline__ double dpp_d(double v, int ctrl_id) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+  switch (ctrl_id) {
+    case 0:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+      break;
+    case 1:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+      break;
+    case 2:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false);
+      break;
+    default:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false);
+      break;
+  }
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_d(v, 0);
+  v += dpp_d(v, 1);
+  v += dpp_d(v, 2);
+  v += dpp_d(v, 3);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
 // Deterministic workgroup sum: fixed butterfly per wavefront (lane 0's result),
 // then the NW wavefront sums in order; every thread returns the same value.
+template <int NW>
+__device__ __forceinline__ double block_sum_dpp(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum_d(v);
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < NW; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
 template <int NW>
 __device__ __forceinline__ double block_sum_w(double v, double* sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -831,7 +881,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     const long long* __restrict__ row_ptr, const int2* __restrict__ entries, const int* __restrict__ frame_of_var,
     const int* __restrict__ var_of, T* minv_sh, T* r0_sh, unsigned long long* ap_words, double* parts, unsigned* bar,
     double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
-    double* __restrict__ stats, int* flags, int precond) {
+    double* __restrict__ stats, int* flags, int precond, unsigned tag_base, unsigned bar_base) {
   extern __shared__ double lds_dyn[];
   __shared__ double sh[(kRepWaves + 1) * kParts];
   __shared__ double red1024[kRepThreads];
@@ -843,6 +893,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   T* p = z + n;
   T* ap = p + n;
   T* minv = ap + n;
+  T* r2 = minv + 36 * nfree;  // the residual alternates between r and r2
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long long v = (long long)blockIdx.x * kRepWaves + wave;  // owned row (if < nfree)
   const bool owner = v < nfree;
@@ -907,7 +958,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   if (trace_slot)
     for (long long e = (long long)blockIdx.x * kRepThreads + tid; e < E; e += (long long)gridDim.x * kRepThreads)
       for (int q = 0; q < 6; ++q) pro[2 + q] += eb[(size_t)e * kEdgeWords + kEEs + q];
-  grid_sums<8, kRepWaves>(pro, parts, bar, nbar, flags, sh, &sh_ok);
+  grid_sums<8, kRepWaves>(pro, parts, bar, nbar, flags, sh, &sh_ok, bar_base);
   const bool bad = pro[1] > 0.0;
   if (blockIdx.x == 0 && tid == 0) {
     if (bad) atomicOr(flags, kFlagNotPD);
@@ -937,7 +988,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   int done = 0;
   for (int k = 0; k < iters && !bad && sh_ok; ++k) {
     if (rz <= 1e-30) break;
-    const unsigned tag = (unsigned)k + 1u;
+    const unsigned tag = tag_base + (unsigned)k + 1u;
     constexpr int WPV = sizeof(T) / 4;  // 32-bit halves per value, each published with the tag
     unsigned long long* apw = ap_words + (size_t)(k & 1) * n * WPV;
     // A: owners compute (A p)_v from register blocks and the LDS copy of p, publish it
@@ -977,11 +1028,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
       }
       double tot[6];
 #pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        double t = (double)acc[b];
-        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-        tot[b] = t;
-      }
+      for (int b = 0; b < 6; ++b) tot[b] = wave_sum_d((double)acc[b]);
       if (lane < 6 * WPV) {
         // lane b*WPV + h publishes half h of value b: (tag << 32) | bits
         const int b = lane / WPV, h = lane % WPV;
@@ -1036,35 +1083,36 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
       __syncthreads();
       for (long long o = tid; o < n; o += kRepThreads) part += (double)p[o] * (double)ap[o];
     }
-    const double pAp = block_sum_w<kRepWaves>(part, sh);
+    const double pAp = block_sum_dpp<kRepWaves>(part, sh);
     if (!sh_ok) break;
     const double alpha = rz / pAp;
     if (owner && lane < 6) xo = (T)((double)xo + alpha * (double)p[6 * v + lane]);
+    // r' = r - alpha A p and z = M^-1 r', one element (row w, component a) per
+    // thread: each thread recomputes its row's six r' values, so the new residual
+    // goes to the other buffer without a barrier
+    T* rc = (k & 1) ? r2 : r;
+    T* rn = (k & 1) ? r : r2;
     part = 0.0;
-    for (long long w = tid; w < nfree; w += kRepThreads) {
-      double rw[6];
+    for (long long o = tid; o < n; o += kRepThreads) {
+      const long long w = o / 6;
+      const int a = (int)(o - 6 * w);
+      double s2 = 0.0, ra = 0.0;
 #pragma unroll
       for (int b = 0; b < 6; ++b) {
-        rw[b] = (double)(T)((double)r[6 * w + b] - alpha * (double)ap[6 * w + b]);
-        r[6 * w + b] = (T)rw[b];
+        const double rb = (double)(T)((double)rc[6 * w + b] - alpha * (double)ap[6 * w + b]);
+        s2 += (double)minv[w * 36 + 6 * a + b] * rb;
+        if (b == a) ra = rb;
       }
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        double s2 = 0.0;
-#pragma unroll
-        for (int b = 0; b < 6; ++b) s2 += (double)minv[w * 36 + 6 * a + b] * rw[b];
-        const T zt = (T)s2;
-        z[6 * w + a] = zt;
-        part += rw[a] * (double)zt;
-      }
+      rn[o] = (T)ra;
+      const T zt = (T)s2;
+      z[o] = zt;
+      part += ra * (double)zt;
     }
-    const double rz_new = block_sum_w<kRepWaves>(part, sh);
+    const double rz_new = block_sum_dpp<kRepWaves>(part, sh);
     const double beta = rz_new / rz;
     rz = rz_new;
     ++done;
-    for (long long w = tid; w < nfree; w += kRepThreads)
-#pragma unroll
-      for (int b = 0; b < 6; ++b) p[6 * w + b] = (T)((double)z[6 * w + b] + beta * (double)p[6 * w + b]);
+    for (long long o = tid; o < n; o += kRepThreads) p[o] = (T)((double)z[o] + beta * (double)p[o]);
     __syncthreads();
   }
   // epilogue: owners publish dx and update their poses
@@ -1204,6 +1252,7 @@ void launch_solve_coop(Context& c, int iters, double* trace_slot, double* delta_
   ensure(c.pcg_partials, sizeof(double) * 2 * kParts * kMaxSolveGroups);
   ensure(c.pcg_barrier, sizeof(unsigned) * 4);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c.stream, c.pcg_barrier.as<unsigned>());
+  c.pcg_tags_dirty = true;  // the barrier counter no longer matches the replicated kernel's running count
   T* x = vec;
   T* r = vec + n;
   T* z = vec + 2 * n;
@@ -1269,7 +1318,7 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   long long nf = c.shape.nfree;
   long long n = 6 * nf;
   long long E = c.shape.E;
-  const size_t lds = sizeof(T) * (4 * (size_t)n + 36 * (size_t)nf);
+  const size_t lds = sizeof(T) * (5 * (size_t)n + 36 * (size_t)nf);
   if (lds > kRepLdsMax) return false;
   auto kern = k_solve_rep<T>;
   static bool attr_set[2] = {false, false};
@@ -1287,11 +1336,26 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   if (per_cu < 1 || G > (long long)per_cu * c.num_cus || G > kMaxSolveGroups) return false;
   ensure(c.pcg_partials, sizeof(double) * 2 * kParts * kMaxSolveGroups);
   ensure(c.pcg_barrier, sizeof(unsigned) * 4);
+  // Exchange words carry an iteration tag that grows across launches, and the
+  // barrier counter only grows, so consecutive launches need no clearing: the
+  // buffer is zeroed when it is (re)allocated, after an error, or before a tag
+  // would wrap.
   const long long nwords = 2 * n * (long long)(sizeof(T) / 4);
   ensure(c.pcg_tags, sizeof(unsigned long long) * (size_t)(nwords + 1));
   unsigned long long* tags = c.pcg_tags.as<unsigned long long>();
-  hipLaunchKernelGGL(k_zero_tags, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, c.stream, tags, nwords,
-                     c.pcg_barrier.as<unsigned>());
+  const unsigned long long tag_end = (unsigned long long)c.pcg_tag_base + (unsigned long long)iters + 1ull;
+  const unsigned long long bar_end = (unsigned long long)c.pcg_bar_base + (unsigned long long)G;
+  if (c.pcg_tags_dirty || c.pcg_tags_ptr != c.pcg_tags.p || tag_end >= 0xffffffffull || bar_end >= 0xffffffffull) {
+    hipLaunchKernelGGL(k_zero_tags, dim3((unsigned)((c.pcg_tags.cap / 8 + 255) / 256)), dim3(256), 0, c.stream, tags,
+                       (long long)(c.pcg_tags.cap / 8), c.pcg_barrier.as<unsigned>());
+    c.pcg_tag_base = 0;
+    c.pcg_bar_base = 0;
+    c.pcg_tags_ptr = c.pcg_tags.p;
+    c.pcg_tags_dirty = false;
+  }
+  unsigned tag_base = c.pcg_tag_base, bar_base = c.pcg_bar_base;
+  c.pcg_tag_base += (unsigned)iters + 1u;
+  c.pcg_bar_base += (unsigned)G;
   T* r0 = vec;
   double* parts = c.pcg_partials.as<double>();
   unsigned* bar = c.pcg_barrier.as<unsigned>();
@@ -1308,7 +1372,7 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   int* fl = c.flags.as<int>();
   int pc = c.precond;
   void* args[] = {&nf, &F, &E, &iters, &eb, &hij, &ip, &jp, &ejs, &rp, &en, &fov, &vof, &minv_sh, &r0, &tags,
-                  &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl, &pc};
+                  &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl, &pc, &tag_base, &bar_base};
   check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)G), dim3(kRepThreads),
                                        args, (unsigned)lds, c.stream),
             "cooperative solve launch");
