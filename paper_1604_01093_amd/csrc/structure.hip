@@ -401,41 +401,68 @@ __global__ void k_free_write(const long long* __restrict__ free_flag, const long
 }
 
 // Per free frame (PCG row): number of incident edges whose other frame is free.
-__global__ void k_row_count(const long long* __restrict__ iptr, const long long* __restrict__ jptr,
-                            const long long* __restrict__ ej_sorted, const int* __restrict__ eij,
-                            const int* __restrict__ var_of, const int* __restrict__ frame_of_var, long long nfree,
-                            long long* __restrict__ cnt) {
-  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v > nfree) return;
+// One wavefront per row, lanes over the incident edges.
+__global__ void __launch_bounds__(64) k_row_count(const long long* __restrict__ iptr,
+                                                  const long long* __restrict__ jptr,
+                                                  const long long* __restrict__ ej_sorted,
+                                                  const int* __restrict__ eij, const int* __restrict__ var_of,
+                                                  const int* __restrict__ frame_of_var, long long nfree,
+                                                  long long* __restrict__ cnt) {
+  const long long v = blockIdx.x;
+  const int lane = threadIdx.x;
   if (v == nfree) {
-    cnt[v] = 0;
+    if (lane == 0) cnt[v] = 0;
     return;
   }
-  int f = frame_of_var[v];
+  const int f = frame_of_var[v];
   long long n = 0;
-  for (long long k = iptr[f]; k < iptr[f + 1]; ++k) n += var_of[eij[2 * k + 1]] >= 0 ? 1 : 0;
-  for (long long k = jptr[f]; k < jptr[f + 1]; ++k) n += var_of[eij[2 * ej_sorted[k]]] >= 0 ? 1 : 0;
-  cnt[v] = n;
+  for (long long k = iptr[f] + lane; k < iptr[f + 1]; k += 64) n += var_of[eij[2 * k + 1]] >= 0 ? 1 : 0;
+  for (long long k = jptr[f] + lane; k < jptr[f + 1]; k += 64) n += var_of[eij[2 * ej_sorted[k]]] >= 0 ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+  if (lane == 0) cnt[v] = n;
 }
 
-// Row entries (partner variable, 2*edge + transposed) in incidence order.
-__global__ void k_row_fill(const long long* __restrict__ iptr, const long long* __restrict__ jptr,
-                           const long long* __restrict__ ej_sorted, const int* __restrict__ eij,
-                           const int* __restrict__ var_of, const int* __restrict__ frame_of_var, long long nfree,
-                           const long long* __restrict__ row_ptr, int2* __restrict__ entries) {
-  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// Row entries (partner variable, 2*edge+transposed) in incidence order: one
+// wavefront per row, positions from a ballot prefix over each 64-edge chunk.
+__global__ void __launch_bounds__(64) k_row_fill(const long long* __restrict__ iptr,
+                                                 const long long* __restrict__ jptr,
+                                                 const long long* __restrict__ ej_sorted,
+                                                 const int* __restrict__ eij, const int* __restrict__ var_of,
+                                                 const int* __restrict__ frame_of_var, long long nfree,
+                                                 const long long* __restrict__ row_ptr, int2* __restrict__ entries) {
+  const long long v = blockIdx.x;
   if (v >= nfree) return;
-  int f = frame_of_var[v];
+  const int lane = threadIdx.x;
+  const int f = frame_of_var[v];
   long long o = row_ptr[v];
-  for (long long k = iptr[f]; k < iptr[f + 1]; ++k) {
-    int w = var_of[eij[2 * k + 1]];
-    if (w >= 0) entries[o++] = make_int2(w, (int)(2 * k));
+  for (int side = 0; side < 2; ++side) {
+    const long long k0 = side == 0 ? iptr[f] : jptr[f], k1 = side == 0 ? iptr[f + 1] : jptr[f + 1];
+    for (long long kb = k0; kb < k1; kb += 64) {
+      const long long k = kb + lane;
+      int w = -1;
+      long long e = 0;
+      if (k < k1) {
+        e = side == 0 ? k : ej_sorted[k];
+        w = var_of[side == 0 ? eij[2 * e + 1] : eij[2 * e]];
+      }
+      const bool keep = w >= 0;
+      const unsigned long long mask = __ballot(keep);
+      const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+      if (keep) entries[o + rank] = make_int2(w, (int)(2 * e + side));
+      o += __popcll(mask);
+    }
   }
-  for (long long k = jptr[f]; k < jptr[f + 1]; ++k) {
-    long long e = ej_sorted[k];
-    int w = var_of[eij[2 * e]];
-    if (w >= 0) entries[o++] = make_int2(w, (int)(2 * e + 1));
-  }
+}
+
+// 1 in *flag if the correspondence keys are not in non-decreasing order.
+__global__ void k_keys_unsorted(const long long* __restrict__ key, long long M, int* __restrict__ flag) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > 0 && c < M && key[c] < key[c - 1]) *flag = 1;
+}
+
+__global__ void k_copy_ll(const long long* __restrict__ a, long long n, long long* __restrict__ o) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) o[k] = a[k];
 }
 
 inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -455,8 +482,11 @@ void raise_device_flags(int fl) {
 
 }  // namespace
 
-int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics& in, const double* poses,
-                           const bf_params& prm) {
+// Pair search in two halves around one host synchronisation: the first launches
+// the per-row tests and the scan (the count ends up in row_off[F]), the second
+// compacts the pairs once the count is known on the host.
+void pair_search_begin(Context& c, const bf_frames& fr, const bf_intrinsics& in, const double* poses,
+                       const bf_params& prm) {
   const int F = fr.num_frames;
   ensure(c.pair_flags, (size_t)F * F);
   ensure(c.row_count, sizeof(long long) * (F + 1));
@@ -472,13 +502,25 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
   cub_call(c, [&](void* t, size_t& b) {
     return hipcub::DeviceScan::ExclusiveSum(t, b, rc, ro, F + 1, c.stream);
   });
-  long long P = 0;
-  check_hip(hipMemcpyAsync(&P, ro + F, sizeof(long long), hipMemcpyDeviceToHost, c.stream), "copy pair count");
-  check_hip(hipStreamSynchronize(c.stream), "synchronise");
+}
+
+void pair_search_finish(Context& c, int F, long long P) {
   ensure(c.pairs, sizeof(int) * 2 * (P + 1));
   ensure(c.pair_keys, sizeof(long long) * (P + 1));
-  hipLaunchKernelGGL(k_pair_compact, dim3(F), dim3(256), 0, c.stream, c.pair_flags.as<uint8_t>(), ro, F,
-                     c.seg_of.as<int>(), c.seg_start.as<int>(), c.pairs.as<int>(), c.pair_keys.as<long long>());
+  hipLaunchKernelGGL(k_pair_compact, dim3(F), dim3(256), 0, c.stream, c.pair_flags.as<uint8_t>(),
+                     c.row_off.as<long long>(), F, c.seg_of.as<int>(), c.seg_start.as<int>(), c.pairs.as<int>(),
+                     c.pair_keys.as<long long>());
+}
+
+int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics& in, const double* poses,
+                           const bf_params& prm) {
+  const int F = fr.num_frames;
+  pair_search_begin(c, fr, in, poses, prm);
+  long long P = 0;
+  check_hip(hipMemcpyAsync(&P, c.row_off.as<long long>() + F, sizeof(long long), hipMemcpyDeviceToHost, c.stream),
+            "copy pair count");
+  check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  pair_search_finish(c, F, P);
   return P;
 }
 
@@ -533,7 +575,9 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
   ensure(c.ky64, sizeof(double) * in.height);
   launch_prepare(c, fr, in, prm);
 
-  // a2: dense pairs
+  // a2: dense pairs (the search's count is read together with the correspondence
+  // check below, in one host synchronisation)
+  const bool search = prm.use_dense && !pairs;
   if (!prm.use_dense) {
     sh.P = 0;
     ensure(c.pairs, 8);
@@ -546,10 +590,11 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
       hipLaunchKernelGGL(k_pairs_check, dim3(blocks_for(sh.P)), dim3(256), 0, c.stream, pairs->ij, (long long)sh.P, F,
                          c.seg_of.as<int>(), c.pairs.as<int>(), c.pair_keys.as<long long>(), c.flags.as<int>());
   } else {
-    sh.P = launch_pair_search(c, fr, in, poses, prm);
+    pair_search_begin(c, fr, in, poses, prm);
   }
 
-  // correspondences: keys, stable sort, groups
+  // correspondences: keys; a stable sort groups them by frame pair -- skipped when
+  // they already arrive grouped in key order (the sort would be the identity)
   const long long M = (prm.use_sparse && co) ? co->count : 0;
   sh.M = M;
   ensure(c.corr_key, sizeof(long long) * (M + 1));
@@ -565,14 +610,36 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
     hipLaunchKernelGGL(k_corr_keys, dim3(blocks_for(M)), dim3(256), 0, c.stream, co->frame_i, co->frame_j, co->p_i,
                        co->p_j, M, F, c.seg_of.as<int>(), c.corr_key.as<long long>(), c.corr_idx.as<long long>(),
                        c.flags.as<int>());
-    int endbit = bits_for((uint64_t)F * (uint64_t)F);
-    long long* k_in = c.corr_key.as<long long>();
+    hipLaunchKernelGGL(k_keys_unsorted, dim3(blocks_for(M)), dim3(256), 0, c.stream, c.corr_key.as<long long>(), M,
+                       reinterpret_cast<int*>(c.counts.as<long long>() + 7));
+  }
+  long long hc0[8];
+  int hf0 = 0;
+  long long P_found = 0;
+  if (search)
+    check_hip(hipMemcpyAsync(&P_found, c.row_off.as<long long>() + F, sizeof(long long), hipMemcpyDeviceToHost,
+                             c.stream), "copy pair count");
+  read_counts(c, hc0, &hf0);
+  raise_device_flags(hf0);
+  const bool unsorted = hc0[7] != 0;
+  if (search) {
+    sh.P = P_found;
+    pair_search_finish(c, F, P_found);
+  }
+  if (M > 0) {
     long long* k_out = c.corr_key_sorted.as<long long>();
-    long long* v_in = c.corr_idx.as<long long>();
     long long* v_out = c.corr_perm.as<long long>();
-    cub_call(c, [&](void* t, size_t& b) {
-      return hipcub::DeviceRadixSort::SortPairs(t, b, k_in, k_out, v_in, v_out, (int)M, 0, endbit, c.stream);
-    });
+    if (unsorted) {
+      int endbit = bits_for((uint64_t)F * (uint64_t)F);
+      long long* k_in = c.corr_key.as<long long>();
+      long long* v_in = c.corr_idx.as<long long>();
+      cub_call(c, [&](void* t, size_t& b) {
+        return hipcub::DeviceRadixSort::SortPairs(t, b, k_in, k_out, v_in, v_out, (int)M, 0, endbit, c.stream);
+      });
+    } else {
+      hipLaunchKernelGGL(k_copy_ll, dim3(blocks_for(M)), dim3(256), 0, c.stream, c.corr_key.as<long long>(), M, k_out);
+      hipLaunchKernelGGL(k_copy_ll, dim3(blocks_for(M)), dim3(256), 0, c.stream, c.corr_idx.as<long long>(), M, v_out);
+    }
     hipLaunchKernelGGL(k_corr_heads, dim3(blocks_for(M)), dim3(256), 0, c.stream, k_out, M,
                        c.corr_head.as<long long>());
     long long* hd = c.corr_head.as<long long>();
@@ -669,7 +736,7 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
   ensure(c.row_cnt, sizeof(long long) * (sh.nfree + 1));
   ensure(c.row_ptr, sizeof(long long) * (sh.nfree + 1));
   ensure(c.row_entries, sizeof(int2) * (2 * sh.E + 1));
-  hipLaunchKernelGGL(k_row_count, dim3(blocks_for(sh.nfree + 1)), dim3(256), 0, c.stream, c.iptr.as<long long>(),
+  hipLaunchKernelGGL(k_row_count, dim3((unsigned)(sh.nfree + 1)), dim3(64), 0, c.stream, c.iptr.as<long long>(),
                      c.jptr.as<long long>(), c.ej_sorted.as<long long>(), c.edge_ij.as<int>(), c.var_of.as<int>(),
                      c.frame_of_var.as<int>(), (long long)sh.nfree, c.row_cnt.as<long long>());
   long long* rcnt = c.row_cnt.as<long long>();
@@ -678,7 +745,7 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
     return hipcub::DeviceScan::ExclusiveSum(t, b, rcnt, rptr, (int)(sh.nfree + 1), c.stream);
   });
   if (sh.nfree > 0)
-    hipLaunchKernelGGL(k_row_fill, dim3(blocks_for(sh.nfree)), dim3(256), 0, c.stream, c.iptr.as<long long>(),
+    hipLaunchKernelGGL(k_row_fill, dim3((unsigned)sh.nfree), dim3(64), 0, c.stream, c.iptr.as<long long>(),
                        c.jptr.as<long long>(), c.ej_sorted.as<long long>(), c.edge_ij.as<int>(), c.var_of.as<int>(),
                        c.frame_of_var.as<int>(), (long long)sh.nfree, rptr, c.row_entries.as<int2>());
   c.shape = sh;
