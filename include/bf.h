@@ -235,6 +235,27 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* frames, const bf_int
                           double* out_trace);
 
 /*
+ * Key-point correspondence filter and surface-area filter (Sec. 4.1.1), run on
+ * candidate correspondences before a solve.  Per unordered frame pair, the
+ * candidates in their given order (the order of match distance) are added one at
+ * a time; after each addition, while the set has at least 3 members, the least-
+ * RMSD rigid transform (Kabsch) is computed and the set must have its largest
+ * residual at most max_res (paper: 0.02 m) and be well determined: the ratio of
+ * the largest to the second largest eigenvalue of the covariance of each side's
+ * points, and of the largest to the second largest singular value of their
+ * cross-covariance, at most max_cond (paper: 100); otherwise the member with the
+ * largest residual is removed.  The pair keeps its final set if it passed with at
+ * least max(min_count, 3) members (paper: 5) and each side's points span at least
+ * min_area (paper: 0.032 m^2) as the box along their two principal axes.
+ *   num_frames: frame indices of `corrs` must lie in [0, num_frames), i != j.
+ *   out_keep (device) [M] uint8: 1 = kept.  out_kept (host, may be NULL): count.
+ * Synchronises the stream.
+ */
+bf_status bf_filter_correspondences(bf_context* ctx, const bf_corrs* corrs, int32_t num_frames, double max_res,
+                                   double max_cond, int32_t min_count, double min_area, uint8_t* out_keep,
+                                   int64_t* out_kept);
+
+/*
  * Dense two-sided verification of frame pairs (Sec. 4.1.1, "Dense Verification"),
  * e.g. of every pair of a chunk after its solve.  For each pair (i, j) and the
  * relative transform of `poses`, each pixel of i with a valid normal is associated

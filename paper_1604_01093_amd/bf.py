@@ -90,6 +90,8 @@ _SIGS = {
     "bf_gauss_newton_pruned": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                        POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_double, c_int32, c_void_p,
                                        POINTER(c_double), c_void_p, c_void_p, POINTER(c_int32), POINTER(c_double)]),
+    "bf_filter_correspondences": (c_int, [c_void_p, POINTER(bf_corrs), c_int32, c_double, c_double, c_int32,
+                                          c_double, c_void_p, POINTER(c_int64)]),
     "bf_verify_pairs": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_pairs), c_void_p,
                                 POINTER(bf_params), c_double, c_double, c_double, c_void_p, c_void_p]),
     "bf_system_matvec": (c_int, [c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32, POINTER(c_double)]),
@@ -437,3 +439,14 @@ def bf_verify_pairs(ctx, prob, pairs, poses, params, tau_c=0.1, max_err=0.075, m
                                        _ptr(poses), ctypes.byref(params), tau_c, max_err, min_frac, _ptr(stats),
                                        _ptr(valid)))
     return stats[:P], valid[:P].bool()
+
+
+def bf_filter_correspondences(ctx, prob, max_res=0.02, max_cond=100.0, min_count=5, min_area=0.032):
+    """Key-point and surface-area filters over the problem's correspondences;
+    returns the keep mask [M] (device, bool) and the number kept."""
+    M = prob.num_corrs
+    keep = torch.empty((max(M, 1),), dtype=torch.uint8, device="cuda")
+    kept = c_int64()
+    ctx._check(ctx.lib.bf_filter_correspondences(ctx.h, ctypes.byref(prob.corrs), prob.num_frames, max_res, max_cond,
+                                                 min_count, min_area, _ptr(keep), ctypes.byref(kept)))
+    return keep[:M].bool(), kept.value

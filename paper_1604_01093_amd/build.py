@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libbf.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "prep.hip", "structure.hip", "dense.hip", "solve.hip", "matvec.hip", "prune.hip", "verify.hip"]
+SOURCES = ["api.hip", "prep.hip", "structure.hip", "dense.hip", "solve.hip", "matvec.hip", "prune.hip", "verify.hip", "filter.hip"]
 ARCH = os.environ.get("BF_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]

@@ -91,14 +91,18 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
     fail(BF_ERR_INVALID_ARG, "bad thresholds");
 }
 
-void validate_problem(const bf_corrs* co, const bf_pairs* pairs, const double* poses) {
-  if (!poses) fail(BF_ERR_INVALID_ARG, "null poses");
+void validate_corrs(const bf_corrs* co) {
   if (co) {
     if (co->count < 0) fail(BF_ERR_INVALID_ARG, "negative correspondence count");
     if (co->count > 0 && (!co->frame_i || !co->frame_j || !co->p_i || !co->p_j))
       fail(BF_ERR_INVALID_ARG, "null correspondence arrays");
     if (co->count > ((int64_t)1 << 31) - 2) fail(BF_ERR_UNSUPPORTED, "too many correspondences");
   }
+}
+
+void validate_problem(const bf_corrs* co, const bf_pairs* pairs, const double* poses) {
+  if (!poses) fail(BF_ERR_INVALID_ARG, "null poses");
+  validate_corrs(co);
   if (pairs) {
     if (pairs->count < 0) fail(BF_ERR_INVALID_ARG, "negative pair count");
     if (pairs->count > 0 && !pairs->ij) fail(BF_ERR_INVALID_ARG, "null pair array");
@@ -574,6 +578,33 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* fr, const bf_i
     check_poses(c, init_poses, fr->num_frames);
     setup(ctx, fr, in, co, pairs, init_poses, prm, frame_offsets, num_problems);
     run_gauss_newton(ctx, in, prm, init_poses, out_poses, out_energy, out_trace, tm, t_start);
+  });
+}
+
+bf_status bf_filter_correspondences(bf_context* ctx, const bf_corrs* co, int32_t num_frames, double max_res,
+                                   double max_cond, int32_t min_count, double min_area, uint8_t* out_keep,
+                                   int64_t* out_kept) {
+  return guarded(ctx, [&] {
+    if (!ctx) fail(BF_ERR_INVALID_ARG, "null context");
+    validate_corrs(co);
+    if (!co) fail(BF_ERR_INVALID_ARG, "null correspondences");
+    if (num_frames < 1 || num_frames > 16384) fail(BF_ERR_INVALID_ARG, "num_frames out of range");
+    if (!(max_res >= 0.0) || !(max_cond >= 1.0) || min_count < 0 || !(min_area >= 0.0))
+      fail(BF_ERR_INVALID_ARG, "bad filter thresholds");
+    if (co->count > 0 && !out_keep) fail(BF_ERR_INVALID_ARG, "null out_keep");
+    Context& c = *ctx;
+    const long long S = group_correspondences(c, *co, num_frames);
+    launch_filters(c, *co, S, max_res, max_cond, min_count, min_area, out_keep);
+    check_hip(hipStreamSynchronize(c.stream), "synchronise");
+    if (out_kept) {
+      long long kept = 0;
+      if (co->count > 0) {
+        std::vector<uint8_t> h((size_t)co->count);
+        check_hip(hipMemcpy(h.data(), out_keep, (size_t)co->count, hipMemcpyDeviceToHost), "copy");
+        for (uint8_t v : h) kept += v;
+      }
+      *out_kept = kept;
+    }
   });
 }
 

@@ -99,6 +99,7 @@ void launch_prepare(Context& c, const bf_frames& fr, const bf_intrinsics& in, co
 // Segments: frames [offsets[b], offsets[b+1]) form independent problem b (host array
 // of nseg + 1 entries; nullptr = one problem of all frames).
 void set_segments(Context& c, int F, const int32_t* offsets, int nseg);
+int64_t group_correspondences(Context& c, const bf_corrs& co, int F);
 void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_corrs* co,
                      const bf_pairs* pairs, const double* poses, const bf_params& prm);
 int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics& in, const double* poses,
@@ -114,6 +115,10 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
                   bool update_poses);
 void launch_energy(Context& c, double* dst8);
 void launch_export_dense(Context& c, double* H, double* g);
+
+// filter.hip: key-point and surface-area filters over grouped correspondences
+void launch_filters(Context& c, const bf_corrs& co, long long S, double max_res, double max_cond, int min_count,
+                    double min_area, uint8_t* keep);
 
 // verify.hip: two-sided dense verification of frame pairs (frames prepared)
 void launch_verify(Context& c, const bf_frames& fr, const bf_intrinsics& in, const int* pairs, long long P,

@@ -524,6 +524,50 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
   return P;
 }
 
+// Correspondences grouped by unordered frame pair (stable: input order within a
+// pair): fills corr_perm (sorted position -> input index), sparse_ptr and
+// sparse_ij; returns the number of pairs.  One problem of F frames.
+int64_t group_correspondences(Context& c, const bf_corrs& co, int F) {
+  set_segments(c, F, nullptr, 1);
+  const long long M = co.count;
+  ensure(c.counts, 8 * sizeof(long long));
+  ensure(c.flags, sizeof(int));
+  check_hip(hipMemsetAsync(c.counts.p, 0, 8 * sizeof(long long), c.stream), "memset counts");
+  ensure(c.corr_key, sizeof(long long) * (M + 1));
+  ensure(c.corr_idx, sizeof(long long) * (M + 1));
+  ensure(c.corr_key_sorted, sizeof(long long) * (M + 1));
+  ensure(c.corr_perm, sizeof(long long) * (M + 1));
+  ensure(c.corr_head, sizeof(long long) * (M + 1));
+  ensure(c.corr_group, sizeof(long long) * (M + 1));
+  ensure(c.sparse_ij, sizeof(int) * 2 * (M + 1));
+  ensure(c.sparse_keys, sizeof(long long) * (M + 1));
+  ensure(c.sparse_ptr, sizeof(long long) * (M + 2));
+  if (M == 0) return 0;
+  hipLaunchKernelGGL(k_corr_keys, dim3(blocks_for(M)), dim3(256), 0, c.stream, co.frame_i, co.frame_j, co.p_i, co.p_j,
+                     M, F, c.seg_of.as<int>(), c.corr_key.as<long long>(), c.corr_idx.as<long long>(),
+                     c.flags.as<int>());
+  int endbit = bits_for((uint64_t)F * (uint64_t)F);
+  long long* k_in = c.corr_key.as<long long>();
+  long long* k_out = c.corr_key_sorted.as<long long>();
+  long long* v_in = c.corr_idx.as<long long>();
+  long long* v_out = c.corr_perm.as<long long>();
+  cub_call(c, [&](void* t, size_t& b) {
+    return hipcub::DeviceRadixSort::SortPairs(t, b, k_in, k_out, v_in, v_out, (int)M, 0, endbit, c.stream);
+  });
+  hipLaunchKernelGGL(k_corr_heads, dim3(blocks_for(M)), dim3(256), 0, c.stream, k_out, M, c.corr_head.as<long long>());
+  long long* hd = c.corr_head.as<long long>();
+  long long* gp = c.corr_group.as<long long>();
+  cub_call(c, [&](void* t, size_t& b) { return hipcub::DeviceScan::InclusiveSum(t, b, hd, gp, (int)M, c.stream); });
+  hipLaunchKernelGGL(k_corr_groups, dim3(blocks_for(M)), dim3(256), 0, c.stream, k_out, gp, M, F,
+                     c.sparse_ij.as<int>(), c.sparse_keys.as<long long>(), c.sparse_ptr.as<long long>(),
+                     c.counts.as<long long>());
+  long long hc[8];
+  int hf = 0;
+  read_counts(c, hc, &hf);
+  raise_device_flags(hf);
+  return hc[1];
+}
+
 void set_segments(Context& c, int F, const int32_t* offsets, int nseg) {
   std::vector<int> h;
   if (offsets) {
