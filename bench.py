@@ -125,6 +125,8 @@ def main():
                     help="global2000: the 2000-keyframe floor (8 GN x 20 PCG); only the solve is measured")
     ap.add_argument("--prune-rounds", type=int, default=0,
                     help="also time one solve with residual pruning (threshold 0.05 m) limited to this many removals")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the correspondence filters and the dense verification (one call each)")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=300)
@@ -246,6 +248,21 @@ def main():
         "phase_us_per_step": {n: round(v, 1) for n, v in zip(
             ["setup", "dense", "edges", "assemble", "pcg", "final", "total"], phase[:7])},
     }
+    if args.extras:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep, kept = bf.bf_filter_correspondences(ctx, dp)
+        t_filter = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, valid = bf.bf_verify_pairs(ctx, dp, st["pairs"], init, params)
+        t_verify = time.perf_counter() - t0
+        line["next_rows"] = {
+            "keypoint_and_area_filters": {"ms": round(1e3 * t_filter, 3), "correspondences": len(prob.corr_i),
+                                          "kept": int(kept)},
+            "dense_verification": {"ms": round(1e3 * t_verify, 3), "pairs": int(P),
+                                   "valid_at_init": int(valid.sum().item())}}
+        log(f"filters: {kept} of {len(prob.corr_i)} kept in {1e3 * t_filter:.2f} ms; verification of {P} pairs "
+            f"in {1e3 * t_verify:.2f} ms")
     if args.prune_rounds > 0:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
