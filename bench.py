@@ -291,8 +291,10 @@ def batched(bf, ctx, chunks, steps):
 
     n_gn, n_pcg = chunks[0].n_gn, chunks[0].n_pcg
     params = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0)
+    gparams = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0, graph=1)
     dp, offs, init = bf.device_batch(chunks)
     out = torch.empty_like(init)
+    gout = torch.empty_like(init)
     singles = [(bf.DeviceProblem.from_numpy(c.depth, c.intensity, c.intrinsics, c.corr_i, c.corr_j, c.corr_p,
                                             c.corr_q), torch.as_tensor(c.init_poses).cuda()) for c in chunks]
     singles_out = [torch.empty_like(i) for _, i in singles]
@@ -300,6 +302,7 @@ def batched(bf, ctx, chunks, steps):
     log("batched: warm-up (first calls time the dense workgroup sizes)")
     for _ in range(2):
         res = bf.bf_gauss_newton_batch(ctx, dp, offs, init, params, out_poses=out)
+        gres = bf.bf_gauss_newton_batch(ctx, dp, offs, init, gparams, out_poses=gout)
     for (d, i), o in zip(singles, singles_out):
         bf.bf_gauss_newton(ctx, d, i, params, out_poses=o)
     torch.cuda.synchronize()
@@ -307,7 +310,20 @@ def batched(bf, ctx, chunks, steps):
     for _ in range(steps):
         res = bf.bf_gauss_newton_batch(ctx, dp, offs, init, params, out_poses=out)
     torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / steps
+    n_cap = ctx.graph_captures()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gres = bf.bf_gauss_newton_batch(ctx, dp, offs, init, gparams, out_poses=gout)
+    torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
+    graph_same = bool(torch.equal(out, gout)) and gres["energy"] == res["energy"]
+    tparams = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0, timing=1)
+    bf.bf_gauss_newton_batch(ctx, dp, offs, init, tparams, out_poses=out)
+    phases = {k: round(v, 1) for k, v in ctx.last_timings().items()}
+    log(f"batched phases (us, eager, timed call): {phases}")
+    log(f"batched: graph replays {t_batch * 1e3:.3f} ms, eager launches {t_eager * 1e3:.3f} ms per batch; "
+        f"captures during the timed replays {ctx.graph_captures() - n_cap}; graph result == eager: {graph_same}")
     t0 = time.perf_counter()
     for (d, i), o in zip(singles, singles_out):
         bf.bf_gauss_newton(ctx, d, i, params, out_poses=o)
@@ -327,9 +343,11 @@ def batched(bf, ctx, chunks, steps):
     return {"metric": "batched solves/sec", "value": round(nb / t_batch, 2), "unit": "solves/s",
             "sequential_value": round(nb / t_seq, 2), "speedup": round(t_seq / t_batch, 2),
             "ms_per_batch": round(1e3 * t_batch, 3), "steps": steps,
+            "eager_value": round(nb / t_eager, 2), "graph_equals_eager": graph_same, "phase_us": phases,
             "max_pose_diff_vs_sequential": {"rad": worst_r, "m": worst_t},
             "config": {"workload": f"{nb} chunk problems, 4-11 frames (sum {offs[-1]}), 160x120, "
-                                   f"{n_gn} GN x {n_pcg} PCG, dense workgroup size timed per shape"}}
+                                   f"{n_gn} GN x {n_pcg} PCG, dense workgroup size timed per shape, "
+                                   f"Gauss-Newton loop replayed as one HIP graph"}}
 
 
 

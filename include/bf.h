@@ -104,7 +104,7 @@ typedef struct bf_params {
                                3 = cooperative grid with replicated vectors (vectors in LDS),
                                4 = one workgroup per problem (the kernel of bf_gauss_newton_batch;
                                    chosen automatically for problems of at most 64 free frames) */
-  int32_t dense_threads;    /* threads per dense pair job: 64, 128, 256 (default) or 512; 0 = the
+  int32_t dense_threads;    /* threads per dense pair job: 64, 128, 256 or 512; 0 (default) = the
                                fastest, timed once per image size, mode and job-count range in
                                this context (the first call of a shape synchronises once).  The
                                lane sums of a job are combined in an order fixed by this value,
@@ -116,7 +116,16 @@ typedef struct bf_params {
   int32_t preconditioner;   /* PCG preconditioner: 0 = 6x6 block-Jacobi (one Cholesky-inverted
                                block per frame), 1 = Jacobi (the diagonal of J^T J, as in
                                Sec. 4.4) */
-  int32_t reserved1;        /* must be 0 */
+  int32_t graph;            /* 1: bf_gauss_newton and bf_gauss_newton_batch run the Gauss-Newton
+                               loop (every iteration and the final energy, after the per-call
+                               setup) as one HIP graph launch.  The loop is captured on the first
+                               call and replayed while the parameters, intrinsics, structure sizes,
+                               pose buffers and workspace are unchanged (else captured again), so
+                               repeated solves of same-sized inputs skip the per-kernel launches.
+                               Results are bitwise those of graph = 0.  Needs the per-problem PCG
+                               kernel (a batch, or at most 64 free frames; else
+                               BF_ERR_UNSUPPORTED); bf_gauss_newton_pruned ignores it.  With
+                               timing = 1 only the setup and total times are reported. */
 } bf_params;
 
 void bf_params_default(bf_params* out);
@@ -337,6 +346,11 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* frames, const 
  * [8]): setup, dense pair jobs (sum over iterations), edge blocks, assembly,
  * PCG + update, final energy, total, and the number of dense pair-job launches. */
 bf_status bf_last_timings(const bf_context* ctx, double* out_us);
+
+/* Number of times this context has captured the Gauss-Newton loop into a HIP
+ * graph (params->graph = 1); a call that replays the captured loop leaves it
+ * unchanged.  -1 for a NULL context. */
+int64_t bf_graph_captures(const bf_context* ctx);
 
 #ifdef __cplusplus
 }

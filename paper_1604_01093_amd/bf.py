@@ -53,7 +53,7 @@ class bf_params(ctypes.Structure):
                 ("solve_kernel", c_int32), ("dense_threads", c_int32),
                 ("tau_dist", c_double), ("tau_normal", c_double), ("max_angle_deg", c_double),
                 ("depth_min", c_double), ("depth_max", c_double), ("preconditioner", c_int32),
-                ("reserved1", c_int32)]
+                ("graph", c_int32)]
 
 
 class bf_structure(ctypes.Structure):
@@ -96,6 +96,7 @@ _SIGS = {
                                 POINTER(bf_params), c_double, c_double, c_double, c_void_p, c_void_p]),
     "bf_system_matvec": (c_int, [c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32, POINTER(c_double)]),
     "bf_last_timings": (c_int, [c_void_p, POINTER(c_double)]),
+    "bf_graph_captures": (ctypes.c_int64, [c_void_p]),
 }
 
 _lib = None
@@ -185,6 +186,10 @@ class Context:
         keys = ["setup_us", "dense_us", "edges_us", "assemble_us", "pcg_us", "final_us", "total_us",
                 "dense_launches"]
         return dict(zip(keys, list(out)))
+
+    def graph_captures(self):
+        """How often this context has captured the Gauss-Newton loop into a graph."""
+        return int(self.lib.bf_graph_captures(self.h))
 
 
 class DeviceProblem:

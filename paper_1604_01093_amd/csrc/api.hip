@@ -22,9 +22,16 @@ void check_hip(hipError_t e, const char* what) {
   }
 }
 
+namespace {
+unsigned long long g_alloc_generation = 0;
+}  // namespace
+
+unsigned long long alloc_generation() { return g_alloc_generation; }
+
 void ensure(Buf& b, size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (b.cap >= bytes) return;
+  ++g_alloc_generation;
   if (b.p) {
     check_hip(hipFree(b.p), "hipFree");
     b.p = nullptr;
@@ -55,6 +62,11 @@ __global__ void k_check_pair_range(const int* __restrict__ ij, long long P, int 
   if (!(i >= 0 && i < F && j >= 0 && j < F && i != j)) raise_flag(flags, kFlagBadIndex);
 }
 
+__global__ void k_copy_d(const double* __restrict__ src, double* __restrict__ dst, int n) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[k];
+}
+
 __global__ void k_copy_if_ok(const double* __restrict__ src, double* __restrict__ dst, int n,
                              const int* __restrict__ flags) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -82,7 +94,7 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
   if (prm->pcg_storage != 0 && prm->pcg_storage != 1) fail(BF_ERR_INVALID_ARG, "pcg_storage must be 0 or 1");
   if (prm->solve_kernel < 0 || prm->solve_kernel > 4) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..4");
   if (prm->preconditioner != 0 && prm->preconditioner != 1) fail(BF_ERR_INVALID_ARG, "preconditioner must be 0 or 1");
-  if (prm->reserved1 != 0) fail(BF_ERR_INVALID_ARG, "reserved1 must be 0");
+  if (prm->graph != 0 && prm->graph != 1) fail(BF_ERR_INVALID_ARG, "graph must be 0 or 1");
   if (prm->dense_threads != 0 && prm->dense_threads != 64 && prm->dense_threads != 128 &&
       prm->dense_threads != 256 && prm->dense_threads != 512)
     fail(BF_ERR_INVALID_ARG, "dense_threads must be 0, 64, 128, 256 or 512");
@@ -287,6 +299,8 @@ void bf_destroy(bf_context* c) {
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->gn_exec) (void)hipGraphExecDestroy(c->gn_exec);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   delete c;
 }
 
@@ -475,43 +489,136 @@ bf_status bf_pcg_solve(bf_context* ctx, int32_t num_iters, double* out_delta, do
 namespace bf {
 namespace {
 
-// The Gauss-Newton loop over the structure built by setup(): nseg problems solved
-// together; energies (host) [nseg][4], trace (host, may be NULL) [nseg][num_gn][4].
-void run_gauss_newton(bf_context* ctx, const bf_intrinsics* in, const bf_params* prm, const double* init_poses,
-                      double* out_poses, double* out_energy, double* out_trace, Timer& tm, int t_start) {
-  Context& c = *ctx;
+// Every launch of the Gauss-Newton loop over the structure built by setup(), in
+// order on c.stream: the initial poses into the work buffer, num_gn iterations of
+// (dense pair jobs, edge blocks, PCG + SE(3) update, or the energy alone when no
+// frame is free), then the energy at the final poses and the poses out (kept only
+// when no error flag is raised).  tm may be null: no timing events.
+void enqueue_loop(Context& c, const bf_intrinsics* in, const bf_params* prm, const double* init_poses,
+                  double* out_poses, Timer* tm) {
   const int F = c.shape.F;
   const int nseg = c.shape.nseg;
-  ensure(c.poses_work, sizeof(double) * 16 * F);
   double* poses = c.poses_work.as<double>();
-  check_hip(hipMemcpyAsync(poses, init_poses, sizeof(double) * 16 * F, hipMemcpyDeviceToDevice, c.stream),
-            "copy poses");
-  int t_setup = tm.mark();
-  tm.span(0, t_start, t_setup);
+  auto mark = [&] { return tm ? tm->mark() : -1; };
+  hipLaunchKernelGGL(k_copy_d, dim3((16 * F + 255) / 256), dim3(256), 0, c.stream, init_poses, poses, 16 * F);
   for (int k = 0; k < prm->num_gn; ++k) {
     double wd = dense_weight(*prm, k);
     double* slot = c.trace.as<double>() + 8 * (size_t)nseg * k;
-    int a = tm.mark();
+    int a = mark();
     launch_dense(c, *in, poses, *prm, wd, true);
-    int b = tm.mark();
+    int b = mark();
     launch_edge_blocks(c, poses, *prm, true);
-    int d = tm.mark();
+    int d = mark();
     if (c.shape.nfree > 0) launch_solve(c, prm->num_pcg, slot, nullptr, poses, nullptr, true);
     else launch_energy(c, slot);
-    int f = tm.mark();
-    tm.span(1, a, b);
-    tm.span(2, b, d);
-    tm.span(4, d, f);
+    int f = mark();
+    if (tm) {
+      tm->span(1, a, b);
+      tm->span(2, b, d);
+      tm->span(4, d, f);
+    }
   }
-  int g0 = tm.mark();
+  int g0 = mark();
   double wd = dense_weight(*prm, prm->num_gn > 0 ? prm->num_gn - 1 : 0);
   launch_dense(c, *in, poses, *prm, wd, false);
   launch_edge_blocks(c, poses, *prm, false);
   launch_energy(c, c.energy.as<double>());
   hipLaunchKernelGGL(k_copy_if_ok, dim3((16 * F + 255) / 256), dim3(256), 0, c.stream, poses, out_poses, 16 * F,
                      c.flags.as<int>());
+  int g1 = mark();
+  if (tm) tm->span(5, g0, g1);
+}
+
+// What a captured loop depends on beyond the contents of device memory: the
+// parameters and intrinsics, the structure's sizes (grids, shared memory), the
+// dense workgroup sizes, the caller's pose buffers and the workspace addresses
+// (through the allocation count).
+std::vector<unsigned char> graph_key(const Context& c, const bf_intrinsics* in, const bf_params* prm,
+                                     const double* init_poses, const double* out_poses, int nt_jac, int nt_eval) {
+  std::vector<unsigned char> k;
+  auto add = [&](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    k.insert(k.end(), b, b + n);
+  };
+  bf_params q = *prm;
+  q.timing = 0;
+  add(&q, sizeof q);
+  add(in, sizeof *in);
+  const Shape& s = c.shape;
+  const int64_t sizes[] = {s.F, s.W, s.H, s.M, s.P, s.S, s.E, s.nfree, s.nseg, s.max_seg_free};
+  add(sizes, sizeof sizes);
+  const unsigned long long gen = alloc_generation();
+  add(&gen, sizeof gen);
+  add(&init_poses, sizeof init_poses);
+  add(&out_poses, sizeof out_poses);
+  const int other[] = {nt_jac, nt_eval, c.pcg_storage, c.precond, c.solve_mode};
+  add(other, sizeof other);
+  return k;
+}
+
+// Run the loop as one graph launch on c.stream, capturing it first (on a private
+// stream) when nothing is captured yet or the key has changed.
+void launch_loop_graph(Context& c, const bf_intrinsics* in, const bf_params* prm, const double* init_poses,
+                       double* out_poses) {
+  if (c.shape.nfree > 0 && !solve_per_problem(c))
+    fail(BF_ERR_UNSUPPORTED,
+         "graph mode needs the per-problem PCG kernel (a batch, or a problem of at most 64 free frames)");
+  // settle, eagerly, what capture must not do: dense workgroup-size timing and
+  // kernel attribute settings
+  const int nt_jac = prm->num_gn > 0 ? dense_threads_for(c, *in, init_poses, *prm, dense_weight(*prm, 0), true) : 0;
+  const int nt_eval = dense_threads_for(c, *in, init_poses, *prm,
+                                        dense_weight(*prm, prm->num_gn > 0 ? prm->num_gn - 1 : 0), false);
+  prepare_solve(c);
+  std::vector<unsigned char> key = graph_key(c, in, prm, init_poses, out_poses, nt_jac, nt_eval);
+  if (!c.gn_exec || key != c.gn_key) {
+    if (c.gn_exec) {
+      check_hip(hipGraphExecDestroy(c.gn_exec), "destroy graph");
+      c.gn_exec = nullptr;
+      c.gn_key.clear();
+    }
+    if (!c.capture_stream)
+      check_hip(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking), "create capture stream");
+    hipStream_t user = c.stream;
+    c.stream = c.capture_stream;
+    hipGraph_t g = nullptr;
+    check_hip(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      enqueue_loop(c, in, prm, init_poses, out_poses, nullptr);
+    } catch (...) {
+      (void)hipStreamEndCapture(c.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      c.stream = user;
+      throw;
+    }
+    hipError_t e = hipStreamEndCapture(c.stream, &g);
+    c.stream = user;
+    check_hip(e, "end capture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    check_hip(e, "instantiate graph");
+    c.gn_exec = x;
+    c.gn_key = std::move(key);
+    ++c.gn_captures;
+  }
+  check_hip(hipGraphLaunch(c.gn_exec, c.stream), "graph launch");
+}
+
+// The Gauss-Newton loop, eager or as a graph (params.graph), then the single copy
+// of energies (and trace) to the host: energies [nseg][4], trace (host, may be
+// NULL) [nseg][num_gn][4].
+void run_gauss_newton(bf_context* ctx, const bf_intrinsics* in, const bf_params* prm, const double* init_poses,
+                      double* out_poses, double* out_energy, double* out_trace, Timer& tm, int t_start,
+                      bool allow_graph = true) {
+  Context& c = *ctx;
+  const int F = c.shape.F;
+  const int nseg = c.shape.nseg;
+  ensure(c.poses_work, sizeof(double) * 16 * F);
+  int t_setup = tm.mark();
+  tm.span(0, t_start, t_setup);
+  if (allow_graph && prm->graph) launch_loop_graph(c, in, prm, init_poses, out_poses);
+  else enqueue_loop(c, in, prm, init_poses, out_poses, &tm);
   int g1 = tm.mark();
-  tm.span(5, g0, g1);
   std::vector<double> e8(8 * (size_t)nseg);
   int hf = 0;
   std::vector<double> tr(8 * (size_t)nseg * (prm->num_gn + 1));
@@ -687,7 +794,8 @@ bf_status bf_gauss_newton_pruned(bf_context* ctx, const bf_frames* fr, const bf_
       bf_pairs pp = prune_valid_pairs(c, c.pr_pairs_all.as<int>(), P);
       Timer tm(ctx, false);
       setup(ctx, fr, in, &cc, &pp, c.pr_poses.as<double>(), prm);
-      run_gauss_newton(ctx, in, prm, c.pr_poses.as<double>(), c.pr_poses.as<double>(), e4, nullptr, tm, -1);
+      run_gauss_newton(ctx, in, prm, c.pr_poses.as<double>(), c.pr_poses.as<double>(), e4, nullptr, tm, -1,
+                       false);
       long long idx = -1;
       rmax = prune_max_residual(c, *co, c.pr_poses.as<double>(), &idx);
       if (idx < 0 || rmax <= r_prune || rounds >= max_rounds) break;
@@ -735,6 +843,8 @@ bf_status bf_system_matvec(bf_context* ctx, const bf_corrs* co, const double* x,
     if (out_us) *out_us = 1000.0 * ms;
   });
 }
+
+int64_t bf_graph_captures(const bf_context* ctx) { return ctx ? ctx->gn_captures : -1; }
 
 bf_status bf_last_timings(const bf_context* ctx, double* out_us) {
   if (!ctx || !out_us) return BF_ERR_INVALID_ARG;

@@ -485,4 +485,10 @@ void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, cons
   launch_any(c, in, poses, prm, wd, with_jacobians, nt);
 }
 
+int dense_threads_for(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
+                      bool with_jacobians) {
+  if (c.shape.P == 0) return 0;
+  return choose_threads(c, in, poses, prm, wd, with_jacobians);
+}
+
 }  // namespace bf

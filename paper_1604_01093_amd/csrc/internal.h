@@ -82,6 +82,12 @@ struct Context {
   void* pcg_tags_ptr = nullptr;
   bool pcg_tags_dirty = true;
   int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative, 3 = replicated vectors
+  // the Gauss-Newton loop captured as a HIP graph: the instantiated graph, the
+  // launch arguments it was captured with, and the stream capture runs on
+  hipGraphExec_t gn_exec = nullptr;
+  std::vector<unsigned char> gn_key;
+  hipStream_t capture_stream = nullptr;
+  long long gn_captures = 0;
 
   hipEvent_t ev[16] = {};
   bool events_ready = false;
@@ -91,6 +97,9 @@ struct Context {
 [[noreturn]] void fail(bf_status s, const std::string& msg);
 void check_hip(hipError_t e, const char* what);
 void ensure(Buf& b, size_t bytes);
+// Count of workspace (re)allocations so far, in every context: a captured graph
+// holds buffer addresses and is valid only while this count is unchanged.
+unsigned long long alloc_generation();
 
 // prep.hip
 void launch_prepare(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_params& prm);
@@ -108,12 +117,21 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
 // dense.hip
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
                   bool with_jacobians);
+// Threads per dense pair job that launch_dense() will use (timing them first when
+// params.dense_threads is 0 and the shape is new in this context).
+int dense_threads_for(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
+                      bool with_jacobians);
 
 // solve.hip
 void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, bool with_jacobians);
 void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
                   bool update_poses);
 void launch_energy(Context& c, double* dst8);
+// Whether the PCG of the current structure runs in the per-problem kernel (no state
+// carried between launches, so it can be captured in a graph); prepare_solve()
+// makes the one-time kernel attribute settings that capture must not make.
+bool solve_per_problem(const Context& c);
+void prepare_solve(Context& c);
 void launch_export_dense(Context& c, double* H, double* g);
 
 // filter.hip: key-point and surface-area filters over grouped correspondences

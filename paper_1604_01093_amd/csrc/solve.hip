@@ -1283,6 +1283,17 @@ void launch_solve_coop(Context& c, int iters, double* trace_slot, double* delta_
 // LDS budget of the single-workgroup solve (dynamic part).
 constexpr size_t kSingleLdsMax = 64 * 1024;
 
+// Raise the dynamic LDS limit of k_solve_single<T, NT> (once per process).
+template <class T, int NT>
+void set_single_lds_limit() {
+  static bool done = false;
+  if (done) return;
+  check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve_single<T, NT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSingleLdsMax),
+            "set LDS limit");
+  done = true;
+}
+
 // One workgroup of NT threads per problem; LDS sized for the largest problem.
 template <class T, int NT>
 bool launch_solve_single(Context& c, int iters, double* trace_slot, double* delta_out, double* poses, double* stats,
@@ -1293,13 +1304,7 @@ bool launch_solve_single(Context& c, int iters, double* trace_slot, double* delt
   if (vec_bytes > kSingleLdsMax) return false;
   const int minv_lds = (vec_bytes + minv_bytes <= kSingleLdsMax) ? 1 : 0;
   const size_t lds = vec_bytes + (minv_lds ? minv_bytes : 0);
-  static bool attr_set[2] = {false, false};
-  if (!attr_set[sizeof(T) == 8]) {
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve_single<T, NT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSingleLdsMax),
-              "set LDS limit");
-    attr_set[sizeof(T) == 8] = true;
-  }
+  set_single_lds_limit<T, NT>();
   hipLaunchKernelGGL((k_solve_single<T, NT>), dim3(c.shape.nseg), dim3(NT), lds, c.stream,
                      c.seg_var_ptr.as<long long>(), c.seg_edge_ptr.as<long long>(), c.seg_start.as<int>(), iters,
                      c.eblocks.as<double>(), hij, c.iptr.as<long long>(), c.jptr.as<long long>(),
@@ -1383,13 +1388,23 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
 // kernel is chosen automatically.
 constexpr long long kPerProblemMaxFree = 64;
 
+bool solve_per_problem(const Context& c) {
+  const bool many = c.shape.nseg > 1;
+  return c.solve_mode == 4 || (c.solve_mode == 0 && (many || c.shape.max_seg_free <= kPerProblemMaxFree));
+}
+
+void prepare_solve(Context& c) {
+  if (c.pcg_storage == 1) set_single_lds_limit<double, 256>();
+  else set_single_lds_limit<float, 256>();
+}
+
 void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
                   bool update_poses) {
   if (c.shape.nfree == 0) return;
   const bool many = c.shape.nseg > 1;
   if (many && c.solve_mode != 0 && c.solve_mode != 4)
     fail(BF_ERR_UNSUPPORTED, "several problems are solved by the per-problem kernel (solve_kernel 0 or 4)");
-  if (c.solve_mode == 4 || (c.solve_mode == 0 && (many || c.shape.max_seg_free <= kPerProblemMaxFree))) {
+  if (solve_per_problem(c)) {
     bool ok = c.pcg_storage == 1
                   ? launch_solve_single<double, 256>(c, iters, trace_slot, delta_out, poses_inout, stats,
                                                      update_poses, c.diag64.as<double>(), c.minv64.as<double>(),
