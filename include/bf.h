@@ -101,7 +101,9 @@ typedef struct bf_params {
   int32_t timing;           /* 1: record HIP events per phase for bf_last_timings() */
   int32_t solve_kernel;     /* PCG kernel: 0 = automatic, 1 = single workgroup (vectors in LDS),
                                2 = cooperative grid with owner-computed vectors (any size),
-                               3 = cooperative grid with replicated vectors (vectors in LDS),
+                               3 = replicated vectors (vectors in LDS of every workgroup; rows
+                                   assembled and inverted by a separate launch; the workgroups
+                                   must all be resident, every wait is bounded),
                                4 = one workgroup per problem (the kernel of bf_gauss_newton_batch;
                                    chosen automatically for problems of at most 64 free frames) */
   int32_t dense_threads;    /* threads per dense pair job: 64, 128, 256 or 512; 0 (default) = the

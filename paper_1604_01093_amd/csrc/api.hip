@@ -468,6 +468,7 @@ bf_status bf_pcg_solve(bf_context* ctx, int32_t num_iters, double* out_delta, do
     if (!c.have_system) fail(BF_ERR_INVALID_ARG, "no system: call bf_build_normal_equations first");
     if (num_iters < 0) fail(BF_ERR_INVALID_ARG, "negative iteration count");
     if (!out_delta) fail(BF_ERR_INVALID_ARG, "null out_delta");
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
     if (c.shape.nfree == 0) {
       check_hip(hipMemsetAsync(out_delta, 0, sizeof(double) * 6 * c.shape.F, c.stream), "memset");
     } else {
@@ -700,6 +701,8 @@ bf_status bf_filter_correspondences(bf_context* ctx, const bf_corrs* co, int32_t
       fail(BF_ERR_INVALID_ARG, "bad filter thresholds");
     if (co->count > 0 && !out_keep) fail(BF_ERR_INVALID_ARG, "null out_keep");
     Context& c = *ctx;
+    ensure(c.flags, sizeof(int));
+    check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
     const long long S = group_correspondences(c, *co, num_frames);
     launch_filters(c, *co, S, max_res, max_cond, min_count, min_area, out_keep);
     check_hip(hipStreamSynchronize(c.stream), "synchronise");

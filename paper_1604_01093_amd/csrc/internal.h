@@ -77,8 +77,8 @@ struct Context {
   // threads per dense pair job chosen by timing, per (pixels per frame, precision mode, Jacobians)
   std::map<long long, int> dense_threads;
   int pcg_grid = 0;       // workgroups of the cooperative PCG kernel (0 = not yet chosen)
-  // replicated-vector PCG: tags and barrier count used so far since the last clear
-  unsigned pcg_tag_base = 0, pcg_bar_base = 0;
+  // replicated-vector PCG: exchange tags used so far since the last clear
+  unsigned pcg_tag_base = 0;
   void* pcg_tags_ptr = nullptr;
   bool pcg_tags_dirty = true;
   int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative, 3 = replicated vectors

@@ -864,28 +864,108 @@ __global__ void __launch_bounds__(NT) k_solve_single(
   }
 }
 
-// Replicated-vector PCG in one cooperative launch, one grid barrier per iteration.
-// Every workgroup keeps the full r, z, p vectors and all block-Jacobi inverses in
-// LDS and updates them redundantly, in the same fixed order, so all copies stay
-// bit-identical; each wavefront owns one matrix row and keeps that row's blocks
-// in registers (one block per lane) for the whole solve.  Per iteration the owners
-// publish (A p)_v; after the barrier every workgroup reads all of A p and
-// performs the vector updates locally.
+// Row assembly for the replicated-vector PCG, one workgroup of 256 per free frame
+// (row v): the diagonal block and gradient are the sums of the frame's incident
+// edge blocks (its "i" edges, then its "j" edges); the four wavefronts take every
+// fourth edge of that list, sixteen loads in flight per lane (one lane per word),
+// and the partial sums are combined in a fixed order.  Wavefront 0 then inverts
+// the diagonal block (6x6 Cholesky, FP64; a block that is not positive definite
+// raises the flag and is replaced by the identity) and stores, in the PCG's
+// storage type, the diagonal block, its inverse and r0 = -g.  One more workgroup
+// (the last) sums the energies and counts over all edges for the trace.
+constexpr int kAsmThreads = 256;
+
+template <class T>
+__global__ void __launch_bounds__(kAsmThreads) k_row_assemble(
+    long long nfree, long long E, const double* __restrict__ eb, const long long* __restrict__ iptr,
+    const long long* __restrict__ jptr, const long long* __restrict__ ej_sorted, const int* __restrict__ frame_of_var,
+    int precond, T* __restrict__ diag_t, T* __restrict__ minv_g, T* __restrict__ r0, double* __restrict__ trace_slot,
+    int* flags) {
+  __shared__ double part[kAsmThreads / 64][48];
+  __shared__ double red[kAsmThreads];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = kAsmThreads / 64;
+  const long long v = blockIdx.x;
+  if (v == nfree) {
+    if (!trace_slot) return;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (long long e = tid; e < E; e += kAsmThreads)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) acc[q] += eb[(size_t)e * kEdgeWords + kEEs + q];
+    double tot[6];
+    for (int q = 0; q < 6; ++q) tot[q] = block_sum<kAsmThreads>(acc[q], red);
+    if (tid == 0) {
+      trace_slot[0] = tot[0] + tot[1] + tot[2];
+      for (int q = 0; q < 6; ++q) trace_slot[1 + q] = tot[q];
+      trace_slot[7] = 0.0;
+    }
+    return;
+  }
+  const int f = frame_of_var[v];
+  const long long i0 = iptr[f], ni = iptr[f + 1] - i0;
+  const long long j0 = jptr[f], cnt = ni + (jptr[f + 1] - j0);
+  if (lane < 42) {
+    const int offI = lane < 36 ? kEHii + lane : kEGi + (lane - 36);
+    const int offJ = lane < 36 ? kEHjj + lane : kEGj + (lane - 36);
+    constexpr int kDepth = 16;
+    double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (long long q0 = wave; q0 < cnt; q0 += (long long)NW * kDepth) {
+      long long off[kDepth];
+#pragma unroll
+      for (int u = 0; u < kDepth; ++u) {
+        const long long q = q0 + (long long)NW * u;
+        off[u] = q >= cnt ? -1
+                 : q < ni ? (long long)(i0 + q) * kEdgeWords + offI
+                          : (long long)ej_sorted[j0 + q - ni] * kEdgeWords + offJ;
+      }
+      double t[kDepth];
+#pragma unroll
+      for (int u = 0; u < kDepth; ++u) t[u] = off[u] >= 0 ? eb[off[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kDepth; ++u) s8[u & 7] += t[u];
+    }
+    part[wave][lane] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  }
+  __syncthreads();
+  if (tid < 42) part[0][tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+  __syncthreads();
+  if (tid < 36) diag_t[v * 36 + tid] = (T)part[0][tid];
+  else if (tid < 42) r0[6 * v + tid - 36] = (T)(-part[0][tid]);
+  if (tid == 0) {
+    double A[36];
+    for (int q = 0; q < 36; ++q) A[q] = part[0][q];
+    if (block_jacobi_inverse6(A, precond) < 0) {
+      atomicOr(flags, kFlagNotPD);
+      for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
+    }
+    for (int q = 0; q < 36; ++q) part[1][q] = A[q];
+  }
+  __syncthreads();
+  if (tid < 36) minv_g[v * 36 + tid] = (T)part[1][tid];
+}
+
+// Replicated-vector PCG in one launch of resident workgroups (at most what the
+// device holds at once; every wait is bounded).  Every workgroup keeps the full
+// r, z, p vectors and all block-Jacobi inverses in LDS and updates them
+// redundantly, in the same fixed order, so all copies stay bit-identical; each
+// wavefront owns one matrix row and keeps that row's blocks in registers (one
+// block per lane) for the whole solve.  Per iteration the owners publish (A p)_v
+// as tagged words; every workgroup polls until it holds all of A p and performs
+// the vector updates locally.
 constexpr int kRepThreads = 512;
 constexpr int kRepWaves = kRepThreads / 64;
 
 template <class T>
 __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
-    long long nfree, int F, long long E, int iters, const double* __restrict__ eb, const T* __restrict__ hij,
-    const long long* __restrict__ iptr, const long long* __restrict__ jptr, const long long* __restrict__ ej_sorted,
-    const long long* __restrict__ row_ptr, const int2* __restrict__ entries, const int* __restrict__ frame_of_var,
-    const int* __restrict__ var_of, T* minv_sh, T* r0_sh, unsigned long long* ap_words, double* parts, unsigned* bar,
-    double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
-    double* __restrict__ stats, int* flags, int precond, unsigned tag_base, unsigned bar_base) {
+    long long nfree, int F, int iters, const T* __restrict__ hij, const long long* __restrict__ row_ptr,
+    const int2* __restrict__ entries, const int* __restrict__ frame_of_var, const int* __restrict__ var_of,
+    const T* __restrict__ diag_t, const T* __restrict__ minv_g, const T* __restrict__ r0,
+    unsigned long long* ap_words, double* __restrict__ delta_out, double* __restrict__ poses, int update,
+    double* __restrict__ stats, int* flags, unsigned tag_base) {
   extern __shared__ double lds_dyn[];
   __shared__ double sh[(kRepWaves + 1) * kParts];
   __shared__ double red1024[kRepThreads];
-  __shared__ double blk[kRepWaves][48];
+  __shared__ double blk[kRepWaves][36];
   __shared__ int sh_ok;
   const long long n = 6 * nfree;
   T* r = reinterpret_cast<T*>(lds_dyn);
@@ -897,40 +977,20 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long long v = (long long)blockIdx.x * kRepWaves + wave;  // owned row (if < nfree)
   const bool owner = v < nfree;
-  unsigned nbar = 0;
   if (tid == 0) sh_ok = 1;
   __syncthreads();
 
-  // ---- prologue: owners assemble their row, invert the diagonal block, publish
-  double pro[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // -, not-PD count, Es, Eg, Ep, ns, ng, np
+  // ---- prologue (rows assembled and inverted by k_row_assemble): owners load
+  // their row's blocks into registers, every workgroup loads r and M^-1 into LDS
+  const bool bad = (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagNotPD) != 0;
   T blockreg[36];
   int partner = -1;
   bool tr = false;
   long long ne = 0;
   if (owner) {
-    const int f = frame_of_var[v];
-    if (lane < 42) {
-      const int offI = lane < 36 ? kEHii + lane : kEGi + (lane - 36);
-      const int offJ = lane < 36 ? kEHjj + lane : kEGj + (lane - 36);
-      double s0 = 0.0, s1 = 0.0;
-      const long long i0 = iptr[f], i1 = iptr[f + 1];
-      long long k = i0;
-      for (; k + 1 < i1; k += 2) {
-        s0 += eb[(size_t)k * kEdgeWords + offI];
-        s1 += eb[(size_t)(k + 1) * kEdgeWords + offI];
-      }
-      if (k < i1) s0 += eb[(size_t)k * kEdgeWords + offI];
-      const long long j0 = jptr[f], j1 = jptr[f + 1];
-      for (k = j0; k + 1 < j1; k += 2) {
-        s0 += eb[(size_t)ej_sorted[k] * kEdgeWords + offJ];
-        s1 += eb[(size_t)ej_sorted[k + 1] * kEdgeWords + offJ];
-      }
-      if (k < j1) s0 += eb[(size_t)ej_sorted[k] * kEdgeWords + offJ];
-      blk[wave][lane] = s0 + s1;
-    }
+    if (lane < 36) blk[wave][lane] = (double)diag_t[v * 36 + lane];
     __builtin_amdgcn_wave_barrier();
-    if (lane < 6) st_shared(&r0_sh[6 * v + lane], (T)(-blk[wave][36 + lane]));
-    // row blocks into registers: lanes < ne hold the off-diagonal entries, lane ne the diagonal
+    // lanes < ne hold the off-diagonal entries, lane ne the diagonal
     ne = row_ptr[v + 1] - row_ptr[v];
     if (lane < ne) {
       const int2 en = entries[row_ptr[v] + lane];
@@ -944,33 +1004,9 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
 #pragma unroll
       for (int q = 0; q < 36; ++q) blockreg[q] = (T)blk[wave][q];
     }
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) {
-      double A[36];
-      for (int q = 0; q < 36; ++q) A[q] = blk[wave][q];
-      if (block_jacobi_inverse6(A, precond) < 0) {
-        pro[1] += 1.0;
-        for (int q = 0; q < 36; ++q) A[q] = (q % 7 == 0) ? 1.0 : 0.0;
-      }
-      for (int q = 0; q < 36; ++q) st_shared(&minv_sh[v * 36 + q], (T)A[q]);
-    }
   }
-  if (trace_slot)
-    for (long long e = (long long)blockIdx.x * kRepThreads + tid; e < E; e += (long long)gridDim.x * kRepThreads)
-      for (int q = 0; q < 6; ++q) pro[2 + q] += eb[(size_t)e * kEdgeWords + kEEs + q];
-  grid_sums<8, kRepWaves>(pro, parts, bar, nbar, flags, sh, &sh_ok, bar_base);
-  const bool bad = pro[1] > 0.0;
-  if (blockIdx.x == 0 && tid == 0) {
-    if (bad) atomicOr(flags, kFlagNotPD);
-    if (trace_slot) {
-      trace_slot[0] = pro[2] + pro[3] + pro[4];
-      for (int q = 0; q < 6; ++q) trace_slot[1 + q] = pro[2 + q];
-      trace_slot[7] = 0.0;
-    }
-  }
-  // every workgroup: full r and M^-1 into LDS, z = M^-1 r, p = z
-  for (long long o = tid; o < n; o += kRepThreads) r[o] = ld_shared(&r0_sh[o]);
-  for (long long o = tid; o < 36 * nfree; o += kRepThreads) minv[o] = ld_shared(&minv_sh[o]);
+  for (long long o = tid; o < n; o += kRepThreads) r[o] = r0[o];
+  for (long long o = tid; o < 36 * nfree; o += kRepThreads) minv[o] = minv_g[o];
   __syncthreads();
   double part = 0.0;
   for (long long o = tid; o < n; o += kRepThreads) {
@@ -1319,68 +1355,61 @@ constexpr size_t kRepLdsMax = 128 * 1024;
 
 template <class T>
 bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_out, double* poses, double* stats,
-                      bool update, T* minv_sh, T* hij, T* vec) {
+                      bool update, T* diag_t, T* minv_g, T* hij, T* vec) {
   long long nf = c.shape.nfree;
   long long n = 6 * nf;
   long long E = c.shape.E;
   const size_t lds = sizeof(T) * (5 * (size_t)n + 36 * (size_t)nf);
   if (lds > kRepLdsMax) return false;
   auto kern = k_solve_rep<T>;
-  static bool attr_set[2] = {false, false};
-  if (!attr_set[sizeof(T) == 8]) {
+  static bool attr_set = false;
+  static int per_cu_at = -1;
+  static size_t per_cu_lds = 0;
+  if (!attr_set) {
     check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)kRepLdsMax),
               "set LDS limit");
-    attr_set[sizeof(T) == 8] = true;
+    attr_set = true;
   }
-  int per_cu = 0;
-  check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kRepThreads,
-                                                         lds),
-            "occupancy query");
+  if (per_cu_at < 0 || per_cu_lds != lds) {
+    int per_cu = 0;
+    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                           kRepThreads, lds),
+              "occupancy query");
+    per_cu_at = per_cu;
+    per_cu_lds = lds;
+  }
+  // every workgroup waits for all others within an iteration: all must be resident
   const long long G = (nf + kRepWaves - 1) / kRepWaves;   // one row per wavefront
-  if (per_cu < 1 || G > (long long)per_cu * c.num_cus || G > kMaxSolveGroups) return false;
-  ensure(c.pcg_partials, sizeof(double) * 2 * kParts * kMaxSolveGroups);
+  if (per_cu_at < 1 || G > (long long)per_cu_at * c.num_cus || G > kMaxSolveGroups) return false;
   ensure(c.pcg_barrier, sizeof(unsigned) * 4);
-  // Exchange words carry an iteration tag that grows across launches, and the
-  // barrier counter only grows, so consecutive launches need no clearing: the
-  // buffer is zeroed when it is (re)allocated, after an error, or before a tag
-  // would wrap.
+  // Exchange words carry an iteration tag that grows across launches, so
+  // consecutive launches need no clearing: the buffer is zeroed when it is
+  // (re)allocated, after an error, or before a tag would wrap.
   const long long nwords = 2 * n * (long long)(sizeof(T) / 4);
   ensure(c.pcg_tags, sizeof(unsigned long long) * (size_t)(nwords + 1));
   unsigned long long* tags = c.pcg_tags.as<unsigned long long>();
   const unsigned long long tag_end = (unsigned long long)c.pcg_tag_base + (unsigned long long)iters + 1ull;
-  const unsigned long long bar_end = (unsigned long long)c.pcg_bar_base + (unsigned long long)G;
-  if (c.pcg_tags_dirty || c.pcg_tags_ptr != c.pcg_tags.p || tag_end >= 0xffffffffull || bar_end >= 0xffffffffull) {
+  if (c.pcg_tags_dirty || c.pcg_tags_ptr != c.pcg_tags.p || tag_end >= 0xffffffffull) {
     hipLaunchKernelGGL(k_zero_tags, dim3((unsigned)((c.pcg_tags.cap / 8 + 255) / 256)), dim3(256), 0, c.stream, tags,
                        (long long)(c.pcg_tags.cap / 8), c.pcg_barrier.as<unsigned>());
     c.pcg_tag_base = 0;
-    c.pcg_bar_base = 0;
     c.pcg_tags_ptr = c.pcg_tags.p;
     c.pcg_tags_dirty = false;
   }
-  unsigned tag_base = c.pcg_tag_base, bar_base = c.pcg_bar_base;
+  const unsigned tag_base = c.pcg_tag_base;
   c.pcg_tag_base += (unsigned)iters + 1u;
-  c.pcg_bar_base += (unsigned)G;
   T* r0 = vec;
-  double* parts = c.pcg_partials.as<double>();
-  unsigned* bar = c.pcg_barrier.as<unsigned>();
-  int F = c.shape.F;
-  int upd = update ? 1 : 0;
-  const double* eb = c.eblocks.as<double>();
-  const long long* ip = c.iptr.as<long long>();
-  const long long* jp = c.jptr.as<long long>();
-  const long long* ejs = c.ej_sorted.as<long long>();
-  const long long* rp = c.row_ptr.as<long long>();
-  const int2* en = c.row_entries.as<int2>();
-  const int* fov = c.frame_of_var.as<int>();
-  const int* vof = c.var_of.as<int>();
+  const int F = c.shape.F;
   int* fl = c.flags.as<int>();
-  int pc = c.precond;
-  void* args[] = {&nf, &F, &E, &iters, &eb, &hij, &ip, &jp, &ejs, &rp, &en, &fov, &vof, &minv_sh, &r0, &tags,
-                  &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl, &pc, &tag_base, &bar_base};
-  check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)G), dim3(kRepThreads),
-                                       args, (unsigned)lds, c.stream),
-            "cooperative solve launch");
+  hipLaunchKernelGGL(k_row_assemble<T>, dim3((unsigned)(nf + 1)), dim3(kAsmThreads), 0, c.stream, nf, E,
+                     c.eblocks.as<double>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
+                     c.ej_sorted.as<long long>(), c.frame_of_var.as<int>(), c.precond, diag_t, minv_g, r0, trace_slot,
+                     fl);
+  hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(kRepThreads), lds, c.stream, nf, F, iters, (const T*)hij,
+                     c.row_ptr.as<long long>(), c.row_entries.as<int2>(), c.frame_of_var.as<int>(),
+                     c.var_of.as<int>(), (const T*)diag_t, (const T*)minv_g, (const T*)r0, tags, delta_out, poses,
+                     update ? 1 : 0, stats, fl, tag_base);
   return true;
 }
 
@@ -1418,9 +1447,11 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
   if (c.solve_mode == 0 || c.solve_mode == 3) {
     bool ok = c.pcg_storage == 1
                   ? launch_solve_rep<double>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
-                                             c.minv64.as<double>(), c.hij64.as<double>(), c.pcg_vec.as<double>())
+                                             c.diag64.as<double>(), c.minv64.as<double>(), c.hij64.as<double>(),
+                                             c.pcg_vec.as<double>())
                   : launch_solve_rep<float>(c, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
-                                            c.minv32.as<float>(), c.hij32.as<float>(), c.pcg_vec.as<float>());
+                                            c.diag32.as<float>(), c.minv32.as<float>(), c.hij32.as<float>(),
+                                            c.pcg_vec.as<float>());
     if (ok) return;
     if (c.solve_mode == 3) fail(BF_ERR_UNSUPPORTED, "replicated-vector solve does not fit");
   }
