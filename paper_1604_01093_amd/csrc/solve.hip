@@ -975,7 +975,8 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   T* minv = ap + n;
   T* r2 = minv + 36 * nfree;  // the residual alternates between r and r2
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long long v = (long long)blockIdx.x * kRepWaves + wave;  // owned row (if < nfree)
+  const long long wg = blockIdx.x, ngroups = gridDim.x;
+  const long long v = wg * kRepWaves + wave;  // owned row (if < nfree)
   const bool owner = v < nfree;
   if (tid == 0) sh_ok = 1;
   __syncthreads();
@@ -1089,25 +1090,24 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
       const long long nw = n * WPV;
       for (long long o0 = tid; o0 < nw; o0 += (long long)kRepThreads * kMaxPer) {
         unsigned long long wv[kMaxPer];
-        bool ready = false;
+        const unsigned long long filler = (unsigned long long)tag << 32;  // past the end: ready
         unsigned spins = 0;
-        while (!ready) {
-          ready = true;
+        for (;;) {
+          // all loads of a poll are issued before any is tested
 #pragma unroll
           for (int q = 0; q < kMaxPer; ++q) {
             const long long o = o0 + (long long)q * kRepThreads;
-            if (o < nw) {
-              wv[q] = ld_shared(&apw[o]);
-              ready = ready && (unsigned)(wv[q] >> 32) == tag;
-            }
+            wv[q] = o < nw ? ld_shared(&apw[o]) : filler;
           }
-          if (!ready) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
-              atomicOr(flags, kFlagTimeout);
-              sh_ok = 0;
-              break;
-            }
+          bool ready = true;
+#pragma unroll
+          for (int q = 0; q < kMaxPer; ++q) ready = ready & ((unsigned)(wv[q] >> 32) == tag);
+          if (ready) break;
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) {
+            atomicOr(flags, kFlagTimeout);
+            sh_ok = 0;
+            break;
           }
         }
 #pragma unroll
@@ -1154,8 +1154,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   // epilogue: owners publish dx and update their poses
   if (owner && lane < 6 && delta_out) delta_out[6LL * frame_of_var[v] + lane] = bad ? 0.0 : (double)xo;
   if (delta_out)
-    for (long long o = (long long)blockIdx.x * kRepThreads + tid; o < 6LL * F;
-         o += (long long)gridDim.x * kRepThreads)
+    for (long long o = wg * kRepThreads + tid; o < 6LL * F; o += ngroups * kRepThreads)
       if (var_of[o / 6] < 0) delta_out[o] = 0.0;
   if (owner && update && !bad && sh_ok) {
     double xi[6];
@@ -1177,7 +1176,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
       }
     }
   }
-  if (blockIdx.x == 0 && tid == 0 && stats) {
+  if (wg == 0 && tid == 0 && stats) {
     stats[0] = rz0;
     stats[1] = rz;
     stats[2] = done;
