@@ -80,6 +80,13 @@ __device__ __forceinline__ void accumulate_jac(LaneAcc<MODE, 31>& A, const V* jg
   A.add(30, ph);
 }
 
+// Load base[i] with a 32-bit byte offset from a wavefront-uniform base (one
+// scalar base plus a vector offset: no 64-bit address arithmetic per lane).
+template <class T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ base, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+
 __device__ __forceinline__ float uniform_f(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
@@ -251,7 +258,7 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
   // step is issued before the current one is processed.
   int x = tid % W, y = tid / W;
   const int sx = NT % W, sy = NT / W;
-  float4 s_next = ndi[tid < HW ? tid : HW - 1];
+  float4 s_next = ld_at(ndi, (unsigned)(tid < HW ? tid : HW - 1));
   for (int base = wave * 64; base < HW; base += NT) {
     const int pix = base + lane;
     const int px = x, py = y;
@@ -264,13 +271,13 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
     const float4 s4 = s_next;
     {
       const int nxt = pix + NT;
-      s_next = ndi[nxt < HW ? nxt : HW - 1];
+      s_next = ld_at(ndi, (unsigned)(nxt < HW ? nxt : HW - 1));
     }
     float wv[kPayload];
     bool valid;
     {
       const float D = s4.w;
-      const float3 d = make_float3(mul_nc(kx[px], D), mul_nc(ky[py], D), D);
+      const float3 d = make_float3(mul_nc(ld_at(kx, (unsigned)px), D), mul_nc(ld_at(ky, (unsigned)py), D), D);
       const float3 c = xform_nc(R, t, d);
       const float iz = 1.0f / c.z;
       const float u = project_nc(in.fx, c.x, iz, in.cx);
@@ -280,11 +287,12 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
       // clamped copies for addressing (fminf/fmaxf also map NaN to the bound)
       const int xh = (int)fminf(fmaxf(xf, 0.0f), fWm1), yh = (int)fminf(fmaxf(yf, 0.0f), fHm1);
       const int xt = (int)fminf(fmaxf(x0f, 0.0f), fWm2), yt = (int)fminf(fmaxf(y0f, 0.0f), fHm2);
-      const float4 tq = ndj[yh * W + xh];
-      const int t0 = yt * W + xt;
-      const float g00 = gj[t0], g10 = gj[t0 + 1], g01 = gj[t0 + W], g11 = gj[t0 + W + 1];
-      float Gi = gi[pix < HW ? pix : HW - 1];
-      const float kxh = kx[xh], kyh = ky[yh];
+      const float4 tq = ld_at(ndj, (unsigned)(yh * W + xh));
+      const unsigned t0 = (unsigned)(yt * W + xt);
+      const float g00 = ld_at(gj, t0), g10 = ld_at(gj, t0 + 1u), g01 = ld_at(gj, t0 + (unsigned)W),
+                  g11 = ld_at(gj, t0 + (unsigned)W + 1u);
+      float Gi = ld_at(gi, (unsigned)(pix < HW ? pix : HW - 1));
+      const float kxh = ld_at(kx, (unsigned)xh), kyh = ld_at(ky, (unsigned)yh);
       valid = pix < HW && !is_nan(s4.x) && c.z > 0.0f && xf >= 0.0f && xf <= fWm1 && yf >= 0.0f && yf <= fHm1 &&
               !is_nan(tq.x);
       const float3 q = make_float3(mul_nc(kxh, tq.w), mul_nc(kyh, tq.w), tq.w);
