@@ -1123,26 +1123,26 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     if (!sh_ok) break;
     const double alpha = rz / pAp;
     if (owner && lane < 6) xo = (T)((double)xo + alpha * (double)p[6 * v + lane]);
-    // r' = r - alpha A p and z = M^-1 r', one element (row w, component a) per
-    // thread: each thread recomputes its row's six r' values, so the new residual
-    // goes to the other buffer without a barrier
+    // r' = r - alpha A p and z = M^-1 r', one block row per thread (its six r'
+    // values read once, the 6x6 inverse as whole rows); the new residual goes to
+    // the other buffer, so no barrier is needed between reading and writing
     T* rc = (k & 1) ? r2 : r;
     T* rn = (k & 1) ? r : r2;
     part = 0.0;
-    for (long long o = tid; o < n; o += kRepThreads) {
-      const long long w = o / 6;
-      const int a = (int)(o - 6 * w);
-      double s2 = 0.0, ra = 0.0;
+    for (long long w = tid; w < nfree; w += kRepThreads) {
+      double rb[6];
 #pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        const double rb = (double)(T)((double)rc[6 * w + b] - alpha * (double)ap[6 * w + b]);
-        s2 += (double)minv[w * 36 + 6 * a + b] * rb;
-        if (b == a) ra = rb;
+      for (int b = 0; b < 6; ++b) rb[b] = (double)(T)((double)rc[6 * w + b] - alpha * (double)ap[6 * w + b]);
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) s2 += (double)minv[w * 36 + 6 * a + b] * rb[b];
+        rn[6 * w + a] = (T)rb[a];
+        const T zt = (T)s2;
+        z[6 * w + a] = zt;
+        part += rb[a] * (double)zt;
       }
-      rn[o] = (T)ra;
-      const T zt = (T)s2;
-      z[o] = zt;
-      part += ra * (double)zt;
     }
     const double rz_new = block_sum_dpp<kRepWaves>(part, sh);
     const double beta = rz_new / rz;
