@@ -79,7 +79,8 @@ def _workers(n_items, workers=None):
     import os
     import sys
     if workers is None:
-        workers = min(16, os.cpu_count() or 1)
+        env = os.environ.get("BF_SYNTH_WORKERS")
+        workers = int(env) if env else min(16, os.cpu_count() or 1)
     torch = sys.modules.get("torch")
     if torch is not None and torch.cuda.is_initialized():
         workers = 1
