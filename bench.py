@@ -116,8 +116,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pcg-storage", type=int, default=0)
-    ap.add_argument("--accumulate", type=int, default=0)
+    ap.add_argument("--pcg-storage", type=int, default=None,
+                    help="0 FP32, 1 FP64 (default 0; 1 for global2000)")
+    ap.add_argument("--accumulate", type=int, default=None,
+                    help="0 FP32, 1 compensated FP32, 2 FP64 lane sums (default 0; 1 for global2000)")
     ap.add_argument("--solve-kernel", type=int, default=0)
     ap.add_argument("--dense-threads", type=int, default=256, help="threads per dense pair job (0 = timed choice)")
     ap.add_argument("--preconditioner", type=int, default=0, help="0 = 6x6 block-Jacobi, 1 = scalar Jacobi")
@@ -149,6 +151,12 @@ def main():
     big = args.workload == "global2000"
     if big:
         args.skip_batched = args.skip_serving = args.no_cpu_baseline = True
+    # global2000 runs the mixed precision that keeps one GN step within 1e-5 of the
+    # oracle (plain FP32 lane sums and PCG storage do not at that size)
+    if args.accumulate is None:
+        args.accumulate = 1 if big else 0
+    if args.pcg_storage is None:
+        args.pcg_storage = 1 if big else 0
     log(f"generating the {args.workload} workload")
     t0 = time.perf_counter()
     prob = make_problem(4 if big else 1)
