@@ -31,6 +31,7 @@ These decisions are taken in FP32 with the fixed operation sequence of
 """
 import numpy as np
 
+from .fp32 import fma32
 from .pairs import relative_pose64
 
 f32 = np.float32
@@ -68,12 +69,15 @@ def sparse_terms(Ti, Tj, p, q):
 # ----------------------------------------------------------------------------- dense
 
 def associate32(fi, fj, R32, t32, intr32, consts32, W, H):
-    """FP32 association decisions for pair job i -> j, fixed operation order:
+    """FP32 association decisions for pair job i -> j, fixed operation sequence
+    with fused multiply-adds (fma(a, b, c) = a*b + c rounded once, oracle.fp32):
 
-      c = ((R0*d.x + R1*d.y) + R2*d.z) + t   (row-wise),  m = (R0*n.x + R1*n.y) + R2*n.z
-      front: c.z > 0;  iz = 1/c.z;  u = ((fx*c.x)*iz) + cx,  v = ((fy*c.y)*iz) + cy
+      c_a = fma(R_a0, d.x, fma(R_a1, d.y, fma(R_a2, d.z, t_a)))   (row a of R_ji)
+      m_a = fma(R_a0, n.x, fma(R_a1, n.y, R_a2*n.z))
+      front: c.z > 0;  iz = 1/c.z;  u = fma(fx*c.x, iz, cx),  v = fma(fy*c.y, iz, cy)
       xh = floor(u + 0.5), yh = floor(v + 0.5) in [0,W-1] x [0,H-1]
-      e = c - q, (e.x*e.x + e.y*e.y) + e.z*e.z < tau_d2,  (m.x*N.x + m.y*N.y) + m.z*N.z > tau_n
+      e = c - q, fma(e.x, e.x, fma(e.y, e.y, e.z*e.z)) < tau_d2,
+      fma(m.x, N.x, fma(m.y, N.y, m.z*N.z)) > tau_n
       photometric: x0 = floor(u), y0 = floor(v) in [0,W-2] x [0,H-2], taps and G_i valid.
     Returns (geo_ok [H*W], photo_ok [H*W], xh, yh, x0, y0) as flat arrays."""
     fx, fy, cx, cy = intr32
@@ -82,14 +86,14 @@ def associate32(fi, fj, R32, t32, intr32, consts32, W, H):
     n = fi.N32.reshape(-1, 3)
     src_ok = fi.normal_ok.reshape(-1)
     with np.errstate(all="ignore"):
-        c = np.stack([((R32[a, 0] * d[:, 0] + R32[a, 1] * d[:, 1]) + R32[a, 2] * d[:, 2]) + t32[a]
-                      for a in range(3)], axis=1).astype(f32)
-        m = np.stack([(R32[a, 0] * n[:, 0] + R32[a, 1] * n[:, 1]) + R32[a, 2] * n[:, 2]
-                      for a in range(3)], axis=1).astype(f32)
+        c = np.stack([fma32(R32[a, 0], d[:, 0], fma32(R32[a, 1], d[:, 1], fma32(R32[a, 2], d[:, 2], t32[a])))
+                      for a in range(3)], axis=1)
+        m = np.stack([fma32(R32[a, 0], n[:, 0], fma32(R32[a, 1], n[:, 1], R32[a, 2] * n[:, 2]))
+                      for a in range(3)], axis=1)
         front = c[:, 2] > f32(0)
         iz = f32(1) / c[:, 2]
-        u = ((fx * c[:, 0]) * iz) + cx
-        v = ((fy * c[:, 1]) * iz) + cy
+        u = fma32(fx * c[:, 0], iz, cx)
+        v = fma32(fy * c[:, 1], iz, cy)
         xf = np.floor(u + f32(0.5))
         yf = np.floor(v + f32(0.5))
         inb = front & (xf >= f32(0)) & (xf <= f32(W - 1)) & (yf >= f32(0)) & (yf <= f32(H - 1))
@@ -99,9 +103,9 @@ def associate32(fi, fj, R32, t32, intr32, consts32, W, H):
         ok &= fj.normal_ok[yh, xh]
         q = fj.P32[yh, xh]
         e = (c - q).astype(f32)
-        dist2 = (e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1]) + e[:, 2] * e[:, 2]
+        dist2 = fma32(e[:, 0], e[:, 0], fma32(e[:, 1], e[:, 1], e[:, 2] * e[:, 2]))
         Nj = fj.N32[yh, xh]
-        dn = (m[:, 0] * Nj[:, 0] + m[:, 1] * Nj[:, 1]) + m[:, 2] * Nj[:, 2]
+        dn = fma32(m[:, 0], Nj[:, 0], fma32(m[:, 1], Nj[:, 1], m[:, 2] * Nj[:, 2]))
         geo = ok & (dist2 < tau_d2) & (dn > tau_n)
         x0f = np.floor(u)
         y0f = np.floor(v)

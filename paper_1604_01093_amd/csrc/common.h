@@ -1,10 +1,10 @@
 // Device-side helpers shared by the kernels of libbf.
 //
 // Decision arithmetic (which pixels associate, which frame pairs exist) is
-// written with floating-point contraction disabled and in a fixed operation
-// order, so that it is reproducible bit for bit: FP32 for the per-pixel
-// association, FP64 for the pair test and the relative poses.  Everything else
-// may use fused multiply-add.
+// written as a fixed operation sequence, so that it is reproducible bit for bit:
+// FP32 with explicit fused multiply-adds (and no other contraction) for the
+// per-pixel association, FP64 without contraction for the pair test and the
+// relative poses.  Everything else may use fused multiply-add.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -45,34 +45,37 @@ __device__ __forceinline__ void relative_pose_nc(const double* __restrict__ Ti, 
   for (int a = 0; a < 3; ++a) t[a] = (Tj[0 * 4 + a] * d0 + Tj[1 * 4 + a] * d1) + Tj[2 * 4 + a] * d2;
 }
 
-// c = R d + t in FP32, row-wise ((R0*d.x + R1*d.y) + R2*d.z) + t, no contraction.
-__device__ __forceinline__ float3 xform_nc(const float* R, const float* t, float3 d) {
-#pragma clang fp contract(off)
+// FP32 association arithmetic, a fixed sequence of fused multiply-adds (each
+// a*b + c rounded once; plain products and sums are never contracted):
+// c = R d + t row-wise, c_a = fma(R_a0, d.x, fma(R_a1, d.y, fma(R_a2, d.z, t_a))).
+__device__ __forceinline__ float3 xform32(const float* R, const float* t, float3 d) {
   float3 c;
-  c.x = ((R[0] * d.x + R[1] * d.y) + R[2] * d.z) + t[0];
-  c.y = ((R[3] * d.x + R[4] * d.y) + R[5] * d.z) + t[1];
-  c.z = ((R[6] * d.x + R[7] * d.y) + R[8] * d.z) + t[2];
+  c.x = __builtin_fmaf(R[0], d.x, __builtin_fmaf(R[1], d.y, __builtin_fmaf(R[2], d.z, t[0])));
+  c.y = __builtin_fmaf(R[3], d.x, __builtin_fmaf(R[4], d.y, __builtin_fmaf(R[5], d.z, t[1])));
+  c.z = __builtin_fmaf(R[6], d.x, __builtin_fmaf(R[7], d.y, __builtin_fmaf(R[8], d.z, t[2])));
   return c;
 }
 
-__device__ __forceinline__ float3 rotate_nc(const float* R, float3 n) {
+// m = R n, m_a = fma(R_a0, n.x, fma(R_a1, n.y, R_a2 * n.z))
+__device__ __forceinline__ float3 rotate32(const float* R, float3 n) {
 #pragma clang fp contract(off)
   float3 m;
-  m.x = (R[0] * n.x + R[1] * n.y) + R[2] * n.z;
-  m.y = (R[3] * n.x + R[4] * n.y) + R[5] * n.z;
-  m.z = (R[6] * n.x + R[7] * n.y) + R[8] * n.z;
+  m.x = __builtin_fmaf(R[0], n.x, __builtin_fmaf(R[1], n.y, R[2] * n.z));
+  m.y = __builtin_fmaf(R[3], n.x, __builtin_fmaf(R[4], n.y, R[5] * n.z));
+  m.z = __builtin_fmaf(R[6], n.x, __builtin_fmaf(R[7], n.y, R[8] * n.z));
   return m;
 }
 
-__device__ __forceinline__ float dot_nc(float3 a, float3 b) {
+// a.b = fma(a.x, b.x, fma(a.y, b.y, a.z * b.z))
+__device__ __forceinline__ float dot32(float3 a, float3 b) {
 #pragma clang fp contract(off)
-  return (a.x * b.x + a.y * b.y) + a.z * b.z;
+  return __builtin_fmaf(a.x, b.x, __builtin_fmaf(a.y, b.y, a.z * b.z));
 }
 
-// u = ((f * c) * iz) + cc, no contraction
-__device__ __forceinline__ float project_nc(float f, float c, float iz, float cc) {
+// u = fma(f * c, iz, cc)
+__device__ __forceinline__ float project32(float f, float c, float iz, float cc) {
 #pragma clang fp contract(off)
-  return (f * c) * iz + cc;
+  return __builtin_fmaf(f * c, iz, cc);
 }
 
 __device__ __forceinline__ float mul_nc(float a, float b) {

@@ -14,8 +14,8 @@
 // frame j.  The frame-i blocks follow per pair in FP64 from the adjoint
 // (J_i = -J_j Ad(T_ji)), so each pixel feeds one 6x6 block: 21 + 6 + 4 values.
 //
-// The association decisions are always taken in FP32 with a fixed operation
-// order and no contraction (reproducible bit for bit).  The residual/Jacobian
+// The association decisions are always taken in FP32 with a fixed sequence of
+// fused multiply-adds (reproducible bit for bit).  The residual/Jacobian
 // values and their accumulation come in three precisions:
 //   mode 0: FP32 values, FP32 lane sums;
 //   mode 1: FP32 values, two-sum compensated FP32 lane sums;
@@ -278,10 +278,10 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
     {
       const float D = s4.w;
       const float3 d = make_float3(mul_nc(ld_at(kx, (unsigned)px), D), mul_nc(ld_at(ky, (unsigned)py), D), D);
-      const float3 c = xform_nc(R, t, d);
+      const float3 c = xform32(R, t, d);
       const float iz = 1.0f / c.z;
-      const float u = project_nc(in.fx, c.x, iz, in.cx);
-      const float v = project_nc(in.fy, c.y, iz, in.cy);
+      const float u = project32(in.fx, c.x, iz, in.cx);
+      const float v = project32(in.fy, c.y, iz, in.cy);
       const float xf = floorf(u + 0.5f), yf = floorf(v + 0.5f);
       const float x0f = floorf(u), y0f = floorf(v);
       // clamped copies for addressing (fminf/fmaxf also map NaN to the bound)
@@ -298,8 +298,8 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
       const float3 q = make_float3(mul_nc(kxh, tq.w), mul_nc(kyh, tq.w), tq.w);
       const float3 e = make_float3(c.x - q.x, c.y - q.y, c.z - q.z);
       const float3 n = make_float3(s4.x, s4.y, s4.z);
-      const float3 m = rotate_nc(R, n);
-      valid = valid && dot_nc(e, e) < tau_d2 && dot_nc(m, make_float3(tq.x, tq.y, tq.z)) > tau_n;
+      const float3 m = rotate32(R, n);
+      valid = valid && dot32(e, e) < tau_d2 && dot32(m, make_float3(tq.x, tq.y, tq.z)) > tau_n;
       const bool ph = x0f >= 0.0f && x0f <= fWm2 && y0f >= 0.0f && y0f <= fHm2 && !is_nan(Gi) &&
                       !(is_nan(g00) || is_nan(g10) || is_nan(g01) || is_nan(g11));
       if (!ph) Gi = __builtin_nanf("");

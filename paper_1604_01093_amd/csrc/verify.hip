@@ -47,11 +47,11 @@ __global__ void __launch_bounds__(256) k_verify(const int* __restrict__ pairs, l
     if (is_nan(s.x)) continue;
     const float D = s.w;
     const float3 d = make_float3(mul_nc(kx[px], D), mul_nc(ky[py], D), D);
-    const float3 c = xform_nc(R, t, d);
+    const float3 c = xform32(R, t, d);
     if (!(c.z > 0.0f)) continue;
     const float iz = 1.0f / c.z;
-    const float u = project_nc(in.fx, c.x, iz, in.cx);
-    const float v = project_nc(in.fy, c.y, iz, in.cy);
+    const float u = project32(in.fx, c.x, iz, in.cx);
+    const float v = project32(in.fy, c.y, iz, in.cy);
     const float xf = floorf(u + 0.5f), yf = floorf(v + 0.5f);
     if (!(xf >= 0.0f && xf <= fWm1 && yf >= 0.0f && yf <= fHm1)) continue;
     const int xh = (int)xf, yh = (int)yf;
@@ -59,10 +59,10 @@ __global__ void __launch_bounds__(256) k_verify(const int* __restrict__ pairs, l
     if (is_nan(tq.x)) continue;
     const float3 q = make_float3(mul_nc(kx[xh], tq.w), mul_nc(ky[yh], tq.w), tq.w);
     const float3 e = make_float3(c.x - q.x, c.y - q.y, c.z - q.z);
-    const float e2 = dot_nc(e, e);
+    const float e2 = dot32(e, e);
     if (!(e2 < tau_d2)) continue;
-    const float3 m = rotate_nc(R, make_float3(s.x, s.y, s.z));
-    if (!(dot_nc(m, make_float3(tq.x, tq.y, tq.z)) > tau_n)) continue;
+    const float3 m = rotate32(R, make_float3(s.x, s.y, s.z));
+    if (!(dot32(m, make_float3(tq.x, tq.y, tq.z)) > tau_n)) continue;
     const float dc = Ca[pix] - Cb[yh * W + xh];
     if (!(fabsf(dc) < tau_c)) continue;
     err += sqrtf(e2);
