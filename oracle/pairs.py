@@ -39,9 +39,11 @@ def relative_pose64(Ti, Tj):
 
 
 def grid_points(W, H):
-    s = W // 80
-    xs = np.array([s * (5 + 10 * a) for a in range(8)])
-    ys = np.array([s * (5 + 10 * b) for b in range(6)])
+    """The 8x6 overlap-test grid: pixels 5, 15, ..., 75 by 5, 15, ..., 55 at 80x60,
+    scaled with the image (x = (5 + 10a) W / 80, y = (5 + 10b) H / 60, integer
+    division), so every grid pixel lies inside the image at any size."""
+    xs = np.array([(5 + 10 * a) * W // 80 for a in range(8)])
+    ys = np.array([(5 + 10 * b) * H // 60 for b in range(6)])
     return xs, ys
 
 

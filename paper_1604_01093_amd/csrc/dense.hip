@@ -277,7 +277,10 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
     bool valid;
     {
       const float D = s4.w;
-      const float3 d = make_float3(mul_nc(ld_at(kx, (unsigned)px), D), mul_nc(ld_at(ky, (unsigned)py), D), D);
+      // past the last pixel (pix >= HW, never valid) the row index runs beyond the
+      // image: clamp it for the load
+      const float3 d = make_float3(mul_nc(ld_at(kx, (unsigned)px), D),
+                                   mul_nc(ld_at(ky, (unsigned)(py < H ? py : H - 1)), D), D);
       const float3 c = xform32(R, t, d);
       const float iz = 1.0f / c.z;
       const float u = project32(in.fx, c.x, iz, in.cx);

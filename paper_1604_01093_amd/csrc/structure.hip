@@ -89,10 +89,10 @@ __global__ void __launch_bounds__(256) k_pair_rows(const float* __restrict__ dep
   __shared__ double Ti[16];
   __shared__ int red[256];
   const int tid = threadIdx.x;
-  const int s = W / 80 > 0 ? W / 80 : 1;
   if (tid < 48) {
-    int a = tid % 8, b = tid / 8;
-    int x = s * (5 + 10 * a), y = s * (5 + 10 * b);
+    // grid pixels 5, 15, ..., 75 by 5, 15, ..., 55 at 80x60, scaled with the image
+    const int a = tid % 8, b = tid / 8;
+    const int x = (int)((long long)(5 + 10 * a) * W / 80), y = (int)((long long)(5 + 10 * b) * H / 60);
     int ok = 0;
     double p0 = 0, p1 = 0, p2 = 0;
     if (x < W && y < H) {

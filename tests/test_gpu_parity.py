@@ -249,3 +249,37 @@ def test_gauss_newton_chunk_jacobi_preconditioner(ctx, chunk, solve_kernel, pcg_
     print(f"chunk jacobi kernel={solve_kernel} storage={pcg_storage}: pose err {rot:.3e} rad {tr:.3e} m", flush=True)
     assert rot < 1e-5 and tr < 1e-5
     assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
+
+
+@pytest.mark.parametrize("W,H", [(3, 3), (7, 5), (37, 23)])
+@pytest.mark.parametrize("dense_threads", [64, 256, 512])
+def test_small_and_ragged_images(ctx, W, H, dense_threads):
+    """Images smaller than one wavefront and sizes that are not a multiple of the
+    workgroup (the last step of every wavefront runs past the last pixel): the
+    records' association counts bit-exact and the energy at the initial poses
+    within 1e-6, then the solve within the pose tolerance, for each dense
+    workgroup size."""
+    f = 72.0 * W / 80.0
+    pr = make_chunk(num_frames=4, W=W, H=H, fx=f, fy=f, cx=W / 2.0, cy=H / 2.0, name=f"small{W}x{H}")
+    prm = Params(num_gn=3, num_pcg=10)
+    setup = Setup(pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q,
+                  pr.init_poses, prm)
+    dp = device_problem(pr)
+    res = bf.bf_eval_residuals(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, dense_threads=dense_threads),
+                               gn_iter=0, records=True)
+    _, _, blocks, en = build_system(setup, pr.init_poses, prm.dense_weight(0))
+    rec = res["records"].cpu().numpy()
+    for e in range(len(setup.edges)):
+        d = setup.edge_dense[e]
+        if d >= 0:
+            o = blocks[e]["dense"]
+            assert rec[d][29] == o["ngeo"] and rec[d][30] == o["nphoto"], e
+    assert res["n_geo"] == en["n_geo"] and res["n_photo"] == en["n_photo"]
+    assert abs(res["total"] - en["total"]) <= 1e-6 * en["total"]
+    ref = solve(pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q, pr.init_poses,
+                prm, linear="pcg")
+    out = bf.bf_gauss_newton(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, dense_threads=dense_threads))
+    rot, tr = pose_errors(out["poses"].cpu().numpy(), ref["poses"])
+    print(f"{W}x{H} threads {dense_threads}: n_geo {en['n_geo']}, pose err {rot:.2e} rad {tr:.2e} m", flush=True)
+    assert rot < 1e-5 and tr < 1e-5
+    assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
