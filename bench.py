@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bidirectional", type=int, default=0,
+                    help="1: dense terms over the pixels of both frames of every pair")
     ap.add_argument("--pcg-storage", type=int, default=None,
                     help="0 FP32, 1 FP64 (default 0; 1 for global2000)")
     ap.add_argument("--accumulate", type=int, default=None,
@@ -184,6 +186,7 @@ def main():
     out = torch.empty_like(init)
     params = bf.bf_params_default(num_gn=prob.n_gn, num_pcg=prob.n_pcg, pcg_storage=args.pcg_storage,
                                   accumulate=args.accumulate, solve_kernel=args.solve_kernel, timing=1,
+                                  bidirectional=args.bidirectional,
                                   dense_threads=args.dense_threads, preconditioner=args.preconditioner)
     st = bf.bf_build_structure(ctx, dp, init, params)
     P = st["pairs"].shape[0]
@@ -216,12 +219,18 @@ def main():
     value = prob.n_gn * args.steps / elapsed
 
     avg_dense_s = dense_us / max(dense_launches, 1) * 1e-6
-    alg_bytes = BYTES_PER_SOURCE_PIXEL * prob.width * prob.height * P
+    jobs = P * (2 if args.bidirectional else 1)
+    alg_bytes = BYTES_PER_SOURCE_PIXEL * prob.width * prob.height * jobs
     achieved = alg_bytes / avg_dense_s / 1e9
     phase /= args.steps
     log("per step (us): " + ", ".join(f"{n}={v:.1f}" for n, v in zip(
         ["setup", "dense", "edges", "assemble", "pcg", "final", "total", "dense_launches"], phase)))
     log(f"energy {res['energy']}")
+    Pout = out.cpu().numpy()
+    gt_rot = max(float(np.arccos(np.clip((np.trace(Pout[f, :3, :3].T @ prob.gt_poses[f][:3, :3]) - 1) / 2, -1, 1)))
+                 for f in range(prob.num_frames))
+    gt_tr = max(float(np.linalg.norm(Pout[f, :3, 3] - prob.gt_poses[f][:3, 3])) for f in range(prob.num_frames))
+    log(f"largest pose error against the generator's ground truth: {gt_rot:.4f} rad, {gt_tr:.4f} m")
 
     line = {
         "metric": ("GN iters/sec (JᵀJ build+PCG) at 2000 keyframes" if big else
@@ -239,10 +248,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": ("global2000: 2000 keyframes, 80x60, 5x5-room floor, lawnmower path, " if big else
                                 "global200: 200 keyframes, 80x60, 3-room apartment loop, ") +
-                               f"{P} dense pair jobs, {len(prob.corr_i)} sparse correspondences, "
+                               f"{jobs} dense pair jobs{' (both directions)' if args.bidirectional else ''}, "
+                               f"{len(prob.corr_i)} sparse correspondences, "
                                f"{prob.n_gn} GN x {prob.n_pcg} PCG",
                    "frames": prob.num_frames, "width": prob.width, "height": prob.height,
-                   "dense_pairs": int(P), "correspondences": int(len(prob.corr_i)),
+                   "dense_pairs": int(P), "dense_jobs": int(jobs), "correspondences": int(len(prob.corr_i)),
                    "gn_iters": prob.n_gn, "pcg_iters": prob.n_pcg,
                    "pcg_storage": "fp64" if args.pcg_storage else "fp32",
                    "accumulate": ["fp32", "fp32-two-sum", "fp64"][args.accumulate],

@@ -128,6 +128,12 @@ typedef struct bf_params {
                                kernel (a batch, or at most 64 free frames; else
                                BF_ERR_UNSUPPORTED); bf_gauss_newton_pruned ignores it.  With
                                timing = 1 only the setup and total times are reported. */
+  int32_t bidirectional;    /* 1: the dense terms are summed over the pixels of both frames of every
+                               pair (jobs i -> j and j -> i), not only over the lower frame's
+                               (Sec. 4.3 sums over the pixels of frame i of each pair in E; this is
+                               the symmetric variant).  Records then hold 2P jobs: pair p at p
+                               and its reverse at P + p. */
+  int32_t reserved2;        /* must be 0 */
 } bf_params;
 
 void bf_params_default(bf_params* out);
@@ -194,7 +200,8 @@ bf_status bf_build_structure(bf_context* ctx, const bf_frames* frames, const bf_
  *   out_energy (host) [4]: total, sparse, geometric, photometric (weighted, no 1/2).
  *   out_counts (host) [3]: sparse correspondences, geometric and photometric
  *                          residuals that were associated.
- *   out_pair_records (device, may be NULL) [num_pairs][32] float64: per dense pair job
+ *   out_pair_records (device, may be NULL) [num_pairs][32] float64 ([2 num_pairs][32]
+ *     with params->bidirectional, the reverse jobs after the forward ones): per dense pair job
  *     the upper triangle of sum w J_j^T J_j (21, row-major), sum w J_j^T r (6), the
  *     weighted geometric and photometric energies and the two residual counts, where
  *     J_j is the Jacobian with respect to the target frame's perturbation.

@@ -63,11 +63,17 @@ def edge_blocks(setup, poses, wd, assoc=None):
             b = sparse_pair_blocks(poses[i], poses[j], setup.pa[lo:hi], setup.qb[lo:hi], prm.w_sparse)
             rec["sparse"] = b
         d = setup.edge_dense[e]
+        rec["dense_rev"] = None
         if d >= 0:
             b = dense_pair_blocks(setup.frames[i], setup.frames[j], poses[i], poses[j], setup.intr, prm, wd,
                                   assoc=None if assoc is None else assoc[e])
             rec["dense"] = b
-        for part in ("sparse", "dense"):
+            if prm.bidirectional:
+                # the sums over the pixels of frame j as well (j -> i), roles swapped
+                r = dense_pair_blocks(setup.frames[j], setup.frames[i], poses[j], poses[i], setup.intr, prm, wd,
+                                      assoc=None if assoc is None else assoc.get(("rev", e)))
+                rec["dense_rev"] = dict(r, Hii=r["Hjj"], Hjj=r["Hii"], Hij=r["Hij"].T, gi=r["gj"], gj=r["gi"])
+        for part in ("sparse", "dense", "dense_rev"):
             if rec[part] is not None:
                 for k in tot:
                     tot[k] = tot[k] + rec[part][k]
@@ -77,11 +83,12 @@ def edge_blocks(setup, poses, wd, assoc=None):
 
 
 def energies(blocks):
+    dense = [b[k] for b in blocks for k in ("dense", "dense_rev") if b.get(k) is not None]
     es = sum(b["sparse"]["E"] for b in blocks if b["sparse"] is not None)
-    eg = sum(b["dense"]["Egeo"] for b in blocks if b["dense"] is not None)
-    ep = sum(b["dense"]["Ephoto"] for b in blocks if b["dense"] is not None)
-    ng = sum(b["dense"]["ngeo"] for b in blocks if b["dense"] is not None)
-    npp = sum(b["dense"]["nphoto"] for b in blocks if b["dense"] is not None)
+    eg = sum(d["Egeo"] for d in dense)
+    ep = sum(d["Ephoto"] for d in dense)
+    ng = sum(d["ngeo"] for d in dense)
+    npp = sum(d["nphoto"] for d in dense)
     ns = sum(b["sparse"]["n"] for b in blocks if b["sparse"] is not None)
     return {"total": es + eg + ep, "sparse": es, "geo": eg, "photo": ep,
             "n_sparse": ns, "n_geo": ng, "n_photo": npp}
@@ -119,6 +126,8 @@ def solve(depth, intensity, intr, corr_i, corr_j, p, q, init_poses, params=None,
         H, g, blocks, en = build_system(setup, poses, wd, assoc)
         if freeze_association and assoc is None:
             assoc = {e: b["dense"]["terms"] for e, b in enumerate(blocks) if b["dense"] is not None}
+            assoc.update({("rev", e): b["dense_rev"]["terms"] for e, b in enumerate(blocks)
+                          if b["dense_rev"] is not None})
         inert = inert_frames(H, setup.free)
         active = setup.free[~inert]
         Hr, gr, _ = reduce_system(H, g, active)

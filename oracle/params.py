@@ -32,6 +32,7 @@ class Params:
     use_dense: bool = True
     use_sparse: bool = True
     preconditioner: str = "block"   # "block": 6x6 block-Jacobi; "jacobi": the diagonal (Sec. 4.4)
+    bidirectional: bool = False     # dense terms of both directions per pair (i -> j and j -> i)
 
     def dense_weight(self, k):
         """w_d for Gauss-Newton iteration k (0-based)."""

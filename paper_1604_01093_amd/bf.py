@@ -53,7 +53,7 @@ class bf_params(ctypes.Structure):
                 ("solve_kernel", c_int32), ("dense_threads", c_int32),
                 ("tau_dist", c_double), ("tau_normal", c_double), ("max_angle_deg", c_double),
                 ("depth_min", c_double), ("depth_max", c_double), ("preconditioner", c_int32),
-                ("graph", c_int32)]
+                ("graph", c_int32), ("bidirectional", c_int32), ("reserved2", c_int32)]
 
 
 class bf_structure(ctypes.Structure):
@@ -292,7 +292,8 @@ def bf_eval_residuals(ctx, prob, poses, params, gn_iter=0, records=False):
     rec = None
     if records:
         st = bf_build_structure(ctx, prob, poses, params)
-        rec = torch.empty((st["pairs"].shape[0], 32), dtype=torch.float64, device=poses.device)
+        jobs = st["pairs"].shape[0] * (2 if params.bidirectional else 1)
+        rec = torch.empty((jobs, 32), dtype=torch.float64, device=poses.device)
     ctx._check(ctx.lib.bf_eval_residuals(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr),
                                          ctypes.byref(prob.corrs), prob._pairs_ref(), _ptr(poses),
                                          ctypes.byref(params), gn_iter, e, n,

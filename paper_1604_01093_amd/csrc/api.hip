@@ -95,6 +95,8 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
   if (prm->solve_kernel < 0 || prm->solve_kernel > 4) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..4");
   if (prm->preconditioner != 0 && prm->preconditioner != 1) fail(BF_ERR_INVALID_ARG, "preconditioner must be 0 or 1");
   if (prm->graph != 0 && prm->graph != 1) fail(BF_ERR_INVALID_ARG, "graph must be 0 or 1");
+  if (prm->bidirectional != 0 && prm->bidirectional != 1) fail(BF_ERR_INVALID_ARG, "bidirectional must be 0 or 1");
+  if (prm->reserved2 != 0) fail(BF_ERR_INVALID_ARG, "reserved2 must be 0");
   if (prm->dense_threads != 0 && prm->dense_threads != 64 && prm->dense_threads != 128 &&
       prm->dense_threads != 256 && prm->dense_threads != 512)
     fail(BF_ERR_INVALID_ARG, "dense_threads must be 0, 64, 128, 256 or 512");
@@ -139,13 +141,14 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
   c.pcg_storage = prm->pcg_storage;
   c.solve_mode = prm->solve_kernel;
   c.precond = prm->preconditioner;
+  c.bidir = prm->bidirectional;
   c.have_system = false;
   ensure(c.counts, 8 * sizeof(long long));
   ensure(c.flags, sizeof(int));
   set_segments(c, fr->num_frames, offsets, nseg);
   build_structure(c, *fr, *in, co, pairs, poses, *prm);
   const Shape& s = c.shape;
-  ensure(c.records, sizeof(double) * kRecWords * (s.P + 1));
+  ensure(c.records, sizeof(double) * kRecWords * ((c.bidir ? 2 : 1) * s.P + 1));
   ensure(c.eblocks, sizeof(double) * kEdgeWords * (s.E + 1));
   if (c.pcg_storage == 1) {
     ensure(c.hij64, sizeof(double) * 36 * (s.E + 1));
@@ -413,7 +416,8 @@ bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* fr, const bf_intri
     launch_edge_blocks(c, poses, *prm, false);
     launch_energy(c, c.energy.as<double>());
     if (out_records && c.shape.P > 0)
-      check_hip(hipMemcpyAsync(out_records, c.records.p, sizeof(double) * kRecWords * c.shape.P,
+      check_hip(hipMemcpyAsync(out_records, c.records.p,
+                               sizeof(double) * kRecWords * (c.bidir ? 2 : 1) * c.shape.P,
                                hipMemcpyDeviceToDevice, c.stream), "copy records");
     double e8[8];
     int hf = 0;

@@ -1,7 +1,8 @@
 // Dense pair jobs (paper Sec. 4.3, E_geo and E_photo; Sec. 4.4: the dense part of
 // J^T J is reduced locally and written once per pair).
 //
-// One workgroup per pair job (i -> j, source = lower index), one source pixel per
+// One workgroup per pair job (i -> j, source = lower index; with both directions
+// per pair a second job j -> i), one source pixel per
 // lane per step.  For each pixel with a valid normal:
 //   d = P_i(x,y), c = T_ji d, m = R_ji n
 //   nearest pixel (floor(u+1/2), floor(v+1/2)) of pi(c) in frame j with a valid
@@ -197,7 +198,7 @@ constexpr int kPayload = 16;
 constexpr int kQueue = 128;
 
 template <int MODE, bool JAC, int NT>
-__global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, long long P,
+__global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, long long P, int bidir,
                                               const float4* __restrict__ nd, const float* __restrict__ grad,
                                               const float* __restrict__ kx, const float* __restrict__ ky,
                                               const double* __restrict__ kx64, const double* __restrict__ ky64,
@@ -217,9 +218,12 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
   // stay in that XCD's L2).  The grid is a multiple of 8.
   const long long per = gridDim.x / 8;
   const long long p = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (p >= P) return;
+  // jobs [0, P): pair p as (i -> j); with both directions, jobs [P, 2P): (j -> i)
+  if (p >= (bidir ? 2 * P : P)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int i = pairs[2 * p], j = pairs[2 * p + 1];
+  const int rev = p >= P ? 1 : 0;
+  const long long pp = p - (rev ? P : 0);
+  const int i = pairs[2 * pp + rev], j = pairs[2 * pp + 1 - rev];
   const int W = in.W, H = in.H, HW = W * H;
 
   // relative pose: FP64 (fixed order), FP32 copy for the decisions; wave-uniform
@@ -415,13 +419,14 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
 template <int MODE, bool JAC, int NT>
 void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd) {
   const long long P = c.shape.P;
+  const long long jobs = c.bidir ? 2 * P : P;
   Intr32 i32{(float)in.fx, (float)in.fy, (float)in.cx, (float)in.cy, in.width, in.height};
   float tau_d2 = (float)(prm.tau_dist * prm.tau_dist);
   float tau_n = (float)prm.tau_normal;
   double swg = sqrt(wd * prm.w_geo);
   double swp = sqrt(wd * prm.w_photo);
-  unsigned grid = (unsigned)(8 * ((P + 7) / 8));
-  hipLaunchKernelGGL((k_dense<MODE, JAC, NT>), dim3(grid), dim3(NT), 0, c.stream, c.pairs.as<int>(), P,
+  unsigned grid = (unsigned)(8 * ((jobs + 7) / 8));
+  hipLaunchKernelGGL((k_dense<MODE, JAC, NT>), dim3(grid), dim3(NT), 0, c.stream, c.pairs.as<int>(), P, c.bidir,
                      c.nd.as<float4>(), c.grad.as<float>(), c.kx.as<float>(), c.ky.as<float>(), c.kx64.as<double>(),
                      c.ky64.as<double>(), poses, i32, in.fx, in.fy, in.cx, in.cy, tau_d2, tau_n, swg, swp,
                      c.records.as<double>());
@@ -458,7 +463,8 @@ int choose_threads(Context& c, const bf_intrinsics& in, const double* poses, con
                    bool jac) {
   if (prm.dense_threads != 0) return prm.dense_threads;
   int bucket = 0;
-  while (bucket < 40 && (1LL << bucket) < c.shape.P) ++bucket;
+  const long long jobs = c.bidir ? 2 * c.shape.P : c.shape.P;
+  while (bucket < 40 && (1LL << bucket) < jobs) ++bucket;
   const long long key = (((long long)in.width * in.height * 4 + prm.accumulate) * 2 + (jac ? 1 : 0)) * 64 + bucket;
   auto it = c.dense_threads.find(key);
   if (it != c.dense_threads.end()) return it->second;

@@ -48,6 +48,7 @@ struct Context {
   bool have_system = false;
   int pcg_storage = 0;
   int precond = 0;          // 0 = 6x6 block-Jacobi, 1 = scalar Jacobi
+  int bidir = 0;            // 1: two dense pair jobs per pair (i -> j, then j -> i at job P + p)
   double timings[8] = {0};
 
   // frames

@@ -43,6 +43,7 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
                                                     const long long* __restrict__ edense,
                                                     const long long* __restrict__ esparse,
                                                     const double* __restrict__ mom, const double* __restrict__ rec,
+                                                    long long P, int bidir,
                                                     const double* __restrict__ poses, double w_sparse, int jac,
                                                     double* __restrict__ eb, T* __restrict__ hij_store) {
   long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,6 +76,28 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
     Ep = r[kRecEp];
     ng = r[kRecNg];
     np = r[kRecNp];
+  }
+  // the reverse job (j -> i, record P + d): its block is the one of frame i
+  double Hii_r[36], gi_r[6];
+  const bool has_rev = bidir && d >= 0;
+  for (int k = 0; k < 36; ++k) Hii_r[k] = 0.0;
+  for (int k = 0; k < 6; ++k) gi_r[k] = 0.0;
+  if (has_rev) {
+    const double* r = rec + (size_t)(P + d) * kRecWords;
+    if (jac) {
+      int k = 0;
+      for (int a = 0; a < 6; ++a)
+        for (int b = a; b < 6; ++b) {
+          Hii_r[6 * a + b] = r[k];
+          Hii_r[6 * b + a] = r[k];
+          ++k;
+        }
+      for (int a = 0; a < 6; ++a) gi_r[a] = r[kRecG + a];
+    }
+    Eg += r[kRecEg];
+    Ep += r[kRecEp];
+    ng += r[kRecNg];
+    np += r[kRecNp];
   }
   double Es = 0, ns = 0;
   // sparse moments
@@ -121,6 +144,41 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
           out[kEHjj + 6 * (a + 3) + (b + 3)] = Hjj_d[6 * (a + 3) + b + 3] + (a == b ? w * n : 0.0);
         }
     }
+    // reverse job: Ad(T_ij) = [[R^T, 0], [[t2]x R^T, R^T]] with t2 = -R^T t;
+    // H_jj += Ad2^T Hii_r Ad2 (symmetrised), H_ij -= Hii_r Ad2, g_j -= Ad2^T gi_r
+    double Y2[36], R2[9], TR2[9];
+    if (has_rev) {
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) R2[3 * a + b] = R[3 * b + a];
+      double t2[3], Tx2[9];
+      for (int a = 0; a < 3; ++a) t2[a] = -(R2[3 * a] * t[0] + R2[3 * a + 1] * t[1] + R2[3 * a + 2] * t[2]);
+      skew(t2, Tx2);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          TR2[3 * a + b] = Tx2[3 * a] * R2[b] + Tx2[3 * a + 1] * R2[3 + b] + Tx2[3 * a + 2] * R2[6 + b];
+    }
+    auto ad2 = [&](int r, int c) -> double {
+      if (r < 3) return c < 3 ? R2[3 * r + c] : 0.0;
+      return c < 3 ? TR2[3 * (r - 3) + c] : R2[3 * (r - 3) + (c - 3)];
+    };
+    if (has_rev) {
+      // Y2 = Hii_r Ad2
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          double v = 0.0;
+          for (int k = 0; k < 6; ++k) v += Hii_r[6 * a + k] * ad2(k, b);
+          Y2[6 * a + b] = v;
+        }
+      double Z[36];
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          double v = 0.0;
+          for (int k = 0; k < 6; ++k) v += ad2(k, a) * Y2[6 * k + b];
+          Z[6 * a + b] = v;
+        }
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) out[kEHjj + 6 * a + b] += 0.5 * (Z[6 * a + b] + Z[6 * b + a]);
+    }
     // H_ii sparse part
     double Hii[36];
     {
@@ -158,7 +216,7 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
       for (int b = 0; b < 6; ++b) {
         double v = 0.0;
         for (int k = 0; k < 6; ++k) v += Y[6 * a + k] * ad(k, b);
-        Hii[6 * a + b] += v;
+        Hii[6 * a + b] += v + Hii_r[6 * a + b];
       }
     // symmetrise: both triangles from the same sums
     for (int a = 0; a < 6; ++a)
@@ -204,7 +262,7 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
         }
     }
     for (int k = 0; k < 36; ++k) {
-      double v = Hij[k] - Y[k];
+      double v = Hij[k] - Y[k] - (has_rev ? Y2[k] : 0.0);
       out[kEHij + k] = v;
       hij_store[(size_t)e * 36 + k] = (T)v;
     }
@@ -238,10 +296,12 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
     }
     // dense: g_j += gj_d, g_i -= Ad^T gj_d
     for (int a = 0; a < 6; ++a) {
-      double v = 0.0;
+      double v = 0.0, v2 = 0.0;
       for (int k = 0; k < 6; ++k) v += ad(k, a) * gj_d[k];
-      out[kEGi + a] = gi[a] - v;
-      out[kEGj + a] = gj[a] + gj_d[a];
+      if (has_rev)
+        for (int k = 0; k < 6; ++k) v2 += ad2(k, a) * gi_r[k];
+      out[kEGi + a] = gi[a] - v + gi_r[a];
+      out[kEGj + a] = gj[a] + gj_d[a] - v2;
     }
   }
   out[kEEs] = Es;
@@ -1259,12 +1319,14 @@ void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, b
   if (c.pcg_storage == 1)
     hipLaunchKernelGGL(k_edge_blocks<double>, dim3(grid), dim3(64), 0, c.stream, c.edge_ij.as<int>(), E,
                        c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.moments.as<double>(),
-                       c.records.as<double>(), poses, prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
+                       c.records.as<double>(), (long long)c.shape.P, c.bidir, poses,
+                       prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
                        c.eblocks.as<double>(), c.hij64.as<double>());
   else
     hipLaunchKernelGGL(k_edge_blocks<float>, dim3(grid), dim3(64), 0, c.stream, c.edge_ij.as<int>(), E,
                        c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.moments.as<double>(),
-                       c.records.as<double>(), poses, prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
+                       c.records.as<double>(), (long long)c.shape.P, c.bidir, poses,
+                       prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
                        c.eblocks.as<double>(), c.hij32.as<float>());
 }
 

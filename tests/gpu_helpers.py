@@ -22,7 +22,7 @@ def bf_params_from(prm: Params, **kw):
         dense_ramp=int(prm.dense_ramp), use_sparse=int(prm.use_sparse), use_dense=int(prm.use_dense),
         num_gn=prm.num_gn, num_pcg=prm.num_pcg, tau_dist=prm.tau_dist, tau_normal=prm.tau_normal,
         max_angle_deg=prm.max_angle_deg, depth_min=prm.depth_min, depth_max=prm.depth_max,
-        preconditioner={"block": 0, "jacobi": 1}[prm.preconditioner])
+        preconditioner={"block": 0, "jacobi": 1}[prm.preconditioner], bidirectional=int(prm.bidirectional))
     for k, v in kw.items():
         setattr(p, k, v)
     return p

@@ -283,3 +283,48 @@ def test_small_and_ragged_images(ctx, W, H, dense_threads):
     print(f"{W}x{H} threads {dense_threads}: n_geo {en['n_geo']}, pose err {rot:.2e} rad {tr:.2e} m", flush=True)
     assert rot < 1e-5 and tr < 1e-5
     assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
+
+
+@pytest.mark.parametrize("solve_kernel,accumulate", [(0, 0), (3, 0), (2, 1)])
+def test_bidirectional_chunk(ctx, chunk, solve_kernel, accumulate):
+    """Dense terms over the pixels of both frames of every pair (a second job
+    j -> i per pair): forward and reverse records' counts bit-exact and their
+    blocks within 1e-5 of the oracle's at fixed poses, the assembled normal
+    equations within 1e-5, and the Gauss-Newton solve within the pose tolerance."""
+    prm = Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg, bidirectional=True)
+    setup = Setup(chunk.depth, chunk.intensity, chunk.intrinsics, chunk.corr_i, chunk.corr_j, chunk.corr_p,
+                  chunk.corr_q, chunk.init_poses, prm)
+    dp = device_problem(chunk)
+    kw = dict(solve_kernel=solve_kernel, accumulate=accumulate)
+    res = bf.bf_eval_residuals(ctx, dp, poses_cuda(chunk.init_poses), bf_params_from(prm, **kw), gn_iter=2,
+                               records=True)
+    rec = res["records"].cpu().numpy()
+    P = len(setup.pairs)
+    assert rec.shape[0] == 2 * P
+    _, _, blocks, en = build_system(setup, chunk.init_poses, prm.dense_weight(2))
+    for e, (i, j) in enumerate(setup.edges):
+        d = setup.edge_dense[e]
+        if d < 0:
+            continue
+        for r, o, blk in ((rec[d], blocks[e]["dense"], "Hjj"), (rec[P + d], blocks[e]["dense_rev"], "Hii")):
+            assert r[29] == o["ngeo"] and r[30] == o["nphoto"], (i, j, blk)
+            assert block_rel_err(r[:21], upper21(o[blk])) < 1e-5, (i, j, blk)
+    assert res["n_geo"] == en["n_geo"] and res["n_photo"] == en["n_photo"]
+    assert abs(res["total"] - en["total"]) <= 1e-6 * en["total"]
+    out = bf.bf_build_normal_equations(ctx, dp, poses_cuda(chunk.init_poses), bf_params_from(prm, **kw), gn_iter=1)
+    H_ref, g_ref, _, _ = build_system(setup, chunk.init_poses, prm.dense_weight(1))
+    H, g = out["H"].cpu().numpy(), out["g"].cpu().numpy()
+    F = chunk.num_frames
+    for a in range(F):
+        for b in range(F):
+            ref = H_ref[6 * a:6 * a + 6, 6 * b:6 * b + 6]
+            if np.abs(ref).max() > 0:
+                assert block_rel_err(H[6 * a:6 * a + 6, 6 * b:6 * b + 6], ref) < 1e-5, (a, b)
+    assert np.linalg.norm(g - g_ref) <= 1e-5 * np.linalg.norm(g_ref)
+    ref = solve(chunk.depth, chunk.intensity, chunk.intrinsics, chunk.corr_i, chunk.corr_j, chunk.corr_p,
+                chunk.corr_q, chunk.init_poses, prm, linear="pcg")
+    sol = bf.bf_gauss_newton(ctx, dp, poses_cuda(chunk.init_poses), bf_params_from(prm, **kw))
+    rot, tr = pose_errors(sol["poses"].cpu().numpy(), ref["poses"])
+    print(f"bidirectional {kw}: pose err {rot:.2e} rad {tr:.2e} m", flush=True)
+    assert rot < 1e-5 and tr < 1e-5
+    assert abs(sol["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]

@@ -137,16 +137,22 @@ def _frozen_residuals(setup, poses, assoc, prm):
             t = dense_terms(setup.frames[i], setup.frames[j], poses[i], poses[j], setup.intr, prm, assoc=assoc[e])
             out.append(np.sqrt(prm.w_geo) * t["rg"])
             out.append(np.sqrt(prm.w_photo) * t["rp"])
+            if prm.bidirectional:
+                t = dense_terms(setup.frames[j], setup.frames[i], poses[j], poses[i], setup.intr, prm,
+                                assoc=assoc[("rev", e)])
+                out.append(np.sqrt(prm.w_geo) * t["rg"])
+                out.append(np.sqrt(prm.w_photo) * t["rp"])
     return np.concatenate(out)
 
 
-@pytest.mark.parametrize("nframes", [2, 3])
-def test_gn_minimum_matches_least_squares(nframes):
+@pytest.mark.parametrize("nframes,bidirectional", [(2, False), (3, False), (3, True)])
+def test_gn_minimum_matches_least_squares(nframes, bidirectional):
     """All terms, association frozen at the converged poses: an independent
     trust-region least-squares minimiser with finite-difference Jacobians, started
-    from several random perturbations, finds the same minimum as Gauss-Newton."""
+    from several random perturbations, finds the same minimum as Gauss-Newton
+    (also with the dense terms of both directions of every pair)."""
     prob = make_chunk(num_frames=nframes, noise=True, config=0, seed_offset=20 + nframes)
-    prm = Params(num_gn=40, dense_ramp=False)
+    prm = Params(num_gn=40, dense_ramp=False, bidirectional=bidirectional)
     res = solve(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p,
                 prob.corr_q, prob.init_poses, prm, freeze_association=True)
     X = res["poses"]

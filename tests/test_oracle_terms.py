@@ -187,10 +187,13 @@ def test_photometric_exact_zero_on_shifted_plane():
     assert np.abs(tb["rp"]).min() > 1e-5
 
 
-def test_assembly_matches_stacked_jacobian(noisy3):
-    """Block-assembled H and g equal J^T J and J^T r of the explicitly stacked J."""
+@pytest.mark.parametrize("bidirectional", [False, True])
+def test_assembly_matches_stacked_jacobian(noisy3, bidirectional):
+    """Block-assembled H and g equal J^T J and J^T r of the explicitly stacked J
+    (with both directions per pair: the j -> i rows, whose Jacobians are taken with
+    respect to frame j as source and frame i as target, placed in their own columns)."""
     prob = noisy3
-    prm = Params(dense_ramp=False, w_photo=0.7, w_sparse=0.3)
+    prm = Params(dense_ramp=False, w_photo=0.7, w_sparse=0.3, bidirectional=bidirectional)
     s = Setup(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p,
               prob.corr_q, prob.init_poses, prm)
     H, g, blocks, _ = build_system(s, prob.init_poses, 1.0)
@@ -207,6 +210,11 @@ def test_assembly_matches_stacked_jacobian(noisy3):
             t = b["dense"]["terms"]
             parts.append((np.sqrt(prm.w_geo), t["rg"], t["Jg_i"], t["Jg_j"]))
             parts.append((np.sqrt(prm.w_photo), t["rp"], t["Jp_i"], t["Jp_j"]))
+        if bidirectional and b["dense"] is not None:
+            t = dense_terms(s.frames[j], s.frames[i], prob.init_poses[j], prob.init_poses[i], prob.intrinsics, prm)
+            assert t["geo"].sum() > 0
+            parts.append((np.sqrt(prm.w_geo), t["rg"], t["Jg_j"], t["Jg_i"]))
+            parts.append((np.sqrt(prm.w_photo), t["rp"], t["Jp_j"], t["Jp_i"]))
         for sw, r, Ji, Jj in parts:
             Jr = np.zeros((len(r), 6 * F))
             Jr[:, 6 * i:6 * i + 6] = sw * Ji
