@@ -1015,7 +1015,9 @@ __global__ void __launch_bounds__(kAsmThreads) k_row_assemble(
 constexpr int kRepThreads = 512;
 constexpr int kRepWaves = kRepThreads / 64;
 
-template <class T>
+// MLDS: the block-Jacobi inverses are copied into LDS (else read from memory,
+// for problems whose vectors fit in LDS but not together with the inverses).
+template <class T, bool MLDS>
 __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     long long nfree, int F, int iters, const T* __restrict__ hij, const long long* __restrict__ row_ptr,
     const int2* __restrict__ entries, const int* __restrict__ frame_of_var, const int* __restrict__ var_of,
@@ -1032,8 +1034,9 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   T* z = r + n;
   T* p = z + n;
   T* ap = p + n;
-  T* minv = ap + n;
-  T* r2 = minv + 36 * nfree;  // the residual alternates between r and r2
+  T* minv_l = ap + n;
+  T* r2 = minv_l + (MLDS ? 36 * nfree : 0);  // the residual alternates between r and r2
+  const T* minv = MLDS ? minv_l : minv_g;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long long wg = blockIdx.x, ngroups = gridDim.x;
   const long long v = wg * kRepWaves + wave;  // owned row (if < nfree)
@@ -1067,7 +1070,8 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     }
   }
   for (long long o = tid; o < n; o += kRepThreads) r[o] = r0[o];
-  for (long long o = tid; o < 36 * nfree; o += kRepThreads) minv[o] = minv_g[o];
+  if constexpr (MLDS)
+    for (long long o = tid; o < 36 * nfree; o += kRepThreads) minv_l[o] = minv_g[o];
   __syncthreads();
   double part = 0.0;
   for (long long o = tid; o < n; o += kRepThreads) {
@@ -1420,25 +1424,30 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   long long nf = c.shape.nfree;
   long long n = 6 * nf;
   long long E = c.shape.E;
-  const size_t lds = sizeof(T) * (5 * (size_t)n + 36 * (size_t)nf);
+  // vectors and inverses in LDS if they fit, else the vectors only
+  const bool mlds = sizeof(T) * (5 * (size_t)n + 36 * (size_t)nf) <= kRepLdsMax;
+  const size_t lds = sizeof(T) * (5 * (size_t)n + (mlds ? 36 * (size_t)nf : 0));
   if (lds > kRepLdsMax) return false;
-  auto kern = k_solve_rep<T>;
+  auto kern = mlds ? k_solve_rep<T, true> : k_solve_rep<T, false>;
   static bool attr_set = false;
   static int per_cu_at = -1;
   static size_t per_cu_lds = 0;
+  static bool per_cu_mlds = false;
   if (!attr_set) {
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)kRepLdsMax),
-              "set LDS limit");
+    for (auto kk : {k_solve_rep<T, true>, k_solve_rep<T, false>})
+      check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kk), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kRepLdsMax),
+                "set LDS limit");
     attr_set = true;
   }
-  if (per_cu_at < 0 || per_cu_lds != lds) {
+  if (per_cu_at < 0 || per_cu_lds != lds || per_cu_mlds != mlds) {
     int per_cu = 0;
     check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
                                                            kRepThreads, lds),
               "occupancy query");
     per_cu_at = per_cu;
     per_cu_lds = lds;
+    per_cu_mlds = mlds;
   }
   // every workgroup waits for all others within an iteration: all must be resident
   const long long G = (nf + kRepWaves - 1) / kRepWaves;   // one row per wavefront

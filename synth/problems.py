@@ -464,6 +464,11 @@ def make_problem(config, seed_offset=0):
     if config in (4, "global2000"):
         return make_global(2000, "floor", config=4, seed_offset=seed_offset, outlier_rate=0.10,
                            corr_range=(200, 200), name="global2000", per_pair_streams=True)
+    if isinstance(config, str) and config.startswith("floor3:"):
+        # a global problem of the serving workload's kind with the given keyframe count
+        n = int(config.split(":")[1])
+        return make_global(n, "floor3", config=3, seed_offset=seed_offset, outlier_rate=0.10,
+                           corr_range=(200, 200), name=f"floor3_{n}", per_pair_streams=True)
     raise ValueError(f"unknown config {config!r}")
 
 
