@@ -104,10 +104,12 @@ def cpu_baseline(prob, n_gn, n_pcg):
         for n, f in enumerate(s.free):
             poses[f] = poses[f] @ exp_se3(dx[6 * n:6 * n + 6])
         t2 = time.perf_counter()
+    import os
     return {"value": 1.0 / (t2 - t1), "unit": "GN iters/s", "cores": 1, "kind": "oracle",
             "sample": f"1 of {n_gn} Gauss-Newton iterations ({n_pcg} PCG) of the same workload, single thread; "
                       f"per-solve setup took {t1 - t0:.1f} s and is excluded",
-            "seconds": round(t2 - t1, 3)}
+            "seconds": round(t2 - t1, 3), "host_cpu_count": os.cpu_count(),
+            "host_affinity_cores": len(os.sched_getaffinity(0))}
 
 
 def main():
@@ -200,6 +202,7 @@ def main():
     dense_us = 0.0
     dense_launches = 0
     phase = np.zeros(8)
+    solve_us = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     last = t0
@@ -207,6 +210,7 @@ def main():
         res = bf.bf_gauss_newton(ctx, dp, init, params, out_poses=out)
         tm = ctx.last_timings()
         dense_us += tm["dense_us"]
+        solve_us.append(tm["total_us"])
         dense_launches += int(tm["dense_launches"])
         phase += np.array([tm[key] for key in ("setup_us", "dense_us", "edges_us", "assemble_us", "pcg_us",
                                                "final_us", "total_us", "dense_launches")])
@@ -263,6 +267,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if big else measured_traffic(), "avg_launch_us": round(avg_dense_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": int(alg_bytes)},
+        "solve_us_hip_events": {"median": round(float(np.median(solve_us)), 1),
+                                "p99": round(float(np.percentile(solve_us, 99)), 1)},
+        "accuracy": {"max_rot_rad_vs_ground_truth": round(gt_rot, 6), "max_trans_m_vs_ground_truth": round(gt_tr, 6),
+                     "oracle_parity": "tests/test_gpu_global200.py, tests/test_gpu_global2000.py"},
         "phase_us_per_step": {n: round(v, 1) for n, v in zip(
             ["setup", "dense", "edges", "assemble", "pcg", "final", "total"], phase[:7])},
     }
