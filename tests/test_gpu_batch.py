@@ -70,10 +70,11 @@ def test_batch_matches_oracle_per_problem(ctx, chunks):
             assert abs(t[0] - ref["trace"][k]["total"]) <= 1e-4 * ref["trace"][k]["total"]
 
 
-def test_batch_equals_alone_bitwise(ctx, chunks):
-    prm = Params(num_gn=chunks[0].n_gn, num_pcg=chunks[0].n_pcg)
+@pytest.mark.parametrize("bidirectional,pcg_storage", [(False, 0), (True, 0), (False, 1)])
+def test_batch_equals_alone_bitwise(ctx, chunks, bidirectional, pcg_storage):
+    prm = Params(num_gn=chunks[0].n_gn, num_pcg=chunks[0].n_pcg, bidirectional=bidirectional)
     members = [chunks[1], single_frame(chunks[0]), chunks[2], chunks[0]]
-    params = bf_params_from(prm, dense_threads=256)
+    params = bf_params_from(prm, dense_threads=256, pcg_storage=pcg_storage)
     dp, offs, init = bf.device_batch(members)
     out = bf.bf_gauss_newton_batch(ctx, dp, offs, init, params)
     for b, pr in enumerate(members):

@@ -111,6 +111,20 @@ def test_graph_recaptures_for_new_structure(ctx, chunks):
     same(t1, t0)
 
 
+def test_graph_bidirectional_fp64_batch(ctx, chunks):
+    """Both dense directions and FP64 PCG storage: replays bitwise the eager call."""
+    dp, offs, init = bf.device_batch(chunks)
+    kw = dict(bidirectional=1, pcg_storage=1)
+    ref = batch(ctx, dp, offs, init, params(chunks[0], 0, **kw), torch.empty_like(init))
+    ref = dict(ref, poses=ref["poses"].clone())
+    out = torch.empty_like(init)
+    n0 = ctx.graph_captures()
+    for rep in range(3):
+        same(batch(ctx, dp, offs, init, params(chunks[0], 1, **kw), out), ref)
+        torch.cuda.synchronize()
+    assert ctx.graph_captures() - n0 == 1
+
+
 def test_graph_plain_chunk(ctx, chunks):
     ch = chunks[1]
     dp = bf.DeviceProblem.from_numpy(ch.depth, ch.intensity, ch.intrinsics, ch.corr_i, ch.corr_j, ch.corr_p,
