@@ -269,6 +269,10 @@ def main():
                      "algorithmic_bytes_per_launch": int(alg_bytes)},
         "solve_us_hip_events": {"median": round(float(np.median(solve_us)), 1),
                                 "p99": round(float(np.percentile(solve_us, 99)), 1)},
+        # the GN iterations alone (dense pair jobs, edge blocks, PCG + update) with the
+        # per-solve setup and the final energy left out, i.e. over cached structure
+        "gn_iters_per_s_structure_cached": round(prob.n_gn * 1e6 / max(phase[1] + phase[2] + phase[3] + phase[4],
+                                                                        1e-9), 1),
         "accuracy": {"max_rot_rad_vs_ground_truth": round(gt_rot, 6), "max_trans_m_vs_ground_truth": round(gt_tr, 6),
                      "oracle_parity": "tests/test_gpu_global200.py, tests/test_gpu_global2000.py"},
         "phase_us_per_step": {n: round(v, 1) for n, v in zip(
