@@ -942,7 +942,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_row_assemble(
     int precond, T* __restrict__ diag_t, T* __restrict__ minv_g, T* __restrict__ r0, double* __restrict__ trace_slot,
     int* flags) {
   __shared__ double part[kAsmThreads / 64][48];
-  __shared__ double red[kAsmThreads];
+  __shared__ double red6s[6][kAsmThreads];  // energy workgroup: six sums at once
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = kAsmThreads / 64;
   const long long v = blockIdx.x;
@@ -952,11 +952,19 @@ __global__ void __launch_bounds__(kAsmThreads) k_row_assemble(
     for (long long e = tid; e < E; e += kAsmThreads)
 #pragma unroll
       for (int q = 0; q < 6; ++q) acc[q] += eb[(size_t)e * kEdgeWords + kEEs + q];
-    double tot[6];
-    for (int q = 0; q < 6; ++q) tot[q] = block_sum<kAsmThreads>(acc[q], red);
+    // the six sums share one tree (the same order per value as a single-value tree)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) red6s[q][tid] = acc[q];
+    __syncthreads();
+    for (int o = kAsmThreads / 2; o > 0; o >>= 1) {
+      if (tid < o)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) red6s[q][tid] += red6s[q][tid + o];
+      __syncthreads();
+    }
     if (tid == 0) {
-      trace_slot[0] = tot[0] + tot[1] + tot[2];
-      for (int q = 0; q < 6; ++q) trace_slot[1 + q] = tot[q];
+      trace_slot[0] = red6s[0][0] + red6s[1][0] + red6s[2][0];
+      for (int q = 0; q < 6; ++q) trace_slot[1 + q] = red6s[q][0];
       trace_slot[7] = 0.0;
     }
     return;
