@@ -30,15 +30,15 @@ import torch
 from . import bf
 
 
-def footprint_bytes(num_frames, width, height, num_corrs, num_pairs=None):
+def footprint_bytes(num_frames, width, height, num_corrs, num_pairs=None, directions=1):
     """Estimated device bytes of one solve: inputs, prepared frames, pair search
-    flags, pair records, edge blocks and correspondence indexing (upper bound on
-    the pair count when it is not known)."""
+    flags, pair records (one per pair job: `directions` per pair), edge blocks and
+    correspondence indexing (upper bound on the pair count when it is not known)."""
     F, HW = int(num_frames), int(width) * int(height)
     P = int(num_pairs) if num_pairs is not None else F * (F - 1) // 2
     frames = F * HW * (8 + 20)
     pair_search = F * F + 24 * (F + 1)
-    records = P * (256 + 16)
+    records = P * (256 * int(directions) + 16)
     edges = (P + F) * (1024 + 144 + 64)
     corr = int(num_corrs) * (24 + 8 + 96)
     return frames + pair_search + records + edges + corr + 64 * F * 16
@@ -59,7 +59,8 @@ class Request:
         self.num_frames = problem.num_frames
         intr = problem.intr
         self.intr_key = (intr.fx, intr.fy, intr.cx, intr.cy, intr.width, intr.height)
-        self.footprint = footprint_bytes(self.num_frames, intr.width, intr.height, problem.num_corrs)
+        self.footprint = footprint_bytes(self.num_frames, intr.width, intr.height, problem.num_corrs,
+                                         directions=2 if getattr(params, "bidirectional", 0) else 1)
         self.t_arrival = None
         self.t_start = None
         self.t_done = None
