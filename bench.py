@@ -141,8 +141,8 @@ def main():
                     help="run a plain copy of this size first (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the solve is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        print(f"bench.py: the solve runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is a design only, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

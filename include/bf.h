@@ -50,7 +50,7 @@ typedef enum bf_status {
   BF_ERR_DEVICE = 3,         /* a HIP runtime call failed */
   BF_ERR_NOT_PD = 4,         /* a 6x6 diagonal block of J^T J is not positive definite */
   BF_ERR_NONFINITE = 5,      /* non-finite correspondence point or pose */
-  BF_ERR_UNSUPPORTED = 6     /* a parameter combination this build does not implement */
+  BF_ERR_UNSUPPORTED = 6     /* a parameter combination the library does not implement */
 } bf_status;
 
 typedef struct bf_context bf_context;
