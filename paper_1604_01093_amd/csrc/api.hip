@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <new>
 #include <vector>
 
@@ -23,10 +24,10 @@ void check_hip(hipError_t e, const char* what) {
 }
 
 namespace {
-unsigned long long g_alloc_generation = 0;
+std::atomic<unsigned long long> g_alloc_generation{0};  // contexts may live on different threads
 }  // namespace
 
-unsigned long long alloc_generation() { return g_alloc_generation; }
+unsigned long long alloc_generation() { return g_alloc_generation.load(); }
 
 void ensure(Buf& b, size_t bytes) {
   if (bytes == 0) bytes = 8;

@@ -14,6 +14,8 @@
 // products and alpha/beta; matrix and vectors in FP32 (default) or FP64.
 // Update: T_f <- T_f Exp(x_f) in FP64 (Sec. 4.3 exponential map).
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 
 #include "internal.h"
 
@@ -1395,12 +1397,12 @@ constexpr size_t kSingleLdsMax = 64 * 1024;
 // Raise the dynamic LDS limit of k_solve_single<T, NT> (once per process).
 template <class T, int NT>
 void set_single_lds_limit() {
-  static bool done = false;
-  if (done) return;
+  static std::atomic<bool> done{false};
+  if (done.load()) return;
   check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve_single<T, NT>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSingleLdsMax),
-            "set LDS limit");
-  done = true;
+            "set LDS limit");  // idempotent: two threads may both set it
+  done.store(true);
 }
 
 // One workgroup of NT threads per problem; LDS sized for the largest problem.
@@ -1437,25 +1439,33 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   const size_t lds = sizeof(T) * (5 * (size_t)n + (mlds ? 36 * (size_t)nf : 0));
   if (lds > kRepLdsMax) return false;
   auto kern = mlds ? k_solve_rep<T, true> : k_solve_rep<T, false>;
+  // kernel attributes once per process; the occupancy for the last LDS size asked
+  // (contexts on several threads share these, hence the lock)
+  static std::mutex mu;
   static bool attr_set = false;
-  static int per_cu_at = -1;
-  static size_t per_cu_lds = 0;
-  static bool per_cu_mlds = false;
-  if (!attr_set) {
-    for (auto kk : {k_solve_rep<T, true>, k_solve_rep<T, false>})
-      check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kk), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kRepLdsMax),
-                "set LDS limit");
-    attr_set = true;
-  }
-  if (per_cu_at < 0 || per_cu_lds != lds || per_cu_mlds != mlds) {
-    int per_cu = 0;
-    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
-                                                           kRepThreads, lds),
-              "occupancy query");
-    per_cu_at = per_cu;
-    per_cu_lds = lds;
-    per_cu_mlds = mlds;
+  static int cached_per_cu = -1;
+  static size_t cached_lds = 0;
+  static bool cached_mlds = false;
+  int per_cu_at;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!attr_set) {
+      for (auto kk : {k_solve_rep<T, true>, k_solve_rep<T, false>})
+        check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kk), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)kRepLdsMax),
+                  "set LDS limit");
+      attr_set = true;
+    }
+    if (cached_per_cu < 0 || cached_lds != lds || cached_mlds != mlds) {
+      int per_cu = 0;
+      check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                             kRepThreads, lds),
+                "occupancy query");
+      cached_per_cu = per_cu;
+      cached_lds = lds;
+      cached_mlds = mlds;
+    }
+    per_cu_at = cached_per_cu;
   }
   // every workgroup waits for all others within an iteration: all must be resident
   const long long G = (nf + kRepWaves - 1) / kRepWaves;   // one row per wavefront
