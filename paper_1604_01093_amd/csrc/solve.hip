@@ -1270,22 +1270,25 @@ __global__ void k_zero_tags(unsigned long long* tags, long long n, unsigned* bar
 __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ eb,
                                                 const long long* __restrict__ seg_edge_ptr,
                                                 double* __restrict__ dst_all) {
-  __shared__ double sh[256];
+  __shared__ double sh6[6][256];  // the six sums share one tree (per value the order of a single tree)
+  const int tid = threadIdx.x;
   const long long E0 = seg_edge_ptr[blockIdx.x], E = seg_edge_ptr[blockIdx.x + 1];
   double* dst = dst_all + 8 * blockIdx.x;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (long long e = E0 + threadIdx.x; e < E; e += 256)
+  for (long long e = E0 + tid; e < E; e += 256)
     for (int k = 0; k < 6; ++k) acc[k] += eb[(size_t)e * kEdgeWords + kEEs + k];
-  double tot[6];
-  for (int k = 0; k < 6; ++k) tot[k] = block_sum<256>(acc[k], sh);
-  if (threadIdx.x == 0) {
-    dst[0] = tot[0] + tot[1] + tot[2];
-    dst[1] = tot[0];
-    dst[2] = tot[1];
-    dst[3] = tot[2];
-    dst[4] = tot[3];
-    dst[5] = tot[4];
-    dst[6] = tot[5];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sh6[k][tid] = acc[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sh6[k][tid] += sh6[k][tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    dst[0] = sh6[0][0] + sh6[1][0] + sh6[2][0];
+    for (int k = 0; k < 6; ++k) dst[1 + k] = sh6[k][0];
     dst[7] = 0.0;
   }
 }
