@@ -237,14 +237,16 @@ __global__ void k_corr_groups(const long long* __restrict__ ks, const long long*
 }
 
 // One wavefront per sparse pair: FP64 moments of its correspondences in sorted order,
-// with the lower frame's point as p.  Fixed reduction tree, read from lane 0.
+// with the lower frame's point as p.  Fixed reduction tree, read from lane 0.  The
+// grid may exceed the number of pairs (counts[1]); the extra wavefronts return.
 __global__ void __launch_bounds__(64) k_moments(const int* __restrict__ fi, const int* __restrict__ fj,
                                                 const float* __restrict__ pi, const float* __restrict__ pj,
                                                 const long long* __restrict__ perm,
-                                                const long long* __restrict__ ptr, long long S,
+                                                const long long* __restrict__ ptr,
+                                                const long long* __restrict__ counts,
                                                 double* __restrict__ mom) {
   long long g = blockIdx.x;
-  if (g >= S) return;
+  if (g >= counts[1]) return;
   const int lane = threadIdx.x;
   double acc[kMomWords - 2];
   for (int k = 0; k < kMomWords - 2; ++k) acc[k] = 0.0;
@@ -300,10 +302,18 @@ __device__ __forceinline__ long long lower_bound_i(const int* a, long long n, in
   return lo;
 }
 
+// The number of sparse pairs nB is read on the device (counts[1]), clamped to the
+// bound the buffers were sized for.
+__device__ __forceinline__ long long sparse_count(const long long* counts, long long nB_max) {
+  const long long n = counts[1];
+  return n < nB_max ? n : nB_max;
+}
+
 __global__ void k_union_inb(const long long* __restrict__ A, long long nA, const long long* __restrict__ B,
-                            long long nB, long long* __restrict__ inb) {
+                            const long long* __restrict__ counts, long long nB_max, long long* __restrict__ inb) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k > nA) return;
+  const long long nB = sparse_count(counts, nB_max);
   if (k == nA) {
     inb[k] = 0;
     return;
@@ -314,10 +324,11 @@ __global__ void k_union_inb(const long long* __restrict__ A, long long nA, const
 
 // rank of a in the union = (#A < a) + (#B < a) - (#common < a); cA = exclusive scan of inb.
 __global__ void k_union_write(const long long* __restrict__ A, long long nA, const long long* __restrict__ B,
-                              long long nB, const long long* __restrict__ cA, int F, long long* __restrict__ ekeys,
+                              long long nB_max, const long long* __restrict__ cA, int F, long long* __restrict__ ekeys,
                               int* __restrict__ eij, long long* __restrict__ edense, long long* __restrict__ esparse,
                               long long* __restrict__ counts) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nB = sparse_count(counts, nB_max);
   if (k == 0) counts[2] = nA + nB - cA[nA];
   if (k < nA) {
     long long key = A[k];
@@ -464,6 +475,11 @@ __global__ void k_copy_ll(const long long* __restrict__ a, long long n, long lon
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) o[k] = a[k];
 }
+
+// Largest bound on the number of sparse pairs for which that number is not read
+// back before the edge union (larger bounds would size the union and the
+// incidence sort far beyond the real count).
+constexpr long long kSparseBoundNoSync = 1 << 17;
 
 inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -694,20 +710,35 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
                        c.counts.as<long long>());
   }
 
+  // The number of sparse pairs S stays on the device while its bound is small: the
+  // kernels up to the incidence are sized by the bound and read S there, and the
+  // host learns it with the edge count.  Distinct keys are pairs inside one problem,
+  // plus the stand-in key of a rejected correspondence.
   long long hc[8];
   int hf = 0;
-  read_counts(c, hc, &hf);
-  raise_device_flags(hf);
-  sh.S = M > 0 ? hc[1] : 0;
+  long long s_bound = 0;
+  if (M > 0) {
+    long long within = 1;
+    for (size_t b = 0; b + 1 < c.seg_host.size(); ++b) {
+      const long long n = c.seg_host[b + 1] - c.seg_host[b];
+      within += n * (n - 1) / 2;
+    }
+    s_bound = std::min(M, within);
+    if (s_bound > kSparseBoundNoSync) {
+      read_counts(c, hc, &hf);
+      raise_device_flags(hf);
+      s_bound = hc[1];
+    }
+  }
 
-  ensure(c.moments, sizeof(double) * kMomWords * (sh.S + 1));
-  if (sh.S > 0)
-    hipLaunchKernelGGL(k_moments, dim3((unsigned)sh.S), dim3(64), 0, c.stream, co->frame_i, co->frame_j, co->p_i,
-                       co->p_j, c.corr_perm.as<long long>(), c.sparse_ptr.as<long long>(), (long long)sh.S,
+  ensure(c.moments, sizeof(double) * kMomWords * (s_bound + 1));
+  if (s_bound > 0)
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)s_bound), dim3(64), 0, c.stream, co->frame_i, co->frame_j, co->p_i,
+                       co->p_j, c.corr_perm.as<long long>(), c.sparse_ptr.as<long long>(), c.counts.as<long long>(),
                        c.moments.as<double>());
 
   // edges = union(dense pairs, sparse pairs)
-  const long long cap = sh.P + sh.S;
+  const long long cap = sh.P + s_bound;
   ensure(c.in_b, sizeof(long long) * (sh.P + 1));
   ensure(c.common_scan, sizeof(long long) * (sh.P + 1));
   ensure(c.edge_keys, sizeof(long long) * (cap + 1));
@@ -717,14 +748,14 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
   long long* A = c.pair_keys.as<long long>();
   long long* B = c.sparse_keys.as<long long>();
   hipLaunchKernelGGL(k_union_inb, dim3(blocks_for(sh.P + 1)), dim3(256), 0, c.stream, A, (long long)sh.P, B,
-                     (long long)sh.S, c.in_b.as<long long>());
+                     c.counts.as<long long>(), s_bound, c.in_b.as<long long>());
   long long* ib = c.in_b.as<long long>();
   long long* cs = c.common_scan.as<long long>();
   cub_call(c, [&](void* t, size_t& b) {
     return hipcub::DeviceScan::ExclusiveSum(t, b, ib, cs, (int)(sh.P + 1), c.stream);
   });
   hipLaunchKernelGGL(k_union_write, dim3(blocks_for(cap > 0 ? cap : 1)), dim3(256), 0, c.stream, A, (long long)sh.P, B,
-                     (long long)sh.S, cs, F, c.edge_keys.as<long long>(), c.edge_ij.as<int>(),
+                     s_bound, cs, F, c.edge_keys.as<long long>(), c.edge_ij.as<int>(),
                      c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.counts.as<long long>());
 
   // incidence: edges sorted by the upper frame (stable), per-frame ranges
@@ -770,6 +801,8 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
                            c.stream), "copy segment variables");
   read_counts(c, hc, &hf);
   raise_device_flags(hf);
+  sh.S = M > 0 ? hc[1] : 0;
+  if (sh.S > s_bound) fail(BF_ERR_DEVICE, "sparse pair count exceeds its bound");
   sh.E = hc[2];
   sh.nfree = hc[3];
   sh.nseg = nseg;
