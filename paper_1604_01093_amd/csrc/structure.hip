@@ -76,20 +76,35 @@ __global__ void k_seg_of(const int* __restrict__ seg_start, int nseg, int F, int
   seg_of[f] = lo;
 }
 
-// One workgroup per source frame i; thread per candidate j > i of the same problem.
-__global__ void __launch_bounds__(256) k_pair_rows(const float* __restrict__ depth, const double* __restrict__ poses,
-                                                   int F, int W, int H, double fx, double fy, double cx, double cy,
-                                                   float dmin, float dmax, double cos_lim,
-                                                   const int* __restrict__ seg_of, const int* __restrict__ seg_start,
-                                                   uint8_t* __restrict__ flags, long long* __restrict__ row_count) {
+// One workgroup per source frame i.  The candidates j > i of the same problem are
+// taken in chunks: first each candidate's orientation test and relative pose (one
+// thread each, into LDS), then all (candidate, grid point) projection tests of the
+// chunk spread over the workgroup, grid point by grid point.  A pair exists if any
+// grid point hits, an OR, so neither the order of the tests nor the tests skipped
+// once a candidate has a hit change the outcome.
+constexpr int kPairThreads = 1024;
+constexpr int kPairChunk = 256;
+constexpr int kGridPoints = 48;
+
+__global__ void __launch_bounds__(kPairThreads) k_pair_rows(const float* __restrict__ depth,
+                                                            const double* __restrict__ poses, int F, int W, int H,
+                                                            double fx, double fy, double cx, double cy, float dmin,
+                                                            float dmax, double cos_lim,
+                                                            const int* __restrict__ seg_of,
+                                                            const int* __restrict__ seg_start,
+                                                            uint8_t* __restrict__ flags,
+                                                            long long* __restrict__ row_count) {
   const int i = blockIdx.x;
   const int jend = seg_start[seg_of[i] + 1];
-  __shared__ double gp[48][3];
-  __shared__ int gvalid[48];
+  __shared__ double gp[3][kGridPoints];
+  __shared__ int gvalid[kGridPoints];
   __shared__ double Ti[16];
-  __shared__ int red[256];
+  __shared__ double rel[12][kPairChunk];  // R (row-major) and t of each candidate, one column each
+  __shared__ int live[kPairChunk];        // orientation test passed
+  __shared__ volatile int hit[kPairChunk];
+  __shared__ int total;
   const int tid = threadIdx.x;
-  if (tid < 48) {
+  if (tid < kGridPoints) {
     // grid pixels 5, 15, ..., 75 by 5, 15, ..., 55 at 80x60, scaled with the image
     const int a = tid % 8, b = tid / 8;
     const int x = (int)((long long)(5 + 10 * a) * W / 80), y = (int)((long long)(5 + 10 * b) * H / 60);
@@ -106,38 +121,55 @@ __global__ void __launch_bounds__(256) k_pair_rows(const float* __restrict__ dep
         ok = 1;
       }
     }
-    gp[tid][0] = p0;
-    gp[tid][1] = p1;
-    gp[tid][2] = p2;
+    gp[0][tid] = p0;
+    gp[1][tid] = p1;
+    gp[2][tid] = p2;
     gvalid[tid] = ok;
   }
   if (tid < 16) Ti[tid] = poses[(size_t)i * 16 + tid];
+  if (tid == 0) total = 0;
   __syncthreads();
   int cnt = 0;
-  for (int j = i + 1 + tid; j < jend; j += blockDim.x) {
-    const double* Tj = poses + (size_t)j * 16;
-    bool hit = false;
-    double dot;
-    {
+  for (int j0 = i + 1; j0 < jend; j0 += kPairChunk) {
+    const int nc = jend - j0 < kPairChunk ? jend - j0 : kPairChunk;
+    if (tid < nc) {
+      const double* Tj = poses + (size_t)(j0 + tid) * 16;
+      double dot;
+      {
 #pragma clang fp contract(off)
-      dot = (Ti[2] * Tj[2] + Ti[6] * Tj[6]) + Ti[10] * Tj[10];
+        dot = (Ti[2] * Tj[2] + Ti[6] * Tj[6]) + Ti[10] * Tj[10];
+      }
+      const bool ok = dot > cos_lim;
+      if (ok) {
+        double R[9], t[3];
+        relative_pose_nc(Ti, Tj, R, t);
+        for (int q = 0; q < 9; ++q) rel[q][tid] = R[q];
+        for (int q = 0; q < 3; ++q) rel[9 + q][tid] = t[q];
+      }
+      live[tid] = ok ? 1 : 0;
+      hit[tid] = 0;
     }
-    if (dot > cos_lim) {
-      double R[9], t[3];
-      relative_pose_nc(Ti, Tj, R, t);
-      for (int k = 0; k < 48 && !hit; ++k)
-        if (gvalid[k]) hit = grid_point_hits(R, t, gp[k][0], gp[k][1], gp[k][2], fx, fy, cx, cy, W, H);
-    }
-    flags[(size_t)i * F + j] = hit ? 1 : 0;
-    cnt += hit ? 1 : 0;
-  }
-  red[tid] = cnt;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
+    for (int q = tid; q < nc * kGridPoints; q += kPairThreads) {
+      const int jj = q % nc, k = q / nc;
+      if (live[jj] && gvalid[k] && !hit[jj]) {
+        double R[9], t[3];
+        for (int m = 0; m < 9; ++m) R[m] = rel[m][jj];
+        for (int m = 0; m < 3; ++m) t[m] = rel[9 + m][jj];
+        if (grid_point_hits(R, t, gp[0][k], gp[1][k], gp[2][k], fx, fy, cx, cy, W, H)) hit[jj] = 1;
+      }
+    }
+    __syncthreads();
+    if (tid < nc) {
+      const int h = hit[tid];
+      flags[(size_t)i * F + j0 + tid] = (uint8_t)h;
+      cnt += h;
+    }
+    __syncthreads();  // the next chunk rewrites rel, live and hit
   }
-  if (tid == 0) row_count[i] = red[0];
+  if (cnt) atomicAdd(&total, cnt);
+  __syncthreads();
+  if (tid == 0) row_count[i] = total;
 }
 
 // One workgroup per row: block-scan the row's flags and write the pairs in order.
@@ -508,7 +540,7 @@ void pair_search_begin(Context& c, const bf_frames& fr, const bf_intrinsics& in,
   ensure(c.row_count, sizeof(long long) * (F + 1));
   ensure(c.row_off, sizeof(long long) * (F + 1));
   double cos_lim = cos(prm.max_angle_deg * (M_PI / 180.0));
-  hipLaunchKernelGGL(k_pair_rows, dim3(F), dim3(256), 0, c.stream, fr.depth, poses, F, in.width, in.height, in.fx,
+  hipLaunchKernelGGL(k_pair_rows, dim3(F), dim3(kPairThreads), 0, c.stream, fr.depth, poses, F, in.width, in.height, in.fx,
                      in.fy, in.cx, in.cy, (float)prm.depth_min, (float)prm.depth_max, cos_lim,
                      c.seg_of.as<int>(), c.seg_start.as<int>(), c.pair_flags.as<uint8_t>(),
                      c.row_count.as<long long>());
