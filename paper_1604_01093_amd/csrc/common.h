@@ -141,31 +141,33 @@ __device__ inline int block_jacobi_inverse6(double* A, int scalar) {
 }
 
 // In-place 6x6 Cholesky inverse of a symmetric positive definite matrix (row-major).
-// Returns false if a pivot is not positive.
+// Returns false if a pivot is not positive.  One reciprocal per pivot, used as a
+// multiplier wherever the factorisation and the triangular inverse divide by it.
 __device__ inline bool spd_inverse6(double* A) {
-  double L[36];
+  double L[36], inv_d[6];
   for (int k = 0; k < 36; ++k) L[k] = 0.0;
   for (int j = 0; j < 6; ++j) {
     double s = A[6 * j + j];
     for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
     if (!(s > 0.0)) return false;
-    double d = sqrt(s);
+    const double d = sqrt(s);
     L[6 * j + j] = d;
+    inv_d[j] = 1.0 / d;
     for (int i = j + 1; i < 6; ++i) {
       double v = A[6 * i + j];
       for (int k = 0; k < j; ++k) v -= L[6 * i + k] * L[6 * j + k];
-      L[6 * i + j] = v / d;
+      L[6 * i + j] = v * inv_d[j];
     }
   }
   // Li = L^-1 (lower), A^-1 = Li^T Li
   double Li[36];
   for (int k = 0; k < 36; ++k) Li[k] = 0.0;
   for (int i = 0; i < 6; ++i) {
-    Li[6 * i + i] = 1.0 / L[6 * i + i];
+    Li[6 * i + i] = inv_d[i];
     for (int j = 0; j < i; ++j) {
       double s = 0.0;
       for (int k = j; k < i; ++k) s += L[6 * i + k] * Li[6 * k + j];
-      Li[6 * i + j] = -s / L[6 * i + i];
+      Li[6 * i + j] = -s * inv_d[i];
     }
   }
   for (int i = 0; i < 6; ++i)

@@ -282,29 +282,52 @@ __global__ void __launch_bounds__(64) k_moments(const int* __restrict__ fi, cons
   const int lane = threadIdx.x;
   double acc[kMomWords - 2];
   for (int k = 0; k < kMomWords - 2; ++k) acc[k] = 0.0;
-  for (long long k = ptr[g] + lane; k < ptr[g + 1]; k += 64) {
-    long long c = perm[k];
-    bool sw = fi[c] > fj[c];
-    const float* P = sw ? pj : pi;
-    const float* Q = sw ? pi : pj;
-    double p[3] = {P[3 * c], P[3 * c + 1], P[3 * c + 2]};
-    double q[3] = {Q[3 * c], Q[3 * c + 1], Q[3 * c + 2]};
-    acc[kMN] += 1.0;
-    for (int a = 0; a < 3; ++a) {
-      acc[kMP + a] += p[a];
-      acc[kMQ + a] += q[a];
-      for (int b = 0; b < 3; ++b) {
-        acc[kMPP + 3 * a + b] += p[a] * p[b];
-        acc[kMQQ + 3 * a + b] += q[a] * q[b];
-        acc[kMPQ + 3 * a + b] += p[a] * q[b];
+  // a lane's correspondences k = k0 + lane + 64 m, in increasing m; the loads of
+  // kAhead of them are issued before any is summed
+  constexpr int kAhead = 4;
+  const long long k0 = ptr[g], k1 = ptr[g + 1];
+  for (long long kb = k0 + lane; kb < k1; kb += 64 * kAhead) {
+    long long cs[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const long long k = kb + 64LL * u;
+      cs[u] = k < k1 ? perm[k] : -1;
+    }
+    float a_[kAhead][3], b_[kAhead][3];
+    bool sw[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const long long c = cs[u] < 0 ? 0 : cs[u];
+      sw[u] = fi[c] > fj[c];
+      for (int m = 0; m < 3; ++m) {
+        a_[u][m] = pi[3 * c + m];
+        b_[u][m] = pj[3 * c + m];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      if (cs[u] < 0) break;
+      double p[3], q[3];
+      for (int m = 0; m < 3; ++m) {
+        p[m] = sw[u] ? b_[u][m] : a_[u][m];
+        q[m] = sw[u] ? a_[u][m] : b_[u][m];
+      }
+      acc[kMN] += 1.0;
+      for (int a = 0; a < 3; ++a) {
+        acc[kMP + a] += p[a];
+        acc[kMQ + a] += q[a];
+        for (int b = 0; b < 3; ++b) {
+          acc[kMPP + 3 * a + b] += p[a] * p[b];
+          acc[kMQQ + 3 * a + b] += q[a] * q[b];
+          acc[kMPQ + 3 * a + b] += p[a] * q[b];
+        }
       }
     }
   }
-  for (int k = 0; k < kMomWords - 2; ++k) {
-    double v = acc[k];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    acc[k] = v;
-  }
+  // butterfly over the lanes, all sums step by step (per sum the same tree)
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < kMomWords - 2; ++k) acc[k] += __shfl_xor(acc[k], o);
   if (lane == 0) {
     for (int k = 0; k < kMomWords - 2; ++k) mom[g * kMomWords + k] = acc[k];
     mom[g * kMomWords + kMomWords - 2] = 0.0;
@@ -315,16 +338,6 @@ __global__ void __launch_bounds__(64) k_moments(const int* __restrict__ fi, cons
 // ---------------------------------------------------------------- edges
 
 __device__ __forceinline__ long long lower_bound_ll(const long long* a, long long n, long long key) {
-  long long lo = 0, hi = n;
-  while (lo < hi) {
-    long long mid = (lo + hi) >> 1;
-    if (a[mid] < key) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ long long lower_bound_i(const int* a, long long n, int key) {
   long long lo = 0, hi = n;
   while (lo < hi) {
     long long mid = (lo + hi) >> 1;
@@ -401,16 +414,33 @@ __global__ void k_incidence(const long long* __restrict__ ekeys, const int* __re
                             long long* __restrict__ jptr, long long* __restrict__ free_flag) {
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f > F) return;
-  long long E = counts[2];
-  iptr[f] = lower_bound_ll(ekeys, E, (long long)f * F);
-  jptr[f] = lower_bound_i(kj_sorted, E, f);
+  const long long E = counts[2];
+  // four lower bounds, advanced together: first edge with i >= f and with i >= f + 1
+  // (keys i*F + j), first with j >= f and with j >= f + 1 (kj_sorted)
+  const long long ka = (long long)f * F, kb = (long long)(f + 1) * F;
+  long long lo[4] = {0, 0, 0, 0}, hi[4] = {E, E, E, E};
+  while (lo[0] < hi[0] || lo[1] < hi[1] || lo[2] < hi[2] || lo[3] < hi[3]) {
+    long long mid[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) mid[s] = (lo[s] + hi[s]) >> 1;
+    const bool go[4] = {lo[0] < hi[0], lo[1] < hi[1], lo[2] < hi[2], lo[3] < hi[3]};
+    const long long v0 = go[0] ? ekeys[mid[0]] : 0, v1 = go[1] ? ekeys[mid[1]] : 0;
+    const int v2 = go[2] ? kj_sorted[mid[2]] : 0, v3 = go[3] ? kj_sorted[mid[3]] : 0;
+    const bool below[4] = {v0 < ka, v1 < kb, v2 < f, v3 < f + 1};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (go[s]) {
+        if (below[s]) lo[s] = mid[s] + 1;
+        else hi[s] = mid[s];
+      }
+  }
+  iptr[f] = lo[0];
+  jptr[f] = lo[2];
   if (f == F) {
     free_flag[F] = 0;
     return;
   }
-  long long ihi = lower_bound_ll(ekeys, E, (long long)(f + 1) * F);
-  long long jhi = lower_bound_i(kj_sorted, E, f + 1);
-  long long deg = (ihi - iptr[f]) + (jhi - jptr[f]);
+  const long long deg = (lo[1] - lo[0]) + (lo[3] - lo[2]);
   free_flag[f] = (f != seg_start[seg_of[f]] && deg > 0) ? 1 : 0;
 }
 
