@@ -49,6 +49,39 @@ void ensure(Buf& b, size_t bytes) {
   b.cap = cap;
 }
 
+long long* readback_small(Context& c) {
+  if (!c.rb_small) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(long long) * kSmallReadbackWords, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(BF_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+    }
+    c.rb_small = static_cast<long long*>(p);
+  }
+  return c.rb_small;
+}
+
+void* readback_big(Context& c, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (c.rb_big_cap < bytes) {
+    if (c.rb_big) {
+      check_hip(hipStreamSynchronize(c.stream), "synchronise");
+      check_hip(hipHostFree(c.rb_big), "hipHostFree");
+      c.rb_big = nullptr;
+      c.rb_big_cap = 0;
+    }
+    const size_t cap = bytes + bytes / 4;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(BF_ERR_OUT_OF_MEMORY, "pinned host allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    c.rb_big = p;
+    c.rb_big_cap = cap;
+  }
+  return c.rb_big;
+}
+
 namespace {
 
 __global__ void k_check_poses(const double* __restrict__ poses, int F, int* __restrict__ flags) {
@@ -170,8 +203,10 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
 }
 
 void sync_and_flags(Context& c, int* hf) {
-  check_hip(hipMemcpyAsync(hf, c.flags.p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy flags");
+  int* rb = reinterpret_cast<int*>(readback_small(c));
+  check_hip(hipMemcpyAsync(rb, c.flags.p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy flags");
   check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  *hf = *rb;
   if (*hf & kFlagTimeout) c.pcg_tags_dirty = true;  // a solve stopped early: clear its exchange state
 }
 
@@ -294,7 +329,7 @@ void bf_destroy(bf_context* c) {
                  &c->ej_idx, &c->ej_key_sorted, &c->ej_sorted, &c->iptr, &c->jptr, &c->free_flag, &c->var_of,
                  &c->frame_of_var, &c->records, &c->eblocks, &c->hij32, &c->hij64, &c->diag32, &c->diag64,
                  &c->minv32, &c->minv64, &c->rhs, &c->poses_work, &c->pcg_vec, &c->stats, &c->trace,
-                 &c->cub_tmp, &c->counts, &c->flags, &c->host_pinned, &c->energy,
+                 &c->cub_tmp, &c->counts, &c->flags, &c->energy,
                  &c->pcg_partials, &c->pcg_barrier, &c->pcg_tags, &c->seg_start, &c->seg_of,
                  &c->seg_var_ptr, &c->seg_edge_ptr, &c->sys_poses, &c->mf_u, &c->pr_active, &c->pr_cnt0,
                  &c->pr_cnt, &c->pr_valid, &c->pr_flag, &c->pr_pos, &c->pr_fi, &c->pr_fj, &c->pr_pi, &c->pr_pj,
@@ -302,6 +337,8 @@ void bf_destroy(bf_context* c) {
                  &c->pr_poses};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  if (c->rb_small) (void)hipHostFree(c->rb_small);
+  if (c->rb_big) (void)hipHostFree(c->rb_big);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   if (c->gn_exec) (void)hipGraphExecDestroy(c->gn_exec);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -625,14 +662,14 @@ void run_gauss_newton(bf_context* ctx, const bf_intrinsics* in, const bf_params*
   if (allow_graph && prm->graph) launch_loop_graph(c, in, prm, init_poses, out_poses);
   else enqueue_loop(c, in, prm, init_poses, out_poses, &tm);
   int g1 = tm.mark();
-  std::vector<double> e8(8 * (size_t)nseg);
+  const size_t n_e8 = 8 * (size_t)nseg;
+  const size_t n_tr = (out_trace && prm->num_gn > 0) ? 8 * (size_t)nseg * prm->num_gn : 0;
+  double* e8 = static_cast<double*>(readback_big(c, sizeof(double) * (n_e8 + n_tr)));
+  double* tr = e8 + n_e8;
   int hf = 0;
-  std::vector<double> tr(8 * (size_t)nseg * (prm->num_gn + 1));
-  check_hip(hipMemcpyAsync(e8.data(), c.energy.p, sizeof(double) * e8.size(), hipMemcpyDeviceToHost, c.stream),
-            "copy energy");
-  if (out_trace && prm->num_gn > 0)
-    check_hip(hipMemcpyAsync(tr.data(), c.trace.p, sizeof(double) * 8 * nseg * prm->num_gn, hipMemcpyDeviceToHost,
-                             c.stream), "copy trace");
+  check_hip(hipMemcpyAsync(e8, c.energy.p, sizeof(double) * n_e8, hipMemcpyDeviceToHost, c.stream), "copy energy");
+  if (n_tr)
+    check_hip(hipMemcpyAsync(tr, c.trace.p, sizeof(double) * n_tr, hipMemcpyDeviceToHost, c.stream), "copy trace");
   sync_and_flags(c, &hf);
   raise_flags(hf);
   for (int b = 0; b < nseg; ++b)

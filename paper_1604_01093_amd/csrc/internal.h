@@ -74,7 +74,13 @@ struct Context {
   Buf seg_start, seg_of, seg_var_ptr, seg_edge_ptr;
   std::vector<int> seg_host;  // offsets currently on the device (seg_start, seg_of)
   // scratch
-  Buf cub_tmp, counts, flags, host_pinned, energy, pcg_partials, pcg_barrier, pcg_tags;
+  Buf cub_tmp, counts, flags, energy, pcg_partials, pcg_barrier, pcg_tags;
+  // pinned host memory for device-to-host readbacks (a copy into pageable memory is
+  // staged by the runtime and costs a round trip of its own): a fixed small area
+  // for counts and flags and a growing one for per-problem arrays
+  long long* rb_small = nullptr;
+  void* rb_big = nullptr;
+  size_t rb_big_cap = 0;
   // threads per dense pair job chosen by timing, per (pixels per frame, precision mode, Jacobians)
   std::map<long long, int> dense_threads;
   int pcg_grid = 0;       // workgroups of the cooperative PCG kernel (0 = not yet chosen)
@@ -98,6 +104,10 @@ struct Context {
 [[noreturn]] void fail(bf_status s, const std::string& msg);
 void check_hip(hipError_t e, const char* what);
 void ensure(Buf& b, size_t bytes);
+// Pinned host readback areas: kSmallReadbackWords words, and one of at least `bytes`.
+constexpr int kSmallReadbackWords = 16;
+long long* readback_small(Context& c);
+void* readback_big(Context& c, size_t bytes);
 // Count of workspace (re)allocations so far, in every context: a captured graph
 // holds buffer addresses and is valid only while this count is unchanged.
 unsigned long long alloc_generation();

@@ -545,11 +545,20 @@ constexpr long long kSparseBoundNoSync = 1 << 17;
 
 inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-void read_counts(Context& c, long long* host_counts, int* host_flags) {
-  check_hip(hipMemcpyAsync(host_counts, c.counts.p, 8 * sizeof(long long), hipMemcpyDeviceToHost, c.stream),
-            "copy counts");
-  check_hip(hipMemcpyAsync(host_flags, c.flags.p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy flags");
+// Counts, flags and optionally `n_extra` words at `extra` (device memory), read back
+// in one round trip through pinned host memory.
+void read_counts(Context& c, long long* host_counts, int* host_flags, const long long* extra = nullptr,
+                 size_t n_extra = 0, long long* host_extra = nullptr) {
+  long long* rb = readback_small(c);
+  long long* rbx = n_extra ? static_cast<long long*>(readback_big(c, sizeof(long long) * n_extra)) : nullptr;
+  check_hip(hipMemcpyAsync(rb, c.counts.p, 8 * sizeof(long long), hipMemcpyDeviceToHost, c.stream), "copy counts");
+  check_hip(hipMemcpyAsync(rb + 8, c.flags.p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy flags");
+  if (n_extra)
+    check_hip(hipMemcpyAsync(rbx, extra, sizeof(long long) * n_extra, hipMemcpyDeviceToHost, c.stream), "copy");
   check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  for (int k = 0; k < 8; ++k) host_counts[k] = rb[k];
+  *host_flags = *reinterpret_cast<const int*>(rb + 8);
+  for (size_t k = 0; k < n_extra; ++k) host_extra[k] = rbx[k];
 }
 
 void raise_device_flags(int fl) {
@@ -594,10 +603,11 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
                            const bf_params& prm) {
   const int F = fr.num_frames;
   pair_search_begin(c, fr, in, poses, prm);
-  long long P = 0;
-  check_hip(hipMemcpyAsync(&P, c.row_off.as<long long>() + F, sizeof(long long), hipMemcpyDeviceToHost, c.stream),
+  long long* rb = readback_small(c);
+  check_hip(hipMemcpyAsync(rb, c.row_off.as<long long>() + F, sizeof(long long), hipMemcpyDeviceToHost, c.stream),
             "copy pair count");
   check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  const long long P = rb[0];
   pair_search_finish(c, F, P);
   return P;
 }
@@ -738,10 +748,8 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
   long long hc0[8];
   int hf0 = 0;
   long long P_found = 0;
-  if (search)
-    check_hip(hipMemcpyAsync(&P_found, c.row_off.as<long long>() + F, sizeof(long long), hipMemcpyDeviceToHost,
-                             c.stream), "copy pair count");
-  read_counts(c, hc0, &hf0);
+  if (search) read_counts(c, hc0, &hf0, c.row_off.as<long long>() + F, 1, &P_found);
+  else read_counts(c, hc0, &hf0);
   raise_device_flags(hf0);
   const bool unsorted = hc0[7] != 0;
   if (search) {
@@ -859,9 +867,7 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
                      c.edge_keys.as<long long>(), c.counts.as<long long>(), F, c.seg_var_ptr.as<long long>(),
                      c.seg_edge_ptr.as<long long>());
   std::vector<long long> svp(nseg + 1);
-  check_hip(hipMemcpyAsync(svp.data(), c.seg_var_ptr.p, sizeof(long long) * (nseg + 1), hipMemcpyDeviceToHost,
-                           c.stream), "copy segment variables");
-  read_counts(c, hc, &hf);
+  read_counts(c, hc, &hf, c.seg_var_ptr.as<long long>(), (size_t)nseg + 1, svp.data());
   raise_device_flags(hf);
   sh.S = M > 0 ? hc[1] : 0;
   if (sh.S > s_bound) fail(BF_ERR_DEVICE, "sparse pair count exceeds its bound");
