@@ -690,6 +690,19 @@ __device__ __forceinline__ double block_sum_dpp(double v, double* sh) {
   return t;
 }
 
+// As block_sum_dpp with one barrier: `sh` must not be written again before every
+// thread of the workgroup has passed another barrier (callers alternate slots).
+template <int NW>
+__device__ __forceinline__ double block_sum_dpp_1(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum_d(v);
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < NW; ++w) t += sh[w];
+  return t;
+}
+
 template <int NW>
 __device__ __forceinline__ double block_sum_w(double v, double* sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1193,7 +1206,9 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
       __syncthreads();
       for (long long o = tid; o < n; o += kRepThreads) part += (double)p[o] * (double)ap[o];
     }
-    const double pAp = block_sum_dpp<kRepWaves>(part, sh);
+    // p.Ap and r.z reduce into separate slots, each behind one barrier: a slot is
+    // written again only after the barriers that follow its reads
+    const double pAp = block_sum_dpp_1<kRepWaves>(part, sh);
     if (!sh_ok) break;
     const double alpha = rz / pAp;
     if (owner && lane < 6) xo = (T)((double)xo + alpha * (double)p[6 * v + lane]);
@@ -1218,7 +1233,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
         part += rb[a] * (double)zt;
       }
     }
-    const double rz_new = block_sum_dpp<kRepWaves>(part, sh);
+    const double rz_new = block_sum_dpp_1<kRepWaves>(part, sh + kRepWaves);
     const double beta = rz_new / rz;
     rz = rz_new;
     ++done;
