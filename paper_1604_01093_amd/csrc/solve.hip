@@ -885,7 +885,9 @@ __global__ void __launch_bounds__(NT) k_solve_single(
         }
       }
     }
-    const double pAp = block_sum<NT>(part, red1024);
+    // p.Ap and r.z reduce into separate slots, each behind one barrier: a slot is
+    // written again only after the barriers that follow its reads
+    const double pAp = block_sum_dpp_1<NT / 64>(part, red1024);
     const double alpha = rz / pAp;
     for (long long o = tid; o < n; o += NT) {
       x[o] = (T)((double)x[o] + alpha * (double)p[o]);
@@ -901,7 +903,7 @@ __global__ void __launch_bounds__(NT) k_solve_single(
       z[o] = (T)s;
       part += (double)r[o] * (double)(T)s;
     }
-    const double rz_new = block_sum<NT>(part, red1024);
+    const double rz_new = block_sum_dpp_1<NT / 64>(part, red1024 + NT / 64);
     const double beta = rz_new / rz;
     rz = rz_new;
     ++done;
