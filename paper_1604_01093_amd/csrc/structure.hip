@@ -226,9 +226,14 @@ __global__ void k_pairs_check(const int* __restrict__ ij, long long P, int F, co
 
 // ---------------------------------------------------------------- correspondences
 
+// Keys and identity indices, written twice: as the sort's input and as its output
+// for input that already arrives grouped (where the sort would be the identity and
+// is skipped; otherwise the sort overwrites the second copy).
 __global__ void k_corr_keys(const int* __restrict__ fi, const int* __restrict__ fj, const float* __restrict__ pi,
                             const float* __restrict__ pj, long long M, int F, const int* __restrict__ seg_of,
-                            long long* __restrict__ key, long long* __restrict__ idx, int* __restrict__ flags) {
+                            long long* __restrict__ key, long long* __restrict__ idx,
+                            long long* __restrict__ key_sorted, long long* __restrict__ perm,
+                            int* __restrict__ flags) {
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= M) return;
   int a = fi[c], b = fj[c];
@@ -238,8 +243,11 @@ __global__ void k_corr_keys(const int* __restrict__ fi, const int* __restrict__ 
   for (int k = 0; k < 3; ++k)
     if (!isfinite(pi[3 * c + k]) || !isfinite(pj[3 * c + k])) raise_flag(flags, kFlagNonFinite);
   int lo = a < b ? a : b, hi = a < b ? b : a;
-  key[c] = ok ? (long long)lo * F + hi : 1;
+  const long long k = ok ? (long long)lo * F + hi : 1;
+  key[c] = k;
   idx[c] = c;
+  key_sorted[c] = k;
+  perm[c] = c;
 }
 
 __global__ void k_corr_heads(const long long* __restrict__ ks, long long M, long long* __restrict__ head) {
@@ -533,11 +541,6 @@ __global__ void k_keys_unsorted(const long long* __restrict__ key, long long M, 
   if (c > 0 && c < M && key[c] < key[c - 1]) *flag = 1;
 }
 
-__global__ void k_copy_ll(const long long* __restrict__ a, long long n, long long* __restrict__ o) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) o[k] = a[k];
-}
-
 // Largest bound on the number of sparse pairs for which that number is not read
 // back before the edge union (larger bounds would size the union and the
 // incidence sort far beyond the real count).
@@ -633,7 +636,7 @@ int64_t group_correspondences(Context& c, const bf_corrs& co, int F) {
   if (M == 0) return 0;
   hipLaunchKernelGGL(k_corr_keys, dim3(blocks_for(M)), dim3(256), 0, c.stream, co.frame_i, co.frame_j, co.p_i, co.p_j,
                      M, F, c.seg_of.as<int>(), c.corr_key.as<long long>(), c.corr_idx.as<long long>(),
-                     c.flags.as<int>());
+                     c.corr_key_sorted.as<long long>(), c.corr_perm.as<long long>(), c.flags.as<int>());
   int endbit = bits_for((uint64_t)F * (uint64_t)F);
   long long* k_in = c.corr_key.as<long long>();
   long long* k_out = c.corr_key_sorted.as<long long>();
@@ -741,7 +744,7 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
   if (M > 0) {
     hipLaunchKernelGGL(k_corr_keys, dim3(blocks_for(M)), dim3(256), 0, c.stream, co->frame_i, co->frame_j, co->p_i,
                        co->p_j, M, F, c.seg_of.as<int>(), c.corr_key.as<long long>(), c.corr_idx.as<long long>(),
-                       c.flags.as<int>());
+                       c.corr_key_sorted.as<long long>(), c.corr_perm.as<long long>(), c.flags.as<int>());
     hipLaunchKernelGGL(k_keys_unsorted, dim3(blocks_for(M)), dim3(256), 0, c.stream, c.corr_key.as<long long>(), M,
                        reinterpret_cast<int*>(c.counts.as<long long>() + 7));
   }
@@ -766,10 +769,7 @@ void build_structure(Context& c, const bf_frames& fr, const bf_intrinsics& in, c
       cub_call(c, [&](void* t, size_t& b) {
         return hipcub::DeviceRadixSort::SortPairs(t, b, k_in, k_out, v_in, v_out, (int)M, 0, endbit, c.stream);
       });
-    } else {
-      hipLaunchKernelGGL(k_copy_ll, dim3(blocks_for(M)), dim3(256), 0, c.stream, c.corr_key.as<long long>(), M, k_out);
-      hipLaunchKernelGGL(k_copy_ll, dim3(blocks_for(M)), dim3(256), 0, c.stream, c.corr_idx.as<long long>(), M, v_out);
-    }
+    }  // else k_corr_keys has already written k_out and v_out
     hipLaunchKernelGGL(k_corr_heads, dim3(blocks_for(M)), dim3(256), 0, c.stream, k_out, M,
                        c.corr_head.as<long long>());
     long long* hd = c.corr_head.as<long long>();
