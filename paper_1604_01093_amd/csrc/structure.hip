@@ -82,11 +82,12 @@ __global__ void k_seg_of(const int* __restrict__ seg_start, int nseg, int F, int
 // chunk spread over the workgroup, grid point by grid point.  A pair exists if any
 // grid point hits, an OR, so neither the order of the tests nor the tests skipped
 // once a candidate has a hit change the outcome.
-constexpr int kPairThreads = 1024;
+// NT threads per workgroup: 1024, or 256 when no problem has more than 32 frames.
 constexpr int kPairChunk = 256;
 constexpr int kGridPoints = 48;
 
-__global__ void __launch_bounds__(kPairThreads) k_pair_rows(const float* __restrict__ depth,
+template <int NT>
+__global__ void __launch_bounds__(NT) k_pair_rows(const float* __restrict__ depth,
                                                             const double* __restrict__ poses, int F, int W, int H,
                                                             double fx, double fy, double cx, double cy, float dmin,
                                                             float dmax, double cos_lim,
@@ -150,7 +151,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_rows(const float* __restr
       hit[tid] = 0;
     }
     __syncthreads();
-    for (int q = tid; q < nc * kGridPoints; q += kPairThreads) {
+    for (int q = tid; q < nc * kGridPoints; q += NT) {
       const int jj = q % nc, k = q / nc;
       if (live[jj] && gvalid[k] && !hit[jj]) {
         double R[9], t[3];
@@ -582,7 +583,10 @@ void pair_search_begin(Context& c, const bf_frames& fr, const bf_intrinsics& in,
   ensure(c.row_count, sizeof(long long) * (F + 1));
   ensure(c.row_off, sizeof(long long) * (F + 1));
   double cos_lim = cos(prm.max_angle_deg * (M_PI / 180.0));
-  hipLaunchKernelGGL(k_pair_rows, dim3(F), dim3(kPairThreads), 0, c.stream, fr.depth, poses, F, in.width, in.height, in.fx,
+  int max_frames = 0;
+  for (size_t b = 0; b + 1 < c.seg_host.size(); ++b) max_frames = std::max(max_frames, c.seg_host[b + 1] - c.seg_host[b]);
+  const bool small = max_frames <= 32;
+  hipLaunchKernelGGL(small ? k_pair_rows<256> : k_pair_rows<1024>, dim3(F), dim3(small ? 256 : 1024), 0, c.stream, fr.depth, poses, F, in.width, in.height, in.fx,
                      in.fy, in.cx, in.cy, (float)prm.depth_min, (float)prm.depth_max, cos_lim,
                      c.seg_of.as<int>(), c.seg_start.as<int>(), c.pair_flags.as<uint8_t>(),
                      c.row_count.as<long long>());
