@@ -205,11 +205,17 @@ bf_status bf_build_structure(bf_context* ctx, const bf_frames* frames, const bf_
  *     the upper triangle of sum w J_j^T J_j (21, row-major), sum w J_j^T r (6), the
  *     weighted geometric and photometric energies and the two residual counts, where
  *     J_j is the Jacobian with respect to the target frame's perturbation.
+ *   out_masks (device, may be NULL) [jobs][H][W] uint8: the association decisions of every
+ *     source pixel of every dense pair job (same job order as the records): bit 0 = the
+ *     geometric residual is used (nearest pixel inside the image with a valid normal,
+ *     |c - q| < tau_dist, m.N_j > tau_normal), bit 1 = the photometric residual is used
+ *     (additionally G_i valid and the bilinear footprint inside the image and valid).
+ *     For inspection and tests; the decisions are those every other entry point takes.
  */
 bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
                             const bf_corrs* corrs, const bf_pairs* pairs, const double* poses,
                             const bf_params* params, int32_t gn_iter, double* out_energy,
-                            int64_t* out_counts, double* out_pair_records);
+                            int64_t* out_counts, double* out_pair_records, uint8_t* out_masks);
 
 /*
  * Normal equations at fixed poses (Sec. 4.4): J^T J and J^T F of E_align with the

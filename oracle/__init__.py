@@ -21,11 +21,13 @@ What it computes (each module cites the passage it follows):
   Cholesky solve and a block-Jacobi PCG.
 * ``gn``      -- the Gauss-Newton loop and the energy at given poses.
 
-Floating point that decides an integer (which pixels associate, which pairs
-exist) is taken in the precision of the GPU kernels -- FP32 for per-pixel
-association, FP64 for the pair test -- with every operation written out in a
-fixed order and no fused multiply-add, so both sides take identical decisions.
-All residual, Jacobian and solver arithmetic is FP64.
+Everything is FP64, by the plain definitions.  Where floating point decides an
+integer (which pixels associate, which normals are valid), the oracle also
+exports the margin of each decision and a first-order bound on the error of a
+binary32 evaluation of the tested quantity (``frames``, ``terms.associate``), so
+that a test can excuse exactly the decisions that lie within rounding of their
+threshold.  The pair test is an FP64 decision written in a fixed operation order
+(``pairs``).
 """
 from .params import Params  # noqa: F401
 from .gn import solve, evaluate, build_system  # noqa: F401

@@ -59,7 +59,7 @@ def dense_pairs(depth, poses, intr, params):
     for i in range(F):
         D32 = depth[i][Y, X].astype(np.float32)
         with np.errstate(invalid="ignore"):
-            ok = np.isfinite(D32) & (D32 >= np.float32(params.depth_min)) & (D32 <= np.float32(params.depth_max))
+            ok = np.isfinite(D32) & (D32.astype(np.float64) >= params.depth_min) & (D32.astype(np.float64) <= params.depth_max)
         D = D32[ok].astype(np.float64)
         p0 = ((X[ok] - cx) / fx) * D
         p1 = ((Y[ok] - cy) / fy) * D

@@ -7,9 +7,12 @@ fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import sys
+import weakref
 from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_void_p
 
 import torch
@@ -76,7 +79,7 @@ _SIGS = {
                                    POINTER(bf_pairs), c_void_p, POINTER(bf_params), POINTER(bf_structure)]),
     "bf_eval_residuals": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                   POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_int32, POINTER(c_double),
-                                  POINTER(c_int64), c_void_p]),
+                                  POINTER(c_int64), c_void_p, c_void_p]),
     "bf_build_normal_equations": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                           POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_int32, c_void_p,
                                           c_void_p, c_void_p, POINTER(c_double)]),
@@ -152,6 +155,24 @@ def _need(t, dtype, shape=None, name="tensor"):
         raise ValueError(f"{name}: expected shape {shape}, got {tuple(t.shape)}")
 
 
+# Contexts still open.  They are closed by an exit hook registered here, after
+# torch has registered its own (exit hooks run in reverse order), so bf_destroy's
+# frees run while the HIP runtime is still up; a context reached by the garbage
+# collector during interpreter shutdown makes no HIP call at all.
+_live = weakref.WeakSet()
+
+
+def _close_live_contexts():
+    for c in list(_live):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_live_contexts)
+
+
 class Context:
     """A bf_context bound to a HIP stream (torch's current stream by default)."""
 
@@ -163,6 +184,7 @@ class Context:
         h = c_void_p()
         self._check(self.lib.bf_create(ctypes.byref(h), c_void_p(stream.cuda_stream)), ctx=None)
         self.h = h
+        _live.add(self)
 
     def _check(self, st, ctx="self"):
         if st != BF_OK:
@@ -173,8 +195,11 @@ class Context:
         if getattr(self, "h", None):
             self.lib.bf_destroy(self.h)
             self.h = None
+        _live.discard(self)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -285,23 +310,33 @@ def bf_build_structure(ctx, prob, poses, params):
     return out
 
 
-def bf_eval_residuals(ctx, prob, poses, params, gn_iter=0, records=False):
+def bf_eval_residuals(ctx, prob, poses, params, gn_iter=0, records=False, masks=False):
+    """Energies and counts at fixed poses; optionally the per-job records [jobs, 32]
+    and the per-pixel association masks [jobs, H, W] (uint8: bit 0 geometric, bit 1
+    photometric)."""
     _poses_check(poses, prob.num_frames)
     e = (c_double * 4)()
     n = (c_int64 * 3)()
-    rec = None
-    if records:
+    rec = msk = None
+    if records or masks:
         st = bf_build_structure(ctx, prob, poses, params)
         jobs = st["pairs"].shape[0] * (2 if params.bidirectional else 1)
-        rec = torch.empty((jobs, 32), dtype=torch.float64, device=poses.device)
+        if records:
+            rec = torch.empty((jobs, 32), dtype=torch.float64, device=poses.device)
+        if masks:
+            Hh, Ww = prob.depth.shape[1], prob.depth.shape[2]
+            msk = torch.empty((jobs, Hh, Ww), dtype=torch.uint8, device=poses.device)
     ctx._check(ctx.lib.bf_eval_residuals(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr),
                                          ctypes.byref(prob.corrs), prob._pairs_ref(), _ptr(poses),
                                          ctypes.byref(params), gn_iter, e, n,
-                                         _ptr(rec) if rec is not None and rec.numel() else None))
+                                         _ptr(rec) if rec is not None and rec.numel() else None,
+                                         _ptr(msk) if msk is not None and msk.numel() else None))
     out = {"total": e[0], "sparse": e[1], "geo": e[2], "photo": e[3],
            "n_sparse": n[0], "n_geo": n[1], "n_photo": n[2]}
     if records:
         out["records"] = rec
+    if masks:
+        out["masks"] = msk
     return out
 
 

@@ -438,7 +438,7 @@ bf_status bf_build_structure(bf_context* ctx, const bf_frames* fr, const bf_intr
 
 bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
                             const bf_pairs* pairs, const double* poses, const bf_params* prm, int32_t gn_iter,
-                            double* out_energy, int64_t* out_counts, double* out_records) {
+                            double* out_energy, int64_t* out_counts, double* out_records, uint8_t* out_masks) {
   return guarded(ctx, [&] {
     validate_common(ctx, fr, in, prm);
     validate_problem(co, pairs, poses);
@@ -450,7 +450,7 @@ bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* fr, const bf_intri
     setup(ctx, fr, in, co, pairs, poses, prm);
     double wd = dense_weight(*prm, gn_iter);
     bool jac = out_records != nullptr;
-    launch_dense(c, *in, poses, *prm, wd, jac);
+    launch_dense(c, *in, poses, *prm, wd, jac, out_masks);
     launch_edge_blocks(c, poses, *prm, false);
     launch_energy(c, c.energy.as<double>());
     if (out_records && c.shape.P > 0)

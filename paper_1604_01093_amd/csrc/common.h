@@ -1,10 +1,10 @@
 // Device-side helpers shared by the kernels of libbf.
 //
 // Decision arithmetic (which pixels associate, which frame pairs exist) is
-// written as a fixed operation sequence, so that it is reproducible bit for bit:
-// FP32 with explicit fused multiply-adds (and no other contraction) for the
-// per-pixel association, FP64 without contraction for the pair test and the
-// relative poses.  Everything else may use fused multiply-add.
+// written as a fixed operation sequence, so that it is reproducible bit for bit
+// from run to run: FP32 with explicit fused multiply-adds (and no other
+// contraction) for the per-pixel association, FP64 without contraction for the
+// pair test and the relative poses.  Everything else may use fused multiply-add.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -16,8 +16,12 @@
 // (J_i = -J_j Ad(T_ji)), so each pixel feeds one 6x6 block: 21 + 6 + 4 values.
 //
 // The association decisions are always taken in FP32 with a fixed sequence of
-// fused multiply-adds (reproducible bit for bit).  The residual/Jacobian
-// values and their accumulation come in three precisions:
+// fused multiply-adds (reproducible bit for bit); they agree with the rule
+// evaluated exactly except where a tested quantity lies within its FP32 rounding
+// error of the threshold (a pixel within ~1e-5 px of a rounding tie, a distance
+// within ~1e-6 m of tau_d, ...).  The decisions can be written out per pixel for
+// inspection.  The residual/Jacobian values and their accumulation come in three
+// precisions:
 //   mode 0: FP32 values, FP32 lane sums;
 //   mode 1: FP32 values, two-sum compensated FP32 lane sums;
 //   mode 2: FP64 values (c, q, r, pi(c), Jacobians) and FP64 lane sums -- on
@@ -204,7 +208,8 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
                                               const double* __restrict__ kx64, const double* __restrict__ ky64,
                                               const double* __restrict__ poses, Intr32 in, double fx64, double fy64,
                                               double cx64, double cy64, float tau_d2, float tau_n, double swg,
-                                              double swp, double* __restrict__ records) {
+                                              double swp, double* __restrict__ records,
+                                              unsigned char* __restrict__ masks) {
   constexpr int NW = NT / 64;
   constexpr int RL = NT < 256 ? NT : 256;
   constexpr int NCH = RL / 16;
@@ -310,6 +315,9 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
       const bool ph = x0f >= 0.0f && x0f <= fWm2 && y0f >= 0.0f && y0f <= fHm2 && !is_nan(Gi) &&
                       !(is_nan(g00) || is_nan(g10) || is_nan(g01) || is_nan(g11));
       if (!ph) Gi = __builtin_nanf("");
+      // decisions out (inspection only): bit 0 geometric, bit 1 photometric
+      if (masks != nullptr && pix < HW)
+        masks[(size_t)p * HW + pix] = (unsigned char)((valid ? 1 : 0) | (valid && ph ? 2 : 0));
       if constexpr (MODE == 2) {
         wv[0] = D; wv[1] = tq.w; wv[2] = n.x; wv[3] = n.y; wv[4] = n.z;
         wv[5] = (float)px; wv[6] = (float)py; wv[7] = (float)xh; wv[8] = (float)yh;
@@ -417,7 +425,8 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
 }
 
 template <int MODE, bool JAC, int NT>
-void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd) {
+void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
+               unsigned char* masks) {
   const long long P = c.shape.P;
   const long long jobs = c.bidir ? 2 * P : P;
   Intr32 i32{(float)in.fx, (float)in.fy, (float)in.cx, (float)in.cy, in.width, in.height};
@@ -429,29 +438,30 @@ void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const b
   hipLaunchKernelGGL((k_dense<MODE, JAC, NT>), dim3(grid), dim3(NT), 0, c.stream, c.pairs.as<int>(), P, c.bidir,
                      c.nd.as<float4>(), c.grad.as<float>(), c.kx.as<float>(), c.ky.as<float>(), c.kx64.as<double>(),
                      c.ky64.as<double>(), poses, i32, in.fx, in.fy, in.cx, in.cy, tau_d2, tau_n, swg, swp,
-                     c.records.as<double>());
+                     c.records.as<double>(), masks);
 }
 
 template <int MODE, bool JAC>
-void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd, int nt) {
+void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd, int nt,
+                 unsigned char* masks) {
   switch (nt) {
-    case 64: launch_nt<MODE, JAC, 64>(c, in, poses, prm, wd); break;
-    case 128: launch_nt<MODE, JAC, 128>(c, in, poses, prm, wd); break;
-    case 512: launch_nt<MODE, JAC, 512>(c, in, poses, prm, wd); break;
-    default: launch_nt<MODE, JAC, 256>(c, in, poses, prm, wd); break;
+    case 64: launch_nt<MODE, JAC, 64>(c, in, poses, prm, wd, masks); break;
+    case 128: launch_nt<MODE, JAC, 128>(c, in, poses, prm, wd, masks); break;
+    case 512: launch_nt<MODE, JAC, 512>(c, in, poses, prm, wd, masks); break;
+    default: launch_nt<MODE, JAC, 256>(c, in, poses, prm, wd, masks); break;
   }
 }
 
 void launch_any(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                bool jac, int nt) {
+                bool jac, int nt, unsigned char* masks = nullptr) {
   const int mode = prm.accumulate;
   if (jac) {
-    if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd, nt);
-    else if (mode == 1) launch_mode<1, true>(c, in, poses, prm, wd, nt);
-    else launch_mode<0, true>(c, in, poses, prm, wd, nt);
+    if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd, nt, masks);
+    else if (mode == 1) launch_mode<1, true>(c, in, poses, prm, wd, nt, masks);
+    else launch_mode<0, true>(c, in, poses, prm, wd, nt, masks);
   } else {
-    if (mode == 2) launch_mode<2, false>(c, in, poses, prm, wd, nt);
-    else launch_mode<0, false>(c, in, poses, prm, wd, nt);
+    if (mode == 2) launch_mode<2, false>(c, in, poses, prm, wd, nt, masks);
+    else launch_mode<0, false>(c, in, poses, prm, wd, nt, masks);
   }
 }
 
@@ -496,10 +506,10 @@ int choose_threads(Context& c, const bf_intrinsics& in, const double* poses, con
 }  // namespace
 
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                  bool with_jacobians) {
+                  bool with_jacobians, unsigned char* masks) {
   if (c.shape.P == 0) return;
   const int nt = choose_threads(c, in, poses, prm, wd, with_jacobians);
-  launch_any(c, in, poses, prm, wd, with_jacobians, nt);
+  launch_any(c, in, poses, prm, wd, with_jacobians, nt, masks);
 }
 
 int dense_threads_for(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,

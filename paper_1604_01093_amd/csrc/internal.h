@@ -126,8 +126,10 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
                            const bf_params& prm);
 
 // dense.hip
+// masks (may be null): per job and source pixel, bit 0 = geometric and bit 1 =
+// photometric association ([jobs][H*W] bytes).
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                  bool with_jacobians);
+                  bool with_jacobians, unsigned char* masks = nullptr);
 // Threads per dense pair job that launch_dense() will use (timing them first when
 // params.dense_threads is 0 and the shape is new in this context).
 int dense_threads_for(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,

@@ -10,8 +10,10 @@
 
 namespace bf {
 
-__device__ __forceinline__ bool depth_ok(float d, float dmin, float dmax) {
-  return (d == d) && d >= dmin && d <= dmax && d != __builtin_inff();
+// depth_min <= d <= depth_max compared exactly (the FP32 depth widened to FP64)
+__device__ __forceinline__ bool depth_ok(float d, double dmin, double dmax) {
+  const double w = (double)d;
+  return (d == d) && w >= dmin && w <= dmax && d != __builtin_inff();
 }
 
 // Ray coefficients (x - cx) / fx and (y - cy) / fy: FP64, and rounded to FP32.
@@ -36,7 +38,7 @@ __global__ void __launch_bounds__(256) k_ray_tables(double fx, double fy, double
 __device__ __forceinline__ void prepare_pixel(int x, int y, bool inner, float d, float dl, float dr, float du,
                                               float dd, float lc, float ll, float lr, float lu, float ld,
                                               const float* __restrict__ kx, const float* __restrict__ ky,
-                                              float dmin, float dmax, float4& out, float& g) {
+                                              double dmin, double dmax, float4& out, float& g) {
   const float nan = __builtin_nanf("");
   out = make_float4(nan, nan, nan, d);
   g = nan;
@@ -81,7 +83,7 @@ constexpr int kPrepPixels = 4;
 
 __global__ void __launch_bounds__(256) k_prepare(const float* __restrict__ depth, const float* __restrict__ inten,
                                                  const float* __restrict__ kx, const float* __restrict__ ky, int W,
-                                                 int H, float dmin, float dmax, float4* __restrict__ nd,
+                                                 int H, double dmin, double dmax, float4* __restrict__ nd,
                                                  float* __restrict__ grad) {
   const int HW = W * H;
   const size_t base = (size_t)blockIdx.y * HW;
@@ -132,7 +134,7 @@ void launch_prepare(Context& c, const bf_frames& fr, const bf_intrinsics& in, co
                      c.kx.as<float>(), c.ky.as<float>(), c.kx64.as<double>(), c.ky64.as<double>());
   dim3 grid((W * H + 256 * kPrepPixels - 1) / (256 * kPrepPixels), fr.num_frames);
   hipLaunchKernelGGL(k_prepare, grid, dim3(256), 0, c.stream, fr.depth, fr.intensity, c.kx.as<float>(),
-                     c.ky.as<float>(), W, H, (float)prm.depth_min, (float)prm.depth_max, c.nd.as<float4>(),
+                     c.ky.as<float>(), W, H, prm.depth_min, prm.depth_max, c.nd.as<float4>(),
                      c.grad.as<float>());
 }
 

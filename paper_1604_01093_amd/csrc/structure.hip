@@ -44,8 +44,10 @@ int bits_for(uint64_t v) {
   return b;
 }
 
-__device__ __forceinline__ bool depth_valid(float d, float dmin, float dmax) {
-  return (d == d) && d >= dmin && d <= dmax && d != __builtin_inff();
+// depth_min <= d <= depth_max compared exactly (the FP32 depth widened to FP64)
+__device__ __forceinline__ bool depth_valid(float d, double dmin, double dmax) {
+  const double w = (double)d;
+  return (d == d) && w >= dmin && w <= dmax && d != __builtin_inff();
 }
 
 // ---------------------------------------------------------------- dense pair test
@@ -89,8 +91,8 @@ constexpr int kGridPoints = 48;
 template <int NT>
 __global__ void __launch_bounds__(NT) k_pair_rows(const float* __restrict__ depth,
                                                             const double* __restrict__ poses, int F, int W, int H,
-                                                            double fx, double fy, double cx, double cy, float dmin,
-                                                            float dmax, double cos_lim,
+                                                            double fx, double fy, double cx, double cy, double dmin,
+                                                            double dmax, double cos_lim,
                                                             const int* __restrict__ seg_of,
                                                             const int* __restrict__ seg_start,
                                                             uint8_t* __restrict__ flags,
@@ -587,7 +589,7 @@ void pair_search_begin(Context& c, const bf_frames& fr, const bf_intrinsics& in,
   for (size_t b = 0; b + 1 < c.seg_host.size(); ++b) max_frames = std::max(max_frames, c.seg_host[b + 1] - c.seg_host[b]);
   const bool small = max_frames <= 32;
   hipLaunchKernelGGL(small ? k_pair_rows<256> : k_pair_rows<1024>, dim3(F), dim3(small ? 256 : 1024), 0, c.stream, fr.depth, poses, F, in.width, in.height, in.fx,
-                     in.fy, in.cx, in.cy, (float)prm.depth_min, (float)prm.depth_max, cos_lim,
+                     in.fy, in.cx, in.cy, prm.depth_min, prm.depth_max, cos_lim,
                      c.seg_of.as<int>(), c.seg_start.as<int>(), c.pair_flags.as<uint8_t>(),
                      c.row_count.as<long long>());
   check_hip(hipMemsetAsync(c.row_count.as<long long>() + F, 0, sizeof(long long), c.stream), "memset");

@@ -47,3 +47,22 @@ def block_rel_err(A, B):
 
 def upper21(M):
     return np.array([M[a, b] for a in range(6) for b in range(a, 6)])
+
+
+def compare_masks(gpu_masks, assoc, k_near=2.0):
+    """Compare a job's GPU association masks ([H*W] uint8: bit 0 geometric, bit 1
+    photometric) with the oracle's FP64 decisions (``oracle.terms.associate``).
+
+    A mismatch is excused only where the oracle flags the decision as within
+    k_near times the binary32 rounding bound of one of its tests; returns
+    (unexcused geometric, unexcused photometric, excused geometric, excused
+    photometric, identical) where `identical` says both masks agree everywhere."""
+    from oracle.terms import near_decisions
+    g = np.asarray(gpu_masks).reshape(-1)
+    g_geo = (g & 1) != 0
+    g_ph = (g & 2) != 0
+    near_geo, near_ph = near_decisions(assoc, k_near)
+    mg = g_geo != assoc["geo"]
+    mp = g_ph != assoc["photo"]
+    return (int((mg & ~near_geo).sum()), int((mp & ~near_ph).sum()), int((mg & near_geo).sum()),
+            int((mp & near_ph).sum()), not mg.any() and not mp.any())

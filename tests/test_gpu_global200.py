@@ -4,17 +4,29 @@ benchmark times (8 GN x 20 PCG, FP32 PCG storage, automatic solve kernel).
 * the dense pair set and the edge list, bit-exact against the oracle's run stored
   in tests/golden/global200_oracle.npz (written by tests/golden/make_golden.py,
   which calls only the oracle);
+* the association masks of all 3720 pair jobs at the initial poses, pixel by
+  pixel against the oracle's FP64 decisions: mismatches only where the oracle
+  flags a decision as within twice its binary32 rounding bound;
 * per-pair dense records at the initial poses on a sample of 64 pair jobs,
-  computed by the oracle one pair at a time: association counts bit-exact,
-  6x6 blocks within 1e-5 of their Frobenius norm;
+  computed by the oracle one pair at a time: counts equal to the GPU's masks,
+  6x6 blocks within 1e-5 of their Frobenius norm (jobs with an excused decision
+  within 1e-2);
 * one Gauss-Newton step at each of the oracle's 8 iterates (same poses, same
   pair set): the GPU increment matches the oracle's within 1e-5 (rad, m);
-* the full 8-iteration solve: energy within 1e-4 relative of the oracle's.  The
-  poses of two independently rounded runs drift apart along this
-  non-converged, re-associating iteration (a 1e-8 difference flips a few of the
-  3 million association decisions, and each step amplifies ~10x), so the
-  end-to-end pose difference (about 1e-4) is reported and bounded by 2e-3 as a
-  regression guard; the strict check is the one-step parity above."""
+* the full 8-iteration solve: energy within 1e-4 relative of the oracle's, and
+  poses within 1e-5 rad / m or within four times the distance by which the
+  oracle's own run moves when its initial poses are moved by 1e-6 (stored in the
+  golden file): the iteration re-decides millions of pixel associations at every
+  step, so a difference of the size of rounding reaches the end amplified (the
+  oracle's own sensitivity is printed), and no two differently rounded
+  implementations can agree to 1e-5 unless the iteration itself does;
+* at convergence: the sparse term alone (a smooth energy, no association
+  decisions) solved to convergence on the GPU (PCG run to convergence) against the
+  oracle's Cholesky Gauss-Newton run to increments below 1e-12, within 1e-5.
+  With the dense terms the iteration does not converge to a point: the oracle's
+  own iterates settle into a cycle of association states (increments of about
+  3e-4 after 15 iterations at 200 keyframes, an exact 4-cycle at about 1.5e-5 on
+  the 11-frame chunk), so the full energy is compared iteration by iteration."""
 import os
 
 import numpy as np
@@ -23,10 +35,13 @@ import torch
 
 from oracle import Params
 from oracle.frames import prepare_frame
+from oracle.pairs import relative_pose64
 from oracle.system import dense_pair_blocks
+from oracle.terms import associate
 from synth import make_problem
 
-from gpu_helpers import bf_params_from, block_rel_err, device_problem, pose_errors, poses_cuda, upper21
+from gpu_helpers import (bf_params_from, block_rel_err, compare_masks, device_problem, pose_errors, poses_cuda,
+                         upper21)
 
 pytestmark = pytest.mark.gpu
 bf = pytest.importorskip("paper_1604_01093_amd.bf")
@@ -67,28 +82,56 @@ def test_pairs_and_edges_bit_exact(ctx, prob, golden):
     assert np.array_equal(st["free"].cpu().numpy(), golden["free"])
 
 
-def test_sampled_pair_records(ctx, prob, golden):
+@pytest.fixture(scope="module")
+def init_masks(ctx, prob, golden):
+    """GPU masks and records at the initial poses (gn_iter 3), the oracle's frames,
+    and the jobs whose masks differ from the oracle's (only at excused decisions)."""
+    prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
+    res = bf.bf_eval_residuals(ctx, device_problem(prob), poses_cuda(prob.init_poses), bf_params_from(prm),
+                               gn_iter=3, records=True, masks=True)
+    masks = res["masks"].cpu().numpy()
+    frames = [prepare_frame(prob.depth[f], prob.intensity[f], prob.intrinsics, prm) for f in range(prob.num_frames)]
+    differ = set()
+    tot = np.zeros(4, np.int64)
+    for k, (i, j) in enumerate(golden["pairs"]):
+        R, t = relative_pose64(prob.init_poses[i], prob.init_poses[j])
+        a = associate(frames[i], frames[j], R, t, prob.intrinsics, prm)
+        ug, up, eg, ep, same = compare_masks(masks[k], a)
+        tot += (ug, up, eg, ep)
+        if not same:
+            differ.add(k)
+    print(f"global200 masks: {len(golden['pairs'])} jobs, {int((masks & 1).astype(bool).sum())} geometric decisions "
+          f"taken; unexcused mismatches geo {tot[0]} photo {tot[1]}; excused geo {tot[2]} photo {tot[3]} in "
+          f"{len(differ)} jobs", flush=True)
+    return res, masks, frames, differ, tot
+
+
+def test_masks_all_jobs(init_masks):
+    _, _, _, differ, tot = init_masks
+    assert tot[0] == 0 and tot[1] == 0
+    assert len(differ) <= 0.02 * 3720
+
+
+def test_sampled_pair_records(ctx, prob, golden, init_masks):
     prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
     k = 3
-    dp = device_problem(prob)
-    res = bf.bf_eval_residuals(ctx, dp, poses_cuda(prob.init_poses), bf_params_from(prm), gn_iter=k, records=True)
+    res, masks, frames, differ, _ = init_masks
     rec = res["records"].cpu().numpy()
     pairs = golden["pairs"]
     rng = np.random.default_rng(11)
     sample = np.sort(rng.choice(len(pairs), 64, replace=False))
-    frames = {}
     for s in sample:
         i, j = pairs[s]
-        for f in (i, j):
-            if f not in frames:
-                frames[f] = prepare_frame(prob.depth[f], prob.intensity[f], prob.intrinsics, prm)
         o = dense_pair_blocks(frames[i], frames[j], prob.init_poses[i], prob.init_poses[j], prob.intrinsics, prm,
                               prm.dense_weight(k))
         r = rec[s]
-        assert r[29] == o["ngeo"] and r[30] == o["nphoto"], (i, j)
+        assert r[29] == int(((masks[s] & 1) != 0).sum()) and r[30] == int(((masks[s] & 2) != 0).sum())
+        tol = 1e-2 if s in differ else 1e-5
+        if s not in differ:
+            assert r[29] == o["ngeo"] and r[30] == o["nphoto"], (i, j)
         if o["ngeo"] > 0:
-            assert block_rel_err(r[:21], upper21(o["Hjj"])) < 1e-5, (i, j)
-            assert abs(r[27] - o["Egeo"]) <= 1e-5 * o["Egeo"] + 1e-12
+            assert block_rel_err(r[:21], upper21(o["Hjj"])) < tol, (i, j)
+            assert abs(r[27] - o["Egeo"]) <= tol * o["Egeo"] + 1e-12
 
 
 @pytest.mark.parametrize("accumulate,pcg_storage", [(0, 0), (2, 1)])
@@ -121,12 +164,30 @@ def test_gauss_newton_global200(ctx, prob, golden, pcg_storage, solve_kernel, ac
     P = out["poses"].cpu().numpy()
     rot, tr = pose_errors(P, golden["poses"])
     e, er = out["energy"]["total"], float(golden["energy"][0])
+    srot, str_ = pose_errors(golden["moved_poses"], golden["poses"])
     print(f"global200 storage={pcg_storage} kernel={solve_kernel} acc={accumulate}: pose err {rot:.3e} rad "
-          f"{tr:.3e} m, energy rel err {abs(e - er) / er:.3e}", flush=True)
+          f"{tr:.3e} m, energy rel err {abs(e - er) / er:.3e}; the oracle moved by 1e-6 at the start ends "
+          f"{srot:.3e} rad {str_:.3e} m from itself", flush=True)
     assert abs(e - er) <= 1e-4 * er
     for k, t in enumerate(out["trace"]):
         assert abs(t[0] - golden["trace"][k][0]) <= 1e-4 * golden["trace"][k][0]
-    assert rot < 2e-3 and tr < 2e-3
+    assert rot < max(1e-5, 4 * srot) and tr < max(1e-5, 4 * str_)
+
+
+@pytest.mark.parametrize("pcg_storage", [0, 1])
+def test_sparse_term_at_convergence(ctx, prob, golden, pcg_storage):
+    """E_sparse alone to convergence (the outliers make it a large-residual
+    problem, on which Gauss-Newton converges linearly): on the GPU as many
+    Gauss-Newton iterations as the oracle needed plus 20, each with 200 PCG
+    iterations, against the oracle's Cholesky run to increments below 1e-11."""
+    prm = Params(num_gn=int(golden["conv_sparse_iters"]) + 20, num_pcg=200, use_dense=False, dense_ramp=False)
+    out = bf.bf_gauss_newton(ctx, device_problem(prob), poses_cuda(prob.init_poses),
+                             bf_params_from(prm, pcg_storage=pcg_storage))
+    rot, tr = pose_errors(out["poses"].cpu().numpy(), golden["conv_sparse_poses"])
+    print(f"global200 sparse term at convergence, storage={pcg_storage}: pose err {rot:.3e} rad {tr:.3e} m "
+          f"(oracle: {int(golden['conv_sparse_iters'])} iterations, last increment "
+          f"{golden['conv_sparse_hist'][-1]:.1e})", flush=True)
+    assert rot < 1e-5 and tr < 1e-5
 
 
 def test_one_step_jacobi_preconditioner(ctx, prob, golden):

@@ -4,20 +4,19 @@ unknowns), against the oracle's run stored in tests/golden/global2000_oracle.npz
 (written by tests/golden/make_golden.py, which calls only the oracle):
 
 * the dense pair set and the variables, bit-exact;
-* energy and residual counts at the initial poses (counts bit-exact, energy within
-  1e-4 relative);
-* per-pair dense records at the initial poses on a sample of 16 pair jobs,
-  computed by the oracle one pair at a time;
-* one Gauss-Newton step at the oracle's first two iterates: the increment within
+* energy and residual counts at the initial poses (energy within 1e-4 relative;
+  the counts differ from the oracle's by at most the excused decisions, about
+  one in a million here);
+* the association masks of a sample of 2000 pair jobs at the initial poses,
+  pixel by pixel against the oracle's FP64 decisions (mismatches only where the
+  oracle flags a decision as within twice its binary32 rounding bound), and the
+  records of 16 of them, computed by the oracle one pair at a time;
+* one Gauss-Newton step at each of the oracle's 8 iterates: the increment within
   1e-5 (rad, m) of the oracle's in the mixed-precision configuration of this
-  workload (compensated FP32 lane sums, FP64 PCG storage) and with FP64 values,
-  and within 5e-4 on the all-FP32 path, whose error at this size is printed: 20
-  PCG iterations on this ill-conditioned system with the matrix and vectors
-  stored in FP32 (largest increment 2.16) move the increment by about 1e-4, as
-  much as a change of a few of the 3.2M association decisions does (at the second
-  iterate one frame receives no residual and is held by both);
-* the full solve: the energies at the start of the first two iterations within
-  1e-4 relative of the oracle's.
+  workload and with FP64 values, and on the all-FP32 path within the bound its
+  arithmetic meets (printed; see the parameter list below);
+* the full solve: the energies at the start of all 8 iterations within 1e-4
+  relative of the oracle's.
 
 The input is generated in a child process (parallel workers; this process holds a
 GPU context and does not fork)."""
@@ -31,9 +30,11 @@ import torch
 
 from oracle import Params
 from oracle.frames import prepare_frame
+from oracle.pairs import relative_pose64
 from oracle.system import dense_pair_blocks
+from oracle.terms import associate
 
-from gpu_helpers import bf_params_from, block_rel_err, device_problem, poses_cuda, upper21
+from gpu_helpers import bf_params_from, block_rel_err, compare_masks, device_problem, poses_cuda, upper21
 
 pytestmark = pytest.mark.gpu
 bf = pytest.importorskip("paper_1604_01093_amd.bf")
@@ -86,28 +87,53 @@ def test_energy_and_counts_at_init(ctx, prob, golden, dp):
     prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
     e = bf.bf_eval_residuals(ctx, dp, poses_cuda(prob.init_poses), bf_params_from(prm), gn_iter=0)
     ref = golden["trace"][0]  # total, sparse, geo, photo, n_sparse, n_geo, n_photo
-    print(f"global2000 energy at init {e['total']:.9g} vs {ref[0]:.9g}", flush=True)
-    assert (e["n_sparse"], e["n_geo"], e["n_photo"]) == tuple(int(v) for v in ref[4:7])
+    print(f"global2000 energy at init {e['total']:.9g} vs {ref[0]:.9g}; counts geo {e['n_geo']} vs {int(ref[5])}, "
+          f"photo {e['n_photo']} vs {int(ref[6])}", flush=True)
+    assert e["n_sparse"] == int(ref[4])
+    assert abs(e["n_geo"] - ref[5]) <= 1e-5 * ref[5] and abs(e["n_photo"] - ref[6]) <= 1e-5 * ref[6]
     for k, name in enumerate(("total", "sparse", "geo", "photo")):
         assert abs(e[name] - ref[k]) <= 1e-4 * ref[k], name
 
 
-def test_sampled_pair_records(ctx, prob, golden, dp):
+def test_sampled_masks_and_records(ctx, prob, golden, dp):
     prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
-    res = bf.bf_eval_residuals(ctx, dp, poses_cuda(prob.init_poses), bf_params_from(prm), gn_iter=0, records=True)
-    rec = res["records"].cpu().numpy()
+    res = bf.bf_eval_residuals(ctx, dp, poses_cuda(prob.init_poses), bf_params_from(prm), gn_iter=0, records=True,
+                               masks=True)
     pairs = golden["pairs"]
     rng = np.random.default_rng(5)
-    for s in np.sort(rng.choice(len(pairs), 16, replace=False)):
+    sample = np.sort(rng.choice(len(pairs), 2000, replace=False))
+    masks = res["masks"][torch.as_tensor(sample).cuda()].cpu().numpy()
+    rec = res["records"].cpu().numpy()
+    del res
+    frames = {}
+
+    def fr(f):
+        if f not in frames:
+            frames[f] = prepare_frame(prob.depth[f], prob.intensity[f], prob.intrinsics, prm)
+        return frames[f]
+
+    tot = np.zeros(4, np.int64)
+    differ = set()
+    for n, s in enumerate(sample):
         i, j = pairs[s]
-        fi = prepare_frame(prob.depth[i], prob.intensity[i], prob.intrinsics, prm)
-        fj = prepare_frame(prob.depth[j], prob.intensity[j], prob.intrinsics, prm)
-        o = dense_pair_blocks(fi, fj, prob.init_poses[i], prob.init_poses[j], prob.intrinsics, prm,
+        R, t = relative_pose64(prob.init_poses[i], prob.init_poses[j])
+        ug, up, eg, ep, same = compare_masks(masks[n], associate(fr(i), fr(j), R, t, prob.intrinsics, prm))
+        tot += (ug, up, eg, ep)
+        if not same:
+            differ.add(int(s))
+    print(f"global2000 masks of {len(sample)} jobs: unexcused geo {tot[0]} photo {tot[1]}, excused geo {tot[2]} "
+          f"photo {tot[3]} in {len(differ)} jobs", flush=True)
+    assert tot[0] == 0 and tot[1] == 0
+    for s in sample[::125]:
+        i, j = pairs[s]
+        o = dense_pair_blocks(fr(i), fr(j), prob.init_poses[i], prob.init_poses[j], prob.intrinsics, prm,
                               prm.dense_weight(0))
         r = rec[s]
-        assert r[29] == o["ngeo"] and r[30] == o["nphoto"], (i, j)
+        tol = 1e-2 if int(s) in differ else 1e-5
+        if int(s) not in differ:
+            assert r[29] == o["ngeo"] and r[30] == o["nphoto"], (i, j)
         if o["ngeo"] > 0:
-            assert block_rel_err(r[:21], upper21(o["Hjj"])) < 1e-5, (i, j)
+            assert block_rel_err(r[:21], upper21(o["Hjj"])) < tol, (i, j)
 
 
 # (accumulate, pcg_storage, bound): the FP32 path (FP32 values, lane sums, PCG
@@ -119,6 +145,7 @@ def test_one_step_parity(ctx, prob, golden, dp, accumulate, pcg_storage, bound):
     free = golden["free"]
     idx = (6 * free[:, None] + np.arange(6)[None, :]).ravel()
     dpp = device_problem(prob, pairs=golden["pairs"])
+    worst = 0.0
     for k in range(len(golden["steps"])):
         bf.bf_build_normal_equations(ctx, dpp, poses_cuda(golden["traj"][k]),
                                      bf_params_from(prm, accumulate=accumulate, pcg_storage=pcg_storage),
@@ -127,9 +154,10 @@ def test_one_step_parity(ctx, prob, golden, dp, accumulate, pcg_storage, bound):
         err = float(np.abs(delta.cpu().numpy()[idx] - golden["steps"][k]).max())
         print(f"global2000 accumulate={accumulate} storage={pcg_storage} step {k}: max |d increment| {err:.2e} "
               f"(max |increment| {np.abs(golden['steps'][k]).max():.3f})", flush=True)
-        assert err < bound
+        worst = max(worst, err)
         held = free[golden["inert"][k]]
         assert not delta.cpu().numpy().reshape(-1, 6)[held].any()
+    assert worst < bound
 
 
 def test_gauss_newton_trace(ctx, prob, golden, dp):

@@ -1,10 +1,14 @@
 """GPU vs oracle parity through the C ABI on the 11-frame chunk workload (and
-variants): per-frame preparation, pair set and indexing (bit-exact), per-pair
-dense records and per-edge blocks at fixed poses, the assembled normal
-equations, PCG, and the full Gauss-Newton solve.
+variants): per-frame preparation, pair set and indexing (bit-exact), per-pixel
+association masks, per-pair dense records and per-edge blocks at fixed poses,
+the assembled normal equations, PCG, and the full Gauss-Newton solve.
 
-Tolerances: integer and index data bit-exact; association counts bit-exact
-(the FP32 decisions follow the same fixed operation order on both sides);
+Tolerances: integer and index data bit-exact.  Association: the kernels decide
+in binary32, the oracle by the plain rule in FP64; the masks must be identical
+pixel by pixel except where the oracle flags a decision as within twice the
+binary32 rounding bound of one of its tests (``oracle.terms.near_decisions``);
+such an excused decision has two correct outcomes, so a job that contains one is
+not held to the block tolerance below (it is checked loosely and counted).
 6x6 blocks within 1e-5 of the block's Frobenius norm; poses within 1e-5 rad /
 1e-5 m; energies within 1e-4 relative."""
 import numpy as np
@@ -12,13 +16,15 @@ import pytest
 import torch
 
 from oracle import Params
-from oracle.frames import prepare_frames
+from oracle.frames import U32, prepare_frames
 from oracle.gn import Setup, build_system, solve
-from oracle.pairs import dense_pairs, edge_list, group_correspondences
+from oracle.pairs import dense_pairs, edge_list, group_correspondences, relative_pose64
 from oracle.system import reduce_system, solve_pcg
+from oracle.terms import associate
 from synth import make_chunk, make_problem
 
-from gpu_helpers import bf_params_from, block_rel_err, device_problem, pose_errors, poses_cuda, upper21
+from gpu_helpers import (bf_params_from, block_rel_err, compare_masks, device_problem, pose_errors, poses_cuda,
+                         upper21)
 
 pytestmark = pytest.mark.gpu
 
@@ -46,11 +52,16 @@ def chunk_setup(chunk):
                  chunk.corr_q, chunk.init_poses, prm)
 
 
-def test_prepare_frames_bit_exact(ctx, chunk):
+def test_prepare_frames(ctx, chunk):
+    """Validity masks identical; binary32 normals within twice the oracle's rounding
+    bound of its FP64 normals (the orientation may differ only where the oracle
+    flags it as within rounding); gradients within 2e-7."""
     depth = chunk.depth.copy()
     depth[3, 10:20, 30:45] = 0.0          # a hole
     depth[4, :, :] = 0.0                  # a frame without depth
     depth[5, 7, 7] = np.nan
+    depth[6, 30, 30] = np.float32(0.1)    # exactly on the depth limit: valid
+    depth[6, 31, 30] = np.nextafter(np.float32(0.1), np.float32(0))   # just below: invalid
     inten = chunk.intensity.copy()
     inten[6, 20, 20] = np.inf
     prm = Params()
@@ -58,14 +69,44 @@ def test_prepare_frames_bit_exact(ctx, chunk):
     nd, g = bf.bf_prepare_frames(ctx, dp, bf_params_from(prm))
     nd, g = nd.cpu().numpy(), g.cpu().numpy()
     fr = prepare_frames(depth, inten, chunk.intrinsics, prm)
+    assert fr[6].depth_ok[30, 30] and not fr[6].depth_ok[31, 30]
+    worst = 0.0
     for f, o in enumerate(fr):
         assert np.array_equal(~np.isnan(nd[f, ..., 0]), o.normal_ok), f
         ok = o.normal_ok
-        assert np.array_equal(nd[f][ok][:, :3], o.N32[ok]), f           # same FP32 bits
+        diff = np.linalg.norm(nd[f][ok][:, :3].astype(np.float64) - o.N[ok], axis=1)
+        flip_ok = o.flip_margin[ok] <= 2.0 * (o.N_sigma[ok] + 4 * U32)
+        flipped = np.linalg.norm(nd[f][ok][:, :3].astype(np.float64) + o.N[ok], axis=1) <= 2.0 * o.N_sigma[ok]
+        good = diff <= 2.0 * o.N_sigma[ok]
+        assert np.all(good | (flipped & flip_ok)), f
+        worst = max(worst, float((diff / o.N_sigma[ok])[good].max(initial=0.0)))
         assert np.array_equal(~np.isnan(g[f]), o.grad_ok), f
         gk = o.grad_ok
         assert np.abs(g[f][gk] - o.G[gk]).max() <= 2e-7 * max(1.0, np.abs(o.G[gk]).max())
+    print(f"normals: largest difference {worst:.3f} x the rounding bound", flush=True)
     assert not (~np.isnan(nd[4, ..., 0])).any()
+
+
+def job_assoc(setup, i, j, poses, prm):
+    """The oracle's FP64 association of pair job i -> j at `poses`."""
+    R, t = relative_pose64(poses[i], poses[j])
+    return associate(setup.frames[i], setup.frames[j], R, t, setup.intr, prm)
+
+
+def check_masks(masks, jobs, setup, poses, prm, label=""):
+    """Every job's GPU mask against the oracle: returns the set of job indices whose
+    masks differ (only at excused decisions) and the totals."""
+    differ = set()
+    tot = np.zeros(4, np.int64)
+    for k, (i, j) in enumerate(jobs):
+        ug, up, eg, ep, same = compare_masks(masks[k], job_assoc(setup, i, j, poses, prm))
+        assert ug == 0 and up == 0, (label, k, i, j, ug, up)
+        tot += (ug, up, eg, ep)
+        if not same:
+            differ.add(k)
+    print(f"masks{label}: {len(jobs)} jobs, excused mismatches geo {tot[2]} photo {tot[3]}, "
+          f"{len(differ)} jobs differ", flush=True)
+    return differ
 
 
 @pytest.mark.parametrize("which", ["chunk", "chunk_perturbed"])
@@ -120,26 +161,49 @@ def test_dense_records_at_fixed_poses(ctx, chunk, chunk_setup):
     wd = prm.dense_weight(k)
     dp = device_problem(chunk)
     res = bf.bf_eval_residuals(ctx, dp, poses_cuda(chunk.init_poses), bf_params_from(prm), gn_iter=k,
-                               records=True)
+                               records=True, masks=True)
     rec = res["records"].cpu().numpy()
+    masks = res["masks"].cpu().numpy()
     _, _, blocks, en = build_system(chunk_setup, chunk.init_poses, wd)
     assert len(rec) == len(chunk_setup.pairs) == 55
+    differ = check_masks(masks, chunk_setup.pairs, chunk_setup, chunk.init_poses, prm)
+    assert len(differ) <= 2
     for e, (i, j) in enumerate(chunk_setup.edges):
         d = chunk_setup.edge_dense[e]
         o = blocks[e]["dense"]
         r = rec[d]
-        assert r[29] == o["ngeo"] and r[30] == o["nphoto"], (i, j)
-        assert block_rel_err(r[:21], upper21(o["Hjj"])) < 1e-5, (i, j)
-        assert block_rel_err(r[21:27], o["gj"]) < 1e-5 * max(1.0, np.linalg.norm(upper21(o["Hjj"])) /
+        assert r[29] == int(((masks[d] & 1) != 0).sum()) and r[30] == int(((masks[d] & 2) != 0).sum())
+        tol = 1e-2 if d in differ else 1e-5
+        if d not in differ:
+            assert r[29] == o["ngeo"] and r[30] == o["nphoto"], (i, j)
+        assert block_rel_err(r[:21], upper21(o["Hjj"])) < tol, (i, j)
+        assert block_rel_err(r[21:27], o["gj"]) < tol * max(1.0, np.linalg.norm(upper21(o["Hjj"])) /
                                                              max(np.linalg.norm(o["gj"]), 1e-30)), (i, j)
-        assert abs(r[27] - o["Egeo"]) <= 1e-5 * o["Egeo"] and abs(r[28] - o["Ephoto"]) <= 1e-5 * o["Ephoto"]
-    assert res["n_geo"] == en["n_geo"] and res["n_photo"] == en["n_photo"] and res["n_sparse"] == en["n_sparse"]
+        assert abs(r[27] - o["Egeo"]) <= tol * o["Egeo"] and abs(r[28] - o["Ephoto"]) <= tol * o["Ephoto"]
+    assert res["n_sparse"] == en["n_sparse"]
+    if not differ:
+        assert res["n_geo"] == en["n_geo"] and res["n_photo"] == en["n_photo"]
     for key in ("total", "sparse", "geo", "photo"):
-        assert abs(res[key] - en[key]) <= 1e-6 * abs(en[key]), key
+        assert abs(res[key] - en[key]) <= (1e-4 if differ else 1e-6) * abs(en[key]), key
+
+
+@pytest.fixture(scope="module")
+def init_differ(ctx, chunk, chunk_setup):
+    """Dense jobs whose GPU masks differ from the oracle's at the initial poses (only
+    at excused decisions), and the frames they touch."""
+    res = bf.bf_eval_residuals(ctx, device_problem(chunk), poses_cuda(chunk.init_poses),
+                               bf_params_from(chunk_setup.params), gn_iter=0, masks=True)
+    differ = check_masks(res["masks"].cpu().numpy(), chunk_setup.pairs, chunk_setup, chunk.init_poses,
+                         chunk_setup.params, " at init")
+    frames = {int(f) for d in differ for f in chunk_setup.pairs[d]}
+    return differ, frames
 
 
 @pytest.mark.parametrize("pcg_storage", [0, 1])
-def test_normal_equations_and_edge_blocks(ctx, chunk, chunk_setup, pcg_storage):
+def test_normal_equations_and_edge_blocks(ctx, chunk, chunk_setup, pcg_storage, init_differ):
+    """Every 6x6 block of H within 1e-5, except blocks summed over a job with an
+    excused decision (1e-2); H bitwise symmetric; g per frame likewise."""
+    differ, dframes = init_differ
     prm = chunk_setup.params
     wd = prm.dense_weight(1)
     dp = device_problem(chunk)
@@ -151,25 +215,30 @@ def test_normal_equations_and_edge_blocks(ctx, chunk, chunk_setup, pcg_storage):
     for a in range(F):
         for b in range(F):
             blk = H_ref[6 * a:6 * a + 6, 6 * b:6 * b + 6]
+            tol = 1e-2 if (a in dframes or b in dframes) else 1e-5
             if np.abs(blk).max() == 0:
                 assert np.abs(H[6 * a:6 * a + 6, 6 * b:6 * b + 6]).max() == 0
             else:
-                assert block_rel_err(H[6 * a:6 * a + 6, 6 * b:6 * b + 6], blk) < 1e-5, (a, b)
+                assert block_rel_err(H[6 * a:6 * a + 6, 6 * b:6 * b + 6], blk) < tol, (a, b)
     assert np.array_equal(H, H.T)
     for f in range(F):
+        tol = 1e-2 if f in dframes else 1e-5
         scale = np.linalg.norm(H_ref[6 * f:6 * f + 6, 6 * f:6 * f + 6])
-        assert np.linalg.norm(g[6 * f:6 * f + 6] - g_ref[6 * f:6 * f + 6]) <= 1e-5 * max(scale * 1e-3, np.linalg.norm(g_ref[6 * f:6 * f + 6]))
+        assert np.linalg.norm(g[6 * f:6 * f + 6] - g_ref[6 * f:6 * f + 6]) <= tol * max(scale * 1e-3, np.linalg.norm(g_ref[6 * f:6 * f + 6]))
     for e in range(len(chunk_setup.edges)):
         o = blocks[e]
-        assert block_rel_err(eb[e, 0:36].reshape(6, 6), o["Hii"]) < 1e-5
-        assert block_rel_err(eb[e, 36:72].reshape(6, 6), o["Hjj"]) < 1e-5
-        assert block_rel_err(eb[e, 72:108].reshape(6, 6), o["Hij"]) < 1e-5
+        tol = 1e-2 if chunk_setup.edge_dense[e] in differ else 1e-5
+        assert block_rel_err(eb[e, 0:36].reshape(6, 6), o["Hii"]) < tol
+        assert block_rel_err(eb[e, 36:72].reshape(6, 6), o["Hjj"]) < tol
+        assert block_rel_err(eb[e, 72:108].reshape(6, 6), o["Hij"]) < tol
         assert abs(eb[e, 120] - o["sparse"]["E"]) <= 1e-9 * o["sparse"]["E"]
-    assert abs(out["energy"][0] - en["total"]) <= 1e-6 * en["total"]
+    assert abs(out["energy"][0] - en["total"]) <= (1e-4 if differ else 1e-6) * en["total"]
 
 
 @pytest.mark.parametrize("pcg_storage,solve_kernel", [(0, 1), (1, 1), (0, 2), (1, 2), (0, 3), (1, 3)])
-def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage, solve_kernel):
+def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage, solve_kernel, init_differ):
+    """The 10-iteration PCG increment element by element within 1e-5 (rad, m) of the
+    oracle's PCG on its own system, and r^T z at the start within 1e-5 relative."""
     prm = chunk_setup.params
     dp = device_problem(chunk)
     bf.bf_build_normal_equations(ctx, dp, poses_cuda(chunk.init_poses),
@@ -182,8 +251,11 @@ def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage, solve_kern
     x, ost = solve_pcg(Hr, gr, 10)
     ref = np.zeros(6 * chunk.num_frames)
     ref[idx] = x
+    err = float(np.abs(delta - ref).max())
+    print(f"chunk PCG storage={pcg_storage} kernel={solve_kernel}: max |d increment| {err:.2e} "
+          f"(max |increment| {np.abs(ref).max():.3f}), {len(init_differ[0])} jobs with excused decisions", flush=True)
     assert st["iters"] == ost["iters"] == 10
-    assert np.linalg.norm(delta - ref) <= 1e-4 * np.linalg.norm(ref)
+    assert err <= 1e-5
     assert abs(st["rz0"] - ost["rz0"]) <= 1e-5 * ost["rz0"]
     assert (delta[:6] == 0).all()
 
@@ -256,9 +328,10 @@ def test_gauss_newton_chunk_jacobi_preconditioner(ctx, chunk, solve_kernel, pcg_
 def test_small_and_ragged_images(ctx, W, H, dense_threads):
     """Images smaller than one wavefront and sizes that are not a multiple of the
     workgroup (the last step of every wavefront runs past the last pixel): the
-    records' association counts bit-exact and the energy at the initial poses
-    within 1e-6, then the solve within the pose tolerance, for each dense
-    workgroup size."""
+    association masks pixel by pixel against the oracle (excused decisions only),
+    the records' counts equal to the masks' and the energy at the initial poses
+    within 1e-6 (1e-4 with an excused decision), then the solve within the pose
+    tolerance, for each dense workgroup size."""
     f = 72.0 * W / 80.0
     pr = make_chunk(num_frames=4, W=W, H=H, fx=f, fy=f, cx=W / 2.0, cy=H / 2.0, name=f"small{W}x{H}")
     prm = Params(num_gn=3, num_pcg=10)
@@ -266,16 +339,16 @@ def test_small_and_ragged_images(ctx, W, H, dense_threads):
                   pr.init_poses, prm)
     dp = device_problem(pr)
     res = bf.bf_eval_residuals(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, dense_threads=dense_threads),
-                               gn_iter=0, records=True)
+                               gn_iter=0, records=True, masks=True)
     _, _, blocks, en = build_system(setup, pr.init_poses, prm.dense_weight(0))
     rec = res["records"].cpu().numpy()
-    for e in range(len(setup.edges)):
-        d = setup.edge_dense[e]
-        if d >= 0:
-            o = blocks[e]["dense"]
-            assert rec[d][29] == o["ngeo"] and rec[d][30] == o["nphoto"], e
-    assert res["n_geo"] == en["n_geo"] and res["n_photo"] == en["n_photo"]
-    assert abs(res["total"] - en["total"]) <= 1e-6 * en["total"]
+    masks = res["masks"].cpu().numpy()
+    differ = check_masks(masks, setup.pairs, setup, pr.init_poses, prm, f" {W}x{H}") if len(setup.pairs) else set()
+    for d in range(len(setup.pairs)):
+        assert rec[d][29] == int(((masks[d] & 1) != 0).sum()) and rec[d][30] == int(((masks[d] & 2) != 0).sum())
+    if not differ:
+        assert res["n_geo"] == en["n_geo"] and res["n_photo"] == en["n_photo"]
+    assert abs(res["total"] - en["total"]) <= (1e-4 if differ else 1e-6) * en["total"]
     ref = solve(pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q, pr.init_poses,
                 prm, linear="pcg")
     out = bf.bf_gauss_newton(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, dense_threads=dense_threads))
@@ -297,30 +370,38 @@ def test_bidirectional_chunk(ctx, chunk, solve_kernel, accumulate):
     dp = device_problem(chunk)
     kw = dict(solve_kernel=solve_kernel, accumulate=accumulate)
     res = bf.bf_eval_residuals(ctx, dp, poses_cuda(chunk.init_poses), bf_params_from(prm, **kw), gn_iter=2,
-                               records=True)
+                               records=True, masks=True)
     rec = res["records"].cpu().numpy()
     P = len(setup.pairs)
     assert rec.shape[0] == 2 * P
+    jobs = np.concatenate([setup.pairs, setup.pairs[:, ::-1]])
+    differ = check_masks(res["masks"].cpu().numpy(), jobs, setup, chunk.init_poses, prm, " both directions")
     _, _, blocks, en = build_system(setup, chunk.init_poses, prm.dense_weight(2))
     for e, (i, j) in enumerate(setup.edges):
         d = setup.edge_dense[e]
         if d < 0:
             continue
-        for r, o, blk in ((rec[d], blocks[e]["dense"], "Hjj"), (rec[P + d], blocks[e]["dense_rev"], "Hii")):
+        for k, r, o, blk in ((d, rec[d], blocks[e]["dense"], "Hjj"), (P + d, rec[P + d], blocks[e]["dense_rev"], "Hii")):
+            if k in differ:
+                assert block_rel_err(r[:21], upper21(o[blk])) < 1e-2, (i, j, blk)
+                continue
             assert r[29] == o["ngeo"] and r[30] == o["nphoto"], (i, j, blk)
             assert block_rel_err(r[:21], upper21(o[blk])) < 1e-5, (i, j, blk)
-    assert res["n_geo"] == en["n_geo"] and res["n_photo"] == en["n_photo"]
-    assert abs(res["total"] - en["total"]) <= 1e-6 * en["total"]
+    if not differ:
+        assert res["n_geo"] == en["n_geo"] and res["n_photo"] == en["n_photo"]
+    assert abs(res["total"] - en["total"]) <= (1e-4 if differ else 1e-6) * en["total"]
     out = bf.bf_build_normal_equations(ctx, dp, poses_cuda(chunk.init_poses), bf_params_from(prm, **kw), gn_iter=1)
     H_ref, g_ref, _, _ = build_system(setup, chunk.init_poses, prm.dense_weight(1))
     H, g = out["H"].cpu().numpy(), out["g"].cpu().numpy()
     F = chunk.num_frames
+    dframes = {int(f) for k in differ for f in jobs[k]}
     for a in range(F):
         for b in range(F):
             ref = H_ref[6 * a:6 * a + 6, 6 * b:6 * b + 6]
             if np.abs(ref).max() > 0:
-                assert block_rel_err(H[6 * a:6 * a + 6, 6 * b:6 * b + 6], ref) < 1e-5, (a, b)
-    assert np.linalg.norm(g - g_ref) <= 1e-5 * np.linalg.norm(g_ref)
+                tol = 1e-2 if (a in dframes or b in dframes) else 1e-5
+                assert block_rel_err(H[6 * a:6 * a + 6, 6 * b:6 * b + 6], ref) < tol, (a, b)
+    assert np.linalg.norm(g - g_ref) <= (1e-2 if differ else 1e-5) * np.linalg.norm(g_ref)
     ref = solve(chunk.depth, chunk.intensity, chunk.intrinsics, chunk.corr_i, chunk.corr_j, chunk.corr_p,
                 chunk.corr_q, chunk.init_poses, prm, linear="pcg")
     sol = bf.bf_gauss_newton(ctx, dp, poses_cuda(chunk.init_poses), bf_params_from(prm, **kw))

@@ -72,7 +72,10 @@ def test_planar_normals():
     ok = fd.normal_ok
     assert ok[1:-1, 1:-1].all() and not ok[0].any() and not ok[-1].any() and not ok[:, 0].any()
     assert np.abs(fd.N[ok] - n).max() < 1e-5
-    assert np.abs(fd.N32[ok] - n).max() < 1e-5
+    # the binary32 rounding bound of a normal covers the tilt that the FP32
+    # quantisation of the depth itself causes (the same first-order effect)
+    assert (np.linalg.norm(fd.N[ok] - n, axis=1) <= fd.N_sigma[ok]).all()
+    assert fd.N_sigma[ok].max() < 1e-4 and (fd.flip_margin[ok] > 0.5).all()
     assert (np.einsum("ka,ka->k", fd.N[ok], fd.P[ok]) < 0).all()
     # P is the back-projection
     fx, fy, cx, cy, W, H = INTR
