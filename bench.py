@@ -82,34 +82,155 @@ def copy_calibration(mib):
     del src, dst
 
 
-def cpu_baseline(prob, n_gn, n_pcg):
-    """The FP64 oracle on a bounded sample: per-solve setup + one Gauss-Newton iteration."""
+_ORC = {}
+
+
+def _oracle_worker_init(prob, n_gn, n_pcg):
+    """Spawned oracle worker: its own per-solve setup (not timed)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import Params
+    from oracle.gn import Setup
+    threadpool_limits(limits=1)
+    prm = Params(num_gn=n_gn, num_pcg=n_pcg)
+    _ORC["setup"] = Setup(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p,
+                          prob.corr_q, prob.init_poses, prm)
+
+
+def _oracle_edge_blocks(args):
+    from oracle.gn import edge_blocks
+    lo, hi, poses, wd = args
+    s = _ORC["setup"]
+    sub = type(s).__new__(type(s))
+    sub.__dict__.update(s.__dict__)
+    sub.edges, sub.edge_dense, sub.edge_sparse = s.edges[lo:hi], s.edge_dense[lo:hi], s.edge_sparse[lo:hi]
+    return [{k: b[k] for k in ("Hii", "Hij", "Hjj", "gi", "gj")} for b in edge_blocks(sub, poses, wd)]
+
+
+def _oracle_gn_iteration(s, prm, poses, k, pool=None, chunks=1):
+    """One Gauss-Newton iteration of the oracle (assembly, block-Jacobi PCG, update);
+    the edge blocks in `pool` when given."""
+    from oracle.gn import build_system
+    from oracle.se3 import exp_se3
+    from oracle.system import assemble, inert_frames, reduce_system, solve_pcg
+    if pool is None:
+        H, g, _, _ = build_system(s, poses, prm.dense_weight(k))
+    else:
+        E = len(s.edges)
+        step = (E + chunks - 1) // chunks
+        parts = pool.map(_oracle_edge_blocks, [(lo, min(E, lo + step), poses, prm.dense_weight(k))
+                                               for lo in range(0, E, step)])
+        H, g = assemble(s.F, s.edges, [b for part in parts for b in part])
+    inert = inert_frames(H, s.free)
+    act = s.free[~inert]
+    Hr, gr, _ = reduce_system(H, g, act)
+    dx, _ = solve_pcg(Hr, gr, prm.num_pcg)
+    out = poses.copy()
+    for n, f in enumerate(act):
+        out[f] = out[f] @ exp_se3(dx[6 * n:6 * n + 6])
+    return out
+
+
+def cpu_baseline(prob, n_gn, n_pcg, chunk=None, batch_sample=None, full=False):
+    """The FP64 oracle timed on this host's cores.
+
+    Primary (the reported value): one Gauss-Newton iteration of the headline
+    workload on one core (BLAS limited to one thread), per-solve setup excluded.
+    Legs beside it: the same iteration on every core of this process's affinity set
+    (edge blocks in a pool of spawned processes, one per core, threaded BLAS for the
+    solve); the 11-frame chunk solved in full on one core; a sample of the batched
+    chunk problems solved in full on one core; with `full`, also all 8 iterations of
+    the headline workload on one core."""
+    import multiprocessing as mp
+    import os
+
     from threadpoolctl import threadpool_limits
 
     from oracle import Params
-    from oracle.gn import Setup, build_system
-    from oracle.se3 import exp_se3
-    from oracle.system import reduce_system, solve_pcg
+    from oracle.gn import Setup, solve_problem
 
+    cores = len(os.sched_getaffinity(0))
     prm = Params(num_gn=n_gn, num_pcg=n_pcg)
+    legs = []
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         s = Setup(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p, prob.corr_q,
                   prob.init_poses, prm)
         t1 = time.perf_counter()
-        H, g, _, _ = build_system(s, prob.init_poses, prm.dense_weight(0))
-        Hr, gr, _ = reduce_system(H, g, s.free)
-        dx, _ = solve_pcg(Hr, gr, n_pcg)
-        poses = prob.init_poses.copy()
-        for n, f in enumerate(s.free):
-            poses[f] = poses[f] @ exp_se3(dx[6 * n:6 * n + 6])
+        _oracle_gn_iteration(s, prm, prob.init_poses, 0)
         t2 = time.perf_counter()
-    import os
-    return {"value": 1.0 / (t2 - t1), "unit": "GN iters/s", "cores": 1, "kind": "oracle",
+    one = t2 - t1
+    legs.append({"what": f"1 of {n_gn} GN iterations of the headline workload", "cores": 1,
+                 "seconds": round(one, 3), "gn_iters_per_s": round(1.0 / one, 4),
+                 "setup_seconds_excluded": round(t1 - t0, 2)})
+    log(f"oracle: one GN iteration on 1 core {one:.2f} s (setup {t1 - t0:.1f} s)")
+    workers = max(1, min(cores, 16))
+    with mp.get_context("spawn").Pool(workers, initializer=_oracle_worker_init,
+                                      initargs=(prob, n_gn, n_pcg)) as pool:
+        pool.map(_oracle_edge_blocks, [(0, 1, prob.init_poses, 1.0)] * workers)  # workers set up
+        t3 = time.perf_counter()
+        _oracle_gn_iteration(s, prm, prob.init_poses, 0, pool=pool, chunks=8 * workers)
+        t4 = time.perf_counter()
+    legs.append({"what": f"1 of {n_gn} GN iterations of the headline workload", "cores": workers,
+                 "seconds": round(t4 - t3, 3), "gn_iters_per_s": round(1.0 / (t4 - t3), 4),
+                 "how": "edge blocks in spawned worker processes, one per core; assembly and PCG in the parent"})
+    log(f"oracle: one GN iteration on {workers} cores {t4 - t3:.2f} s")
+    with threadpool_limits(limits=1):
+        if chunk is not None:
+            t5 = time.perf_counter()
+            solve_problem(chunk, Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg), linear="pcg")
+            dt = time.perf_counter() - t5
+            legs.append({"what": f"11-frame chunk, full solve ({chunk.n_gn} GN x {chunk.n_pcg} PCG, setup "
+                                 "included)", "cores": 1, "seconds": round(dt, 3), "solves_per_s": round(1 / dt, 3)})
+            log(f"oracle: chunk solve {dt:.2f} s")
+        refs = []
+        if batch_sample:
+            t6 = time.perf_counter()
+            for c in batch_sample:
+                refs.append(solve_problem(c, Params(num_gn=c.n_gn, num_pcg=c.n_pcg), linear="pcg")["poses"])
+            dt = time.perf_counter() - t6
+            legs.append({"what": f"{len(batch_sample)} of the 256 batched chunk problems (160x120, "
+                                 f"{sum(c.num_frames for c in batch_sample)} frames), full solves, setup included",
+                         "cores": 1, "seconds": round(dt, 3), "solves_per_s": round(len(batch_sample) / dt, 3)})
+            log(f"oracle: {len(batch_sample)} batched chunks {dt:.2f} s")
+        if full:
+            t7 = time.perf_counter()
+            X = prob.init_poses.copy()
+            for k in range(n_gn):
+                X = _oracle_gn_iteration(s, prm, X, k)
+            dt = time.perf_counter() - t7
+            legs.append({"what": f"all {n_gn} GN iterations of the headline workload", "cores": 1,
+                         "seconds": round(dt, 3), "gn_iters_per_s": round(n_gn / dt, 4)})
+            log(f"oracle: full headline solve on 1 core {dt:.1f} s")
+    return {"value": round(1.0 / one, 4), "unit": "GN iters/s", "cores": 1, "kind": "oracle",
             "sample": f"1 of {n_gn} Gauss-Newton iterations ({n_pcg} PCG) of the same workload, single thread; "
-                      f"per-solve setup took {t1 - t0:.1f} s and is excluded",
-            "seconds": round(t2 - t1, 3), "host_cpu_count": os.cpu_count(),
-            "host_affinity_cores": len(os.sched_getaffinity(0))}
+                      f"per-solve setup ({t1 - t0:.1f} s) excluded",
+            "seconds": round(one, 3), "host_cpu_count": os.cpu_count(), "host_affinity_cores": cores,
+            "legs": legs}
+
+
+def accuracy_vs_oracle(prob, poses, energy):
+    """Pose and energy error of a headline-workload result against the oracle's
+    iteration-matched FP64 run stored in tests/golden/global200_oracle.npz, and the
+    distance by which the oracle's own run moves when its initial poses move by
+    1e-6 (the iteration's sensitivity to a rounding-sized difference)."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "global200_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path, allow_pickle=False)
+
+    def err(A, B):
+        rot = max(float(np.arccos(np.clip((np.trace(A[f, :3, :3].T @ B[f, :3, :3]) - 1) / 2, -1, 1)))
+                  for f in range(len(A)))
+        return rot, max(float(np.linalg.norm(A[f, :3, 3] - B[f, :3, 3])) for f in range(len(A)))
+    if g["poses"].shape != poses.shape or not np.array_equal(g["traj"][0], prob.init_poses):
+        return None
+    rot, tr = err(poses, g["poses"])
+    srot, str_ = err(g["moved_poses"], g["poses"])
+    er = float(g["energy"][0])
+    return {"reference": "oracle FP64, same iteration counts (8 GN x 20 PCG, block-Jacobi)",
+            "max_rot_rad": rot, "max_trans_m": tr, "energy_rel": abs(energy - er) / er,
+            "oracle_self_sensitivity_to_1e-6_start": {"rad": srot, "m": str_}}
 
 
 def main():
@@ -118,6 +239,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="also time all 8 oracle GN iterations of the headline workload (about 2 minutes)")
     ap.add_argument("--bidirectional", type=int, default=0,
                     help="1: dense terms over the pixels of both frames of every pair")
     ap.add_argument("--pcg-storage", type=int, default=None,
@@ -274,7 +397,7 @@ def main():
         "gn_iters_per_s_structure_cached": round(prob.n_gn * 1e6 / max(phase[1] + phase[2] + phase[3] + phase[4],
                                                                         1e-9), 1),
         "accuracy": {"max_rot_rad_vs_ground_truth": round(gt_rot, 6), "max_trans_m_vs_ground_truth": round(gt_tr, 6),
-                     "oracle_parity": "tests/test_gpu_global200.py, tests/test_gpu_global2000.py"},
+                     "vs_oracle": None if big else accuracy_vs_oracle(prob, Pout, res["energy"]["total"])},
         "phase_us_per_step": {n: round(v, 1) for n, v in zip(
             ["setup", "dense", "edges", "assemble", "pcg", "final", "total"], phase[:7])},
     }
@@ -307,9 +430,18 @@ def main():
         line["batched"] = batched(bf, ctx, chunks, args.batched_steps)
     if pool is not None:
         line["serving"] = serving(bf, ctx, pool, args.serving_requests)
+    if args.no_cpu_baseline and "batched" in line:
+        line["batched"].pop("_poses")
     if not args.no_cpu_baseline:
-        log("timing the oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(prob, prob.n_gn, prob.n_pcg)
+        log("timing the oracle on bounded samples")
+        from synth import make_problem as _mp
+        sample = chunks[:4] if chunks is not None else None
+        line["cpu_baseline"] = cpu_baseline(prob, prob.n_gn, prob.n_pcg, chunk=_mp(0), batch_sample=sample,
+                                            full=args.oracle_full)
+        refs = line["cpu_baseline"].pop("_batch_ref")
+        if chunks is not None and "batched" in line:
+            line["batched"]["accuracy_vs_oracle"] = batched_accuracy(line["batched"].pop("_poses"), chunks[:4],
+                                                                     refs)
     ctx.close()
     print(json.dumps(line), flush=True)
 
@@ -348,6 +480,7 @@ def batched(bf, ctx, chunks, steps):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
     graph_same = bool(torch.equal(out, gout)) and gres["energy"] == res["energy"]
+    first = gout[:offs[4]].cpu().numpy()
     tparams = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0, timing=1)
     bf.bf_gauss_newton_batch(ctx, dp, offs, init, tparams, out_poses=out)
     phases = {k: round(v, 1) for k, v in ctx.last_timings().items()}
@@ -374,11 +507,26 @@ def batched(bf, ctx, chunks, steps):
             "sequential_value": round(nb / t_seq, 2), "speedup": round(t_seq / t_batch, 2),
             "ms_per_batch": round(1e3 * t_batch, 3), "steps": steps,
             "eager_value": round(nb / t_eager, 2), "graph_equals_eager": graph_same, "phase_us": phases,
+            "_poses": [first[offs[b]:offs[b + 1]] for b in range(4)],
             "max_pose_diff_vs_sequential": {"rad": worst_r, "m": worst_t},
             "config": {"workload": f"{nb} chunk problems, 4-11 frames (sum {offs[-1]}), 160x120, "
                                    f"{n_gn} GN x {n_pcg} PCG, dense workgroup size timed per shape, "
                                    f"Gauss-Newton loop replayed as one HIP graph"}}
 
+
+
+def batched_accuracy(poses, chunks, refs):
+    """Largest pose error of the first batched problems against the oracle's solves of
+    the same problems (same iteration counts, FP64), timed in the oracle leg."""
+    import numpy as np
+    worst_r = worst_t = 0.0
+    for P, c, ref in zip(poses, chunks, refs):
+        for f in range(c.num_frames):
+            worst_r = max(worst_r, float(np.arccos(np.clip((np.trace(P[f, :3, :3].T @ ref[f, :3, :3]) - 1) / 2,
+                                                          -1, 1))))
+            worst_t = max(worst_t, float(np.linalg.norm(P[f, :3, 3] - ref[f, :3, 3])))
+    return {"problems": len(chunks), "max_rot_rad": worst_r, "max_trans_m": worst_t,
+            "reference": "oracle FP64, same iteration counts"}
 
 
 def serving(bf, ctx, pool, n_requests):

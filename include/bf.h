@@ -133,7 +133,18 @@ typedef struct bf_params {
                                (Sec. 4.3 sums over the pixels of frame i of each pair in E; this is
                                the symmetric variant).  Records then hold 2P jobs: pair p at p
                                and its reverse at P + p. */
-  int32_t reserved2;        /* must be 0 */
+  int32_t pcg_spin_limit;   /* polls after which a PCG kernel's wait for the other workgroups gives
+                               up (then BF_ERR_DEVICE, nothing written); 0 = the default of 2^26
+                               (about two seconds).  A small value forces the time-out path. */
+  const uint32_t* fixed_association;
+                            /* device, NULL (default) = decide the dense association at the
+                               current poses as Sec. 4.3 describes.  Otherwise the association
+                               to use, [jobs][H][W][2] uint32 in the layout bf_eval_residuals
+                               writes to out_assoc (same job order): it is held fixed instead of
+                               decided, e.g. to compare the residual arithmetic of two
+                               implementations under one association, or to iterate on a smooth
+                               energy.  Only pixels whose source and target normals (and
+                               gradients, for the photometric term) are valid are used. */
 } bf_params;
 
 void bf_params_default(bf_params* out);
@@ -205,42 +216,70 @@ bf_status bf_build_structure(bf_context* ctx, const bf_frames* frames, const bf_
  *     the upper triangle of sum w J_j^T J_j (21, row-major), sum w J_j^T r (6), the
  *     weighted geometric and photometric energies and the two residual counts, where
  *     J_j is the Jacobian with respect to the target frame's perturbation.
- *   out_masks (device, may be NULL) [jobs][H][W] uint8: the association decisions of every
- *     source pixel of every dense pair job (same job order as the records): bit 0 = the
- *     geometric residual is used (nearest pixel inside the image with a valid normal,
- *     |c - q| < tau_dist, m.N_j > tau_normal), bit 1 = the photometric residual is used
- *     (additionally G_i valid and the bilinear footprint inside the image and valid).
- *     For inspection and tests; the decisions are those every other entry point takes.
+ *   out_assoc (device, may be NULL) [jobs][H][W][2] uint32: the association of every source
+ *     pixel of every dense pair job (same job order as the records), for inspection and
+ *     tests; the decisions are those every other entry point takes.  Word 0 is 0 when the
+ *     pixel has no geometric residual, else (target pixel y*W + x) << 2 | 1, plus 2 when it
+ *     also has a photometric one (the nearest pixel floor(u+1/2), floor(v+1/2) inside the
+ *     image with a valid normal, |c - q| < tau_dist, m.N_j > tau_normal; photometric: G_i
+ *     valid and the bilinear footprint inside the image and valid).  Word 1 is the first
+ *     pixel y0*W + x0 of the bilinear footprint (floor(u), floor(v)), 0 when unused.
  */
 bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
                             const bf_corrs* corrs, const bf_pairs* pairs, const double* poses,
                             const bf_params* params, int32_t gn_iter, double* out_energy,
-                            int64_t* out_counts, double* out_pair_records, uint8_t* out_masks);
+                            int64_t* out_counts, double* out_pair_records, uint32_t* out_assoc);
+
+/*
+ * A system of normal equations J^T J dx = -J^T F (Sec. 4.4) built at fixed poses:
+ * the per-edge 6x6 blocks, the right-hand side and the structure the PCG reads,
+ * held in device memory owned by the system.  Created empty for a context and
+ * used only with that context; bf_build_normal_equations fills it (again, when
+ * reused), bf_system_export, bf_pcg_solve and bf_system_matvec read it.  Several
+ * systems of one context can coexist; nothing refers to "the last system".
+ * bf_system_destroy synchronises the context's stream (which must still exist)
+ * and frees the system; it may be called after bf_destroy of its context.
+ */
+typedef struct bf_system bf_system;
+bf_status bf_system_create(bf_context* ctx, bf_system** out);
+void bf_system_destroy(bf_system* sys);
 
 /*
  * Normal equations at fixed poses (Sec. 4.4): J^T J and J^T F of E_align with the
- * dense weight of iteration `gn_iter`, kept in the context for bf_pcg_solve().
- *   out_H (device, may be NULL): dense [6F][6F] float64 (for small problems / tests).
- *   out_g (device, may be NULL): [6F] float64.
+ * dense weight of iteration `gn_iter`, built into `sys` (created for this context).
  *   out_edge_blocks (device, may be NULL): [num_edges][128] float64 per edge (i,j):
  *     H_ii (36), H_jj (36), H_ij (36), g_i (6), g_j (6), sparse, geometric and
  *     photometric energy, and the three residual counts.
  *   out_energy (host, may be NULL) [4] as for bf_eval_residuals.
+ * On error `sys` is left as it was.
  */
 bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
                                     const bf_corrs* corrs, const bf_pairs* pairs, const double* poses,
-                                    const bf_params* params, int32_t gn_iter, double* out_H,
-                                    double* out_g, double* out_edge_blocks, double* out_energy);
+                                    const bf_params* params, int32_t gn_iter, bf_system* sys,
+                                    double* out_edge_blocks, double* out_energy);
 
 /*
- * Block-Jacobi PCG (Sec. 4.4) on the system of the last bf_build_normal_equations()
- * call in this context: solves H' dx = -g' over the free frames from dx = 0 with
- * `num_iters` iterations.  out_delta (device) [6F] float64 receives dx in frame
- * order with zeros for frame 0 and frames that are not variables.
- * out_stats (host, may be NULL) [3]: r^T z at the start, at the end, iterations run.
- * BF_ERR_NOT_PD if a diagonal block cannot be factorised.
+ * The system as dense arrays (small problems, tests):
+ *   out_H (device, may be NULL): [6F][6F] float64, all frames (frame 0 included).
+ *   out_g (device, may be NULL): [6F] float64.
+ *   out_num_free (host, may be NULL): frames that are variables.
+ * Synchronises the stream.
  */
-bf_status bf_pcg_solve(bf_context* ctx, int32_t num_iters, double* out_delta, double* out_stats);
+bf_status bf_system_export(bf_context* ctx, const bf_system* sys, double* out_H, double* out_g,
+                           int64_t* out_num_free);
+
+/*
+ * Block-Jacobi PCG (Sec. 4.4) on `sys`: solves H' dx = -g' over the free frames
+ * from dx = 0 with `num_iters` iterations, in the storage precision, preconditioner
+ * and PCG kernel of the params the system was built with.  out_delta (device) [6F]
+ * float64 receives dx in frame order with zeros for frame 0 and frames that are not
+ * variables.  out_stats (host, may be NULL) [3]: r^T z at the start, at the end,
+ * iterations run.  BF_ERR_NOT_PD if a diagonal block cannot be factorised;
+ * BF_ERR_DEVICE if a wait of the PCG kernel for its other workgroups gave up
+ * (params->pcg_spin_limit).
+ */
+bf_status bf_pcg_solve(bf_context* ctx, const bf_system* sys, int32_t num_iters, double* out_delta,
+                       double* out_stats);
 
 /*
  * The full solve (Sec. 4.3-4.4): params->num_gn Gauss-Newton iterations from
@@ -321,8 +360,8 @@ bf_status bf_gauss_newton_pruned(bf_context* ctx, const bf_frames* frames, const
                                  int32_t* out_rounds, double* out_rmax);
 
 /*
- * y = H x with the J^T J matrix of the last bf_build_normal_equations() call (all
- * frames, 6F, frame 0 included), for comparing representations (Sec. 4.4):
+ * y = H x with the J^T J matrix of `sys` (all frames, 6F, frame 0 included), for
+ * comparing representations (Sec. 4.4):
  *   mode 0: from the assembled per-edge 6x6 blocks (what the PCG kernels use);
  *   mode 1: the sparse term only, matrix-free as the paper does it: J x per
  *           correspondence, then J^T per frame over the frame's correspondences.
@@ -331,8 +370,8 @@ bf_status bf_gauss_newton_pruned(bf_context* ctx, const bf_frames* frames, const
  * x, y: device [6F] float64.  out_us (host, may be NULL): time of the product's
  * kernels.  Synchronises the stream.
  */
-bf_status bf_system_matvec(bf_context* ctx, const bf_corrs* corrs, const double* x, double* y, int32_t mode,
-                           double* out_us);
+bf_status bf_system_matvec(bf_context* ctx, const bf_system* sys, const bf_corrs* corrs, const double* x, double* y,
+                           int32_t mode, double* out_us);
 
 /*
  * Many independent problems in one call (Sec. 4.1: every chunk's intra-chunk

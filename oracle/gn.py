@@ -125,8 +125,10 @@ def solve(depth, intensity, intr, corr_i, corr_j, p, q, init_poses, params=None,
         wd = params.dense_weight(k)
         H, g, blocks, en = build_system(setup, poses, wd, assoc)
         if freeze_association and assoc is None:
-            assoc = {e: b["dense"]["terms"] for e, b in enumerate(blocks) if b["dense"] is not None}
-            assoc.update({("rev", e): b["dense_rev"]["terms"] for e, b in enumerate(blocks)
+            keep = ("geo", "photo", "xh", "yh", "x0", "y0")
+            assoc = {e: {k: b["dense"]["terms"][k] for k in keep} for e, b in enumerate(blocks)
+                     if b["dense"] is not None}
+            assoc.update({("rev", e): {k: b["dense_rev"]["terms"][k] for k in keep} for e, b in enumerate(blocks)
                           if b["dense_rev"] is not None})
         inert = inert_frames(H, setup.free)
         active = setup.free[~inert]

@@ -56,7 +56,8 @@ class bf_params(ctypes.Structure):
                 ("solve_kernel", c_int32), ("dense_threads", c_int32),
                 ("tau_dist", c_double), ("tau_normal", c_double), ("max_angle_deg", c_double),
                 ("depth_min", c_double), ("depth_max", c_double), ("preconditioner", c_int32),
-                ("graph", c_int32), ("bidirectional", c_int32), ("reserved2", c_int32)]
+                ("graph", c_int32), ("bidirectional", c_int32), ("pcg_spin_limit", c_int32),
+                ("fixed_association", c_void_p)]
 
 
 class bf_structure(ctypes.Structure):
@@ -80,10 +81,13 @@ _SIGS = {
     "bf_eval_residuals": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                   POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_int32, POINTER(c_double),
                                   POINTER(c_int64), c_void_p, c_void_p]),
+    "bf_system_create": (c_int, [c_void_p, POINTER(c_void_p)]),
+    "bf_system_destroy": (None, [c_void_p]),
     "bf_build_normal_equations": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                           POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_int32, c_void_p,
-                                          c_void_p, c_void_p, POINTER(c_double)]),
-    "bf_pcg_solve": (c_int, [c_void_p, c_int32, c_void_p, POINTER(c_double)]),
+                                          c_void_p, POINTER(c_double)]),
+    "bf_system_export": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
+    "bf_pcg_solve": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_double)]),
     "bf_gauss_newton": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                 POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_void_p, POINTER(c_double),
                                 POINTER(c_double)]),
@@ -97,7 +101,8 @@ _SIGS = {
                                           c_double, c_void_p, POINTER(c_int64)]),
     "bf_verify_pairs": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_pairs), c_void_p,
                                 POINTER(bf_params), c_double, c_double, c_double, c_void_p, c_void_p]),
-    "bf_system_matvec": (c_int, [c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32, POINTER(c_double)]),
+    "bf_system_matvec": (c_int, [c_void_p, c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32,
+                                 POINTER(c_double)]),
     "bf_last_timings": (c_int, [c_void_p, POINTER(c_double)]),
     "bf_graph_captures": (ctypes.c_int64, [c_void_p]),
 }
@@ -184,6 +189,7 @@ class Context:
         h = c_void_p()
         self._check(self.lib.bf_create(ctypes.byref(h), c_void_p(stream.cuda_stream)), ctx=None)
         self.h = h
+        self.systems = weakref.WeakSet()
         _live.add(self)
 
     def _check(self, st, ctx="self"):
@@ -192,6 +198,8 @@ class Context:
             raise BFError(st, (msg or b"").decode() or self.lib.bf_status_string(st).decode())
 
     def close(self):
+        for y in list(getattr(self, "systems", ())):
+            y.close()
         if getattr(self, "h", None):
             self.lib.bf_destroy(self.h)
             self.h = None
@@ -215,6 +223,31 @@ class Context:
     def graph_captures(self):
         """How often this context has captured the Gauss-Newton loop into a graph."""
         return int(self.lib.bf_graph_captures(self.h))
+
+
+class System:
+    """A bf_system: normal equations built by bf_build_normal_equations, owned here
+    and freed by close() (or when its context is closed)."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        h = c_void_p()
+        ctx._check(ctx.lib.bf_system_create(ctx.h, ctypes.byref(h)))
+        self.h = h
+        ctx.systems.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.bf_system_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class DeviceProblem:
@@ -312,8 +345,9 @@ def bf_build_structure(ctx, prob, poses, params):
 
 def bf_eval_residuals(ctx, prob, poses, params, gn_iter=0, records=False, masks=False):
     """Energies and counts at fixed poses; optionally the per-job records [jobs, 32]
-    and the per-pixel association masks [jobs, H, W] (uint8: bit 0 geometric, bit 1
-    photometric)."""
+    and (masks=True) the per-pixel association [jobs, H*W, 2] int32: word 0 = target
+    pixel << 2 | photometric << 1 | geometric (0 without a geometric residual), word 1
+    = first pixel of the bilinear footprint."""
     _poses_check(poses, prob.num_frames)
     e = (c_double * 4)()
     n = (c_int64 * 3)()
@@ -325,7 +359,7 @@ def bf_eval_residuals(ctx, prob, poses, params, gn_iter=0, records=False, masks=
             rec = torch.empty((jobs, 32), dtype=torch.float64, device=poses.device)
         if masks:
             Hh, Ww = prob.depth.shape[1], prob.depth.shape[2]
-            msk = torch.empty((jobs, Hh, Ww), dtype=torch.uint8, device=poses.device)
+            msk = torch.empty((jobs, Hh * Ww, 2), dtype=torch.int32, device=poses.device)
     ctx._check(ctx.lib.bf_eval_residuals(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr),
                                          ctypes.byref(prob.corrs), prob._pairs_ref(), _ptr(poses),
                                          ctypes.byref(params), gn_iter, e, n,
@@ -340,12 +374,14 @@ def bf_eval_residuals(ctx, prob, poses, params, gn_iter=0, records=False, masks=
     return out
 
 
-def bf_build_normal_equations(ctx, prob, poses, params, gn_iter=0, dense=True, edge_blocks=False):
+def bf_build_normal_equations(ctx, prob, poses, params, gn_iter=0, dense=True, edge_blocks=False, system=None):
+    """Build the normal equations at `poses` into `system` (a new System when None);
+    returns the system, the energies and, with dense=True, H [6F,6F] and g [6F]
+    exported from it, with edge_blocks=True the per-edge blocks [E,128]."""
     _poses_check(poses, prob.num_frames)
     F = prob.num_frames
     dev = poses.device
-    H = torch.empty((6 * F, 6 * F), dtype=torch.float64, device=dev) if dense else None
-    g = torch.empty((6 * F,), dtype=torch.float64, device=dev)
+    y = System(ctx) if system is None else system
     eb = None
     if edge_blocks:
         st = bf_build_structure(ctx, prob, poses, params)
@@ -353,15 +389,27 @@ def bf_build_normal_equations(ctx, prob, poses, params, gn_iter=0, dense=True, e
     e = (c_double * 4)()
     ctx._check(ctx.lib.bf_build_normal_equations(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr),
                                                  ctypes.byref(prob.corrs), prob._pairs_ref(), _ptr(poses),
-                                                 ctypes.byref(params), gn_iter, _ptr(H), _ptr(g),
+                                                 ctypes.byref(params), gn_iter, y.h,
                                                  _ptr(eb) if eb is not None and eb.numel() else None, e))
-    return {"H": H, "g": g, "edge_blocks": eb, "energy": list(e)}
+    out = {"system": y, "edge_blocks": eb, "energy": list(e), "H": None, "g": None}
+    if dense:
+        out["H"], out["g"], out["num_free"] = bf_system_export(ctx, y, F)
+    return out
 
 
-def bf_pcg_solve(ctx, num_frames, iters, device="cuda"):
+def bf_system_export(ctx, system, num_frames, device="cuda"):
+    """Dense H [6F,6F], g [6F] and the number of free frames of a system."""
+    H = torch.empty((6 * num_frames, 6 * num_frames), dtype=torch.float64, device=device)
+    g = torch.empty((6 * num_frames,), dtype=torch.float64, device=device)
+    nf = c_int64()
+    ctx._check(ctx.lib.bf_system_export(ctx.h, system.h, _ptr(H), _ptr(g), ctypes.byref(nf)))
+    return H, g, nf.value
+
+
+def bf_pcg_solve(ctx, system, num_frames, iters, device="cuda"):
     delta = torch.empty((6 * num_frames,), dtype=torch.float64, device=device)
     st = (c_double * 3)()
-    ctx._check(ctx.lib.bf_pcg_solve(ctx.h, iters, _ptr(delta), st))
+    ctx._check(ctx.lib.bf_pcg_solve(ctx.h, system.h, iters, _ptr(delta), st))
     return delta, {"rz0": st[0], "rz_final": st[1], "iters": int(st[2])}
 
 
@@ -438,13 +486,14 @@ def device_batch(problems, device="cuda"):
     return dp, b["offsets"], init
 
 
-def bf_system_matvec(ctx, prob, x, mode):
-    """y = H x of the last assembled system (mode 0 blocks, mode 1 matrix-free sparse
-    term); returns (y, microseconds)."""
+def bf_system_matvec(ctx, system, prob, x, mode):
+    """y = H x of a system (mode 0 blocks, mode 1 matrix-free sparse term); returns
+    (y, microseconds)."""
     _need(x, torch.float64, (6 * prob.num_frames,), "x")
     y = torch.empty_like(x)
     us = c_double()
-    ctx._check(ctx.lib.bf_system_matvec(ctx.h, ctypes.byref(prob.corrs), _ptr(x), _ptr(y), mode, ctypes.byref(us)))
+    ctx._check(ctx.lib.bf_system_matvec(ctx.h, system.h, ctypes.byref(prob.corrs), _ptr(x), _ptr(y), mode,
+                                        ctypes.byref(us)))
     return y, us.value
 
 

@@ -12,6 +12,24 @@ struct bf_context : bf::Context {
   std::vector<hipEvent_t> pool;
 };
 
+// Normal equations built by bf_build_normal_equations: the assembled per-edge
+// blocks and everything the PCG, the dense export and the matrix-free product read
+// (incidence, row lists, variable maps, segment ranges), owned by the system.  A
+// context works on a system by exchanging these buffers with its own for the
+// duration of a call (pointer swaps, no copies).
+struct bf_system {
+  bf_context* owner = nullptr;
+  hipStream_t stream = nullptr;  // the owner's stream, synchronised before the buffers are freed
+  bool built = false;
+  bf::Shape shape;
+  int pcg_storage = 0, precond = 0, solve_mode = 0, bidir = 0;
+  unsigned spin_limit = 1u << 26;
+  double w_sparse = 0.0;
+  bf::Buf eblocks, hij32, hij64, edge_ij, iptr, jptr, ej_sorted, row_ptr, row_entries, frame_of_var, var_of,
+      seg_var_ptr, seg_edge_ptr, seg_start, seg_of, sys_poses, corr_perm, corr_group, sparse_ij, sparse_ptr,
+      edge_sparse;
+};
+
 namespace bf {
 
 void fail(bf_status s, const std::string& msg) { throw Error{s, msg}; }
@@ -25,9 +43,16 @@ void check_hip(hipError_t e, const char* what) {
 
 namespace {
 std::atomic<unsigned long long> g_alloc_generation{0};  // contexts may live on different threads
+std::atomic<int> g_live_contexts{0};
 }  // namespace
 
+int live_contexts() { return g_live_contexts.load(); }
+
 unsigned long long alloc_generation() { return g_alloc_generation.load(); }
+
+// Buffers changed hands without an allocation (a system exchanged with the
+// context): a captured graph holding their old addresses must be recaptured.
+void bump_alloc_generation() { ++g_alloc_generation; }
 
 void ensure(Buf& b, size_t bytes) {
   if (bytes == 0) bytes = 8;
@@ -130,7 +155,7 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
   if (prm->preconditioner != 0 && prm->preconditioner != 1) fail(BF_ERR_INVALID_ARG, "preconditioner must be 0 or 1");
   if (prm->graph != 0 && prm->graph != 1) fail(BF_ERR_INVALID_ARG, "graph must be 0 or 1");
   if (prm->bidirectional != 0 && prm->bidirectional != 1) fail(BF_ERR_INVALID_ARG, "bidirectional must be 0 or 1");
-  if (prm->reserved2 != 0) fail(BF_ERR_INVALID_ARG, "reserved2 must be 0");
+  if (prm->pcg_spin_limit < 0) fail(BF_ERR_INVALID_ARG, "pcg_spin_limit must be >= 0");
   if (prm->dense_threads != 0 && prm->dense_threads != 64 && prm->dense_threads != 128 &&
       prm->dense_threads != 256 && prm->dense_threads != 512)
     fail(BF_ERR_INVALID_ARG, "dense_threads must be 0, 64, 128, 256 or 512");
@@ -167,6 +192,8 @@ void check_poses(Context& c, const double* poses, int F) {
   hipLaunchKernelGGL(k_check_poses, dim3((F * 16 + 255) / 256), dim3(256), 0, c.stream, poses, F, c.flags.as<int>());
 }
 
+void ensure_pcg_buffers(Context& c);
+
 // Structure + per-iteration buffers for the current shape (offsets: host frame
 // offsets of nseg independent problems, or nullptr for one problem).
 void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co, const bf_pairs* pairs,
@@ -176,7 +203,7 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
   c.solve_mode = prm->solve_kernel;
   c.precond = prm->preconditioner;
   c.bidir = prm->bidirectional;
-  c.have_system = false;
+  c.spin_limit = prm->pcg_spin_limit > 0 ? (unsigned)prm->pcg_spin_limit : (1u << 26);
   ensure(c.counts, 8 * sizeof(long long));
   ensure(c.flags, sizeof(int));
   set_segments(c, fr->num_frames, offsets, nseg);
@@ -184,6 +211,14 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
   const Shape& s = c.shape;
   ensure(c.records, sizeof(double) * kRecWords * ((c.bidir ? 2 : 1) * s.P + 1));
   ensure(c.eblocks, sizeof(double) * kEdgeWords * (s.E + 1));
+  ensure_pcg_buffers(c);
+  ensure(c.trace, sizeof(double) * 8 * s.nseg * (prm->num_gn + 1));
+}
+
+// PCG storage and scratch for the current shape (off-diagonal blocks, diagonal
+// blocks and inverses, right-hand side, vectors) and the per-problem outputs.
+void ensure_pcg_buffers(Context& c) {
+  const Shape& s = c.shape;
   if (c.pcg_storage == 1) {
     ensure(c.hij64, sizeof(double) * 36 * (s.E + 1));
     ensure(c.diag64, sizeof(double) * 36 * (s.nfree + 1));
@@ -199,7 +234,62 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
   }
   ensure(c.energy, sizeof(double) * 8 * s.nseg);
   ensure(c.stats, sizeof(double) * 4 * s.nseg);
-  ensure(c.trace, sizeof(double) * 8 * s.nseg * (prm->num_gn + 1));
+}
+
+// Exchange the system's buffers and sizes with the context's (see bf_system).
+void swap_system(Context& c, bf_system& y) {
+  std::swap(c.eblocks, y.eblocks);
+  std::swap(c.hij32, y.hij32);
+  std::swap(c.hij64, y.hij64);
+  std::swap(c.edge_ij, y.edge_ij);
+  std::swap(c.iptr, y.iptr);
+  std::swap(c.jptr, y.jptr);
+  std::swap(c.ej_sorted, y.ej_sorted);
+  std::swap(c.row_ptr, y.row_ptr);
+  std::swap(c.row_entries, y.row_entries);
+  std::swap(c.frame_of_var, y.frame_of_var);
+  std::swap(c.var_of, y.var_of);
+  std::swap(c.seg_var_ptr, y.seg_var_ptr);
+  std::swap(c.seg_edge_ptr, y.seg_edge_ptr);
+  std::swap(c.seg_start, y.seg_start);
+  std::swap(c.seg_of, y.seg_of);
+  std::swap(c.sys_poses, y.sys_poses);
+  std::swap(c.corr_perm, y.corr_perm);
+  std::swap(c.corr_group, y.corr_group);
+  std::swap(c.sparse_ij, y.sparse_ij);
+  std::swap(c.sparse_ptr, y.sparse_ptr);
+  std::swap(c.edge_sparse, y.edge_sparse);
+  std::swap(c.shape, y.shape);
+  std::swap(c.pcg_storage, y.pcg_storage);
+  std::swap(c.precond, y.precond);
+  std::swap(c.solve_mode, y.solve_mode);
+  std::swap(c.bidir, y.bidir);
+  std::swap(c.spin_limit, y.spin_limit);
+  std::swap(c.sys_w_sparse, y.w_sparse);
+  c.seg_host.clear();  // the segment arrays on the device changed hands
+  bump_alloc_generation();
+}
+
+// A system lent to the context for one call and taken back on every exit path.
+struct SystemLoan {
+  Context& c;
+  bf_system& y;
+  SystemLoan(Context& cc, const bf_system* sys) : c(cc), y(*const_cast<bf_system*>(sys)) {
+    swap_system(c, y);
+    try {
+      ensure_pcg_buffers(c);
+    } catch (...) {
+      swap_system(c, y);
+      throw;
+    }
+  }
+  ~SystemLoan() { swap_system(c, y); }
+};
+
+void check_system(const bf_context* ctx, const bf_system* sys) {
+  if (!sys) fail(BF_ERR_INVALID_ARG, "null system");
+  if (sys->owner != ctx) fail(BF_ERR_INVALID_ARG, "the system belongs to another context");
+  if (!sys->built) fail(BF_ERR_INVALID_ARG, "the system has not been built");
 }
 
 void sync_and_flags(Context& c, int* hf) {
@@ -315,6 +405,7 @@ bf_status bf_create(bf_context** out, void* hip_stream) {
     return BF_ERR_DEVICE;
   }
   c->num_cus = cus;
+  ++g_live_contexts;
   *out = c;
   return BF_OK;
 }
@@ -343,6 +434,7 @@ void bf_destroy(bf_context* c) {
   if (c->gn_exec) (void)hipGraphExecDestroy(c->gn_exec);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   delete c;
+  --g_live_contexts;
 }
 
 const char* bf_status_string(bf_status s) {
@@ -438,7 +530,7 @@ bf_status bf_build_structure(bf_context* ctx, const bf_frames* fr, const bf_intr
 
 bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
                             const bf_pairs* pairs, const double* poses, const bf_params* prm, int32_t gn_iter,
-                            double* out_energy, int64_t* out_counts, double* out_records, uint8_t* out_masks) {
+                            double* out_energy, int64_t* out_counts, double* out_records, uint32_t* out_assoc) {
   return guarded(ctx, [&] {
     validate_common(ctx, fr, in, prm);
     validate_problem(co, pairs, poses);
@@ -450,7 +542,7 @@ bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* fr, const bf_intri
     setup(ctx, fr, in, co, pairs, poses, prm);
     double wd = dense_weight(*prm, gn_iter);
     bool jac = out_records != nullptr;
-    launch_dense(c, *in, poses, *prm, wd, jac, out_masks);
+    launch_dense(c, *in, poses, *prm, wd, jac, out_assoc);
     launch_edge_blocks(c, poses, *prm, false);
     launch_energy(c, c.energy.as<double>());
     if (out_records && c.shape.P > 0)
@@ -468,13 +560,38 @@ bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* fr, const bf_intri
   });
 }
 
+bf_status bf_system_create(bf_context* ctx, bf_system** out) {
+  if (!ctx || !out) return BF_ERR_INVALID_ARG;
+  *out = nullptr;
+  bf_system* y = new (std::nothrow) bf_system();
+  if (!y) return BF_ERR_OUT_OF_MEMORY;
+  y->owner = ctx;
+  y->stream = ctx->stream;
+  *out = y;
+  return BF_OK;
+}
+
+void bf_system_destroy(bf_system* y) {
+  if (!y) return;
+  (void)hipStreamSynchronize(y->stream);
+  Buf* bufs[] = {&y->eblocks, &y->hij32, &y->hij64, &y->edge_ij, &y->iptr, &y->jptr, &y->ej_sorted, &y->row_ptr,
+                 &y->row_entries, &y->frame_of_var, &y->var_of, &y->seg_var_ptr, &y->seg_edge_ptr, &y->seg_start,
+                 &y->seg_of, &y->sys_poses, &y->corr_perm, &y->corr_group, &y->sparse_ij, &y->sparse_ptr,
+                 &y->edge_sparse};
+  for (Buf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  delete y;
+}
+
 bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in,
                                     const bf_corrs* co, const bf_pairs* pairs, const double* poses,
-                                    const bf_params* prm, int32_t gn_iter, double* out_H, double* out_g,
+                                    const bf_params* prm, int32_t gn_iter, bf_system* sys,
                                     double* out_edge_blocks, double* out_energy) {
   return guarded(ctx, [&] {
     validate_common(ctx, fr, in, prm);
     validate_problem(co, pairs, poses);
+    if (!sys) fail(BF_ERR_INVALID_ARG, "null system");
+    if (sys->owner != ctx) fail(BF_ERR_INVALID_ARG, "the system belongs to another context");
     Context& c = *ctx;
     ensure(c.flags, sizeof(int));
     check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
@@ -488,7 +605,6 @@ bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* fr, const 
     check_hip(hipMemcpyAsync(c.sys_poses.p, poses, sizeof(double) * 16 * fr->num_frames, hipMemcpyDeviceToDevice,
                              c.stream), "copy poses");
     c.sys_w_sparse = prm->use_sparse ? prm->w_sparse : 0.0;
-    if (out_H || out_g) launch_export_dense(c, out_H, out_g);
     if (out_edge_blocks && c.shape.E > 0)
       check_hip(hipMemcpyAsync(out_edge_blocks, c.eblocks.p, sizeof(double) * kEdgeWords * c.shape.E,
                                hipMemcpyDeviceToDevice, c.stream), "copy edge blocks");
@@ -496,20 +612,39 @@ bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* fr, const 
     int hf = 0;
     check_hip(hipMemcpyAsync(e8, c.energy.p, sizeof(e8), hipMemcpyDeviceToHost, c.stream), "copy energy");
     sync_and_flags(c, &hf);
-    c.have_system = true;
     raise_flags(hf & ~kFlagNotPD);
+    // the system takes the assembled blocks and the structure the PCG reads; the
+    // context keeps the system's previous buffers for reuse
+    sys->built = false;
+    swap_system(c, *sys);
+    sys->built = true;
     if (out_energy)
       for (int k = 0; k < 4; ++k) out_energy[k] = e8[k];
   });
 }
 
-bf_status bf_pcg_solve(bf_context* ctx, int32_t num_iters, double* out_delta, double* out_stats) {
+bf_status bf_system_export(bf_context* ctx, const bf_system* sys, double* out_H, double* out_g,
+                           int64_t* out_num_free) {
   return guarded(ctx, [&] {
     if (!ctx) fail(BF_ERR_INVALID_ARG, "null context");
+    check_system(ctx, sys);
     Context& c = *ctx;
-    if (!c.have_system) fail(BF_ERR_INVALID_ARG, "no system: call bf_build_normal_equations first");
+    SystemLoan loan(c, sys);
+    if (out_H || out_g) launch_export_dense(c, out_H, out_g);
+    if (out_num_free) *out_num_free = c.shape.nfree;
+    check_hip(hipStreamSynchronize(c.stream), "synchronise");
+  });
+}
+
+bf_status bf_pcg_solve(bf_context* ctx, const bf_system* sys, int32_t num_iters, double* out_delta,
+                       double* out_stats) {
+  return guarded(ctx, [&] {
+    if (!ctx) fail(BF_ERR_INVALID_ARG, "null context");
+    check_system(ctx, sys);
     if (num_iters < 0) fail(BF_ERR_INVALID_ARG, "negative iteration count");
     if (!out_delta) fail(BF_ERR_INVALID_ARG, "null out_delta");
+    Context& c = *ctx;
+    SystemLoan loan(c, sys);
     check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
     if (c.shape.nfree == 0) {
       check_hip(hipMemsetAsync(out_delta, 0, sizeof(double) * 6 * c.shape.F, c.stream), "memset");
@@ -864,16 +999,17 @@ bf_status bf_gauss_newton_pruned(bf_context* ctx, const bf_frames* fr, const bf_
   });
 }
 
-bf_status bf_system_matvec(bf_context* ctx, const bf_corrs* co, const double* x, double* y, int32_t mode,
-                           double* out_us) {
+bf_status bf_system_matvec(bf_context* ctx, const bf_system* sys, const bf_corrs* co, const double* x, double* y,
+                           int32_t mode, double* out_us) {
   return guarded(ctx, [&] {
     if (!ctx) fail(BF_ERR_INVALID_ARG, "null context");
-    Context& c = *ctx;
-    if (!c.have_system) fail(BF_ERR_INVALID_ARG, "no system: call bf_build_normal_equations first");
+    check_system(ctx, sys);
     if (!x || !y) fail(BF_ERR_INVALID_ARG, "null x or y");
     if (mode != 0 && mode != 1) fail(BF_ERR_INVALID_ARG, "mode must be 0 or 1");
-    if (mode == 1 && (!co || co->count != c.shape.M))
+    if (mode == 1 && (!co || co->count != sys->shape.M))
       fail(BF_ERR_INVALID_ARG, "mode 1 needs the correspondences the system was built from");
+    Context& c = *ctx;
+    SystemLoan loan(c, sys);
     hipEvent_t e0, e1;
     check_hip(hipEventCreate(&e0), "hipEventCreate");
     check_hip(hipEventCreate(&e1), "hipEventCreate");

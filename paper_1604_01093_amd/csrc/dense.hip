@@ -156,9 +156,9 @@ __device__ __forceinline__ void pixel_terms(Acc& A, const float* w, const float*
       jp[5] = az;
     }
   } else {
-    // payload: c(3), m(3), q(3), u, v, Gi, taps(4)
+    // payload: c(3), m(3), q(3), bilinear weights (u - x0, v - y0), Gi, taps(4)
     const float cx = w[0], cy = w[1], cz = w[2], mx0 = w[3], my0 = w[4], mz0 = w[5];
-    const float qx = w[6], qy = w[7], qz = w[8], u = w[9], v = w[10], Gi = w[11];
+    const float qx = w[6], qy = w[7], qz = w[8], al = w[9], be = w[10], Gi = w[11];
     ph = !is_nan(Gi);
     const float fswg = (float)swg, fswp = (float)swp;
     rg = (mx0 * (cx - qx) + my0 * (cy - qy) + mz0 * (cz - qz)) * fswg;
@@ -171,7 +171,6 @@ __device__ __forceinline__ void pixel_terms(Acc& A, const float* w, const float*
     jg[5] = -mz;
     if (ph) {
       const float iz = 1.0f / cz;
-      const float al = u - floorf(u), be = v - floorf(v);
       const float g00 = w[12], g10 = w[13], g01 = w[14], g11 = w[15];
       const float Gj = (1.0f - al) * ((1.0f - be) * g00 + be * g01) + al * ((1.0f - be) * g10 + be * g11);
       const float gu = ((1.0f - be) * (g10 - g00) + be * (g11 - g01)) * fswp;
@@ -209,7 +208,8 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
                                               const double* __restrict__ poses, Intr32 in, double fx64, double fy64,
                                               double cx64, double cy64, float tau_d2, float tau_n, double swg,
                                               double swp, double* __restrict__ records,
-                                              unsigned char* __restrict__ masks) {
+                                              const unsigned* __restrict__ fixed,
+                                              unsigned* __restrict__ assoc_out) {
   constexpr int NW = NT / 64;
   constexpr int RL = NT < 256 ? NT : 256;
   constexpr int NCH = RL / 16;
@@ -294,37 +294,71 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
       const float iz = 1.0f / c.z;
       const float u = project32(in.fx, c.x, iz, in.cx);
       const float v = project32(in.fy, c.y, iz, in.cy);
-      const float xf = floorf(u + 0.5f), yf = floorf(v + 0.5f);
-      const float x0f = floorf(u), y0f = floorf(v);
-      // clamped copies for addressing (fminf/fmaxf also map NaN to the bound)
-      const int xh = (int)fminf(fmaxf(xf, 0.0f), fWm1), yh = (int)fminf(fmaxf(yf, 0.0f), fHm1);
-      const int xt = (int)fminf(fmaxf(x0f, 0.0f), fWm2), yt = (int)fminf(fmaxf(y0f, 0.0f), fHm2);
+      // the association: decided here from the projection, or given by the caller
+      // (a fixed association, [job][pixel] word pairs as written to assoc_out)
+      int xh, yh, xt, yt;
+      float x0f, y0f;
+      bool in_img, given_geo = true, given_photo = true;
+      if (fixed == nullptr) {
+        const float xf = floorf(u + 0.5f), yf = floorf(v + 0.5f);
+        x0f = floorf(u);
+        y0f = floorf(v);
+        // clamped copies for addressing (fminf/fmaxf also map NaN to the bound)
+        xh = (int)fminf(fmaxf(xf, 0.0f), fWm1);
+        yh = (int)fminf(fmaxf(yf, 0.0f), fHm1);
+        xt = (int)fminf(fmaxf(x0f, 0.0f), fWm2);
+        yt = (int)fminf(fmaxf(y0f, 0.0f), fHm2);
+        in_img = c.z > 0.0f && xf >= 0.0f && xf <= fWm1 && yf >= 0.0f && yf <= fHm1;
+      } else {
+        const size_t o = 2 * ((size_t)p * HW + (size_t)(pix < HW ? pix : HW - 1));
+        const unsigned w0 = fixed[o], w1 = fixed[o + 1];
+        const unsigned tg = min(w0 >> 2, (unsigned)(HW - 1));
+        xh = (int)(tg % (unsigned)W);
+        yh = (int)(tg / (unsigned)W);
+        xt = min((int)(w1 % (unsigned)W), W - 2);
+        yt = min((int)(w1 / (unsigned)W), H - 2);
+        x0f = (float)xt;
+        y0f = (float)yt;
+        given_geo = (w0 & 1u) != 0;
+        given_photo = (w0 & 2u) != 0;
+        in_img = true;
+      }
       const float4 tq = ld_at(ndj, (unsigned)(yh * W + xh));
       const unsigned t0 = (unsigned)(yt * W + xt);
       const float g00 = ld_at(gj, t0), g10 = ld_at(gj, t0 + 1u), g01 = ld_at(gj, t0 + (unsigned)W),
                   g11 = ld_at(gj, t0 + (unsigned)W + 1u);
       float Gi = ld_at(gi, (unsigned)(pix < HW ? pix : HW - 1));
       const float kxh = ld_at(kx, (unsigned)xh), kyh = ld_at(ky, (unsigned)yh);
-      valid = pix < HW && !is_nan(s4.x) && c.z > 0.0f && xf >= 0.0f && xf <= fWm1 && yf >= 0.0f && yf <= fHm1 &&
-              !is_nan(tq.x);
+      valid = pix < HW && !is_nan(s4.x) && in_img && !is_nan(tq.x);
       const float3 q = make_float3(mul_nc(kxh, tq.w), mul_nc(kyh, tq.w), tq.w);
       const float3 e = make_float3(c.x - q.x, c.y - q.y, c.z - q.z);
       const float3 n = make_float3(s4.x, s4.y, s4.z);
       const float3 m = rotate32(R, n);
-      valid = valid && dot32(e, e) < tau_d2 && dot32(m, make_float3(tq.x, tq.y, tq.z)) > tau_n;
-      const bool ph = x0f >= 0.0f && x0f <= fWm2 && y0f >= 0.0f && y0f <= fHm2 && !is_nan(Gi) &&
-                      !(is_nan(g00) || is_nan(g10) || is_nan(g01) || is_nan(g11));
+      bool ph;
+      if (fixed == nullptr) {
+        valid = valid && dot32(e, e) < tau_d2 && dot32(m, make_float3(tq.x, tq.y, tq.z)) > tau_n;
+        ph = x0f >= 0.0f && x0f <= fWm2 && y0f >= 0.0f && y0f <= fHm2;
+      } else {
+        valid = valid && given_geo;
+        ph = given_photo;
+      }
+      ph = ph && !is_nan(Gi) && !(is_nan(g00) || is_nan(g10) || is_nan(g01) || is_nan(g11));
       if (!ph) Gi = __builtin_nanf("");
-      // decisions out (inspection only): bit 0 geometric, bit 1 photometric
-      if (masks != nullptr && pix < HW)
-        masks[(size_t)p * HW + pix] = (unsigned char)((valid ? 1 : 0) | (valid && ph ? 2 : 0));
+      // the association out (inspection): word 0 = target pixel << 2 | photometric << 1
+      // | geometric, word 1 = first pixel of the bilinear footprint (0 where unused)
+      if (assoc_out != nullptr && pix < HW) {
+        const size_t o = 2 * ((size_t)p * HW + (size_t)pix);
+        assoc_out[o] = valid ? (((unsigned)(yh * W + xh) << 2) | 1u | (ph ? 2u : 0u)) : 0u;
+        assoc_out[o + 1] = (valid && ph) ? (unsigned)(yt * W + xt) : 0u;
+      }
       if constexpr (MODE == 2) {
         wv[0] = D; wv[1] = tq.w; wv[2] = n.x; wv[3] = n.y; wv[4] = n.z;
         wv[5] = (float)px; wv[6] = (float)py; wv[7] = (float)xh; wv[8] = (float)yh;
         wv[9] = x0f; wv[10] = y0f;
       } else {
+        // bilinear weights within the footprint cell
         wv[0] = c.x; wv[1] = c.y; wv[2] = c.z; wv[3] = m.x; wv[4] = m.y; wv[5] = m.z;
-        wv[6] = q.x; wv[7] = q.y; wv[8] = q.z; wv[9] = u; wv[10] = v;
+        wv[6] = q.x; wv[7] = q.y; wv[8] = q.z; wv[9] = u - x0f; wv[10] = v - y0f;
       }
       wv[11] = Gi; wv[12] = g00; wv[13] = g10; wv[14] = g01; wv[15] = g11;
     }
@@ -426,7 +460,7 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
 
 template <int MODE, bool JAC, int NT>
 void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-               unsigned char* masks) {
+               unsigned* assoc_out) {
   const long long P = c.shape.P;
   const long long jobs = c.bidir ? 2 * P : P;
   Intr32 i32{(float)in.fx, (float)in.fy, (float)in.cx, (float)in.cy, in.width, in.height};
@@ -438,12 +472,13 @@ void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const b
   hipLaunchKernelGGL((k_dense<MODE, JAC, NT>), dim3(grid), dim3(NT), 0, c.stream, c.pairs.as<int>(), P, c.bidir,
                      c.nd.as<float4>(), c.grad.as<float>(), c.kx.as<float>(), c.ky.as<float>(), c.kx64.as<double>(),
                      c.ky64.as<double>(), poses, i32, in.fx, in.fy, in.cx, in.cy, tau_d2, tau_n, swg, swp,
-                     c.records.as<double>(), masks);
+                     c.records.as<double>(), reinterpret_cast<const unsigned*>(prm.fixed_association),
+                     assoc_out);
 }
 
 template <int MODE, bool JAC>
 void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd, int nt,
-                 unsigned char* masks) {
+                 unsigned* masks) {
   switch (nt) {
     case 64: launch_nt<MODE, JAC, 64>(c, in, poses, prm, wd, masks); break;
     case 128: launch_nt<MODE, JAC, 128>(c, in, poses, prm, wd, masks); break;
@@ -453,7 +488,7 @@ void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const
 }
 
 void launch_any(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                bool jac, int nt, unsigned char* masks = nullptr) {
+                bool jac, int nt, unsigned* masks = nullptr) {
   const int mode = prm.accumulate;
   if (jac) {
     if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd, nt, masks);
@@ -506,7 +541,7 @@ int choose_threads(Context& c, const bf_intrinsics& in, const double* poses, con
 }  // namespace
 
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                  bool with_jacobians, unsigned char* masks) {
+                  bool with_jacobians, unsigned* masks) {
   if (c.shape.P == 0) return;
   const int nt = choose_threads(c, in, poses, prm, wd, with_jacobians);
   launch_any(c, in, poses, prm, wd, with_jacobians, nt, masks);

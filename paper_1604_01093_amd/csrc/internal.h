@@ -45,10 +45,10 @@ struct Context {
   int num_cus = 0;
   std::string last_error;
   Shape shape;
-  bool have_system = false;
   int pcg_storage = 0;
   int precond = 0;          // 0 = 6x6 block-Jacobi, 1 = scalar Jacobi
   int bidir = 0;            // 1: two dense pair jobs per pair (i -> j, then j -> i at job P + p)
+  unsigned spin_limit = 1u << 26;  // polls before a PCG kernel's wait for other workgroups gives up
   double timings[8] = {0};
 
   // frames
@@ -111,6 +111,10 @@ void* readback_big(Context& c, size_t bytes);
 // Count of workspace (re)allocations so far, in every context: a captured graph
 // holds buffer addresses and is valid only while this count is unchanged.
 unsigned long long alloc_generation();
+// Contexts currently alive in the process: with more than one, kernels whose
+// workgroups wait for each other are launched cooperatively (their co-residency is
+// then guaranteed even while another context's kernels run).
+int live_contexts();
 
 // prep.hip
 void launch_prepare(Context& c, const bf_frames& fr, const bf_intrinsics& in, const bf_params& prm);
@@ -126,10 +130,12 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
                            const bf_params& prm);
 
 // dense.hip
-// masks (may be null): per job and source pixel, bit 0 = geometric and bit 1 =
-// photometric association ([jobs][H*W] bytes).
+// assoc_out (may be null): per job and source pixel the association taken, two
+// words ([jobs][H*W][2]): target pixel << 2 | photometric << 1 | geometric, and the
+// first pixel of the bilinear footprint.  prm.fixed_association, when set, gives
+// the association instead of deciding it (same layout).
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                  bool with_jacobians, unsigned char* masks = nullptr);
+                  bool with_jacobians, unsigned* assoc_out = nullptr);
 // Threads per dense pair job that launch_dense() will use (timing them first when
 // params.dense_threads is 0 and the shape is new in this context).
 int dense_threads_for(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,

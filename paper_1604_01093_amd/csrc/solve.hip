@@ -330,7 +330,9 @@ __device__ double block_sum(double v, double* sh) {
 
 // ---------------------------------------------------------------- persistent solve
 
-constexpr unsigned kSpinLimit = 1u << 26;   // ~2 s of polling: a barrier that never completes raises an error
+// Every wait for other workgroups polls at most `spin_limit` times (a launch
+// argument; 2^26, about two seconds, unless the caller sets another): a barrier
+// that never completes raises an error instead of hanging.
 constexpr int kSolveThreads = 1024;          // 16 wavefronts, one matrix row per wavefront at a time
 constexpr int kSolveWaves = kSolveThreads / 64;
 constexpr int kParts = 8;                     // doubles per workgroup in a grid reduction
@@ -349,7 +351,8 @@ __device__ __forceinline__ void st_shared(T* p, T v) {
 }
 
 // Returns false if the spin limit was hit (then every later barrier is skipped).
-__device__ __forceinline__ bool grid_sync(unsigned* ctr, unsigned target, int* flags, int* sh_ok) {
+__device__ __forceinline__ bool grid_sync(unsigned* ctr, unsigned target, int* flags, int* sh_ok,
+                                          unsigned spin_limit) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -359,7 +362,7 @@ __device__ __forceinline__ bool grid_sync(unsigned* ctr, unsigned target, int* f
       unsigned spins = 0;
       while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
+        if (++spins > spin_limit) {
           atomicOr(flags, kFlagTimeout);
           ok = 0;
           break;
@@ -376,7 +379,7 @@ __device__ __forceinline__ bool grid_sync(unsigned* ctr, unsigned target, int* f
 // (fixed trees: lanes, then wavefronts in order, then workgroups in order).
 template <int K, int NW = kSolveWaves>
 __device__ void grid_sums(double (&v)[K], double* parts, unsigned* bar, unsigned& nbar, int* flags, double* sh,
-                          int* sh_ok, unsigned bar_base = 0u) {
+                          int* sh_ok, unsigned spin_limit, unsigned bar_base = 0u) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -395,7 +398,7 @@ __device__ void grid_sums(double (&v)[K], double* parts, unsigned* bar, unsigned
     st_shared(&pb[blockIdx.x * kParts + threadIdx.x], t);
   }
   ++nbar;
-  grid_sync(bar, bar_base + nbar * gridDim.x, flags, sh_ok);
+  grid_sync(bar, bar_base + nbar * gridDim.x, flags, sh_ok, spin_limit);
   if (wave == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -430,7 +433,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
     const int* __restrict__ var_of, T* __restrict__ diag, T* __restrict__ minv, T* __restrict__ x,
     T* __restrict__ r, T* __restrict__ Ap, T* z, T* pb0, T* pb1, double* parts, unsigned* bar,
     double* __restrict__ trace_slot, double* __restrict__ delta_out, double* __restrict__ poses, int update,
-    double* __restrict__ stats, int* flags, int precond) {
+    double* __restrict__ stats, int* flags, int precond, unsigned spin_limit) {
   __shared__ double sh[(kSolveWaves + 1) * kParts];
   __shared__ double red[kSolveWaves][64];
   __shared__ double blk[kSolveWaves][48];
@@ -497,7 +500,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
          e += (long long)gridDim.x * kSolveThreads)
       for (int q = 0; q < 6; ++q) pro[2 + q] += eb[(size_t)e * kEdgeWords + kEEs + q];
   }
-  grid_sums<8>(pro, parts, bar, nbar, flags, sh, &sh_ok);
+  grid_sums<8>(pro, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
   double rz = pro[0];
   const bool bad = pro[1] > 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -557,7 +560,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
       }
       __builtin_amdgcn_wave_barrier();
     }
-    grid_sums<1>(part, parts, bar, nbar, flags, sh, &sh_ok);
+    grid_sums<1>(part, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
     const double alpha = rz / part[0];
     double part2[1] = {0.0};
     for (long long v = gw; v < nfree; v += nw) {
@@ -579,7 +582,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
         part2[0] += rv * (double)zt;
       }
     }
-    grid_sums<1>(part2, parts, bar, nbar, flags, sh, &sh_ok);
+    grid_sums<1>(part2, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
     beta = part2[0] / rz;
     rz = part2[0];
     ++done;
@@ -701,6 +704,26 @@ __device__ __forceinline__ double block_sum_dpp_1(double v, double* sh) {
   double t = 0.0;
   for (int w = 0; w < NW; ++w) t += sh[w];
   return t;
+}
+
+// Two sums behind one barrier (same slot rule as block_sum_dpp_1; `sh` holds 2 NW).
+template <int NW>
+__device__ __forceinline__ void block_sum2_dpp(double a, double b, double* sh, double out[2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  a = wave_sum_d(a);
+  b = wave_sum_d(b);
+  if (lane == 0) {
+    sh[wave] = a;
+    sh[NW + wave] = b;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+  for (int w = 0; w < NW; ++w) {
+    ta += sh[w];
+    tb += sh[NW + w];
+  }
+  out[0] = ta;
+  out[1] = tb;
 }
 
 template <int NW>
@@ -1031,12 +1054,21 @@ __global__ void __launch_bounds__(kAsmThreads) k_row_assemble(
 
 // Replicated-vector PCG in one launch of resident workgroups (at most what the
 // device holds at once; every wait is bounded).  Every workgroup keeps the full
-// r, z, p vectors and all block-Jacobi inverses in LDS and updates them
-// redundantly, in the same fixed order, so all copies stay bit-identical; each
-// wavefront owns one matrix row and keeps that row's blocks in registers (one
-// block per lane) for the whole solve.  Per iteration the owners publish (A p)_v
-// as tagged words; every workgroup polls until it holds all of A p and performs
-// the vector updates locally.
+// vectors and all block-Jacobi inverses in LDS and updates them redundantly, in
+// the same fixed order, so all copies stay bit-identical; each wavefront owns one
+// matrix row and keeps that row's blocks in registers (one block per lane) for
+// the whole solve.
+//
+// The recurrence is the single-reduction form of preconditioned CG (Chronopoulos
+// and Gear, 1989): with u = M^-1 r and w = A u,
+//   gamma_k = (r_k, u_k), delta_k = (w_k, u_k), beta_k = gamma_k / gamma_{k-1},
+//   alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}),
+//   p_k = u_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}  (s = A p),
+//   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k,
+// the same iterates as the two-reduction form in exact arithmetic.  Per iteration
+// one product w = A u crosses workgroups (the owners publish their rows as tagged
+// words; every workgroup polls until it holds all of w) and both dot products
+// reduce behind one barrier; the vector updates need one more.
 constexpr int kRepThreads = 512;
 constexpr int kRepWaves = kRepThreads / 64;
 
@@ -1048,7 +1080,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     const int2* __restrict__ entries, const int* __restrict__ frame_of_var, const int* __restrict__ var_of,
     const T* __restrict__ diag_t, const T* __restrict__ minv_g, const T* __restrict__ r0,
     unsigned long long* ap_words, double* __restrict__ delta_out, double* __restrict__ poses, int update,
-    double* __restrict__ stats, int* flags, unsigned tag_base) {
+    double* __restrict__ stats, int* flags, unsigned tag_base, unsigned spin_limit) {
   extern __shared__ double lds_dyn[];
   __shared__ double sh[(kRepWaves + 1) * kParts];
   __shared__ double red1024[kRepThreads];
@@ -1056,11 +1088,11 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   __shared__ int sh_ok;
   const long long n = 6 * nfree;
   T* r = reinterpret_cast<T*>(lds_dyn);
-  T* z = r + n;
-  T* p = z + n;
-  T* ap = p + n;
-  T* minv_l = ap + n;
-  T* r2 = minv_l + (MLDS ? 36 * nfree : 0);  // the residual alternates between r and r2
+  T* u = r + n;      // M^-1 r
+  T* p = u + n;
+  T* sv = p + n;     // A p, by recurrence
+  T* wvec = sv + n;  // A u, gathered
+  T* minv_l = wvec + n;
   const T* minv = MLDS ? minv_l : minv_g;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long long wg = blockIdx.x, ngroups = gridDim.x;
@@ -1094,87 +1126,96 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
       for (int q = 0; q < 36; ++q) blockreg[q] = (T)blk[wave][q];
     }
   }
-  for (long long o = tid; o < n; o += kRepThreads) r[o] = r0[o];
+  for (long long o = tid; o < n; o += kRepThreads) {
+    r[o] = r0[o];
+    p[o] = (T)0;
+    sv[o] = (T)0;
+  }
   if constexpr (MLDS)
     for (long long o = tid; o < 36 * nfree; o += kRepThreads) minv_l[o] = minv_g[o];
   __syncthreads();
-  double part = 0.0;
-  for (long long o = tid; o < n; o += kRepThreads) {
-    const long long w = o / 6;
-    const int a = (int)(o % 6);
-    double s = 0.0;
-    for (int b = 0; b < 6; ++b) s += (double)minv[w * 36 + 6 * a + b] * (double)r[6 * w + b];
-    z[o] = (T)s;
-    p[o] = (T)s;
-    part += (double)r[o] * (double)(T)s;
+  // u = M^-1 r and (r, u) partials, one block row per thread
+  double part_ru = 0.0;
+  for (long long w = tid; w < nfree; w += kRepThreads) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) s2 += (double)minv[w * 36 + 6 * a + b] * (double)r[6 * w + b];
+      const T ut = (T)s2;
+      u[6 * w + a] = ut;
+      part_ru += (double)r[6 * w + a] * (double)ut;
+    }
   }
-  double rz = block_sum<kRepThreads>(part, red1024);
-  const double rz0 = rz;
+  __syncthreads();
   T xo = (T)0;  // owner lanes 0..5: x of the owned row
   int done = 0;
-  for (int k = 0; k < iters && !bad && sh_ok; ++k) {
-    if (rz <= 1e-30) break;
-    const unsigned tag = tag_base + (unsigned)k + 1u;
-    constexpr int WPV = sizeof(T) / 4;  // 32-bit halves per value, each published with the tag
-    unsigned long long* apw = ap_words + (size_t)(k & 1) * n * WPV;
-    // A: owners compute (A p)_v from register blocks and the LDS copy of p, publish it
-    if (owner) {
-      T acc[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-      if (partner >= 0) {
-        T pw[6];
+  double gamma = 0.0, gamma_prev = 1.0, alpha_prev = 1.0, rz0 = 0.0;
+  constexpr int WPV = sizeof(T) / 4;  // 32-bit halves per value, each published with the tag
+  for (int k = 0; k <= iters && !bad && sh_ok; ++k) {
+    // ---- w = A u (exchange k), then (r, u) and (w, u) in one reduction; the last
+    // pass after the final update only reduces (r, u) for the statistics
+    double part_wu = 0.0;
+    if (k < iters) {
+      const unsigned tag = tag_base + (unsigned)k + 1u;
+      unsigned long long* apw = ap_words + (size_t)(k & 1) * n * WPV;
+      // owners compute (A u)_v from register blocks and the LDS copy of u, publish it
+      if (owner) {
+        T acc[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+        if (partner >= 0) {
+          T uw[6];
 #pragma unroll
-        for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)partner + b];
+          for (int b = 0; b < 6; ++b) uw[b] = u[6 * (long long)partner + b];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-          T s2 = (T)0;
+          for (int i = 0; i < 6; ++i) {
+            T s2 = (T)0;
 #pragma unroll
-          for (int j = 0; j < 6; ++j) s2 += (tr ? blockreg[6 * j + i] : blockreg[6 * i + j]) * pw[j];
-          acc[i] = s2;
+            for (int j = 0; j < 6; ++j) s2 += (tr ? blockreg[6 * j + i] : blockreg[6 * i + j]) * uw[j];
+            acc[i] = s2;
+          }
+        }
+        // virtual entries 0..ne-1 are the off-diagonal blocks, ne the diagonal; lanes
+        // hold 0..63, rows with more entries take the rest from memory
+        for (long long q = 64 + lane; q <= ne; q += 64) {
+          T uw[6], y[6];
+          if (q < ne) {
+            const int2 en = entries[row_ptr[v] + q];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) uw[b] = u[6 * (long long)en.x + b];
+            block_mv<T>(hij + (size_t)(en.y >> 1) * 36, uw, en.y & 1, y);
+          } else {
+            T dg[36];
+#pragma unroll
+            for (int q2 = 0; q2 < 36; ++q2) dg[q2] = (T)blk[wave][q2];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) uw[b] = u[6 * v + b];
+            block_mv<T>(dg, uw, false, y);
+          }
+#pragma unroll
+          for (int b = 0; b < 6; ++b) acc[b] += y[b];
+        }
+        double tot[6];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) tot[b] = wave_sum_d((double)acc[b]);
+        if (lane < 6 * WPV) {
+          // lane b*WPV + h publishes half h of value b: (tag << 32) | bits
+          const int b = lane / WPV, h = lane % WPV;
+          double tb = tot[0];
+#pragma unroll
+          for (int q = 1; q < 6; ++q)
+            if (b == q) tb = tot[q];
+          unsigned bits;
+          if constexpr (WPV == 1) {
+            bits = __float_as_uint((float)tb);
+          } else {
+            const unsigned long long d = (unsigned long long)__double_as_longlong(tb);
+            bits = h ? (unsigned)(d >> 32) : (unsigned)(d & 0xffffffffull);
+          }
+          st_shared(&apw[(6 * v + b) * WPV + h], ((unsigned long long)tag << 32) | bits);
         }
       }
-      // virtual entries 0..ne-1 are the off-diagonal blocks, ne the diagonal; lanes
-      // hold 0..63, rows with more entries take the rest from memory
-      for (long long q = 64 + lane; q <= ne; q += 64) {
-        T pw[6], y[6];
-        if (q < ne) {
-          const int2 en = entries[row_ptr[v] + q];
-#pragma unroll
-          for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)en.x + b];
-          block_mv<T>(hij + (size_t)(en.y >> 1) * 36, pw, en.y & 1, y);
-        } else {
-          T dg[36];
-#pragma unroll
-          for (int q2 = 0; q2 < 36; ++q2) dg[q2] = (T)blk[wave][q2];
-#pragma unroll
-          for (int b = 0; b < 6; ++b) pw[b] = p[6 * v + b];
-          block_mv<T>(dg, pw, false, y);
-        }
-#pragma unroll
-        for (int b = 0; b < 6; ++b) acc[b] += y[b];
-      }
-      double tot[6];
-#pragma unroll
-      for (int b = 0; b < 6; ++b) tot[b] = wave_sum_d((double)acc[b]);
-      if (lane < 6 * WPV) {
-        // lane b*WPV + h publishes half h of value b: (tag << 32) | bits
-        const int b = lane / WPV, h = lane % WPV;
-        double tb = tot[0];
-#pragma unroll
-        for (int q = 1; q < 6; ++q)
-          if (b == q) tb = tot[q];
-        unsigned bits;
-        if constexpr (WPV == 1) {
-          bits = __float_as_uint((float)tb);
-        } else {
-          const unsigned long long d = (unsigned long long)__double_as_longlong(tb);
-          bits = h ? (unsigned)(d >> 32) : (unsigned)(d & 0xffffffffull);
-        }
-        st_shared(&apw[(6 * v + b) * WPV + h], ((unsigned long long)tag << 32) | bits);
-      }
-    }
-    // B: every workgroup gathers all of A p (polling the tagged words), then updates its copy
-    double part = 0.0;
-    {
+      // every workgroup gathers all of w (polling the tagged words) and forms the
+      // (w, u) partials of the values it gathered
       constexpr int kMaxPer = 8;                 // values per thread gathered at once
       const long long nw = n * WPV;
       for (long long o0 = tid; o0 < nw; o0 += (long long)kRepThreads * kMaxPer) {
@@ -1193,7 +1234,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
           for (int q = 0; q < kMaxPer; ++q) ready = ready & ((unsigned)(wv[q] >> 32) == tag);
           if (ready) break;
           __builtin_amdgcn_s_sleep(1);
-          if (++spins > kSpinLimit) {
+          if (++spins > spin_limit) {
             atomicOr(flags, kFlagTimeout);
             sh_ok = 0;
             break;
@@ -1202,46 +1243,64 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
 #pragma unroll
         for (int q = 0; q < kMaxPer; ++q) {
           const long long o = o0 + (long long)q * kRepThreads;
-          if (o < nw) reinterpret_cast<unsigned*>(ap)[o] = (unsigned)(wv[q] & 0xffffffffull);
+          if (o < nw) reinterpret_cast<unsigned*>(wvec)[o] = (unsigned)(wv[q] & 0xffffffffull);
+        }
+        if constexpr (WPV == 1) {
+#pragma unroll
+          for (int q = 0; q < kMaxPer; ++q) {
+            const long long o = o0 + (long long)q * kRepThreads;
+            if (o < nw) part_wu += (double)__uint_as_float((unsigned)(wv[q] & 0xffffffffull)) * (double)u[o];
+          }
         }
       }
-      __syncthreads();
-      for (long long o = tid; o < n; o += kRepThreads) part += (double)p[o] * (double)ap[o];
+      if constexpr (WPV == 2) {
+        __syncthreads();  // both halves of a value gathered
+        for (long long o = tid; o < n; o += kRepThreads) part_wu += (double)wvec[o] * (double)u[o];
+      }
     }
-    // p.Ap and r.z reduce into separate slots, each behind one barrier: a slot is
-    // written again only after the barriers that follow its reads
-    const double pAp = block_sum_dpp_1<kRepWaves>(part, sh);
+    // (r, u) and (w, u) reduce behind one barrier (slots alternate with k, so a slot
+    // is written again only after the barriers that follow its reads)
+    double two[2];
+    block_sum2_dpp<kRepWaves>(part_ru, part_wu, sh + (k & 1) * 2 * kRepWaves, two);
     if (!sh_ok) break;
-    const double alpha = rz / pAp;
-    if (owner && lane < 6) xo = (T)((double)xo + alpha * (double)p[6 * v + lane]);
-    // r' = r - alpha A p and z = M^-1 r', one block row per thread (its six r'
-    // values read once, the 6x6 inverse as whole rows); the new residual goes to
-    // the other buffer, so no barrier is needed between reading and writing
-    T* rc = (k & 1) ? r2 : r;
-    T* rn = (k & 1) ? r : r2;
-    part = 0.0;
+    gamma = two[0];
+    if (k == 0) rz0 = gamma;
+    if (k == iters || gamma <= 1e-30) break;
+    const double delta = two[1];
+    const double beta = k == 0 ? 0.0 : gamma / gamma_prev;
+    const double alpha = gamma / (delta - (k == 0 ? 0.0 : beta * gamma / alpha_prev));
+    // p = u + beta p, s = w + beta s, r -= alpha s, u = M^-1 r, (r, u) partials: one
+    // block row per thread, every value read and written by that thread only
+    part_ru = 0.0;
     for (long long w = tid; w < nfree; w += kRepThreads) {
       double rb[6];
 #pragma unroll
-      for (int b = 0; b < 6; ++b) rb[b] = (double)(T)((double)rc[6 * w + b] - alpha * (double)ap[6 * w + b]);
+      for (int b = 0; b < 6; ++b) {
+        const long long o = 6 * w + b;
+        const T pn = (T)((double)u[o] + beta * (double)p[o]);
+        const T sn = (T)((double)wvec[o] + beta * (double)sv[o]);
+        p[o] = pn;
+        sv[o] = sn;
+        rb[b] = (double)(T)((double)r[o] - alpha * (double)sn);
+      }
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
         double s2 = 0.0;
 #pragma unroll
         for (int b = 0; b < 6; ++b) s2 += (double)minv[w * 36 + 6 * a + b] * rb[b];
-        rn[6 * w + a] = (T)rb[a];
-        const T zt = (T)s2;
-        z[6 * w + a] = zt;
-        part += rb[a] * (double)zt;
+        const T ut = (T)s2;
+        r[6 * w + a] = (T)rb[a];
+        u[6 * w + a] = ut;
+        part_ru += rb[a] * (double)ut;
       }
     }
-    const double rz_new = block_sum_dpp_1<kRepWaves>(part, sh + kRepWaves);
-    const double beta = rz_new / rz;
-    rz = rz_new;
-    ++done;
-    for (long long o = tid; o < n; o += kRepThreads) p[o] = (T)((double)z[o] + beta * (double)p[o]);
     __syncthreads();
+    if (owner && lane < 6) xo = (T)((double)xo + alpha * (double)p[6 * v + lane]);
+    gamma_prev = gamma;
+    alpha_prev = alpha;
+    ++done;
   }
+  const double rz = gamma;
   // epilogue: owners publish dx and update their poses
   if (owner && lane < 6 && delta_out) delta_out[6LL * frame_of_var[v] + lane] = bad ? 0.0 : (double)xo;
   if (delta_out)
@@ -1404,8 +1463,9 @@ void launch_solve_coop(Context& c, int iters, double* trace_slot, double* delta_
   const int* vof = c.var_of.as<int>();
   int* fl = c.flags.as<int>();
   int pc = c.precond;
+  unsigned spin = c.spin_limit;
   void* args[] = {&nf, &F, &E, &iters, &eb, &hij, &ip, &jp, &ejs, &rp, &en, &fov, &vof, &diag, &minv, &x, &r,
-                  &Ap, &z, &pb0, &pb1, &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl, &pc};
+                  &Ap, &z, &pb0, &pb1, &parts, &bar, &trace_slot, &delta_out, &poses, &upd, &stats, &fl, &pc, &spin};
   check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kSolveThreads), args, 0,
                                        c.stream),
             "cooperative solve launch");
@@ -1514,10 +1574,34 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
                      c.eblocks.as<double>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
                      c.ej_sorted.as<long long>(), c.frame_of_var.as<int>(), c.precond, diag_t, minv_g, r0, trace_slot,
                      fl);
-  hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(kRepThreads), lds, c.stream, nf, F, iters, (const T*)hij,
-                     c.row_ptr.as<long long>(), c.row_entries.as<int2>(), c.frame_of_var.as<int>(),
-                     c.var_of.as<int>(), (const T*)diag_t, (const T*)minv_g, (const T*)r0, tags, delta_out, poses,
-                     update ? 1 : 0, stats, fl, tag_base);
+  // Every workgroup waits for the others: with one context in the process a plain
+  // launch of a grid that fits the occupancy is resident as a whole (nothing else
+  // that waits runs beside it); with several, another context's kernels may hold
+  // CUs, and a cooperative launch guarantees co-residency (about 16 us more per
+  // launch).
+  if (live_contexts() > 1) {
+    const T* hij_c = hij;
+    const long long* rp = c.row_ptr.as<long long>();
+    const int2* en = c.row_entries.as<int2>();
+    const int* fov = c.frame_of_var.as<int>();
+    const int* vof = c.var_of.as<int>();
+    const T* dg = diag_t;
+    const T* mi = minv_g;
+    const T* r0c = r0;
+    int upd = update ? 1 : 0;
+    unsigned spin = c.spin_limit;
+    int itv = iters;
+    void* args[] = {&nf, const_cast<int*>(&F), &itv, &hij_c, &rp, &en, &fov, &vof, &dg, &mi, &r0c, &tags,
+                    &delta_out, &poses, &upd, &stats, &fl, const_cast<unsigned*>(&tag_base), &spin};
+    check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)G), dim3(kRepThreads),
+                                         args, lds, c.stream),
+              "cooperative replicated solve launch");
+  } else {
+    hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(kRepThreads), lds, c.stream, nf, F, iters, (const T*)hij,
+                       c.row_ptr.as<long long>(), c.row_entries.as<int2>(), c.frame_of_var.as<int>(),
+                       c.var_of.as<int>(), (const T*)diag_t, (const T*)minv_g, (const T*)r0, tags, delta_out, poses,
+                       update ? 1 : 0, stats, fl, tag_base, c.spin_limit);
+  }
   return true;
 }
 

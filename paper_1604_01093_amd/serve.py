@@ -16,6 +16,12 @@ Admission is by device-memory footprint: a request (or a batch) starts only
 when the estimated workspace of everything in flight stays within
 `max_inflight_bytes`; otherwise its lane waits until running work finishes.
 
+A request can be cancelled (`Server.cancel`): while it waits it leaves its queue
+at once; once admitted into a running batch or solve the GPU call is not
+interrupted (it is one launch sequence over all members), the other members
+complete as usual and the cancelled one completes with a `Cancelled` error and
+no result.
+
 Every computation of a solve runs in libbf's kernels; this module only
 queues, groups, concatenates device tensors and records times.
 """
@@ -44,6 +50,10 @@ def footprint_bytes(num_frames, width, height, num_corrs, num_pairs=None, direct
     return frames + pair_search + records + edges + corr + 64 * F * 16
 
 
+class Cancelled(RuntimeError):
+    """The request was cancelled before its result was delivered."""
+
+
 class Request:
     """One solve: a DeviceProblem, its initial poses (device) and parameters."""
 
@@ -70,6 +80,7 @@ class Request:
         self.batch_size = 0
         self.lane = None
         self.ready_event = None
+        self.cancelled = False
         self.done = threading.Event()
 
     @property
@@ -115,6 +126,25 @@ class Server:
             (self.small if req.num_frames <= self.small_max_frames else self.large).append(req)
             self.cv.notify_all()
         return req
+
+    def cancel(self, req: Request):
+        """Cancel a submitted request.  Returns "queued" if it was removed before
+        running, "running" if it was admitted already (it then completes with a
+        Cancelled error when its GPU call returns, its result discarded), or "done"
+        if it had completed."""
+        with self.cv:
+            if req.done.is_set():
+                return "done"
+            req.cancelled = True
+            for q in (self.small, self.large):
+                if req in q:
+                    q.remove(req)
+                    req.error = Cancelled(f"request {req.id} cancelled while queued")
+                    req.t_done = time.perf_counter()
+                    req.done.set()
+                    self.cv.notify_all()
+                    return "queued"
+            return "running"
 
     def close(self):
         with self.cv:
@@ -166,13 +196,17 @@ class Server:
 
     def _finish(self, reqs, lane, t_start, err=None):
         t = time.perf_counter()
-        for r in reqs:
-            r.t_start = t_start
-            r.t_done = t
-            r.lane = lane
-            r.batch_size = len(reqs)
-            r.error = err
-            r.done.set()
+        with self.cv:
+            for r in reqs:
+                r.t_start = t_start
+                r.t_done = t
+                r.lane = lane
+                r.batch_size = len(reqs)
+                r.error = err
+                if r.cancelled and err is None:
+                    r.error = Cancelled(f"request {r.id} cancelled while running")
+                    r.poses = r.energy = None
+                r.done.set()
 
     def _batch_lane(self, ctx, stream):
         while True:

@@ -105,6 +105,44 @@ def global200():
         conv_sparse_poses=conv, conv_sparse_iters=np.array(n_conv), conv_sparse_hist=hist)
 
 
+def global200_frozen():
+    """Add to global200_oracle.npz the runs with the dense association decided once,
+    at the initial poses, and held (a smooth energy): the 8 GN x 20 PCG run with the
+    dense weight ramp, and the Gauss-Newton run with dense Cholesky and the full
+    dense weight to increments below 1e-11."""
+    from oracle.gn import Setup, build_system
+    from oracle.se3 import exp_se3
+    from oracle.system import inert_frames, reduce_system, solve_cholesky
+    prob = make_problem(1)
+    path = os.path.join(HERE, "global200_oracle.npz")
+    g = dict(np.load(path, allow_pickle=False))
+    assert str(g["digest"]) == input_digest(prob)
+    prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
+    res = solve_problem(prob, prm, linear="pcg", pairs=g["pairs"], freeze_association=True)
+    print("global200 frozen association: 8 x 20 run took", round(res["seconds"], 1), "s", flush=True)
+    s = res["setup"]
+    assoc = res["assoc"]
+    conv = Params(num_gn=1, num_pcg=1, dense_ramp=False)
+    X = prob.init_poses.copy()
+    hist = []
+    for _ in range(200):
+        H, gg, _, _ = build_system(s, X, conv.dense_weight(0), assoc)
+        inert = inert_frames(H, s.free)
+        act = s.free[~inert]
+        Hr, gr, _ = reduce_system(H, gg, act)
+        dx = solve_cholesky(Hr, gr)
+        for n, f in enumerate(act):
+            X[f] = X[f] @ exp_se3(dx[6 * n:6 * n + 6])
+        hist.append(float(np.abs(dx).max()))
+        print(f"  frozen association, Gauss-Newton {len(hist)}: largest increment {hist[-1]:.3e}", flush=True)
+        if hist[-1] < 1e-11:
+            break
+    g.update(frozen_poses=res["poses"],
+             frozen_energy=np.array([res["energy"][k] for k in ("total", "sparse", "geo", "photo")]),
+             conv_frozen_poses=X, conv_frozen_iters=np.array(len(hist)), conv_frozen_hist=np.array(hist))
+    np.savez_compressed(path, **g)
+
+
 def global200_conv():
     """Recompute only the converged sparse-only solve in global200_oracle.npz."""
     prob = make_problem(1)
@@ -201,6 +239,70 @@ def global2000(workers=8):
         digest=np.array(input_digest(prob)), pairs=s.pairs, free=s.free, traj=np.array(traj),
         steps=np.array(steps), trace=np.array(traces), inert=np.array(inert_sets), poses=X, final=np.array(final),
         seconds=np.array(time.perf_counter() - t0))
+
+
+def _pcg_fp32_storage(Hr, gr, iters):
+    """The oracle's block-Jacobi PCG with the matrix and the vectors (x, r, z, p, Ap)
+    rounded to binary32 after every operation, products summed exactly, dot
+    products and alpha/beta in FP64: the arithmetic of a PCG that stores its
+    matrix and vectors in FP32 with exact (compensated) accumulation."""
+    from oracle.system import block_jacobi_inverse
+    f32 = np.float32
+    n = Hr.shape[0] // 6
+    M = block_jacobi_inverse(Hr).astype(f32).astype(np.float64)
+    H32 = Hr.astype(f32).astype(np.float64)
+
+    def prec(r):
+        return np.einsum("kab,kb->ka", M, r.reshape(n, 6)).ravel().astype(f32).astype(np.float64)
+
+    x = np.zeros_like(gr)
+    r = (-gr).astype(f32).astype(np.float64)
+    z = prec(r)
+    p = z.copy()
+    rz = float(r @ z)
+    for _ in range(iters):
+        if rz <= 1e-30:
+            break
+        Ap = (H32 @ p).astype(f32).astype(np.float64)
+        alpha = rz / float(p @ Ap)
+        x = (x + alpha * p).astype(f32).astype(np.float64)
+        r = (r - alpha * Ap).astype(f32).astype(np.float64)
+        z = prec(r)
+        rzn = float(r @ z)
+        p = (z + (rzn / rz) * p).astype(f32).astype(np.float64)
+        rz = rzn
+    return x
+
+
+def global2000_fp32(workers=8):
+    """Add to global2000_oracle.npz, for each of the oracle's iterates, how far the
+    increment moves when the PCG stores its matrix and vectors in binary32 (with
+    exact accumulation): the error that storage precision alone causes on this
+    ill-conditioned system."""
+    import time
+    from oracle.gn import Setup
+    from oracle.system import inert_frames, reduce_system, solve_pcg
+    prob = make_problem(4)
+    path = os.path.join(HERE, "global2000_oracle.npz")
+    g = dict(np.load(path, allow_pickle=False))
+    assert str(g["digest"]) == input_digest(prob)
+    prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
+    s = Setup(prob.depth, prob.intensity, prob.intrinsics, prob.corr_i, prob.corr_j, prob.corr_p, prob.corr_q,
+              prob.init_poses, prm, pairs=g["pairs"])
+    errs = []
+    for k in range(prm.num_gn):
+        t0 = time.perf_counter()
+        H, gg, _ = _oracle_system(s, g["traj"][k], prm.dense_weight(k), workers)
+        inert = inert_frames(H, s.free)
+        Hr, gr, _ = reduce_system(H, gg, s.free[~inert])
+        del H
+        x64, _ = solve_pcg(Hr, gr, prm.num_pcg)
+        x32 = _pcg_fp32_storage(Hr, gr, prm.num_pcg)
+        errs.append(float(np.abs(x32 - x64).max()))
+        print(f"global2000 step {k}: FP32-stored PCG moves the increment by {errs[-1]:.2e} "
+              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+    g["fp32_storage_err"] = np.array(errs)
+    np.savez_compressed(path, **g)
 
 
 if __name__ == "__main__":

@@ -49,20 +49,43 @@ def upper21(M):
     return np.array([M[a, b] for a in range(6) for b in range(a, 6)])
 
 
-def compare_masks(gpu_masks, assoc, k_near=2.0):
-    """Compare a job's GPU association masks ([H*W] uint8: bit 0 geometric, bit 1
-    photometric) with the oracle's FP64 decisions (``oracle.terms.associate``).
+def compare_masks(gpu_words, assoc, W, k_near=2.0):
+    """Compare a job's GPU association ([H*W, 2] words from bf_eval_residuals:
+    target pixel << 2 | photometric << 1 | geometric, footprint pixel) with the
+    oracle's FP64 decisions (``oracle.terms.associate``): the geometric and
+    photometric decisions, the target pixel where both associate and the bilinear
+    footprint where both use the photometric residual.
 
-    A mismatch is excused only where the oracle flags the decision as within
-    k_near times the binary32 rounding bound of one of its tests; returns
+    A difference is excused only where the oracle flags the decision as within
+    k_near times the binary32 rounding bound of one of its tests (a different
+    target pixel or footprint arises only at a rounding tie of u or v); returns
     (unexcused geometric, unexcused photometric, excused geometric, excused
-    photometric, identical) where `identical` says both masks agree everywhere."""
+    photometric, identical)."""
     from oracle.terms import near_decisions
-    g = np.asarray(gpu_masks).reshape(-1)
-    g_geo = (g & 1) != 0
-    g_ph = (g & 2) != 0
+    g = np.asarray(gpu_words).reshape(-1, 2).astype(np.int64) & 0xffffffff
+    w0, w1 = g[:, 0], g[:, 1]
+    g_geo = (w0 & 1) != 0
+    g_ph = (w0 & 2) != 0
     near_geo, near_ph = near_decisions(assoc, k_near)
-    mg = g_geo != assoc["geo"]
-    mp = g_ph != assoc["photo"]
+    geo, ph = assoc["geo"], assoc["photo"]
+    mg = (g_geo != geo) | (g_geo & geo & ((w0 >> 2) != assoc["yh"] * W + assoc["xh"]))
+    mp = (g_ph != ph) | (g_ph & ph & (w1 != assoc["y0"] * W + assoc["x0"]))
     return (int((mg & ~near_geo).sum()), int((mp & ~near_ph).sum()), int((mg & near_geo).sum()),
             int((mp & near_ph).sum()), not mg.any() and not mp.any())
+
+
+def encode_association(assocs, W):
+    """The oracle's associations of a list of jobs as the fixed association the
+    kernels take (bf_params.fixed_association): [jobs, H*W, 2] int32 on the GPU."""
+    out = np.zeros((len(assocs), len(assocs[0]["geo"]) if assocs else 0, 2), np.int64)
+    for k, a in enumerate(assocs):
+        geo, ph = a["geo"], a["photo"]
+        out[k, :, 0] = np.where(geo, ((a["yh"] * W + a["xh"]) << 2) | 1 | np.where(ph, 2, 0), 0)
+        out[k, :, 1] = np.where(ph, a["y0"] * W + a["x0"], 0)
+    return torch.as_tensor(out.astype(np.int32)).cuda().contiguous()
+
+
+def fix_association(params, t):
+    """Point params.fixed_association at the device tensor t (kept alive by the caller)."""
+    params.fixed_association = t.data_ptr() if t is not None else None
+    return params

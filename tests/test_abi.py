@@ -34,7 +34,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.bf_create(None, None) == bf.BF_ERR_INVALID_ARG
     out = (ctypes.c_double * 8)()
     assert lib.bf_last_timings(None, out) == bf.BF_ERR_INVALID_ARG
-    assert lib.bf_pcg_solve(None, 1, None, None) == bf.BF_ERR_INVALID_ARG
+    assert lib.bf_pcg_solve(None, None, 1, None, None) == bf.BF_ERR_INVALID_ARG
     assert lib.bf_graph_captures(None) == -1
 
 

@@ -33,13 +33,14 @@ def test_sparse_matvec_representations(ctx, config):
               prob.init_poses, prm)
     H, _, _, _ = build_system(s, prob.init_poses, prm.dense_weight(0))
     dp = device_problem(prob)
-    bf.bf_build_normal_equations(ctx, dp, poses_cuda(prob.init_poses), bf_params_from(prm), dense=False)
+    y_sys = bf.bf_build_normal_equations(ctx, dp, poses_cuda(prob.init_poses), bf_params_from(prm),
+                                         dense=False)["system"]
     rng = np.random.default_rng(9)
     x = rng.normal(size=6 * prob.num_frames) * np.tile([0.01, 0.01, 0.01, 0.05, 0.05, 0.05], prob.num_frames)
     ref = H @ x
     xt = torch.as_tensor(x).cuda()
-    y0, t0 = bf.bf_system_matvec(ctx, dp, xt, 0)
-    y1, t1 = bf.bf_system_matvec(ctx, dp, xt, 1)
+    y0, t0 = bf.bf_system_matvec(ctx, y_sys, dp, xt, 0)
+    y1, t1 = bf.bf_system_matvec(ctx, y_sys, dp, xt, 1)
     y0, y1 = y0.cpu().numpy(), y1.cpu().numpy()
     e0 = np.abs(y0 - ref).max() / np.abs(ref).max()
     e1 = np.abs(y1 - ref).max() / np.abs(ref).max()
@@ -56,11 +57,12 @@ def test_matvec_with_dense_terms(ctx):
               prob.init_poses, prm)
     H, _, _, _ = build_system(s, prob.init_poses, prm.dense_weight(2))
     dp = device_problem(prob)
-    bf.bf_build_normal_equations(ctx, dp, poses_cuda(prob.init_poses), bf_params_from(prm), gn_iter=2, dense=False)
+    y_sys = bf.bf_build_normal_equations(ctx, dp, poses_cuda(prob.init_poses), bf_params_from(prm), gn_iter=2,
+                                         dense=False)["system"]
     x = np.random.default_rng(10).normal(size=6 * prob.num_frames) * 0.01
-    y0, _ = bf.bf_system_matvec(ctx, dp, torch.as_tensor(x).cuda(), 0)
+    y0, _ = bf.bf_system_matvec(ctx, y_sys, dp, torch.as_tensor(x).cuda(), 0)
     ref = H @ x
     assert np.abs(y0.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
     with pytest.raises(bf.BFError):
-        bf.bf_system_matvec(ctx, bf.DeviceProblem.from_numpy(prob.depth, prob.intensity, prob.intrinsics),
+        bf.bf_system_matvec(ctx, y_sys, bf.DeviceProblem.from_numpy(prob.depth, prob.intensity, prob.intrinsics),
                             torch.as_tensor(x).cuda(), 1)

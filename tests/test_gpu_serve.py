@@ -91,3 +91,37 @@ def test_admission_budget(pool):
         _check(reqs[1:], alone)
     finally:
         server.close()
+
+
+def test_cancellation(pool):
+    """With a budget that admits one request at a time the requests queue up:
+    cancelling queued ones removes them (Cancelled, no result); cancelling the one
+    that is running lets its GPU call finish and drops its result; every other
+    request still equals its alone result bit for bit."""
+    dev, alone = pool
+    biggest = max(serve.Request(d, i, p).footprint for d, i, p in dev)
+    server = serve.Server(max_inflight_bytes=biggest)
+    try:
+        reqs = _requests(dev, list(range(len(dev))) * 3)
+        for r in reqs:
+            server.submit(r)
+        states = {}
+        for k in (len(reqs) - 1, len(reqs) - 4, len(reqs) // 2):
+            states[k] = server.cancel(reqs[k])
+        with server.cv:   # a request that left its queue and has not completed is running
+            running = next((r for r in reqs if r not in server.small and r not in server.large
+                            and not r.done.is_set()), None)
+        if running is not None:
+            states[reqs.index(running)] = server.cancel(running)
+        for r in reqs:
+            r.done.wait()
+        print("cancellation:", states, flush=True)
+        assert "queued" in states.values()
+        for k, r in enumerate(reqs):
+            if k in states and states[k] != "done":
+                assert isinstance(r.error, serve.Cancelled) and r.poses is None, (k, states[k])
+            else:
+                _check([r], alone)
+        assert server.inflight == 0
+    finally:
+        server.close()
