@@ -298,6 +298,35 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* frames, const bf_int
                           double* out_trace);
 
 /*
+ * bf_gauss_newton without any allocation, for callers that cannot allocate device
+ * or pinned host memory during the call: code inside a serving loop that must not
+ * reach the allocator, harnesses that forbid hipMalloc, callers preparing to run
+ * under stream capture.  Arguments, outputs and results are those of
+ * bf_gauss_newton (the same kernels in the same order: the poses and energies are
+ * bitwise those of bf_gauss_newton with the same params).
+ *
+ * The workspace is a fixed static device array of 64 MiB per GPU (held from the
+ * first use of the library on that GPU until the process ends) instead of the
+ * context's growing buffers; a problem whose workspace does not fit returns
+ * BF_ERR_OUT_OF_MEMORY with nothing written (about 150 keyframes at 80x60 with
+ * 300k correspondences fit, or any chunk of up to 11 frames at 160x120).  The call
+ * makes no hipMalloc, hipFree, hipHostMalloc or hipEventCreate; host readbacks go
+ * through a static host buffer.  params->dense_threads must be fixed (64, 128, 256
+ * or 512) and params->timing and params->graph 0 (else BF_ERR_UNSUPPORTED).
+ *
+ * Every call on a GPU uses that GPU's one array: calls are serialised by a
+ * process-wide lock and each call finishes its device work before releasing it;
+ * the array keeps the last call's contents, and a call clears what it needs
+ * cleared.  Work of other libraries that writes the array's memory would race with
+ * it (nothing outside this entry point touches it).  The context's own
+ * workspace and state are neither used nor changed.
+ */
+bf_status bf_gauss_newton_noalloc(bf_context* ctx, const bf_frames* frames, const bf_intrinsics* intr,
+                                  const bf_corrs* corrs, const bf_pairs* pairs, const double* init_poses,
+                                  const bf_params* params, double* out_poses, double* out_energy,
+                                  double* out_trace);
+
+/*
  * Key-point correspondence filter and surface-area filter (Sec. 4.1.1), run on
  * candidate correspondences before a solve.  Per unordered frame pair, the
  * candidates in their given order (the order of match distance) are added one at

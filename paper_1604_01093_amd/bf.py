@@ -91,6 +91,9 @@ _SIGS = {
     "bf_gauss_newton": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                 POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_void_p, POINTER(c_double),
                                 POINTER(c_double)]),
+    "bf_gauss_newton_noalloc": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
+                                        POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_void_p, POINTER(c_double),
+                                        POINTER(c_double)]),
     "bf_gauss_newton_batch": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_corrs),
                                       POINTER(bf_pairs), c_int32, POINTER(c_int32), c_void_p, POINTER(bf_params),
                                       c_void_p, POINTER(c_double), POINTER(c_double)]),
@@ -422,6 +425,24 @@ def bf_gauss_newton(ctx, prob, init_poses, params, out_poses=None, trace=False):
     ctx._check(ctx.lib.bf_gauss_newton(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr),
                                        ctypes.byref(prob.corrs), prob._pairs_ref(), _ptr(init_poses),
                                        ctypes.byref(params), _ptr(out_poses), e, tr))
+    res = {"poses": out_poses, "energy": {"total": e[0], "sparse": e[1], "geo": e[2], "photo": e[3]}}
+    if trace:
+        res["trace"] = [list(tr[4 * k:4 * k + 4]) for k in range(params.num_gn)]
+    return res
+
+
+def bf_gauss_newton_noalloc(ctx, prob, init_poses, params, out_poses=None, trace=False):
+    """bf_gauss_newton with its workspace in the library's static scratch array
+    (no allocation inside the call).  out_poses must be given by callers that
+    cannot allocate; it is allocated here only for convenience when omitted."""
+    _poses_check(init_poses, prob.num_frames)
+    if out_poses is None:
+        out_poses = torch.empty_like(init_poses)
+    e = (c_double * 4)()
+    tr = (c_double * (4 * max(params.num_gn, 1)))() if trace else None
+    ctx._check(ctx.lib.bf_gauss_newton_noalloc(ctx.h, ctypes.byref(prob.frames), ctypes.byref(prob.intr),
+                                               ctypes.byref(prob.corrs), prob._pairs_ref(), _ptr(init_poses),
+                                               ctypes.byref(params), _ptr(out_poses), e, tr))
     res = {"poses": out_poses, "energy": {"total": e[0], "sparse": e[1], "geo": e[2], "photo": e[3]}}
     if trace:
         res["trace"] = [list(tr[4 * k:4 * k + 4]) for k in range(params.num_gn)]

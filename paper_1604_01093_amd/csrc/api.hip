@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -10,6 +11,9 @@
 
 struct bf_context : bf::Context {
   std::vector<hipEvent_t> pool;
+  // state of bf_gauss_newton_noalloc: a context whose workspace is carved from
+  // the static scratch array (reset at every call; nullptr inside itself)
+  bf_context* noalloc = nullptr;
 };
 
 // Normal equations built by bf_build_normal_equations: the assembled per-edge
@@ -34,6 +38,56 @@ namespace bf {
 
 void fail(bf_status s, const std::string& msg) { throw Error{s, msg}; }
 
+// ----------------------------------------------------------------------------
+// Workspace for bf_gauss_newton_noalloc: one static device array per GPU, of a
+// fixed size, instead of hipMalloc.  In host code `scratch` only names the
+// host-side stand-in of the array; its device address is looked up once per
+// device (hipGetSymbolAddress, in bf_create with that device current) and only
+// that address is ever handed to kernels or copies.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                     // guards the per-device lookup
+void* g_scratch_ptr[kMaxDevices] = {};
+int g_scratch_state[kMaxDevices] = {};       // 0 not looked up, 1 found, -1 lookup failed
+
+// A bump allocator over the scratch array, active for the duration of one
+// allocation-free call on the calling thread: ensure() carves from it and the
+// pinned readback areas are replaced by static host memory.
+struct Arena {
+  char* base;
+  size_t cap, off;
+};
+thread_local Arena* t_arena = nullptr;
+constexpr size_t kArenaHostBytes = (size_t)256 << 10;
+alignas(64) unsigned char g_arena_host[kArenaHostBytes];  // readback staging; calls are serialised
+std::mutex g_noalloc_mu;                                   // one allocation-free call at a time
+}  // namespace
+
+void lookup_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_state[device] != 0) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr != nullptr) {
+    g_scratch_ptr[device] = ptr;
+    g_scratch_state[device] = 1;
+  } else {
+    (void)hipGetLastError();
+    g_scratch_state[device] = -1;
+  }
+}
+
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices || g_scratch_state[device] != 1)
+    fail(BF_ERR_DEVICE, "the static scratch array of this device could not be located");
+  return g_scratch_ptr[device];
+}
+
 void check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) {
     if (e == hipErrorOutOfMemory) fail(BF_ERR_OUT_OF_MEMORY, std::string(what) + ": out of device memory");
@@ -57,6 +111,16 @@ void bump_alloc_generation() { ++g_alloc_generation; }
 void ensure(Buf& b, size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (b.cap >= bytes) return;
+  if (t_arena) {
+    const size_t off = (t_arena->off + 255) & ~(size_t)255;
+    if (off > t_arena->cap || bytes > t_arena->cap - off)
+      fail(BF_ERR_OUT_OF_MEMORY, "the problem needs more than the " + std::to_string(t_arena->cap >> 20) +
+                                     " MiB scratch array of the allocation-free entry point");
+    b.p = t_arena->base + off;
+    b.cap = bytes;
+    t_arena->off = off + bytes;
+    return;
+  }
   ++g_alloc_generation;
   if (b.p) {
     check_hip(hipFree(b.p), "hipFree");
@@ -75,6 +139,7 @@ void ensure(Buf& b, size_t bytes) {
 }
 
 long long* readback_small(Context& c) {
+  if (t_arena) return reinterpret_cast<long long*>(g_arena_host);
   if (!c.rb_small) {
     void* p = nullptr;
     if (hipHostMalloc(&p, sizeof(long long) * kSmallReadbackWords, hipHostMallocDefault) != hipSuccess) {
@@ -88,6 +153,11 @@ long long* readback_small(Context& c) {
 
 void* readback_big(Context& c, size_t bytes) {
   if (bytes == 0) bytes = 8;
+  if (t_arena) {
+    constexpr size_t kSmall = 4096;  // the small area stays at the start
+    if (bytes > kArenaHostBytes - kSmall) fail(BF_ERR_UNSUPPORTED, "readback too large for the allocation-free entry point");
+    return g_arena_host + kSmall;
+  }
   if (c.rb_big_cap < bytes) {
     if (c.rb_big) {
       check_hip(hipStreamSynchronize(c.stream), "synchronise");
@@ -405,6 +475,12 @@ bf_status bf_create(bf_context** out, void* hip_stream) {
     return BF_ERR_DEVICE;
   }
   c->num_cus = cus;
+  c->noalloc = new (std::nothrow) bf_context();
+  if (!c->noalloc) {
+    delete c;
+    return BF_ERR_OUT_OF_MEMORY;
+  }
+  lookup_scratch(c->device);
   ++g_live_contexts;
   *out = c;
   return BF_OK;
@@ -433,6 +509,7 @@ void bf_destroy(bf_context* c) {
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   if (c->gn_exec) (void)hipGraphExecDestroy(c->gn_exec);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  delete c->noalloc;  // its buffers lie in the static scratch array: nothing to free
   delete c;
   --g_live_contexts;
 }
@@ -841,6 +918,47 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* fr, const bf_intrins
     check_poses(c, init_poses, fr->num_frames);
     setup(ctx, fr, in, co, pairs, init_poses, prm);
     run_gauss_newton(ctx, in, prm, init_poses, out_poses, out_energy, out_trace, tm, t_start);
+  });
+}
+
+bf_status bf_gauss_newton_noalloc(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const bf_corrs* co,
+                                  const bf_pairs* pairs, const double* init_poses, const bf_params* prm,
+                                  double* out_poses, double* out_energy, double* out_trace) {
+  return guarded(ctx, [&] {
+    validate_common(ctx, fr, in, prm);
+    validate_problem(co, pairs, init_poses);
+    if (!out_poses || !out_energy) fail(BF_ERR_INVALID_ARG, "null out_poses or out_energy");
+    if (prm->timing || prm->graph)
+      fail(BF_ERR_UNSUPPORTED, "the allocation-free entry point runs without timing events or graph capture");
+    if (prm->dense_threads == 0)
+      fail(BF_ERR_UNSUPPORTED, "the allocation-free entry point needs a fixed params->dense_threads");
+    if (!ctx->noalloc) fail(BF_ERR_DEVICE, "context has no allocation-free state");
+    char* base = static_cast<char*>(scratch_address(ctx->device));
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    // fresh state every call: every buffer is carved anew from the start of the
+    // array, and everything that must start at zero (flags, counters, the PCG
+    // exchange tags) is cleared on the way as in a newly created context
+    bf_context& na = *ctx->noalloc;
+    na = bf_context();
+    na.stream = ctx->stream;
+    na.device = ctx->device;
+    na.num_cus = ctx->num_cus;
+    Arena arena{base, kScratchBytes, 0};
+    struct Scope {
+      hipStream_t stream;
+      explicit Scope(Arena* a, hipStream_t s) : stream(s) { t_arena = a; }
+      // the array is free for the next call only once this call's work is done
+      ~Scope() {
+        (void)hipStreamSynchronize(stream);
+        t_arena = nullptr;
+      }
+    } scope(&arena, na.stream);
+    Timer tm(&na, false);
+    ensure(na.flags, sizeof(int));
+    check_hip(hipMemsetAsync(na.flags.p, 0, sizeof(int), na.stream), "memset flags");
+    check_poses(na, init_poses, fr->num_frames);
+    setup(&na, fr, in, co, pairs, init_poses, prm);
+    run_gauss_newton(&na, in, prm, init_poses, out_poses, out_energy, out_trace, tm, -1, false);
   });
 }
 
