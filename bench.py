@@ -205,7 +205,7 @@ def cpu_baseline(prob, n_gn, n_pcg, chunk=None, batch_sample=None, full=False):
             "sample": f"1 of {n_gn} Gauss-Newton iterations ({n_pcg} PCG) of the same workload, single thread; "
                       f"per-solve setup ({t1 - t0:.1f} s) excluded",
             "seconds": round(one, 3), "host_cpu_count": os.cpu_count(), "host_affinity_cores": cores,
-            "legs": legs}
+            "legs": legs, "_batch_ref": refs}
 
 
 def accuracy_vs_oracle(prob, poses, energy):
@@ -248,7 +248,9 @@ def main():
     ap.add_argument("--accumulate", type=int, default=None,
                     help="0 FP32, 1 compensated FP32, 2 FP64 lane sums (default 0; 1 for global2000)")
     ap.add_argument("--solve-kernel", type=int, default=0)
-    ap.add_argument("--dense-threads", type=int, default=256, help="threads per dense pair job (0 = timed choice)")
+    ap.add_argument("--dense-threads", type=int, default=0,
+                    help="threads per dense pair job; 0 (default) = threads and tiles chosen by timing")
+    ap.add_argument("--dense-tiles", type=int, default=1, help="workgroups (pixel tiles) per dense pair job")
     ap.add_argument("--preconditioner", type=int, default=0, help="0 = 6x6 block-Jacobi, 1 = scalar Jacobi")
     ap.add_argument("--workload", choices=["global200", "global2000"], default="global200",
                     help="global2000: the 2000-keyframe floor (8 GN x 20 PCG); only the solve is measured")
@@ -312,7 +314,8 @@ def main():
     params = bf.bf_params_default(num_gn=prob.n_gn, num_pcg=prob.n_pcg, pcg_storage=args.pcg_storage,
                                   accumulate=args.accumulate, solve_kernel=args.solve_kernel, timing=1,
                                   bidirectional=args.bidirectional,
-                                  dense_threads=args.dense_threads, preconditioner=args.preconditioner)
+                                  dense_threads=args.dense_threads, dense_tiles=args.dense_tiles,
+                                  preconditioner=args.preconditioner)
     st = bf.bf_build_structure(ctx, dp, init, params)
     P = st["pairs"].shape[0]
     log(f"structure: {P} dense pair jobs, {st['sparse_ij'].shape[0]} sparse pairs, {st['edges'].shape[0]} edges")
@@ -384,7 +387,8 @@ def main():
                    "pcg_storage": "fp64" if args.pcg_storage else "fp32",
                    "accumulate": ["fp32", "fp32-two-sum", "fp64"][args.accumulate],
                    "solve_kernel": ["auto", "single", "coop", "replicated", "per-problem"][args.solve_kernel],
-                   "dense_threads": args.dense_threads,
+                   "dense_launch": (f"{args.dense_threads} threads x {args.dense_tiles} tiles per pair job"
+                                    if args.dense_threads else "threads and tiles per pair job timed per shape"),
                    "preconditioner": ["block-jacobi", "jacobi"][args.preconditioner]},
         "roofline": {"bound": "hbm", "kernel": "k_dense<jacobians>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -416,6 +420,24 @@ def main():
                                    "valid_at_init": int(valid.sum().item())}}
         log(f"filters: {kept} of {len(prob.corr_i)} kept in {1e3 * t_filter:.2f} ms; verification of {P} pairs "
             f"in {1e3 * t_verify:.2f} ms")
+        # the paper's PCG variant (sparse term matrix-free in every iteration) against the
+        # sparse term's assembled blocks, both in the distributed-vector kernel, and the
+        # default kernel; PCG time per solve (row assembly + iterations + update)
+        variants = {}
+        for name, kw in (("default_kernel_assembled", {}), ("distributed_assembled", {"solve_kernel": 5}),
+                         ("distributed_matrix_free_sparse", {"solve_kernel": 5, "sparse_matrix_free": 1})):
+            pv = bf.bf_params_default(num_gn=prob.n_gn, num_pcg=prob.n_pcg, pcg_storage=args.pcg_storage,
+                                      accumulate=args.accumulate, timing=1, dense_threads=args.dense_threads,
+                                      dense_tiles=args.dense_tiles, **kw)
+            pcg = []
+            for r in range(6):
+                res_v = bf.bf_gauss_newton(ctx, dp, init, pv, out_poses=out)
+                if r >= 2:
+                    pcg.append(ctx.last_timings()["pcg_us"])
+            variants[name] = {"pcg_us_per_solve": round(float(np.median(pcg)), 1),
+                              "energy": res_v["energy"]["total"]}
+        line["next_rows"]["paper_solver_variant"] = variants
+        log("PCG per solve: " + ", ".join(f"{k} {v['pcg_us_per_solve']} us" for k, v in variants.items()))
     if args.prune_rounds > 0:
         torch.cuda.synchronize()
         t0 = time.perf_counter()

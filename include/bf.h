@@ -105,12 +105,19 @@ typedef struct bf_params {
                                    assembled and inverted by a separate launch; the workgroups
                                    must all be resident, every wait is bounded),
                                4 = one workgroup per problem (the kernel of bf_gauss_newton_batch;
-                                   chosen automatically for problems of at most 64 free frames) */
-  int32_t dense_threads;    /* threads per dense pair job: 64, 128, 256 or 512; 0 (default) = the
-                               fastest, timed once per image size, mode and job-count range in
-                               this context (the first call of a shape synchronises once).  The
-                               lane sums of a job are combined in an order fixed by this value,
-                               so results are bitwise reproducible for a fixed value. */
+                                   chosen automatically for problems of at most 64 free frames),
+                               5 = distributed vectors (one wavefront per row keeps its row's
+                                   x, r and A p; every workgroup rebuilds the search direction in
+                                   its LDS after each reduction; for problems whose vectors do not
+                                   fit kernel 3 but whose search direction fits one workgroup's LDS:
+                                   up to 5461 free frames in FP32, 2730 in FP64).  Automatic: 4 for
+                                   small problems, else 3 if it fits, else 5 if it fits, else 2. */
+  int32_t dense_threads;    /* threads per dense pair job (per tile): 64, 128, 256 or 512; 0
+                               (default) = threads and tiles chosen together, the fastest of
+                               several shapes timed once per image size, mode and job-count range
+                               in this context (the first call of a shape synchronises once).  The
+                               lane sums of a job are combined in an order fixed by these values,
+                               so results are bitwise reproducible for fixed values. */
   double tau_dist;          /* dense association: |c - q| < tau_dist (metres) */
   double tau_normal;        /* dense association: normal dot product > tau_normal */
   double max_angle_deg;     /* dense pair test: viewing directions within this angle */
@@ -133,6 +140,9 @@ typedef struct bf_params {
                                (Sec. 4.3 sums over the pixels of frame i of each pair in E; this is
                                the symmetric variant).  Records then hold 2P jobs: pair p at p
                                and its reverse at P + p. */
+  int32_t dense_tiles;      /* tiles per dense pair job (its pixels split into this many parts, each a
+                               workgroup, their sums added in tile order); with dense_threads set,
+                               0 means 1; with dense_threads = 0 both are chosen by timing */
   int32_t pcg_spin_limit;   /* polls after which a PCG kernel's wait for the other workgroups gives
                                up (then BF_ERR_DEVICE, nothing written); 0 = the default of 2^26
                                (about two seconds).  A small value forces the time-out path. */
@@ -145,6 +155,16 @@ typedef struct bf_params {
                                implementations under one association, or to iterate on a smooth
                                energy.  Only pixels whose source and target normals (and
                                gradients, for the photometric term) are valid are used. */
+  int32_t sparse_matrix_free;
+                            /* 1: the PCG applies the sparse term matrix-free, as Sec. 4.4 does:
+                               in every iteration, per sparse frame pair, J p for each of its
+                               correspondences and at once J^T of it summed over the pair (FP64,
+                               fixed order), instead of the pair's assembled 6x6 blocks; the
+                               dense term keeps its blocks and the block-Jacobi preconditioner
+                               keeps the full diagonal blocks.  Runs in the distributed-vector
+                               PCG kernel (solve_kernel 0 or 5; BF_ERR_UNSUPPORTED where the
+                               search direction does not fit one workgroup's LDS) and only in
+                               bf_gauss_newton and bf_gauss_newton_noalloc. */
 } bf_params;
 
 void bf_params_default(bf_params* out);
@@ -344,8 +364,8 @@ bf_status bf_gauss_newton_noalloc(bf_context* ctx, const bf_frames* frames, cons
  * Synchronises the stream.
  */
 bf_status bf_filter_correspondences(bf_context* ctx, const bf_corrs* corrs, int32_t num_frames, double max_res,
-                                   double max_cond, int32_t min_count, double min_area, uint8_t* out_keep,
-                                   int64_t* out_kept);
+                                   double max_cond, int32_t cond_mode, int32_t min_count, double min_area,
+                                   uint8_t* out_keep, int64_t* out_kept);
 
 /*
  * Dense two-sided verification of frame pairs (Sec. 4.1.1, "Dense Verification"),

@@ -13,11 +13,12 @@ cross-covariance must be at most max_cond.  While a check fails, the
 correspondence with the largest residual is removed.  A pair keeps its final set
 only if that set has at least min_count correspondences and passes both checks.
 
-Condition number (reading of "condition analysis"): the ratio of the largest to
-the second largest eigenvalue of each 3x3 covariance, and of the largest to the
-second largest singular value of the cross-covariance.  It detects point sets on
-a line, the ambiguity the filter exists for; the ratio to the smallest value
-would also reject every planar set, which determines a rigid transform fine.
+Condition number (reading of "condition analysis"), two modes: mode 0 (the
+default) the ratio of the largest to the second largest eigenvalue of each 3x3
+covariance, and of the largest to the second largest singular value of the
+cross-covariance -- it detects point sets on a line, the ambiguity the filter
+exists for, and keeps planar sets, which determine a rigid transform fine; mode 1
+the plain definition, largest over smallest, which also rejects planar sets.
 
 Surface-area filter: for the kept p's and q's separately, the points are
 projected onto the plane of their two principal axes (covariance eigenvectors
@@ -38,19 +39,21 @@ def kabsch(P, Q):
     return R, qm - R @ pm
 
 
-def condition_numbers(P, Q):
-    """Largest / second-largest eigenvalue of cov(P) and cov(Q), and largest /
-    second-largest singular value of the cross-covariance (inf if undefined)."""
+def condition_numbers(P, Q, mode=0):
+    """Largest / second-largest (mode 0) or largest / smallest (mode 1) eigenvalue
+    of cov(P) and cov(Q), and the same ratio of the singular values of the
+    cross-covariance (inf if undefined)."""
     pm, qm = P.mean(axis=0), Q.mean(axis=0)
     n = len(P)
     ratio = lambda a, b: a / b if b > 0 else np.inf
     ep = np.linalg.eigvalsh((P - pm).T @ (P - pm) / n)[::-1]
     eq = np.linalg.eigvalsh((Q - qm).T @ (Q - qm) / n)[::-1]
     sv = np.linalg.svd((P - pm).T @ (Q - qm) / n, compute_uv=False)
-    return ratio(ep[0], ep[1]), ratio(eq[0], eq[1]), ratio(sv[0], sv[1])
+    lo = 2 if mode else 1
+    return ratio(ep[0], ep[lo]), ratio(eq[0], eq[lo]), ratio(sv[0], sv[lo])
 
 
-def keypoint_filter(P, Q, max_res=0.02, max_cond=100.0, min_count=5):
+def keypoint_filter(P, Q, max_res=0.02, max_cond=100.0, min_count=5, cond_mode=0):
     """Indices (into P, Q) of the correspondences the filter keeps, in order; an
     empty array when the pair is discarded."""
     P = np.asarray(P, np.float64)
@@ -63,7 +66,7 @@ def keypoint_filter(P, Q, max_res=0.02, max_cond=100.0, min_count=5):
         while len(cur) >= 3:
             R, t = kabsch(P[cur], Q[cur])
             res = np.linalg.norm(P[cur] @ R.T + t - Q[cur], axis=1)
-            stable = max(condition_numbers(P[cur], Q[cur])) <= max_cond
+            stable = max(condition_numbers(P[cur], Q[cur], cond_mode)) <= max_cond
             if res.max() <= max_res and stable:
                 ok = True
                 break
@@ -83,7 +86,7 @@ def principal_area(X):
     return float(ext[0] * ext[1])
 
 
-def filter_pairs(ci, cj, p, q, max_res=0.02, max_cond=100.0, min_count=5, min_area=0.032):
+def filter_pairs(ci, cj, p, q, max_res=0.02, max_cond=100.0, min_count=5, min_area=0.032, cond_mode=0):
     """Both filters over all correspondences, grouped by unordered frame pair in
     input order.  Returns a keep mask [M]."""
     ci = np.asarray(ci)
@@ -98,7 +101,7 @@ def filter_pairs(ci, cj, p, q, max_res=0.02, max_cond=100.0, min_count=5, min_ar
     keys = lo.astype(np.int64) * (int(max(hi.max(initial=0), 0)) + 1) + hi
     for key in np.unique(keys):
         idx = np.nonzero(keys == key)[0]   # input order
-        kept = keypoint_filter(P[idx], Q[idx], max_res, max_cond, min_count)
+        kept = keypoint_filter(P[idx], Q[idx], max_res, max_cond, min_count, cond_mode)
         if len(kept) == 0:
             continue
         if principal_area(P[idx[kept]]) < min_area or principal_area(Q[idx[kept]]) < min_area:

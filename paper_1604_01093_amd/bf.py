@@ -56,8 +56,9 @@ class bf_params(ctypes.Structure):
                 ("solve_kernel", c_int32), ("dense_threads", c_int32),
                 ("tau_dist", c_double), ("tau_normal", c_double), ("max_angle_deg", c_double),
                 ("depth_min", c_double), ("depth_max", c_double), ("preconditioner", c_int32),
-                ("graph", c_int32), ("bidirectional", c_int32), ("pcg_spin_limit", c_int32),
-                ("fixed_association", c_void_p)]
+                ("graph", c_int32), ("bidirectional", c_int32), ("dense_tiles", c_int32),
+                ("pcg_spin_limit", c_int32), ("fixed_association", c_void_p),
+                ("sparse_matrix_free", c_int32)]
 
 
 class bf_structure(ctypes.Structure):
@@ -101,7 +102,7 @@ _SIGS = {
                                        POINTER(bf_pairs), c_void_p, POINTER(bf_params), c_double, c_int32, c_void_p,
                                        POINTER(c_double), c_void_p, c_void_p, POINTER(c_int32), POINTER(c_double)]),
     "bf_filter_correspondences": (c_int, [c_void_p, POINTER(bf_corrs), c_int32, c_double, c_double, c_int32,
-                                          c_double, c_void_p, POINTER(c_int64)]),
+                                          c_int32, c_double, c_void_p, POINTER(c_int64)]),
     "bf_verify_pairs": (c_int, [c_void_p, POINTER(bf_frames), POINTER(bf_intrinsics), POINTER(bf_pairs), c_void_p,
                                 POINTER(bf_params), c_double, c_double, c_double, c_void_p, c_void_p]),
     "bf_system_matvec": (c_int, [c_void_p, c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32,
@@ -208,8 +209,9 @@ class Context:
             self.h = None
         _live.discard(self)
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: at interpreter exit the module's globals may be gone
+        if _finalizing():
             return
         try:
             self.close()
@@ -244,8 +246,9 @@ class System:
             self.ctx.lib.bf_system_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: at interpreter exit the module's globals may be gone
+        if _finalizing():
             return
         try:
             self.close()
@@ -552,12 +555,13 @@ def bf_verify_pairs(ctx, prob, pairs, poses, params, tau_c=0.1, max_err=0.075, m
     return stats[:P], valid[:P].bool()
 
 
-def bf_filter_correspondences(ctx, prob, max_res=0.02, max_cond=100.0, min_count=5, min_area=0.032):
+def bf_filter_correspondences(ctx, prob, max_res=0.02, max_cond=100.0, min_count=5, min_area=0.032, cond_mode=0):
     """Key-point and surface-area filters over the problem's correspondences;
-    returns the keep mask [M] (device, bool) and the number kept."""
+    returns the keep mask [M] (device, bool) and the number kept.  cond_mode 0:
+    condition numbers as largest / second largest value, 1: largest / smallest."""
     M = prob.num_corrs
     keep = torch.empty((max(M, 1),), dtype=torch.uint8, device="cuda")
     kept = c_int64()
     ctx._check(ctx.lib.bf_filter_correspondences(ctx.h, ctypes.byref(prob.corrs), prob.num_frames, max_res, max_cond,
-                                                 min_count, min_area, _ptr(keep), ctypes.byref(kept)))
+                                                 cond_mode, min_count, min_area, _ptr(keep), ctypes.byref(kept)))
     return keep[:M].bool(), kept.value

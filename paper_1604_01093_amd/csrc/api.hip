@@ -221,11 +221,18 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
     fail(BF_ERR_INVALID_ARG, "weights must be finite and >= 0");
   if (prm->accumulate < 0 || prm->accumulate > 2) fail(BF_ERR_INVALID_ARG, "accumulate must be 0, 1 or 2");
   if (prm->pcg_storage != 0 && prm->pcg_storage != 1) fail(BF_ERR_INVALID_ARG, "pcg_storage must be 0 or 1");
-  if (prm->solve_kernel < 0 || prm->solve_kernel > 4) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..4");
+  if (prm->solve_kernel < 0 || prm->solve_kernel > 5) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..5");
   if (prm->preconditioner != 0 && prm->preconditioner != 1) fail(BF_ERR_INVALID_ARG, "preconditioner must be 0 or 1");
   if (prm->graph != 0 && prm->graph != 1) fail(BF_ERR_INVALID_ARG, "graph must be 0 or 1");
   if (prm->bidirectional != 0 && prm->bidirectional != 1) fail(BF_ERR_INVALID_ARG, "bidirectional must be 0 or 1");
   if (prm->pcg_spin_limit < 0) fail(BF_ERR_INVALID_ARG, "pcg_spin_limit must be >= 0");
+  if (prm->sparse_matrix_free != 0 && prm->sparse_matrix_free != 1)
+    fail(BF_ERR_INVALID_ARG, "sparse_matrix_free must be 0 or 1");
+  if (prm->sparse_matrix_free && prm->solve_kernel != 0 && prm->solve_kernel != 5)
+    fail(BF_ERR_UNSUPPORTED, "the matrix-free sparse term runs in the distributed-vector PCG (solve_kernel 0 or 5)");
+  if (prm->sparse_matrix_free && prm->graph)
+    fail(BF_ERR_UNSUPPORTED, "the matrix-free sparse term is not replayed as a graph");
+  if (prm->dense_tiles < 0 || prm->dense_tiles > 16) fail(BF_ERR_INVALID_ARG, "dense_tiles must be within [0, 16]");
   if (prm->dense_threads != 0 && prm->dense_threads != 64 && prm->dense_threads != 128 &&
       prm->dense_threads != 256 && prm->dense_threads != 512)
     fail(BF_ERR_INVALID_ARG, "dense_threads must be 0, 64, 128, 256 or 512");
@@ -279,6 +286,8 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
   set_segments(c, fr->num_frames, offsets, nseg);
   build_structure(c, *fr, *in, co, pairs, poses, *prm);
   const Shape& s = c.shape;
+  c.mf_w_sparse = prm->use_sparse ? prm->w_sparse : 0.0;
+  if (prm->sparse_matrix_free) launch_mf_points(c, co);
   ensure(c.records, sizeof(double) * kRecWords * ((c.bidir ? 2 : 1) * s.P + 1));
   ensure(c.eblocks, sizeof(double) * kEdgeWords * (s.E + 1));
   ensure_pcg_buffers(c);
@@ -622,10 +631,7 @@ bf_status bf_eval_residuals(bf_context* ctx, const bf_frames* fr, const bf_intri
     launch_dense(c, *in, poses, *prm, wd, jac, out_assoc);
     launch_edge_blocks(c, poses, *prm, false);
     launch_energy(c, c.energy.as<double>());
-    if (out_records && c.shape.P > 0)
-      check_hip(hipMemcpyAsync(out_records, c.records.p,
-                               sizeof(double) * kRecWords * (c.bidir ? 2 : 1) * c.shape.P,
-                               hipMemcpyDeviceToDevice, c.stream), "copy records");
+    if (out_records && c.shape.P > 0) export_records(c, out_records);
     double e8[8];
     int hf = 0;
     check_hip(hipMemcpyAsync(e8, c.energy.p, sizeof(e8), hipMemcpyDeviceToHost, c.stream), "copy energy");
@@ -669,6 +675,7 @@ bf_status bf_build_normal_equations(bf_context* ctx, const bf_frames* fr, const 
     validate_problem(co, pairs, poses);
     if (!sys) fail(BF_ERR_INVALID_ARG, "null system");
     if (sys->owner != ctx) fail(BF_ERR_INVALID_ARG, "the system belongs to another context");
+    if (prm->sparse_matrix_free) fail(BF_ERR_UNSUPPORTED, "a system holds assembled blocks (sparse_matrix_free = 0)");
     Context& c = *ctx;
     ensure(c.flags, sizeof(int));
     check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
@@ -764,7 +771,7 @@ void enqueue_loop(Context& c, const bf_intrinsics* in, const bf_params* prm, con
     int b = mark();
     launch_edge_blocks(c, poses, *prm, true);
     int d = mark();
-    if (c.shape.nfree > 0) launch_solve(c, prm->num_pcg, slot, nullptr, poses, nullptr, true);
+    if (c.shape.nfree > 0) launch_solve(c, prm->num_pcg, slot, nullptr, poses, nullptr, true, prm->sparse_matrix_free);
     else launch_energy(c, slot);
     int f = mark();
     if (tm) {
@@ -973,6 +980,7 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* fr, const bf_i
     if (!out_poses || !out_energy) fail(BF_ERR_INVALID_ARG, "null out_poses or out_energy");
     if (prm->solve_kernel != 0 && prm->solve_kernel != 4)
       fail(BF_ERR_UNSUPPORTED, "a batch is solved by the per-problem kernel (solve_kernel 0 or 4)");
+    if (prm->sparse_matrix_free) fail(BF_ERR_UNSUPPORTED, "a batch uses assembled sparse blocks (sparse_matrix_free = 0)");
     Context& c = *ctx;
     Timer tm(ctx, prm->timing != 0);
     int t_start = tm.mark();
@@ -985,8 +993,8 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* fr, const bf_i
 }
 
 bf_status bf_filter_correspondences(bf_context* ctx, const bf_corrs* co, int32_t num_frames, double max_res,
-                                   double max_cond, int32_t min_count, double min_area, uint8_t* out_keep,
-                                   int64_t* out_kept) {
+                                   double max_cond, int32_t cond_mode, int32_t min_count, double min_area,
+                                   uint8_t* out_keep, int64_t* out_kept) {
   return guarded(ctx, [&] {
     if (!ctx) fail(BF_ERR_INVALID_ARG, "null context");
     validate_corrs(co);
@@ -994,12 +1002,13 @@ bf_status bf_filter_correspondences(bf_context* ctx, const bf_corrs* co, int32_t
     if (num_frames < 1 || num_frames > 16384) fail(BF_ERR_INVALID_ARG, "num_frames out of range");
     if (!(max_res >= 0.0) || !(max_cond >= 1.0) || min_count < 0 || !(min_area >= 0.0))
       fail(BF_ERR_INVALID_ARG, "bad filter thresholds");
+    if (cond_mode != 0 && cond_mode != 1) fail(BF_ERR_INVALID_ARG, "cond_mode must be 0 or 1");
     if (co->count > 0 && !out_keep) fail(BF_ERR_INVALID_ARG, "null out_keep");
     Context& c = *ctx;
     ensure(c.flags, sizeof(int));
     check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
     const long long S = group_correspondences(c, *co, num_frames);
-    launch_filters(c, *co, S, max_res, max_cond, min_count, min_area, out_keep);
+    launch_filters(c, *co, S, max_res, max_cond, min_count, min_area, cond_mode, out_keep);
     check_hip(hipStreamSynchronize(c.stream), "synchronise");
     if (out_kept) {
       long long kept = 0;
@@ -1057,6 +1066,7 @@ bf_status bf_gauss_newton_pruned(bf_context* ctx, const bf_frames* fr, const bf_
     if (!co) fail(BF_ERR_INVALID_ARG, "null correspondences");
     if (!out_poses || !out_energy) fail(BF_ERR_INVALID_ARG, "null out_poses or out_energy");
     if (!(r_prune >= 0.0) || max_rounds < 0) fail(BF_ERR_INVALID_ARG, "bad pruning threshold or round limit");
+    if (prm->sparse_matrix_free) fail(BF_ERR_UNSUPPORTED, "pruning uses assembled sparse blocks (sparse_matrix_free = 0)");
     Context& c = *ctx;
     const int F = fr->num_frames;
     ensure(c.flags, sizeof(int));

@@ -201,7 +201,7 @@ constexpr int kPayload = 16;
 constexpr int kQueue = 128;
 
 template <int MODE, bool JAC, int NT>
-__global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, long long P, int bidir,
+__global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, long long P, int bidir, int tiles,
                                               const float4* __restrict__ nd, const float* __restrict__ grad,
                                               const float* __restrict__ kx, const float* __restrict__ ky,
                                               const double* __restrict__ kx64, const double* __restrict__ ky64,
@@ -222,14 +222,20 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
   // each XCD a contiguous block of pair jobs (neighbouring jobs share frames and
   // stay in that XCD's L2).  The grid is a multiple of 8.
   const long long per = gridDim.x / 8;
-  const long long p = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  // jobs [0, P): pair p as (i -> j); with both directions, jobs [P, 2P): (j -> i)
+  const long long pt = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;  // tile of a pair job
+  // jobs [0, P): pair p as (i -> j); with both directions, jobs [P, 2P): (j -> i);
+  // job p's pixels are split into `tiles` contiguous tiles pt = p * tiles + tile
+  const long long p = pt / tiles;
   if (p >= (bidir ? 2 * P : P)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rev = p >= P ? 1 : 0;
   const long long pp = p - (rev ? P : 0);
   const int i = pairs[2 * pp + rev], j = pairs[2 * pp + 1 - rev];
   const int W = in.W, H = in.H, HW = W * H;
+  // this tile's pixels [lo, hi): tiles of whole wavefront steps
+  const int tile_len = (((HW + tiles - 1) / tiles) + 63) & ~63;
+  const int lo = (int)(pt - p * tiles) * tile_len;
+  const int hi = min(HW, lo + tile_len);
 
   // relative pose: FP64 (fixed order), FP32 copy for the decisions; wave-uniform
   float R[9], t[3];
@@ -265,10 +271,10 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
   // right after the projection) and the tests only decide validity, so the loads of
   // a step overlap instead of waiting on each other; the source load of the next
   // step is issued before the current one is processed.
-  int x = tid % W, y = tid / W;
+  int x = (lo + tid) % W, y = (lo + tid) / W;
   const int sx = NT % W, sy = NT / W;
-  float4 s_next = ld_at(ndi, (unsigned)(tid < HW ? tid : HW - 1));
-  for (int base = wave * 64; base < HW; base += NT) {
+  float4 s_next = ld_at(ndi, (unsigned)(lo + tid < hi ? lo + tid : HW - 1));
+  for (int base = lo + wave * 64; base < hi; base += NT) {
     const int pix = base + lane;
     const int px = x, py = y;
     x += sx;
@@ -280,7 +286,7 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
     const float4 s4 = s_next;
     {
       const int nxt = pix + NT;
-      s_next = ld_at(ndi, (unsigned)(nxt < HW ? nxt : HW - 1));
+      s_next = ld_at(ndi, (unsigned)(nxt < hi ? nxt : HW - 1));
     }
     float wv[kPayload];
     bool valid;
@@ -310,7 +316,7 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
         yt = (int)fminf(fmaxf(y0f, 0.0f), fHm2);
         in_img = c.z > 0.0f && xf >= 0.0f && xf <= fWm1 && yf >= 0.0f && yf <= fHm1;
       } else {
-        const size_t o = 2 * ((size_t)p * HW + (size_t)(pix < HW ? pix : HW - 1));
+        const size_t o = 2 * ((size_t)p * HW + (size_t)(pix < hi ? pix : HW - 1));
         const unsigned w0 = fixed[o], w1 = fixed[o + 1];
         const unsigned tg = min(w0 >> 2, (unsigned)(HW - 1));
         xh = (int)(tg % (unsigned)W);
@@ -323,13 +329,15 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
         given_photo = (w0 & 2u) != 0;
         in_img = true;
       }
-      const float4 tq = ld_at(ndj, (unsigned)(yh * W + xh));
-      const unsigned t0 = (unsigned)(yt * W + xt);
+      // pixel indices below 2^24: 24-bit multiplies (full rate, unlike 32-bit ones)
+      const unsigned th = __umul24((unsigned)yh, (unsigned)W) + (unsigned)xh;
+      const unsigned t0 = __umul24((unsigned)yt, (unsigned)W) + (unsigned)xt;
+      const float4 tq = ld_at(ndj, th);
       const float g00 = ld_at(gj, t0), g10 = ld_at(gj, t0 + 1u), g01 = ld_at(gj, t0 + (unsigned)W),
                   g11 = ld_at(gj, t0 + (unsigned)W + 1u);
-      float Gi = ld_at(gi, (unsigned)(pix < HW ? pix : HW - 1));
+      float Gi = ld_at(gi, (unsigned)(pix < hi ? pix : HW - 1));
       const float kxh = ld_at(kx, (unsigned)xh), kyh = ld_at(ky, (unsigned)yh);
-      valid = pix < HW && !is_nan(s4.x) && in_img && !is_nan(tq.x);
+      valid = pix < hi && !is_nan(s4.x) && in_img && !is_nan(tq.x);
       const float3 q = make_float3(mul_nc(kxh, tq.w), mul_nc(kyh, tq.w), tq.w);
       const float3 e = make_float3(c.x - q.x, c.y - q.y, c.z - q.z);
       const float3 n = make_float3(s4.x, s4.y, s4.z);
@@ -346,10 +354,10 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
       if (!ph) Gi = __builtin_nanf("");
       // the association out (inspection): word 0 = target pixel << 2 | photometric << 1
       // | geometric, word 1 = first pixel of the bilinear footprint (0 where unused)
-      if (assoc_out != nullptr && pix < HW) {
+      if (assoc_out != nullptr && pix < hi) {
         const size_t o = 2 * ((size_t)p * HW + (size_t)pix);
-        assoc_out[o] = valid ? (((unsigned)(yh * W + xh) << 2) | 1u | (ph ? 2u : 0u)) : 0u;
-        assoc_out[o + 1] = (valid && ph) ? (unsigned)(yt * W + xt) : 0u;
+        assoc_out[o] = valid ? ((th << 2) | 1u | (ph ? 2u : 0u)) : 0u;
+        assoc_out[o + 1] = (valid && ph) ? t0 : 0u;
       }
       if constexpr (MODE == 2) {
         wv[0] = D; wv[1] = tq.w; wv[2] = n.x; wv[3] = n.y; wv[4] = n.z;
@@ -454,12 +462,12 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
     } else {
       if (tid >= kRecEg && tid <= kRecNp) val = out[tid - kRecEg];
     }
-    records[(size_t)p * kRecWords + tid] = val;
+    records[(size_t)pt * kRecWords + tid] = val;
   }
 }
 
 template <int MODE, bool JAC, int NT>
-void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
+void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd, int tiles,
                unsigned* assoc_out) {
   const long long P = c.shape.P;
   const long long jobs = c.bidir ? 2 * P : P;
@@ -468,89 +476,128 @@ void launch_nt(Context& c, const bf_intrinsics& in, const double* poses, const b
   float tau_n = (float)prm.tau_normal;
   double swg = sqrt(wd * prm.w_geo);
   double swp = sqrt(wd * prm.w_photo);
-  unsigned grid = (unsigned)(8 * ((jobs + 7) / 8));
+  unsigned grid = (unsigned)(8 * ((jobs * tiles + 7) / 8));
   hipLaunchKernelGGL((k_dense<MODE, JAC, NT>), dim3(grid), dim3(NT), 0, c.stream, c.pairs.as<int>(), P, c.bidir,
-                     c.nd.as<float4>(), c.grad.as<float>(), c.kx.as<float>(), c.ky.as<float>(), c.kx64.as<double>(),
-                     c.ky64.as<double>(), poses, i32, in.fx, in.fy, in.cx, in.cy, tau_d2, tau_n, swg, swp,
-                     c.records.as<double>(), reinterpret_cast<const unsigned*>(prm.fixed_association),
+                     tiles, c.nd.as<float4>(), c.grad.as<float>(), c.kx.as<float>(), c.ky.as<float>(),
+                     c.kx64.as<double>(), c.ky64.as<double>(), poses, i32, in.fx, in.fy, in.cx, in.cy, tau_d2, tau_n,
+                     swg, swp, c.records.as<double>(), reinterpret_cast<const unsigned*>(prm.fixed_association),
                      assoc_out);
 }
 
 template <int MODE, bool JAC>
 void launch_mode(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd, int nt,
-                 unsigned* masks) {
+                 int tiles, unsigned* masks) {
   switch (nt) {
-    case 64: launch_nt<MODE, JAC, 64>(c, in, poses, prm, wd, masks); break;
-    case 128: launch_nt<MODE, JAC, 128>(c, in, poses, prm, wd, masks); break;
-    case 512: launch_nt<MODE, JAC, 512>(c, in, poses, prm, wd, masks); break;
-    default: launch_nt<MODE, JAC, 256>(c, in, poses, prm, wd, masks); break;
+    case 64: launch_nt<MODE, JAC, 64>(c, in, poses, prm, wd, tiles, masks); break;
+    case 128: launch_nt<MODE, JAC, 128>(c, in, poses, prm, wd, tiles, masks); break;
+    case 512: launch_nt<MODE, JAC, 512>(c, in, poses, prm, wd, tiles, masks); break;
+    default: launch_nt<MODE, JAC, 256>(c, in, poses, prm, wd, tiles, masks); break;
   }
+}
+
+// Records of `tiles` partial records per job (the workspace grows only here, and is
+// settled before any graph capture by dense_threads_for).
+void ensure_records(Context& c, int tiles) {
+  const long long jobs = (c.bidir ? 2 : 1) * c.shape.P;
+  ensure(c.records, sizeof(double) * kRecWords * (size_t)(jobs * tiles + 1));
 }
 
 void launch_any(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                bool jac, int nt, unsigned* masks = nullptr) {
+                bool jac, int nt, int tiles, unsigned* masks = nullptr) {
+  ensure_records(c, tiles);
+  c.dense_tiles = tiles;
   const int mode = prm.accumulate;
   if (jac) {
-    if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd, nt, masks);
-    else if (mode == 1) launch_mode<1, true>(c, in, poses, prm, wd, nt, masks);
-    else launch_mode<0, true>(c, in, poses, prm, wd, nt, masks);
+    if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd, nt, tiles, masks);
+    else if (mode == 1) launch_mode<1, true>(c, in, poses, prm, wd, nt, tiles, masks);
+    else launch_mode<0, true>(c, in, poses, prm, wd, nt, tiles, masks);
   } else {
-    if (mode == 2) launch_mode<2, false>(c, in, poses, prm, wd, nt, masks);
-    else launch_mode<0, false>(c, in, poses, prm, wd, nt, masks);
+    if (mode == 2) launch_mode<2, false>(c, in, poses, prm, wd, nt, tiles, masks);
+    else launch_mode<0, false>(c, in, poses, prm, wd, nt, tiles, masks);
   }
 }
 
-// Threads per pair job for this launch: the caller's choice, or the fastest of the
+// Launch shape of the dense pair jobs: threads per workgroup and tiles per job.
+struct DenseShape {
+  int nt, tiles;
+};
+
+// The caller's shape (dense_threads, and dense_tiles or 1), or the fastest of the
 // candidates, timed once per (pixels per frame, precision mode, Jacobians, range of
 // job counts) in this context.  Timing runs the real launch (it only rewrites the
-// records) and synchronises the stream once.
-int choose_threads(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                   bool jac) {
-  if (prm.dense_threads != 0) return prm.dense_threads;
+// records) and synchronises the stream once.  Candidates: 64..512 threads with the
+// job whole, and 128 or 256 threads with the job split into 2 or 4 tiles (more
+// workgroups for the last round of a grid, shorter dependent loops per workgroup).
+DenseShape choose_shape(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
+                        bool jac) {
+  if (prm.dense_threads != 0) return {prm.dense_threads, prm.dense_tiles > 0 ? prm.dense_tiles : 1};
   int bucket = 0;
   const long long jobs = c.bidir ? 2 * c.shape.P : c.shape.P;
   while (bucket < 40 && (1LL << bucket) < jobs) ++bucket;
   const long long key = (((long long)in.width * in.height * 4 + prm.accumulate) * 2 + (jac ? 1 : 0)) * 64 + bucket;
   auto it = c.dense_threads.find(key);
-  if (it != c.dense_threads.end()) return it->second;
-  static const int cand[4] = {64, 128, 256, 512};
+  if (it != c.dense_threads.end()) return {it->second / 16, it->second % 16};
+  static const DenseShape cand[] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {128, 2}, {256, 2}, {128, 4}, {256, 4}};
   hipEvent_t e0, e1;
   check_hip(hipEventCreate(&e0), "hipEventCreate");
   check_hip(hipEventCreate(&e1), "hipEventCreate");
-  int best = 256;
+  DenseShape best{256, 1};
   float best_ms = 1e30f;
-  for (int nt : cand) {
-    launch_any(c, in, poses, prm, wd, jac, nt);  // warm-up
+  for (const DenseShape& d : cand) {
+    launch_any(c, in, poses, prm, wd, jac, d.nt, d.tiles);  // warm-up
     check_hip(hipEventRecord(e0, c.stream), "hipEventRecord");
-    for (int r = 0; r < 3; ++r) launch_any(c, in, poses, prm, wd, jac, nt);
+    for (int r = 0; r < 3; ++r) launch_any(c, in, poses, prm, wd, jac, d.nt, d.tiles);
     check_hip(hipEventRecord(e1, c.stream), "hipEventRecord");
     check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
     float ms = 0.f;
     check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
     if (ms < best_ms) {
       best_ms = ms;
-      best = nt;
+      best = d;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c.dense_threads[key] = best;
+  c.dense_threads[key] = best.nt * 16 + best.tiles;
   return best;
+}
+
+// Whole-job records [jobs][kRecWords] from the tile records (the tiles of a job
+// summed in tile order, as the edge kernel sums them).
+__global__ void k_combine_records(const double* __restrict__ tiled, long long jobs, int tiles,
+                                  double* __restrict__ out) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= jobs * kRecWords) return;
+  const long long job = k / kRecWords;
+  const int w = (int)(k % kRecWords);
+  double s = 0.0;
+  for (int t = 0; t < tiles; ++t) s += tiled[((size_t)job * tiles + t) * kRecWords + w];
+  out[k] = s;
 }
 
 }  // namespace
 
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
-                  bool with_jacobians, unsigned* masks) {
+                  bool with_jacobians, unsigned* assoc_out) {
   if (c.shape.P == 0) return;
-  const int nt = choose_threads(c, in, poses, prm, wd, with_jacobians);
-  launch_any(c, in, poses, prm, wd, with_jacobians, nt, masks);
+  const DenseShape d = choose_shape(c, in, poses, prm, wd, with_jacobians);
+  launch_any(c, in, poses, prm, wd, with_jacobians, d.nt, d.tiles, assoc_out);
 }
 
 int dense_threads_for(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
                       bool with_jacobians) {
   if (c.shape.P == 0) return 0;
-  return choose_threads(c, in, poses, prm, wd, with_jacobians);
+  const DenseShape d = choose_shape(c, in, poses, prm, wd, with_jacobians);
+  ensure_records(c, d.tiles);
+  return d.nt * 16 + d.tiles;
+}
+
+void export_records(Context& c, double* out) {
+  const long long jobs = (c.bidir ? 2 : 1) * c.shape.P;
+  if (jobs == 0) return;
+  const long long n = jobs * kRecWords;
+  hipLaunchKernelGGL(k_combine_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+                     c.records.as<double>(), jobs, c.dense_tiles, out);
 }
 
 }  // namespace bf

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(64) k_keypoint_filter(const int* __restrict__ 
                                                         const long long* __restrict__ perm,
                                                         const long long* __restrict__ ptr, long long S,
                                                         double max_res, double max_cond, int min_count,
-                                                        double min_area, uint8_t* keep) {
+                                                        double min_area, int cond_mode, uint8_t* keep) {
   const long long g = blockIdx.x;
   if (g >= S) return;
   const int lane = threadIdx.x;
@@ -179,8 +179,11 @@ __global__ void __launch_bounds__(64) k_keypoint_filter(const int* __restrict__ 
       for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) HtH[3 * a + b] = H[a] * H[b] + H[3 + a] * H[3 + b] + H[6 + a] * H[6 + b];
       sym_eig3(HtH, ws, V);
-      const double s0 = sqrt(fmax(ws[0], 0.0)), s1 = sqrt(fmax(ws[1], 0.0));
-      const double cond = fmax(fmax(ratio(wp[0], wp[1]), ratio(wq[0], wq[1])), ratio(s0, s1));
+      const double s0 = sqrt(fmax(ws[0], 0.0)), s1 = sqrt(fmax(ws[1], 0.0)), s2 = sqrt(fmax(ws[2], 0.0));
+      // condition number: largest over second largest value (cond_mode 0), or over
+      // the smallest (cond_mode 1, the plain definition)
+      const int lo = cond_mode ? 2 : 1;
+      const double cond = fmax(fmax(ratio(wp[0], wp[lo]), ratio(wq[0], wq[lo])), ratio(s0, cond_mode ? s2 : s1));
       double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
       if (s1 > 0.0) {
         double U[9];
@@ -278,11 +281,11 @@ __global__ void __launch_bounds__(64) k_keypoint_filter(const int* __restrict__ 
 }  // namespace
 
 void launch_filters(Context& c, const bf_corrs& co, long long S, double max_res, double max_cond, int min_count,
-                    double min_area, uint8_t* keep) {
+                    double min_area, int cond_mode, uint8_t* keep) {
   if (S == 0) return;
   hipLaunchKernelGGL(k_keypoint_filter, dim3((unsigned)S), dim3(64), 0, c.stream, co.frame_i, co.frame_j, co.p_i,
                      co.p_j, c.corr_perm.as<long long>(), c.sparse_ptr.as<long long>(), S, max_res, max_cond,
-                     min_count, min_area, keep);
+                     min_count, min_area, cond_mode, keep);
 }
 
 }  // namespace bf

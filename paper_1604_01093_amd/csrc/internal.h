@@ -49,6 +49,8 @@ struct Context {
   int precond = 0;          // 0 = 6x6 block-Jacobi, 1 = scalar Jacobi
   int bidir = 0;            // 1: two dense pair jobs per pair (i -> j, then j -> i at job P + p)
   unsigned spin_limit = 1u << 26;  // polls before a PCG kernel's wait for other workgroups gives up
+  int dense_tiles = 1;      // tiles per dense pair job of the last dense launch (records per job)
+  double mf_w_sparse = 0.0; // sparse weight of the matrix-free sparse PCG product
   double timings[8] = {0};
 
   // frames
@@ -69,6 +71,8 @@ struct Context {
       pr_pairs_all, pr_bval, pr_bidx, pr_poses;
   // the poses and sparse weight of the last assembled system; matrix-free scratch
   Buf sys_poses, mf_u;
+  // matrix-free sparse PCG: sorted correspondence points, per-pair sums, dense diagonal parts
+  Buf mf_pts, mf_y, ediag_dense;
   double sys_w_sparse = 0.0;
   // independent problems: frame offsets, segment of each frame, variable and edge ranges
   Buf seg_start, seg_of, seg_var_ptr, seg_edge_ptr;
@@ -88,7 +92,8 @@ struct Context {
   unsigned pcg_tag_base = 0;
   void* pcg_tags_ptr = nullptr;
   bool pcg_tags_dirty = true;
-  int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative, 3 = replicated vectors
+  int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative, 3 = replicated vectors,
+                          // 4 = per problem, 5 = distributed vectors
   // the Gauss-Newton loop captured as a HIP graph: the instantiated graph, the
   // launch arguments it was captured with, and the stream capture runs on
   hipGraphExec_t gn_exec = nullptr;
@@ -136,15 +141,20 @@ int64_t launch_pair_search(Context& c, const bf_frames& fr, const bf_intrinsics&
 // the association instead of deciding it (same layout).
 void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
                   bool with_jacobians, unsigned* assoc_out = nullptr);
-// Threads per dense pair job that launch_dense() will use (timing them first when
-// params.dense_threads is 0 and the shape is new in this context).
+// Launch shape launch_dense() will use, threads * 16 + tiles per job (timing the
+// candidates first when params.dense_threads is 0 and the shape is new in this
+// context); also sizes the records for it.
 int dense_threads_for(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
                       bool with_jacobians);
+// Whole-job records [jobs][kRecWords] of the last dense launch (its tiles summed).
+void export_records(Context& c, double* out);
 
 // solve.hip
 void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, bool with_jacobians);
+// Correspondence points in sorted order for the matrix-free sparse PCG.
+void launch_mf_points(Context& c, const bf_corrs* co);
 void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
-                  bool update_poses);
+                  bool update_poses, bool sparse_matrix_free = false);
 void launch_energy(Context& c, double* dst8);
 // Whether the PCG of the current structure runs in the per-problem kernel (no state
 // carried between launches, so it can be captured in a graph); prepare_solve()
@@ -155,7 +165,7 @@ void launch_export_dense(Context& c, double* H, double* g);
 
 // filter.hip: key-point and surface-area filters over grouped correspondences
 void launch_filters(Context& c, const bf_corrs& co, long long S, double max_res, double max_cond, int min_count,
-                    double min_area, uint8_t* keep);
+                    double min_area, int cond_mode, uint8_t* keep);
 
 // verify.hip: two-sided dense verification of frame pairs (frames prepared)
 void launch_verify(Context& c, const bf_frames& fr, const bf_intrinsics& in, const int* pairs, long long P,

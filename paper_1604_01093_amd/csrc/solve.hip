@@ -45,9 +45,10 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
                                                     const long long* __restrict__ edense,
                                                     const long long* __restrict__ esparse,
                                                     const double* __restrict__ mom, const double* __restrict__ rec,
-                                                    long long P, int bidir,
+                                                    long long P, int bidir, int tiles,
                                                     const double* __restrict__ poses, double w_sparse, int jac,
-                                                    double* __restrict__ eb, T* __restrict__ hij_store) {
+                                                    double* __restrict__ eb, T* __restrict__ hij_store,
+                                                    double* __restrict__ ediag_dense) {
   long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
   const int i = eij[2 * e], j = eij[2 * e + 1];
@@ -62,22 +63,26 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
   for (int k = 0; k < 36; ++k) Hjj_d[k] = 0.0;
   for (int k = 0; k < 6; ++k) gj_d[k] = 0.0;
   double Eg = 0, Ep = 0, ng = 0, np = 0;
+  // a pair job's record is the sum of its `tiles` partial records, in tile order
   if (d >= 0) {
-    const double* r = rec + (size_t)d * kRecWords;
-    if (jac) {
-      int k = 0;
-      for (int a = 0; a < 6; ++a)
-        for (int b = a; b < 6; ++b) {
-          Hjj_d[6 * a + b] = r[k];
-          Hjj_d[6 * b + a] = r[k];
-          ++k;
-        }
-      for (int a = 0; a < 6; ++a) gj_d[a] = r[kRecG + a];
+    for (int tl = 0; tl < tiles; ++tl) {
+      const double* r = rec + ((size_t)d * tiles + tl) * kRecWords;
+      if (jac) {
+        int k = 0;
+        for (int a = 0; a < 6; ++a)
+          for (int b = a; b < 6; ++b) {
+            Hjj_d[6 * a + b] += r[k];
+            ++k;
+          }
+        for (int a = 0; a < 6; ++a) gj_d[a] += r[kRecG + a];
+      }
+      Eg += r[kRecEg];
+      Ep += r[kRecEp];
+      ng += r[kRecNg];
+      np += r[kRecNp];
     }
-    Eg = r[kRecEg];
-    Ep = r[kRecEp];
-    ng = r[kRecNg];
-    np = r[kRecNp];
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < a; ++b) Hjj_d[6 * a + b] = Hjj_d[6 * b + a];
   }
   // the reverse job (j -> i, record P + d): its block is the one of frame i
   double Hii_r[36], gi_r[6];
@@ -85,21 +90,24 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
   for (int k = 0; k < 36; ++k) Hii_r[k] = 0.0;
   for (int k = 0; k < 6; ++k) gi_r[k] = 0.0;
   if (has_rev) {
-    const double* r = rec + (size_t)(P + d) * kRecWords;
-    if (jac) {
-      int k = 0;
-      for (int a = 0; a < 6; ++a)
-        for (int b = a; b < 6; ++b) {
-          Hii_r[6 * a + b] = r[k];
-          Hii_r[6 * b + a] = r[k];
-          ++k;
-        }
-      for (int a = 0; a < 6; ++a) gi_r[a] = r[kRecG + a];
+    for (int tl = 0; tl < tiles; ++tl) {
+      const double* r = rec + ((size_t)(P + d) * tiles + tl) * kRecWords;
+      if (jac) {
+        int k = 0;
+        for (int a = 0; a < 6; ++a)
+          for (int b = a; b < 6; ++b) {
+            Hii_r[6 * a + b] += r[k];
+            ++k;
+          }
+        for (int a = 0; a < 6; ++a) gi_r[a] += r[kRecG + a];
+      }
+      Eg += r[kRecEg];
+      Ep += r[kRecEp];
+      ng += r[kRecNg];
+      np += r[kRecNp];
     }
-    Eg += r[kRecEg];
-    Ep += r[kRecEp];
-    ng += r[kRecNg];
-    np += r[kRecNp];
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < a; ++b) Hii_r[6 * a + b] = Hii_r[6 * b + a];
   }
   double Es = 0, ns = 0;
   // sparse moments
@@ -163,6 +171,7 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
       if (r < 3) return c < 3 ? R2[3 * r + c] : 0.0;
       return c < 3 ? TR2[3 * (r - 3) + c] : R2[3 * (r - 3) + (c - 3)];
     };
+    double Z2[36];
     if (has_rev) {
       // Y2 = Hii_r Ad2
       for (int a = 0; a < 6; ++a)
@@ -171,15 +180,14 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
           for (int k = 0; k < 6; ++k) v += Hii_r[6 * a + k] * ad2(k, b);
           Y2[6 * a + b] = v;
         }
-      double Z[36];
       for (int a = 0; a < 6; ++a)
         for (int b = 0; b < 6; ++b) {
           double v = 0.0;
           for (int k = 0; k < 6; ++k) v += ad2(k, a) * Y2[6 * k + b];
-          Z[6 * a + b] = v;
+          Z2[6 * a + b] = v;
         }
       for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) out[kEHjj + 6 * a + b] += 0.5 * (Z[6 * a + b] + Z[6 * b + a]);
+        for (int b = 0; b < 6; ++b) out[kEHjj + 6 * a + b] += 0.5 * (Z2[6 * a + b] + Z2[6 * b + a]);
     }
     // H_ii sparse part
     double Hii[36];
@@ -219,7 +227,26 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
         double v = 0.0;
         for (int k = 0; k < 6; ++k) v += Y[6 * a + k] * ad(k, b);
         Hii[6 * a + b] += v + Hii_r[6 * a + b];
+        // the dense term's part alone (matrix-free sparse mode: the product takes the
+        // sparse part per correspondence)
+        if (ediag_dense) ediag_dense[(size_t)e * 72 + 6 * a + b] = v + Hii_r[6 * a + b];
       }
+    if (ediag_dense) {
+      double* dd = ediag_dense + (size_t)e * 72;
+      for (int a = 0; a < 6; ++a)
+        for (int b = a + 1; b < 6; ++b) {
+          const double v = 0.5 * (dd[6 * a + b] + dd[6 * b + a]);
+          dd[6 * a + b] = v;
+          dd[6 * b + a] = v;
+        }
+      // H_jj of the dense term: the forward job's block and the reverse job's, as above
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          double v = Hjj_d[6 * a + b];
+          if (has_rev) v += 0.5 * (Z2[6 * a + b] + Z2[6 * b + a]);
+          dd[36 + 6 * a + b] = v;
+        }
+    }
     // symmetrise: both triangles from the same sums
     for (int a = 0; a < 6; ++a)
       for (int b = a + 1; b < 6; ++b) {
@@ -264,9 +291,11 @@ __global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij,
         }
     }
     for (int k = 0; k < 36; ++k) {
+      const double vd = -Y[k] - (has_rev ? Y2[k] : 0.0);
       double v = Hij[k] - Y[k] - (has_rev ? Y2[k] : 0.0);
       out[kEHij + k] = v;
-      hij_store[(size_t)e * 36 + k] = (T)v;
+      // the PCG's copy: the dense term's block alone in matrix-free sparse mode
+      hij_store[(size_t)e * 36 + k] = (T)(ediag_dense ? vd : v);
     }
     // gradients.  g_i sparse = w [sp x (R^T t) - sum p x (R^T q); sp + n R^T t - R^T sq]
     //             g_j sparse = -w [sum q x (R p) + sq x t; R sp + n t - sq]
@@ -738,6 +767,37 @@ __device__ __forceinline__ double block_sum_w(double v, double* sh) {
   return t;
 }
 
+// Six sums over the 64 lanes at once (transpose-reduce, fixed order): values 6
+// and 7 are zero; lanes 32 apart exchange half of their eight values and each
+// keeps the sum of the half it owns (bit 5 of the lane picks the half), then lanes
+// 16 apart halve the four, lanes 8 apart the two, and the eight lanes of each group
+// add their one value (DPP: swap neighbours, swap pairs, mirror within 8).  Value
+// b ends in lanes 8b .. 8b + 7: seven exchanges instead of six full sums' 36.
+__device__ __forceinline__ double wave_sum6_d(const double (&v)[6]) {
+  const int lane = threadIdx.x & 63;
+  const double x8[8] = {v[0], v[1], v[2], v[3], v[4], v[5], 0.0, 0.0};
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+  double k4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double send = h5 ? x8[i] : x8[4 + i];
+    const double keep = h5 ? x8[4 + i] : x8[i];
+    k4[i] = keep + __shfl_xor(send, 32);
+  }
+  double k2[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = h4 ? k4[i] : k4[2 + i];
+    const double keep = h4 ? k4[2 + i] : k4[i];
+    k2[i] = keep + __shfl_xor(send, 16);
+  }
+  double k1 = (h3 ? k2[1] : k2[0]) + __shfl_xor(h3 ? k2[0] : k2[1], 8);
+  k1 += dpp_d(k1, 0);
+  k1 += dpp_d(k1, 1);
+  k1 += dpp_d(k1, 2);
+  return k1;
+}
+
 // y = B p (or B^T p) for one 6x6 block, 16-byte loads, FP32 or FP64 arithmetic.
 template <class T>
 __device__ __forceinline__ void block_mv(const T* __restrict__ B, const T* pw, bool tr, T y[6]) {
@@ -1104,26 +1164,39 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
   // ---- prologue (rows assembled and inverted by k_row_assemble): owners load
   // their row's blocks into registers, every workgroup loads r and M^-1 into LDS
   const bool bad = (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagNotPD) != 0;
-  T blockreg[36];
-  int partner = -1;
-  bool tr = false;
+  // NB register blocks per lane: rows of up to 64 NB - 1 off-diagonal blocks keep
+  // every block in registers (two per lane in FP32; FP64 holds one)
+  constexpr int NB = sizeof(T) == 4 ? 2 : 1;
+  T blockreg[NB][36];
+  int partner[NB];
+  bool tr[NB];
   long long ne = 0;
+#pragma unroll
+  for (int s = 0; s < NB; ++s) {
+    partner[s] = -1;
+    tr[s] = false;
+  }
   if (owner) {
     if (lane < 36) blk[wave][lane] = (double)diag_t[v * 36 + lane];
     __builtin_amdgcn_wave_barrier();
-    // lanes < ne hold the off-diagonal entries, lane ne the diagonal
+    // virtual entries 0..ne-1 are the off-diagonal blocks, ne the diagonal; lane l
+    // holds entries l, l + 64, ...
     ne = row_ptr[v + 1] - row_ptr[v];
-    if (lane < ne) {
-      const int2 en = entries[row_ptr[v] + lane];
-      partner = en.x;
-      tr = en.y & 1;
-      const T* B = hij + (size_t)(en.y >> 1) * 36;
 #pragma unroll
-      for (int q = 0; q < 36; ++q) blockreg[q] = B[q];
-    } else if (lane == ne) {
-      partner = (int)v;
+    for (int s = 0; s < NB; ++s) {
+      const long long q = lane + 64 * s;
+      if (q < ne) {
+        const int2 en = entries[row_ptr[v] + q];
+        partner[s] = en.x;
+        tr[s] = en.y & 1;
+        const T* B = hij + (size_t)(en.y >> 1) * 36;
 #pragma unroll
-      for (int q = 0; q < 36; ++q) blockreg[q] = (T)blk[wave][q];
+        for (int e = 0; e < 36; ++e) blockreg[s][e] = B[e];
+      } else if (q == ne) {
+        partner[s] = (int)v;
+#pragma unroll
+        for (int e = 0; e < 36; ++e) blockreg[s][e] = (T)blk[wave][e];
+      }
     }
   }
   for (long long o = tid; o < n; o += kRepThreads) {
@@ -1162,21 +1235,24 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
       // owners compute (A u)_v from register blocks and the LDS copy of u, publish it
       if (owner) {
         T acc[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-        if (partner >= 0) {
-          T uw[6];
 #pragma unroll
-          for (int b = 0; b < 6; ++b) uw[b] = u[6 * (long long)partner + b];
+        for (int s = 0; s < NB; ++s) {
+          if (partner[s] >= 0) {
+            T uw[6];
 #pragma unroll
-          for (int i = 0; i < 6; ++i) {
-            T s2 = (T)0;
+            for (int b = 0; b < 6; ++b) uw[b] = u[6 * (long long)partner[s] + b];
 #pragma unroll
-            for (int j = 0; j < 6; ++j) s2 += (tr ? blockreg[6 * j + i] : blockreg[6 * i + j]) * uw[j];
-            acc[i] = s2;
+            for (int i = 0; i < 6; ++i) {
+              T s2 = (T)0;
+#pragma unroll
+              for (int j = 0; j < 6; ++j)
+                s2 += (tr[s] ? blockreg[s][6 * j + i] : blockreg[s][6 * i + j]) * uw[j];
+              acc[i] += s2;
+            }
           }
         }
-        // virtual entries 0..ne-1 are the off-diagonal blocks, ne the diagonal; lanes
-        // hold 0..63, rows with more entries take the rest from memory
-        for (long long q = 64 + lane; q <= ne; q += 64) {
+        // rows with more entries than the registers hold take the rest from memory
+        for (long long q = 64 * NB + lane; q <= ne; q += 64) {
           T uw[6], y[6];
           if (q < ne) {
             const int2 en = entries[row_ptr[v] + q];
@@ -1194,16 +1270,13 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
 #pragma unroll
           for (int b = 0; b < 6; ++b) acc[b] += y[b];
         }
-        double tot[6];
+        double accd[6];
 #pragma unroll
-        for (int b = 0; b < 6; ++b) tot[b] = wave_sum_d((double)acc[b]);
-        if (lane < 6 * WPV) {
-          // lane b*WPV + h publishes half h of value b: (tag << 32) | bits
-          const int b = lane / WPV, h = lane % WPV;
-          double tb = tot[0];
-#pragma unroll
-          for (int q = 1; q < 6; ++q)
-            if (b == q) tb = tot[q];
+        for (int b = 0; b < 6; ++b) accd[b] = (double)acc[b];
+        const double tb = wave_sum6_d(accd);  // value lane / 8
+        if ((lane >> 3) < 6 && (lane & 7) < WPV) {
+          // lane 8b + h publishes half h of value b: (tag << 32) | bits
+          const int b = lane >> 3, h = lane & 7;
           unsigned bits;
           if constexpr (WPV == 1) {
             bits = __float_as_uint((float)tb);
@@ -1269,29 +1342,39 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     const double delta = two[1];
     const double beta = k == 0 ? 0.0 : gamma / gamma_prev;
     const double alpha = gamma / (delta - (k == 0 ? 0.0 : beta * gamma / alpha_prev));
-    // p = u + beta p, s = w + beta s, r -= alpha s, u = M^-1 r, (r, u) partials: one
-    // block row per thread, every value read and written by that thread only
+    // p = u + beta p, s = w + beta s, r -= alpha s element by element, then u = M^-1 r
+    // and the (r, u) partials per block row: each wavefront takes ten block rows at
+    // a time, six lanes per row (lanes 60..63 idle), so consecutive lanes touch
+    // consecutive values; a row's six new r values are read back from LDS after a
+    // wavefront barrier (the same wavefront wrote them).  (Updating all of a
+    // wavefront's rows before any of their u measured slower: 1.56 against 1.09 us.)
     part_ru = 0.0;
-    for (long long w = tid; w < nfree; w += kRepThreads) {
-      double rb[6];
+    {
+      const int rr = lane / 6, a = lane - 6 * rr;
+      for (long long w0 = (long long)wave * 10; w0 < nfree; w0 += 10 * kRepWaves) {
+        const long long w = w0 + rr;
+        const bool act = lane < 60 && w < nfree;
+        double rb = 0.0;
+        if (act) {
+          const long long o = 6 * w + a;
+          const T pn = (T)((double)u[o] + beta * (double)p[o]);
+          const T sn = (T)((double)wvec[o] + beta * (double)sv[o]);
+          p[o] = pn;
+          sv[o] = sn;
+          const T rn = (T)((double)r[o] - alpha * (double)sn);
+          r[o] = rn;
+          rb = (double)rn;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (act) {
+          double s2 = 0.0;
 #pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        const long long o = 6 * w + b;
-        const T pn = (T)((double)u[o] + beta * (double)p[o]);
-        const T sn = (T)((double)wvec[o] + beta * (double)sv[o]);
-        p[o] = pn;
-        sv[o] = sn;
-        rb[b] = (double)(T)((double)r[o] - alpha * (double)sn);
-      }
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        double s2 = 0.0;
-#pragma unroll
-        for (int b = 0; b < 6; ++b) s2 += (double)minv[w * 36 + 6 * a + b] * rb[b];
-        const T ut = (T)s2;
-        r[6 * w + a] = (T)rb[a];
-        u[6 * w + a] = ut;
-        part_ru += rb[a] * (double)ut;
+          for (int b = 0; b < 6; ++b) s2 += (double)minv[w * 36 + 6 * a + b] * (double)r[6 * w + b];
+          const T ut = (T)s2;
+          u[6 * w + a] = ut;
+          part_ru += rb * (double)ut;
+        }
       }
     }
     __syncthreads();
@@ -1327,6 +1410,290 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     }
   }
   if (wg == 0 && tid == 0 && stats) {
+    stats[0] = rz0;
+    stats[1] = rz;
+    stats[2] = done;
+  }
+}
+
+// The sparse term applied matrix-free inside the distributed PCG (Sec. 4.4): per
+// sparse frame pair g = (a, b), sorted correspondence positions [ptr[g], ptr[g+1])
+// with points pts[m] = (P in frame a, Q in frame b), and y_g = w J^T J p over them,
+// 12 values per pair (frame a's six, then frame b's).
+struct MfArgs {
+  const float* pts;
+  const long long* ptr;
+  const int* ij;
+  long long S;
+  const long long* edge_sparse;
+  const long long* iptr;       // edges of frame f as their lower frame: [iptr[f], iptr[f+1])
+  const long long* jptr;       // ... as their upper frame: ej_sorted[jptr[f] ..]
+  const long long* ej_sorted;
+  double w;
+  double* y;
+};
+
+// Correspondence points in sorted position order, oriented as their pair (a < b).
+__global__ void k_mf_points(const int* __restrict__ fi, const int* __restrict__ fj, const float* __restrict__ pi,
+                            const float* __restrict__ pj, const long long* __restrict__ perm, long long M,
+                            float* __restrict__ pts) {
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const long long c = perm[m];
+  const bool sw = fi[c] > fj[c];
+  const float* P = sw ? pj : pi;
+  const float* Q = sw ? pi : pj;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pts[6 * m + k] = P[3 * c + k];
+    pts[6 * m + 3 + k] = Q[3 * c + k];
+  }
+}
+
+// Diagonal blocks of the dense term alone per free frame (one wavefront per row,
+// the frame's edges in list order), for the product in matrix-free sparse mode.
+template <class T>
+__global__ void __launch_bounds__(64) k_row_dense_diag(const double* __restrict__ ediag,
+                                                       const long long* __restrict__ iptr,
+                                                       const long long* __restrict__ jptr,
+                                                       const long long* __restrict__ ej_sorted,
+                                                       const int* __restrict__ frame_of_var, T* __restrict__ diag_t) {
+  const long long v = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (lane >= 36) return;
+  const int f = frame_of_var[v];
+  double s = 0.0;
+  for (long long k = iptr[f]; k < iptr[f + 1]; ++k) s += ediag[(size_t)k * 72 + lane];
+  for (long long k = jptr[f]; k < jptr[f + 1]; ++k) s += ediag[(size_t)ej_sorted[k] * 72 + 36 + lane];
+  diag_t[v * 36 + lane] = (T)s;
+}
+
+// Distributed-vector PCG (the two-reduction block-Jacobi recurrence of the
+// cooperative kernel) for problems whose vectors do not fit in LDS five times
+// over but whose search direction fits once.  Rows are assembled and inverted by
+// k_row_assemble before it.  One wavefront owns one row (or several, in turn) and
+// keeps that row's x, r and A p to itself (in memory only it touches); z is
+// published by the owners, and every workgroup rebuilds the full search direction
+// p = z + beta p in its LDS after each grid reduction, so the product A p reads
+// partner values from LDS instead of remote memory.  The owner's lanes take the
+// row's blocks (lane l: entries l, l + 64, ...; entry ne is the diagonal block),
+// streamed from memory every iteration with the next entry index fetched ahead,
+// and the six row sums close with a fixed butterfly.  Per iteration: gather p,
+// A p, barrier (p.Ap), update x, r, z, barrier (r.z).
+constexpr int kDistThreads = 512;
+constexpr int kDistWaves = kDistThreads / 64;
+constexpr size_t kDistLdsMax = 128 * 1024;
+
+template <class T, bool MF>
+__global__ void __launch_bounds__(kDistThreads) k_solve_dist(
+    long long nfree, int F, int iters, const T* __restrict__ hij, const long long* __restrict__ row_ptr,
+    const int2* __restrict__ entries, const int* __restrict__ frame_of_var, const int* __restrict__ var_of,
+    const T* __restrict__ diag_t, const T* __restrict__ minv_g, const T* __restrict__ r0, T* zpub,
+    T* __restrict__ xv, T* __restrict__ rv, T* __restrict__ apv, double* parts, unsigned* bar,
+    double* __restrict__ delta_out, double* __restrict__ poses, int update, double* __restrict__ stats, int* flags,
+    unsigned spin_limit, MfArgs mf) {
+  extern __shared__ double lds_dyn[];
+  T* p = reinterpret_cast<T*>(lds_dyn);  // the full search direction, one copy per workgroup
+  __shared__ double sh[(kDistWaves + 1) * kParts];
+  __shared__ int sh_ok;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long gw = (long long)blockIdx.x * kDistWaves + wave, nw = (long long)gridDim.x * kDistWaves;
+  const long long n = 6 * nfree;
+  unsigned nbar = 0;
+  if (tid == 0) sh_ok = 1;
+  __syncthreads();
+  const bool bad = (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagNotPD) != 0;
+
+  // z = M^-1 r for the rows of this wavefront (lanes 0..5), published; (r, z) partial
+  auto precondition = [&](long long v, double rb, double& part) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const double rbb = __shfl(rb, b);
+      if (lane < 6) s += (double)minv_g[v * 36 + 6 * lane + b] * rbb;
+    }
+    if (lane < 6) {
+      const T zt = (T)s;
+      st_shared(&zpub[6 * v + lane], zt);
+      part += rb * (double)zt;
+    }
+  };
+
+  double rz = 0.0, rz0 = 0.0, beta = 0.0;
+  int done = 0;
+  if (!bad) {
+    double part[1] = {0.0};
+    for (long long v = gw; v < nfree; v += nw) {
+      const double rb = lane < 6 ? (double)r0[6 * v + lane] : 0.0;
+      if (lane < 6) {
+        xv[6 * v + lane] = (T)0;
+        rv[6 * v + lane] = (T)rb;
+      }
+      precondition(v, rb, part[0]);
+    }
+    grid_sums<1, kDistWaves>(part, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
+    rz = rz0 = part[0];
+  }
+  for (int k = 0; k < iters && !bad && sh_ok; ++k) {
+    if (rz <= 1e-30) break;
+    // p = z (first iteration) or z + beta p; z was published before the last barrier
+    const T tb = (T)beta;
+    for (long long o = tid; o < n; o += kDistThreads) {
+      const T zo = ld_shared(&zpub[o]);
+      p[o] = k == 0 ? zo : (T)(zo + tb * p[o]);
+    }
+    __syncthreads();
+    if constexpr (MF) {
+      // y_g = w sum_m J^T (J_a p_a + J_b p_b) per sparse pair, one wavefront per pair:
+      // r = T_a P - T_b Q, J_a x = R_a (omega_a x P + v_a), J_b x = -R_b (omega_b x Q + v_b)
+      for (long long g = gw; g < mf.S; g += nw) {
+        const int fa = mf.ij[2 * g], fb = mf.ij[2 * g + 1];
+        const int va = var_of[fa], vb = var_of[fb];
+        double Ra[9], Rb[9], xa[6], xb[6];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          Ra[q] = poses[(size_t)fa * 16 + 4 * (q / 3) + q % 3];
+          Rb[q] = poses[(size_t)fb * 16 + 4 * (q / 3) + q % 3];
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          xa[q] = va >= 0 ? (double)p[6 * (long long)va + q] : 0.0;
+          xb[q] = vb >= 0 ? (double)p[6 * (long long)vb + q] : 0.0;
+        }
+        double ya[6] = {0, 0, 0, 0, 0, 0}, yb[6] = {0, 0, 0, 0, 0, 0};
+        for (long long m = mf.ptr[g] + lane; m < mf.ptr[g + 1]; m += 64) {
+          const double P[3] = {mf.pts[6 * m], mf.pts[6 * m + 1], mf.pts[6 * m + 2]};
+          const double Q[3] = {mf.pts[6 * m + 3], mf.pts[6 * m + 4], mf.pts[6 * m + 5]};
+          const double la[3] = {xa[1] * P[2] - xa[2] * P[1] + xa[3], xa[2] * P[0] - xa[0] * P[2] + xa[4],
+                                xa[0] * P[1] - xa[1] * P[0] + xa[5]};
+          const double lb[3] = {xb[1] * Q[2] - xb[2] * Q[1] + xb[3], xb[2] * Q[0] - xb[0] * Q[2] + xb[4],
+                                xb[0] * Q[1] - xb[1] * Q[0] + xb[5]};
+          double u[3];
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            u[r] = (Ra[3 * r] * la[0] + Ra[3 * r + 1] * la[1] + Ra[3 * r + 2] * la[2]) -
+                   (Rb[3 * r] * lb[0] + Rb[3 * r + 1] * lb[1] + Rb[3 * r + 2] * lb[2]);
+          double aR[3], bR[3];  // R_a^T u, R_b^T u
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            aR[r] = Ra[r] * u[0] + Ra[3 + r] * u[1] + Ra[6 + r] * u[2];
+            bR[r] = Rb[r] * u[0] + Rb[3 + r] * u[1] + Rb[6 + r] * u[2];
+          }
+          ya[0] += P[1] * aR[2] - P[2] * aR[1];
+          ya[1] += P[2] * aR[0] - P[0] * aR[2];
+          ya[2] += P[0] * aR[1] - P[1] * aR[0];
+          yb[0] -= Q[1] * bR[2] - Q[2] * bR[1];
+          yb[1] -= Q[2] * bR[0] - Q[0] * bR[2];
+          yb[2] -= Q[0] * bR[1] - Q[1] * bR[0];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            ya[3 + r] += aR[r];
+            yb[3 + r] -= bR[r];
+          }
+        }
+        const double sa = wave_sum6_d(ya), sb = wave_sum6_d(yb);  // value lane / 8
+        if ((lane & 7) == 0 && (lane >> 3) < 6) {
+          st_shared(&mf.y[12 * g + (lane >> 3)], mf.w * sa);
+          st_shared(&mf.y[12 * g + 6 + (lane >> 3)], mf.w * sb);
+        }
+      }
+      ++nbar;
+      if (!grid_sync(bar, nbar * (unsigned)gridDim.x, flags, &sh_ok, spin_limit)) break;
+    }
+    double part[1] = {0.0};
+    for (long long v = gw; v < nfree; v += nw) {
+      const long long e0 = row_ptr[v], ne = row_ptr[v + 1] - e0;
+      double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int2 en_next = lane < ne ? entries[e0 + lane] : make_int2((int)v, -1);
+      for (long long q = lane; q <= ne; q += 64) {
+        const int2 en = en_next;
+        if (q + 64 <= ne) en_next = q + 64 < ne ? entries[e0 + q + 64] : make_int2((int)v, -1);
+        const T* B = en.y >= 0 ? hij + (size_t)(en.y >> 1) * 36 : diag_t + (size_t)v * 36;
+        T pw[6], y[6];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)en.x + b];
+        block_mv<T>(B, pw, en.y >= 0 && (en.y & 1), y);
+#pragma unroll
+        for (int b = 0; b < 6; ++b) acc[b] += (double)y[b];
+      }
+      if constexpr (MF) {
+        // the sparse pairs' sums over every edge of the frame, also those whose other
+        // frame is not a variable (the gauge frame, held frames): as frame a (lower)
+        // of the edges it starts, as frame b of the others
+        const int f = frame_of_var[v];
+        const long long ni = mf.iptr[f + 1] - mf.iptr[f], nj = mf.jptr[f + 1] - mf.jptr[f];
+        for (long long q = lane; q < ni + nj; q += 64) {
+          const long long e = q < ni ? mf.iptr[f] + q : mf.ej_sorted[mf.jptr[f] + q - ni];
+          const long long g = mf.edge_sparse[e];
+          if (g >= 0) {
+            const double* yg = mf.y + 12 * g + (q < ni ? 0 : 6);
+#pragma unroll
+            for (int b = 0; b < 6; ++b) acc[b] += ld_shared(&yg[b]);
+          }
+        }
+      }
+      double tot[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) tot[b] = wave_sum_d(acc[b]);
+      if (lane < 6) {
+        double t = tot[0];
+#pragma unroll
+        for (int q = 1; q < 6; ++q)
+          if (lane == q) t = tot[q];
+        const T ap = (T)t;
+        apv[6 * v + lane] = ap;
+        part[0] += (double)p[6 * v + lane] * (double)ap;
+      }
+    }
+    grid_sums<1, kDistWaves>(part, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
+    if (!sh_ok) break;
+    const double alpha = rz / part[0];
+    double part2[1] = {0.0};
+    for (long long v = gw; v < nfree; v += nw) {
+      double rb = 0.0;
+      if (lane < 6) {
+        const long long o = 6 * v + lane;
+        xv[o] = (T)((double)xv[o] + alpha * (double)p[o]);
+        rb = (double)(T)((double)rv[o] - alpha * (double)apv[o]);
+        rv[o] = (T)rb;
+      }
+      precondition(v, rb, part2[0]);
+    }
+    grid_sums<1, kDistWaves>(part2, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
+    if (!sh_ok) break;
+    beta = part2[0] / rz;
+    rz = part2[0];
+    ++done;
+  }
+  if (delta_out) {
+    for (long long v = gw; v < nfree; v += nw)
+      if (lane < 6) delta_out[6LL * frame_of_var[v] + lane] = bad ? 0.0 : (double)xv[6 * v + lane];
+    for (long long o = (long long)blockIdx.x * kDistThreads + tid; o < 6LL * F;
+         o += (long long)gridDim.x * kDistThreads)
+      if (var_of[o / 6] < 0) delta_out[o] = 0.0;
+  }
+  if (update && !bad && sh_ok) {
+    for (long long v = gw; v < nfree; v += nw) {
+      if (lane != 0) continue;
+      double xi[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) xi[q] = (double)xv[6 * v + q];
+      double dR[9], dt[3];
+      exp_se3(xi, dR, dt);
+      double* T4 = poses + (size_t)frame_of_var[v] * 16;
+      double Rn[9], tn[3];
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+          Rn[3 * i + j] = T4[4 * i] * dR[j] + T4[4 * i + 1] * dR[3 + j] + T4[4 * i + 2] * dR[6 + j];
+        tn[i] = T4[4 * i] * dt[0] + T4[4 * i + 1] * dt[1] + T4[4 * i + 2] * dt[2] + T4[4 * i + 3];
+      }
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) T4[4 * i + j] = Rn[3 * i + j];
+        T4[4 * i + 3] = tn[i];
+      }
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0 && stats) {
     stats[0] = rz0;
     stats[1] = rz;
     stats[2] = done;
@@ -1406,21 +1773,28 @@ __global__ void k_export_off(const double* __restrict__ eb, const int* __restric
 }  // namespace
 
 void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, bool with_jacobians) {
+  // matrix-free sparse mode: the PCG's blocks hold the dense term only, and the
+  // dense term's diagonal parts go beside them
+  double* ed = nullptr;
+  if (prm.sparse_matrix_free && with_jacobians) {
+    ensure(c.ediag_dense, sizeof(double) * 72 * (size_t)(c.shape.E + 1));
+    ed = c.ediag_dense.as<double>();
+  }
   const long long E = c.shape.E;
   if (E == 0) return;
   unsigned grid = (unsigned)((E + 63) / 64);
   if (c.pcg_storage == 1)
     hipLaunchKernelGGL(k_edge_blocks<double>, dim3(grid), dim3(64), 0, c.stream, c.edge_ij.as<int>(), E,
                        c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.moments.as<double>(),
-                       c.records.as<double>(), (long long)c.shape.P, c.bidir, poses,
+                       c.records.as<double>(), (long long)c.shape.P, c.bidir, c.dense_tiles, poses,
                        prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
-                       c.eblocks.as<double>(), c.hij64.as<double>());
+                       c.eblocks.as<double>(), c.hij64.as<double>(), ed);
   else
     hipLaunchKernelGGL(k_edge_blocks<float>, dim3(grid), dim3(64), 0, c.stream, c.edge_ij.as<int>(), E,
                        c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.moments.as<double>(),
-                       c.records.as<double>(), (long long)c.shape.P, c.bidir, poses,
+                       c.records.as<double>(), (long long)c.shape.P, c.bidir, c.dense_tiles, poses,
                        prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
-                       c.eblocks.as<double>(), c.hij32.as<float>());
+                       c.eblocks.as<double>(), c.hij32.as<float>(), ed);
 }
 
 template <class T>
@@ -1605,6 +1979,122 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   return true;
 }
 
+// Occupancy of k_solve_dist<T, MF> at a dynamic LDS size (attributes set once per
+// process; contexts on several threads share them, hence the lock).
+template <class T, bool MF>
+int dist_blocks_per_cu(size_t lds) {
+  static std::mutex mu;
+  static bool attr_set = false;
+  static int cached = -1;
+  static size_t cached_lds = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!attr_set) {
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve_dist<T, MF>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDistLdsMax),
+              "set LDS limit");
+    attr_set = true;
+  }
+  if (cached < 0 || cached_lds != lds) {
+    int q = 0;
+    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, reinterpret_cast<const void*>(k_solve_dist<T, MF>),
+                                                           kDistThreads, lds),
+              "occupancy query");
+    cached = q;
+    cached_lds = lds;
+  }
+  return cached;
+}
+
+template <class T, bool MF>
+bool launch_solve_dist(Context& c, int iters, double* trace_slot, double* delta_out, double* poses, double* stats,
+                       bool update, T* diag_t, T* minv_g, T* hij, T* vec) {
+  long long nf = c.shape.nfree;
+  long long n = 6 * nf;
+  long long E = c.shape.E;
+  const size_t lds = sizeof(T) * (size_t)n;
+  if (lds > kDistLdsMax) return false;
+  const int per_cu = dist_blocks_per_cu<T, MF>(lds);
+  if (per_cu < 1) return false;
+  // one row per wavefront while the grid fits the device at once, else rows in
+  // turn; the matrix-free product spreads its sparse pairs over every resident
+  // workgroup
+  const long long resident = std::min<long long>((long long)per_cu * c.num_cus, kMaxSolveGroups);
+  long long G = MF ? resident : std::min<long long>((nf + kDistWaves - 1) / kDistWaves, resident);
+  if (G < 1) G = 1;
+  ensure(c.pcg_partials, sizeof(double) * 2 * kParts * kMaxSolveGroups);
+  ensure(c.pcg_barrier, sizeof(unsigned) * 4);
+  MfArgs mf{nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr};
+  if (MF) {
+    ensure(c.mf_y, sizeof(double) * 12 * (size_t)(c.shape.S + 1));
+    mf = MfArgs{c.mf_pts.as<float>(), c.sparse_ptr.as<long long>(), c.sparse_ij.as<int>(), (long long)c.shape.S,
+                c.edge_sparse.as<long long>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
+                c.ej_sorted.as<long long>(), c.mf_w_sparse, c.mf_y.as<double>()};
+  }
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c.stream, c.pcg_barrier.as<unsigned>());
+  c.pcg_tags_dirty = true;  // the barrier counter no longer matches the replicated kernel's running count
+  T* r0 = vec;
+  T* z = vec + n;
+  T* xv = vec + 2 * n;
+  T* rv = vec + 3 * n;
+  T* apv = vec + 4 * n;
+  int* fl = c.flags.as<int>();
+  hipLaunchKernelGGL(k_row_assemble<T>, dim3((unsigned)(nf + 1)), dim3(kAsmThreads), 0, c.stream, nf, E,
+                     c.eblocks.as<double>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
+                     c.ej_sorted.as<long long>(), c.frame_of_var.as<int>(), c.precond, diag_t, minv_g, r0, trace_slot,
+                     fl);
+  // matrix-free sparse term: the product's diagonal blocks hold the dense term only
+  // (the preconditioner above keeps the full blocks)
+  if (MF)
+    hipLaunchKernelGGL(k_row_dense_diag<T>, dim3((unsigned)nf), dim3(64), 0, c.stream, c.ediag_dense.as<double>(),
+                       c.iptr.as<long long>(), c.jptr.as<long long>(), c.ej_sorted.as<long long>(),
+                       c.frame_of_var.as<int>(), diag_t);
+  const T* hij_c = hij;
+  const long long* rp = c.row_ptr.as<long long>();
+  const int2* en = c.row_entries.as<int2>();
+  const int* fov = c.frame_of_var.as<int>();
+  const int* vof = c.var_of.as<int>();
+  const T* dg = diag_t;
+  const T* mi = minv_g;
+  const T* r0c = r0;
+  double* parts = c.pcg_partials.as<double>();
+  unsigned* bar = c.pcg_barrier.as<unsigned>();
+  int F = c.shape.F;
+  int upd = update ? 1 : 0;
+  unsigned spin = c.spin_limit;
+  int itv = iters;
+  // all workgroups wait for each other: a plain launch when this context is the
+  // only one in the process (the grid fits the occupancy), else a cooperative one
+  if (live_contexts() > 1) {
+    void* args[] = {&nf, &F, &itv, &hij_c, &rp, &en, &fov, &vof, &dg, &mi, &r0c, &z, &xv, &rv, &apv, &parts, &bar,
+                    &delta_out, &poses, &upd, &stats, &fl, &spin, &mf};
+    check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_solve_dist<T, MF>), dim3((unsigned)G),
+                                         dim3(kDistThreads), args, lds, c.stream),
+              "cooperative distributed solve launch");
+  } else {
+    hipLaunchKernelGGL((k_solve_dist<T, MF>), dim3((unsigned)G), dim3(kDistThreads), lds, c.stream, nf, F, itv,
+                       hij_c, rp, en, fov, vof, dg, mi, r0c, z, xv, rv, apv, parts, bar, delta_out, poses, upd, stats,
+                       fl, spin, mf);
+  }
+  return true;
+}
+
+template <class T>
+bool launch_solve_dist_any(Context& c, bool mf, int iters, double* trace_slot, double* delta_out, double* poses,
+                           double* stats, bool update, T* diag_t, T* minv_g, T* hij, T* vec) {
+  return mf ? launch_solve_dist<T, true>(c, iters, trace_slot, delta_out, poses, stats, update, diag_t, minv_g, hij,
+                                         vec)
+            : launch_solve_dist<T, false>(c, iters, trace_slot, delta_out, poses, stats, update, diag_t, minv_g, hij,
+                                          vec);
+}
+
+void launch_mf_points(Context& c, const bf_corrs* co) {
+  const long long M = c.shape.M;
+  ensure(c.mf_pts, sizeof(float) * 6 * (size_t)(M + 1));
+  if (M == 0 || !co) return;
+  hipLaunchKernelGGL(k_mf_points, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, c.stream, co->frame_i, co->frame_j,
+                     co->p_i, co->p_j, c.corr_perm.as<long long>(), M, c.mf_pts.as<float>());
+}
+
 // Largest problem (free frames) solved by the per-problem workgroup kernel when the
 // kernel is chosen automatically.
 constexpr long long kPerProblemMaxFree = 64;
@@ -1620,8 +2110,24 @@ void prepare_solve(Context& c) {
 }
 
 void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
-                  bool update_poses) {
+                  bool update_poses, bool sparse_matrix_free) {
   if (c.shape.nfree == 0) return;
+  auto dist = [&](bool mf) {
+    return c.pcg_storage == 1
+               ? launch_solve_dist_any<double>(c, mf, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
+                                               c.diag64.as<double>(), c.minv64.as<double>(), c.hij64.as<double>(),
+                                               c.pcg_vec.as<double>())
+               : launch_solve_dist_any<float>(c, mf, iters, trace_slot, delta_out, poses_inout, stats, update_poses,
+                                              c.diag32.as<float>(), c.minv32.as<float>(), c.hij32.as<float>(),
+                                              c.pcg_vec.as<float>());
+  };
+  if (sparse_matrix_free) {
+    if (c.solve_mode != 0 && c.solve_mode != 5)
+      fail(BF_ERR_UNSUPPORTED, "the matrix-free sparse term runs in the distributed-vector PCG (solve_kernel 0 or 5)");
+    if (c.shape.nseg > 1) fail(BF_ERR_UNSUPPORTED, "the matrix-free sparse term solves one problem at a time");
+    if (!dist(true)) fail(BF_ERR_UNSUPPORTED, "the search direction does not fit in one workgroup's LDS");
+    return;
+  }
   const bool many = c.shape.nseg > 1;
   if (many && c.solve_mode != 0 && c.solve_mode != 4)
     fail(BF_ERR_UNSUPPORTED, "several problems are solved by the per-problem kernel (solve_kernel 0 or 4)");
@@ -1646,6 +2152,10 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
                                             c.pcg_vec.as<float>());
     if (ok) return;
     if (c.solve_mode == 3) fail(BF_ERR_UNSUPPORTED, "replicated-vector solve does not fit");
+  }
+  if (c.solve_mode == 0 || c.solve_mode == 5) {
+    if (dist(false)) return;
+    if (c.solve_mode == 5) fail(BF_ERR_UNSUPPORTED, "the search direction does not fit in one workgroup's LDS");
   }
   if (c.solve_mode == 1) {
     bool ok = c.pcg_storage == 1

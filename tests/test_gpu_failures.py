@@ -80,16 +80,16 @@ def test_singular_diagonal_block(ctx):
     with pytest.raises(NotPositiveDefinite):
         solve(pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p, pr.corr_q, pr.init_poses,
               prm, linear="cholesky")
-    for kernel in (0, 2):
+    for kernel in (0, 2, 5):
         msg = _solve_expect(ctx, pr, poses_cuda(pr.init_poses), bf_params_from(prm, solve_kernel=kernel),
                             bf.BF_ERR_NOT_PD)
     print("singular block:", msg, flush=True)
 
 
-@pytest.mark.parametrize("solve_kernel", [3, 2])
+@pytest.mark.parametrize("solve_kernel", [3, 2, 5])
 def test_pcg_wait_gives_up(ctx, solve_kernel):
-    """A 120-keyframe window (PCG in the replicated-vector kernel, or the
-    cooperative one): one poll per wait, then BF_ERR_DEVICE; afterwards a solve with
+    """A 120-keyframe window (PCG in the replicated-vector kernel, the cooperative
+    one or the distributed-vector one): one poll per wait, then BF_ERR_DEVICE; afterwards a solve with
     the default limit equals a fresh context's."""
     pr = window(make_problem(1), 40, 120)
     dp = device_problem(pr)

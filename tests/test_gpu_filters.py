@@ -25,10 +25,10 @@ def ctx():
     c.close()
 
 
-def _run(ctx, F, ci, cj, p, q):
+def _run(ctx, F, ci, cj, p, q, cond_mode=0):
     depth = np.zeros((F, 4, 4), np.float32)
     dp = bf.DeviceProblem.from_numpy(depth, depth, (2.0, 2.0, 2.0, 2.0, 4, 4), ci, cj, p, q)
-    keep, kept = bf.bf_filter_correspondences(ctx, dp)
+    keep, kept = bf.bf_filter_correspondences(ctx, dp, cond_mode=cond_mode)
     keep = keep.cpu().numpy()
     assert kept == int(keep.sum())
     return keep
@@ -43,7 +43,8 @@ def test_filters_chunk(ctx):
     assert np.array_equal(keep, ref)
 
 
-def test_filters_constructed(ctx):
+@pytest.mark.parametrize("cond_mode", [0, 1])
+def test_filters_constructed(ctx, cond_mode):
     rng = np.random.default_rng(7)
     T = exp_se3(np.array([0.2, -0.1, 0.3, 0.4, 0.1, -0.2]))
     R, t = T[:3, :3], T[:3, 3]
@@ -63,14 +64,18 @@ def test_filters_constructed(ctx):
     add(0, 3, Pl, Pl @ R.T + t)                                # planar: kept
     ci, cj = np.array(ci, np.int32), np.array(cj, np.int32)
     p, q = np.array(p, np.float32), np.array(q, np.float32)
-    ref = filter_pairs(ci, cj, p, q)
-    keep = _run(ctx, 4, ci, cj, p, q)
+    ref = filter_pairs(ci, cj, p, q, cond_mode=cond_mode)
+    keep = _run(ctx, 4, ci, cj, p, q, cond_mode)
     assert np.array_equal(keep, ref)
-    assert not keep[[3, 20, 41, 59]].any() and keep[:60].sum() >= 50
-    assert not keep[60:110].any() and keep[110:].all()
+    if cond_mode == 0:
+        assert not keep[[3, 20, 41, 59]].any() and keep[:60].sum() >= 50
+        assert not keep[60:110].any() and keep[110:].all()
+    else:
+        assert not keep.any()   # the plain reading discards every set (its checks start at three points)
 
 
-def test_filters_global200_sample(ctx):
+@pytest.mark.parametrize("cond_mode", [0, 1])
+def test_filters_global200_sample(ctx, cond_mode):
     pr = make_problem(1)
     lo, hi = np.minimum(pr.corr_i, pr.corr_j), np.maximum(pr.corr_i, pr.corr_j)
     keys = lo.astype(np.int64) * pr.num_frames + hi
@@ -78,8 +83,8 @@ def test_filters_global200_sample(ctx):
     pick = np.random.default_rng(1).choice(uk, 40, replace=False)
     m = np.isin(keys, pick)
     ci, cj, p, q = pr.corr_i[m], pr.corr_j[m], pr.corr_p[m], pr.corr_q[m]
-    ref = filter_pairs(ci, cj, p, q)
-    keep = _run(ctx, pr.num_frames, ci, cj, p, q)
-    print(f"global200 sample: kept {keep.sum()} of {len(keep)}, outliers kept {(keep & pr.outlier[m]).sum()} "
-          f"of {pr.outlier[m].sum()}", flush=True)
+    ref = filter_pairs(ci, cj, p, q, cond_mode=cond_mode)
+    keep = _run(ctx, pr.num_frames, ci, cj, p, q, cond_mode)
+    print(f"global200 sample, condition mode {cond_mode}: kept {keep.sum()} of {len(keep)}, outliers kept "
+          f"{(keep & pr.outlier[m]).sum()} of {pr.outlier[m].sum()}", flush=True)
     assert np.array_equal(keep, ref)

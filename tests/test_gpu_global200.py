@@ -179,7 +179,37 @@ def test_one_step_parity_along_oracle_trajectory(ctx, prob, golden, init_masks, 
     assert worst_dec < 1e-4
 
 
-@pytest.mark.parametrize("pcg_storage,solve_kernel,accumulate", [(0, 0, 0), (1, 2, 2)])
+@pytest.mark.parametrize("pcg_storage,accumulate", [(0, 0), (1, 2)])
+def test_one_step_matrix_free_sparse(ctx, prob, golden, init_masks, pcg_storage, accumulate):
+    """The matrix-free sparse PCG (Sec. 4.4's variant) for one Gauss-Newton step from
+    each of the oracle's 8 iterates, with the oracle's association at that iterate
+    and its dense weight: the new poses within 1e-5 (rad, m) of the iterate moved by
+    the oracle's increment."""
+    from gpu_helpers import fix_association
+    from oracle.se3 import exp_se3
+    _, _, frames, _, _ = init_masks
+    prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
+    dp = device_problem(prob, pairs=golden["pairs"])
+    free = golden["free"]
+    worst = 0.0
+    for k in range(prob.n_gn):
+        X = golden["traj"][k]
+        fixed = _oracle_association(prob, frames, golden["pairs"], X, prm)
+        p = fix_association(bf_params_from(prm, accumulate=accumulate, pcg_storage=pcg_storage, sparse_matrix_free=1,
+                                           num_gn=1, dense_ramp=0, w_dense=prm.dense_weight(k)), fixed)
+        out = bf.bf_gauss_newton(ctx, dp, poses_cuda(X), p)
+        del fixed
+        ref = X.copy()
+        step = golden["steps"][k].reshape(-1, 6)
+        for q, f in enumerate(free):
+            ref[f] = X[f] @ exp_se3(step[q])
+        rot, tr = pose_errors(out["poses"].cpu().numpy(), ref)
+        worst = max(worst, rot, tr)
+        print(f"step {k}: matrix-free sparse, pose difference {rot:.2e} rad {tr:.2e} m", flush=True)
+    assert worst < 1e-5
+
+
+@pytest.mark.parametrize("pcg_storage,solve_kernel,accumulate", [(0, 0, 0), (1, 2, 2), (1, 5, 2), (0, 5, 0)])
 def test_gauss_newton_fixed_association(ctx, prob, golden, init_masks, pcg_storage, solve_kernel, accumulate):
     """The oracle's association at the initial poses held through the solve (a smooth
     energy): the full 8 x 20 solve within 1e-5 rad / m and 1e-4 in energy of the

@@ -235,7 +235,8 @@ def test_normal_equations_and_edge_blocks(ctx, chunk, chunk_setup, pcg_storage, 
     assert abs(out["energy"][0] - en["total"]) <= (1e-4 if differ else 1e-6) * en["total"]
 
 
-@pytest.mark.parametrize("pcg_storage,solve_kernel", [(0, 1), (1, 1), (0, 2), (1, 2), (0, 3), (1, 3)])
+@pytest.mark.parametrize("pcg_storage,solve_kernel", [(0, 1), (1, 1), (0, 2), (1, 2), (0, 3), (1, 3), (0, 5),
+                                                    (1, 5)])
 def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage, solve_kernel, init_differ):
     """The 10-iteration PCG increment element by element within 1e-5 (rad, m) of the
     oracle's PCG on its own system, and r^T z at the start within 1e-5 relative."""
@@ -261,7 +262,8 @@ def test_pcg_matches_oracle_pcg(ctx, chunk, chunk_setup, pcg_storage, solve_kern
 
 
 @pytest.mark.parametrize("pcg_storage,accumulate,solve_kernel",
-                         [(0, 0, 1), (1, 0, 1), (0, 1, 1), (0, 2, 1), (0, 0, 2), (1, 0, 2), (0, 0, 3), (1, 2, 3)])
+                         [(0, 0, 1), (1, 0, 1), (0, 1, 1), (0, 2, 1), (0, 0, 2), (1, 0, 2), (0, 0, 3), (1, 2, 3),
+                          (0, 0, 5), (1, 2, 5)])
 def test_gauss_newton_chunk(ctx, chunk, pcg_storage, accumulate, solve_kernel):
     prm = Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg)
     ref = solve(chunk.depth, chunk.intensity, chunk.intrinsics, chunk.corr_i, chunk.corr_j, chunk.corr_p,
@@ -285,7 +287,7 @@ def test_gauss_newton_chunk(ctx, chunk, pcg_storage, accumulate, solve_kernel):
     assert torch.equal(again["poses"], out["poses"])
 
 
-@pytest.mark.parametrize("solve_kernel", [0, 1, 2, 3])
+@pytest.mark.parametrize("solve_kernel", [0, 1, 2, 3, 5])
 def test_frame_without_residuals_is_held(ctx, solve_kernel):
     """A variable frame that no residual touches (no valid depth, no
     correspondences, but dense pairs from lower frames) keeps its pose; the rest
@@ -309,7 +311,7 @@ def test_frame_without_residuals_is_held(ctx, solve_kernel):
     assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
 
 
-@pytest.mark.parametrize("solve_kernel,pcg_storage", [(0, 0), (1, 0), (2, 0), (3, 0), (3, 1)])
+@pytest.mark.parametrize("solve_kernel,pcg_storage", [(0, 0), (1, 0), (2, 0), (3, 0), (3, 1), (5, 0), (5, 1)])
 def test_gauss_newton_chunk_jacobi_preconditioner(ctx, chunk, solve_kernel, pcg_storage):
     """The paper's scalar Jacobi preconditioner (Sec. 4.4) in every solve kernel."""
     prm = Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg, preconditioner="jacobi")
@@ -321,6 +323,46 @@ def test_gauss_newton_chunk_jacobi_preconditioner(ctx, chunk, solve_kernel, pcg_
     print(f"chunk jacobi kernel={solve_kernel} storage={pcg_storage}: pose err {rot:.3e} rad {tr:.3e} m", flush=True)
     assert rot < 1e-5 and tr < 1e-5
     assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
+
+
+@pytest.mark.parametrize("pcg_storage,accumulate", [(0, 0), (1, 2)])
+def test_gauss_newton_chunk_matrix_free_sparse(ctx, chunk, pcg_storage, accumulate):
+    """The paper's PCG variant (Sec. 4.4): the sparse term applied matrix-free in
+    every PCG iteration (J p per correspondence, J^T of it per frame pair) instead of
+    its assembled blocks; the linear system is the same, so the solve meets the
+    oracle's PCG within 1e-5 like every other kernel, and its energy within 1e-4."""
+    prm = Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg)
+    ref = solve(chunk.depth, chunk.intensity, chunk.intrinsics, chunk.corr_i, chunk.corr_j, chunk.corr_p,
+                chunk.corr_q, chunk.init_poses, prm, linear="pcg")
+    kw = dict(pcg_storage=pcg_storage, accumulate=accumulate)
+    out = bf.bf_gauss_newton(ctx, device_problem(chunk), poses_cuda(chunk.init_poses),
+                             bf_params_from(prm, sparse_matrix_free=1, **kw))
+    asm = bf.bf_gauss_newton(ctx, device_problem(chunk), poses_cuda(chunk.init_poses),
+                             bf_params_from(prm, solve_kernel=5, **kw))
+    rot, tr = pose_errors(out["poses"].cpu().numpy(), ref["poses"])
+    rot_a, tr_a = pose_errors(out["poses"].cpu().numpy(), asm["poses"].cpu().numpy())
+    print(f"chunk matrix-free sparse {kw}: pose err {rot:.2e} rad {tr:.2e} m vs oracle, {rot_a:.2e} / {tr_a:.2e} vs "
+          f"assembled blocks in the same kernel", flush=True)
+    assert rot < 1e-5 and tr < 1e-5
+    assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
+
+
+def test_matrix_free_sparse_refusals(ctx, chunk):
+    """Matrix-free sparse mode runs in the distributed-vector PCG of
+    bf_gauss_newton only: other kernels, graphs, systems and batches refuse it."""
+    dp = device_problem(chunk)
+    init = poses_cuda(chunk.init_poses)
+    prm = Params(num_gn=2, num_pcg=5)
+    for kw in (dict(solve_kernel=3), dict(solve_kernel=1), dict(graph=1)):
+        with pytest.raises(bf.BFError) as e:
+            bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, sparse_matrix_free=1, **kw))
+        assert e.value.status == bf.BF_ERR_UNSUPPORTED, kw
+    with pytest.raises(bf.BFError) as e:
+        bf.bf_build_normal_equations(ctx, dp, init, bf_params_from(prm, sparse_matrix_free=1), gn_iter=0)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    with pytest.raises(bf.BFError) as e:
+        bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, sparse_matrix_free=2))
+    assert e.value.status == bf.BF_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("W,H", [(3, 3), (7, 5), (37, 23)])
@@ -411,7 +453,7 @@ def test_bidirectional_chunk(ctx, chunk, solve_kernel, accumulate):
     assert abs(sol["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
 
 
-@pytest.mark.parametrize("pcg_storage,accumulate,solve_kernel", [(0, 0, 0), (1, 2, 2), (0, 1, 3)])
+@pytest.mark.parametrize("pcg_storage,accumulate,solve_kernel", [(0, 0, 0), (1, 2, 2), (0, 1, 3), (1, 2, 5)])
 def test_gauss_newton_chunk_fixed_association(ctx, chunk, pcg_storage, accumulate, solve_kernel):
     """The dense association decided once by the oracle at the initial poses and held
     (bf_params.fixed_association, the oracle's freeze_association): with no decision
@@ -435,3 +477,47 @@ def test_gauss_newton_chunk_fixed_association(ctx, chunk, pcg_storage, accumulat
           f"{rot:.2e} rad {tr:.2e} m", flush=True)
     assert rot < 1e-5 and tr < 1e-5
     assert abs(out["energy"]["total"] - ref["energy"]["total"]) <= 1e-4 * ref["energy"]["total"]
+
+
+@pytest.mark.parametrize("W,H,nt,tiles,accumulate", [(80, 60, 256, 2, 2), (80, 60, 128, 4, 2), (37, 23, 64, 3, 2),
+                                                    (160, 120, 256, 4, 2), (80, 60, 256, 2, 0),
+                                                    (160, 120, 128, 4, 0)])
+def test_dense_tiles(ctx, W, H, nt, tiles, accumulate):
+    """A pair job split into tiles of its pixels (one workgroup each, partial records
+    summed in tile order): the association identical pixel by pixel to the untiled
+    job and the counts equal; every pixel's products are computed alike, only the
+    order of the sums differs.
+
+    FP64 lane sums (accumulate 2): records within 1e-12 relative, a solve within 1e-9.
+    FP32 lane sums (accumulate 0): a lane takes at most ceil(H W / threads) + 1 pixels
+    off its wavefront's queue, each with a geometric and a photometric product, so it
+    adds at most m = 2 (ceil(H W / threads) + 1) products and each record word moves
+    by at most m u (u = 2^-24) times the sum of
+    its terms' magnitudes, which is at most the record's norm (|J_a J_b| and |J_a r|
+    are at most half of J_a^2 + J_b^2 and J_a^2 + r^2); over the 29 words and both
+    launches, sqrt(29) 2 m u relative.  The solve then stays within 1e-6, a tenth of
+    the 1e-5 the FP32 path is held to against the oracle."""
+    f = 72.0 * W / 80.0
+    pr = make_chunk(num_frames=5, W=W, H=H, fx=f, fy=f, cx=W / 2.0, cy=H / 2.0, name=f"tiles{W}x{H}")
+    dp = device_problem(pr)
+    prm = Params(num_gn=3, num_pcg=10)
+    kw = dict(dense_threads=nt, accumulate=accumulate)
+    base = bf.bf_eval_residuals(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, **kw), gn_iter=1,
+                                records=True, masks=True)
+    tl = bf.bf_eval_residuals(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, dense_tiles=tiles, **kw),
+                              gn_iter=1, records=True, masks=True)
+    assert torch.equal(base["masks"], tl["masks"])
+    r0, r1 = base["records"].cpu().numpy(), tl["records"].cpu().numpy()
+    assert np.array_equal(r0[:, 29:31], r1[:, 29:31])
+    m = 2 * (-(-W * H // nt) + 1)
+    rec_tol = 1e-12 if accumulate == 2 else np.sqrt(29.0) * 2 * m * 2.0 ** -24
+    worst = max(block_rel_err(r1[k, :29], r0[k, :29]) for k in range(len(r0)))
+    assert worst <= rec_tol, (worst, rec_tol)
+    assert abs(tl["total"] - base["total"]) <= rec_tol * base["total"]
+    a = bf.bf_gauss_newton(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, **kw))
+    b = bf.bf_gauss_newton(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, dense_tiles=tiles, **kw))
+    rot, tr = pose_errors(a["poses"].cpu().numpy(), b["poses"].cpu().numpy())
+    print(f"{W}x{H} {nt} threads x {tiles} tiles, accumulate {accumulate}: records {worst:.1e} (bound "
+          f"{rec_tol:.1e}), pose difference to one tile {rot:.1e} rad {tr:.1e} m", flush=True)
+    pose_tol = 1e-9 if accumulate == 2 else 1e-6
+    assert rot < pose_tol and tr < pose_tol

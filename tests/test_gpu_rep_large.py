@@ -1,8 +1,8 @@
 """The replicated-vector PCG above the size where its block-Jacobi inverses fit in
-LDS next to the vectors (they are then read from memory): one Gauss-Newton step
-of a 400-keyframe and of an 800-keyframe problem of the serving workload's kind
-agrees with the cooperative PCG kernel, which keeps nothing in LDS, within
-rounding (FP64 PCG storage: 400 keyframes, 528 B per frame do not fit in 128 KB;
+LDS next to the vectors (they are then read from memory), and the
+distributed-vector PCG: one Gauss-Newton step of a 400-keyframe and of an
+800-keyframe problem of the serving workload's kind agrees with the cooperative
+PCG kernel, which keeps nothing in LDS, within rounding (FP64 PCG storage: 400 keyframes, 528 B per frame do not fit in 128 KB;
 FP32 storage: 800 keyframes, 264 B per frame do not)."""
 import shutil
 import tempfile
@@ -44,13 +44,14 @@ def test_one_step_replicated_vs_cooperative(ctx, frames, pcg_storage, bound):
     dp = device_problem(prob)
     init = poses_cuda(prob.init_poses)
     out = {}
-    for kernel in (3, 2):
+    for kernel in (3, 2, 5):
         out[kernel] = bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, solve_kernel=kernel,
                                                                       pcg_storage=pcg_storage))
-    rot, tr = pose_errors(out[3]["poses"].cpu().numpy(), out[2]["poses"].cpu().numpy())
     step = pose_errors(out[2]["poses"].cpu().numpy(), prob.init_poses)
-    print(f"{frames} keyframes, storage {pcg_storage}: replicated vs cooperative {rot:.2e} rad {tr:.2e} m "
-          f"(step {step[0]:.3f} rad {step[1]:.3f} m)", flush=True)
-    assert rot < bound and tr < bound
-    e3, e2 = out[3]["energy"]["total"], out[2]["energy"]["total"]
-    assert abs(e3 - e2) <= 1e-6 * e2
+    for kernel, name in ((3, "replicated"), (5, "distributed")):
+        rot, tr = pose_errors(out[kernel]["poses"].cpu().numpy(), out[2]["poses"].cpu().numpy())
+        print(f"{frames} keyframes, storage {pcg_storage}: {name} vs cooperative {rot:.2e} rad {tr:.2e} m "
+              f"(step {step[0]:.3f} rad {step[1]:.3f} m)", flush=True)
+        assert rot < bound and tr < bound
+        ek, e2 = out[kernel]["energy"]["total"], out[2]["energy"]["total"]
+        assert abs(ek - e2) <= 1e-6 * e2

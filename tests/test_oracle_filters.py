@@ -27,6 +27,30 @@ def test_condition_numbers_closed_forms():
     assert abs(cp - 4.0) < 1e-12 and abs(cq - 4.0) < 1e-12 and abs(cx - 4.0) < 1e-12
     line = np.outer(np.linspace(-1, 1, 9), [0.3, 0.4, 0.5])
     assert max(condition_numbers(line, line)) > 1e12
+    # the plain definition (largest / smallest): 1 / 0.01 = 100 for the box (the
+    # eigenvalues of the covariance of a centred +-a box are a^2), a rotated copy alike
+    cp, cq, cx = condition_numbers(g, g, mode=1)
+    assert abs(cp - 100.0) < 1e-9 and abs(cq - 100.0) < 1e-9 and abs(cx - 100.0) < 1e-9
+    R, t, _ = _rigid(9)
+    assert abs(max(condition_numbers(g @ R.T + t, g, mode=1)) - 100.0) < 1e-8
+    plane = g.copy()
+    plane[:, 2] = 0.0
+    assert condition_numbers(plane, plane, mode=0)[0] == 4.0 and condition_numbers(plane, plane, mode=1)[0] == np.inf
+
+
+def test_plain_condition_rejects_every_set():
+    """With the largest / smallest ratio the incremental filter, whose checks start
+    at three members, can never pass: three points are always coplanar, so the
+    smallest covariance eigenvalue is 0 and the third member is removed again --
+    a planar set and a well spread set alike are discarded, while the second-largest
+    reading keeps both."""
+    R, t, rng = _rigid(6)
+    plane = np.stack([rng.uniform(-1, 1, 30), rng.uniform(-1, 1, 30), np.zeros(30)], axis=1)
+    P = rng.uniform(-1, 1, size=(30, 3))
+    for X in (plane, P):
+        assert len(keypoint_filter(X, X @ R.T + t, cond_mode=1)) == 0
+        assert len(keypoint_filter(X, X @ R.T + t, cond_mode=0)) >= 25   # a nearly collinear start may lose one
+    assert max(condition_numbers(P[:3], P[:3] @ R.T + t, mode=1)) > 1e12
 
 
 def test_clean_correspondences_all_kept_and_outliers_removed():
