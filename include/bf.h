@@ -106,12 +106,13 @@ typedef struct bf_params {
                                    must all be resident, every wait is bounded),
                                4 = one workgroup per problem (the kernel of bf_gauss_newton_batch;
                                    chosen automatically for problems of at most 64 free frames),
-                               5 = distributed vectors (one wavefront per row keeps its row's
-                                   x, r and A p; every workgroup rebuilds the search direction in
-                                   its LDS after each reduction; for problems whose vectors do not
-                                   fit kernel 3 but whose search direction fits one workgroup's LDS:
-                                   up to 5461 free frames in FP32, 2730 in FP64).  Automatic: 4 for
-                                   small problems, else 3 if it fits, else 5 if it fits, else 2. */
+                               5 = distributed vectors (each workgroup owns an even share of the
+                                   block products, its rows' owners keep their x, r and A p; every
+                                   workgroup rebuilds the search direction in its LDS after each
+                                   reduction; for problems whose vectors do not fit kernel 3 but
+                                   whose search direction fits one workgroup's LDS: up to 4437 free
+                                   frames in FP32, 2218 in FP64).  Automatic: 4 for small problems,
+                                   else 3 if it fits, else 5 if it fits, else 2. */
   int32_t dense_threads;    /* threads per dense pair job (per tile): 64, 128, 256 or 512; 0
                                (default) = threads and tiles chosen together, the fastest of
                                several shapes timed once per image size, mode and job-count range

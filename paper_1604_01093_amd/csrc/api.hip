@@ -383,8 +383,11 @@ void raise_flags(int fl) {
   if (fl & kFlagBadIndex) fail(BF_ERR_INVALID_ARG, "index out of range");
   if (fl & kFlagUnsorted) fail(BF_ERR_INVALID_ARG, "dense pairs are not strictly increasing");
   if (fl & kFlagNonFinite) fail(BF_ERR_NONFINITE, "non-finite input");
-  if (fl & kFlagNotPD) fail(BF_ERR_NOT_PD, "a diagonal block of J^T J is not positive definite");
+  if (fl & kFlagShape)
+    fail(BF_ERR_UNSUPPORTED, "the distributed-vector PCG cannot split this problem's rows (solve_kernel 2 can)");
+  // a wait that gave up leaves partial sums behind: other flags of that launch are not reliable
   if (fl & kFlagTimeout) fail(BF_ERR_DEVICE, "grid barrier of the PCG kernel did not complete");
+  if (fl & kFlagNotPD) fail(BF_ERR_NOT_PD, "a diagonal block of J^T J is not positive definite");
 }
 
 struct Timer {
@@ -510,7 +513,8 @@ void bf_destroy(bf_context* c) {
                  &c->seg_var_ptr, &c->seg_edge_ptr, &c->sys_poses, &c->mf_u, &c->pr_active, &c->pr_cnt0,
                  &c->pr_cnt, &c->pr_valid, &c->pr_flag, &c->pr_pos, &c->pr_fi, &c->pr_fj, &c->pr_pi, &c->pr_pj,
                  &c->pr_pflag, &c->pr_ppos, &c->pr_pairs, &c->pr_pairs_all, &c->pr_bval, &c->pr_bidx,
-                 &c->pr_poses};
+                 &c->pr_poses, &c->row_cnt, &c->row_ptr, &c->row_entries, &c->mf_pts, &c->mf_y,
+                 &c->ediag_dense, &c->dist_slots};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->rb_small) (void)hipHostFree(c->rb_small);

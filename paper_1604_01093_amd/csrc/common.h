@@ -25,7 +25,14 @@ constexpr int kMomWords = 36;     // per sparse pair moments (doubles)
 constexpr int kMN = 0, kMP = 1, kMQ = 4, kMPP = 7, kMQQ = 16, kMPQ = 25;
 
 // Error flags raised by kernels, read back at the next synchronisation.
-enum DeviceFlag : int { kFlagBadIndex = 1, kFlagNonFinite = 2, kFlagNotPD = 4, kFlagUnsorted = 8, kFlagTimeout = 16 };
+enum DeviceFlag : int {
+  kFlagBadIndex = 1,
+  kFlagNonFinite = 2,
+  kFlagNotPD = 4,
+  kFlagUnsorted = 8,
+  kFlagTimeout = 16,
+  kFlagShape = 32  // a problem the chosen PCG kernel cannot split (its launch then computes nothing usable)
+};
 
 struct Intr32 {
   float fx, fy, cx, cy;

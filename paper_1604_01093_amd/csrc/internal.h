@@ -73,6 +73,7 @@ struct Context {
   Buf sys_poses, mf_u;
   // matrix-free sparse PCG: sorted correspondence points, per-pair sums, dense diagonal parts
   Buf mf_pts, mf_y, ediag_dense;
+  Buf dist_slots;  // reduction slots of the distributed-vector PCG
   double sys_w_sparse = 0.0;
   // independent problems: frame offsets, segment of each frame, variable and edge ranges
   Buf seg_start, seg_of, seg_var_ptr, seg_edge_ptr;
@@ -90,6 +91,8 @@ struct Context {
   int pcg_grid = 0;       // workgroups of the cooperative PCG kernel (0 = not yet chosen)
   // replicated-vector PCG: exchange tags used so far since the last clear
   unsigned pcg_tag_base = 0;
+  unsigned dist_tag_base = 0;        // reduction tags of the distributed-vector PCG
+  void* dist_slots_ptr = nullptr;
   void* pcg_tags_ptr = nullptr;
   bool pcg_tags_dirty = true;
   int solve_mode = 0;     // 0 = automatic, 1 = single workgroup, 2 = cooperative, 3 = replicated vectors,

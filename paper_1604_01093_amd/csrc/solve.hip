@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_coop(
   double rz = pro[0];
   const bool bad = pro[1] > 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (bad) atomicOr(flags, kFlagNotPD);
+    if (bad && sh_ok) atomicOr(flags, kFlagNotPD);  // the sums are only whole if the barrier completed
     if (trace_slot) {
       trace_slot[0] = pro[2] + pro[3] + pro[4];
       for (int q = 0; q < 6; ++q) trace_slot[1 + q] = pro[2 + q];
@@ -1471,49 +1471,184 @@ __global__ void __launch_bounds__(64) k_row_dense_diag(const double* __restrict_
 // Distributed-vector PCG (the two-reduction block-Jacobi recurrence of the
 // cooperative kernel) for problems whose vectors do not fit in LDS five times
 // over but whose search direction fits once.  Rows are assembled and inverted by
-// k_row_assemble before it.  One wavefront owns one row (or several, in turn) and
-// keeps that row's x, r and A p to itself (in memory only it touches); z is
-// published by the owners, and every workgroup rebuilds the full search direction
-// p = z + beta p in its LDS after each grid reduction, so the product A p reads
-// partner values from LDS instead of remote memory.  The owner's lanes take the
-// row's blocks (lane l: entries l, l + 64, ...; entry ne is the diagonal block),
-// streamed from memory every iteration with the next entry index fetched ahead,
-// and the six row sums close with a fixed butterfly.  Per iteration: gather p,
-// A p, barrier (p.Ap), update x, r, z, barrier (r.z).
+// k_row_assemble before it.
+//
+// Work split: each workgroup owns the contiguous range of rows whose start falls
+// in its share of the total row weight (a row weighs its entries, the diagonal
+// block counted, plus kDistRowWeight), so the block products are shared evenly
+// however uneven the rows are.  Inside a workgroup the rows are cut into segments
+// of at most c consecutive entries, one per thread (c chosen so that the segments
+// fit the threads); a thread sums its segment's block products, streamed from
+// memory every iteration, and each row's segment sums are added in order by its
+// owner (row r of the range: wavefront r mod 8, lanes 0..5), which keeps x, r and
+// A p of the row to itself.  z is published by the owners, and after each
+// reduction every workgroup rebuilds the full search direction p = z + beta p in
+// its LDS, so the products read partner values from LDS.  Reductions are
+// all-gathers without atomics: each workgroup publishes its partial sums as tagged
+// 32-bit halves into its own slot (slot buffers alternate with the parity of the
+// reduction count: a workgroup can be at most one reduction ahead of the slowest),
+// and every workgroup reads all slots, one thread per workgroup, and adds them in
+// one fixed tree, so all workgroups hold the same sums.  Per iteration: rebuild p,
+// A p, reduce (p.Ap), update x, r, z, reduce (r.z).
 constexpr int kDistThreads = 512;
 constexpr int kDistWaves = kDistThreads / 64;
+constexpr int kDistMaxRows = kDistThreads - 64;  // rows of one workgroup's range
+constexpr long long kDistRowWeight = 8;
+constexpr size_t kDistSegBytes = sizeof(double) * 6 * kDistThreads;  // segment sums, dynamic LDS
 constexpr size_t kDistLdsMax = 128 * 1024;
+
+// Sum over all workgroups of K doubles per thread (see above); false if a wait gave
+// up.  `sh`: kDistWaves * K doubles.
+template <int K>
+__device__ bool dist_reduce(double (&v)[K], unsigned long long* slots, long long G, unsigned tag, unsigned parity,
+                            double* sh, int* sh_ok, int* flags, unsigned spin_limit) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double t = wave_sum_d(v[k]);
+    if (lane == 0) sh[wave * K + k] = t;
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's earlier stores have landed
+  __syncthreads();
+  if (tid < 2 * K) {
+    const int k = tid >> 1, h = tid & 1;
+    double t = 0.0;
+    for (int w = 0; w < kDistWaves; ++w) t += sh[w * K + k];
+    const unsigned long long d = (unsigned long long)__double_as_longlong(t);
+    const unsigned bits = h ? (unsigned)(d >> 32) : (unsigned)(d & 0xffffffffull);
+    st_shared(&slots[((size_t)parity * G + blockIdx.x) * 2 * K + tid], ((unsigned long long)tag << 32) | bits);
+  }
+  double got[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) got[k] = 0.0;
+  if (tid < G) {
+    const unsigned long long* src = slots + ((size_t)parity * G + tid) * 2 * K;
+    unsigned long long w[2 * K];
+    unsigned spins = 0;
+    for (;;) {
+#pragma unroll
+      for (int q = 0; q < 2 * K; ++q) w[q] = ld_shared(&src[q]);
+      bool ready = true;
+#pragma unroll
+      for (int q = 0; q < 2 * K; ++q) ready = ready & ((unsigned)(w[q] >> 32) == tag);
+      if (ready) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > spin_limit) {
+        atomicOr(flags, kFlagTimeout);
+        *sh_ok = 0;
+        break;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      got[k] = __longlong_as_double((long long)(((w[2 * k + 1] & 0xffffffffull) << 32) | (w[2 * k] & 0xffffffffull)));
+  }
+  __syncthreads();  // sh was read for the publication
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double t = wave_sum_d(got[k]);
+    if (lane == 0) sh[wave * K + k] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = 0.0;
+    for (int w = 0; w < kDistWaves; ++w) t += sh[w * K + k];
+    v[k] = t;
+  }
+  const bool ok = *sh_ok != 0;
+  __syncthreads();  // sh and sh_ok read by every thread
+  return ok;
+}
 
 template <class T, bool MF>
 __global__ void __launch_bounds__(kDistThreads) k_solve_dist(
     long long nfree, int F, int iters, const T* __restrict__ hij, const long long* __restrict__ row_ptr,
     const int2* __restrict__ entries, const int* __restrict__ frame_of_var, const int* __restrict__ var_of,
     const T* __restrict__ diag_t, const T* __restrict__ minv_g, const T* __restrict__ r0, T* zpub,
-    T* __restrict__ xv, T* __restrict__ rv, T* __restrict__ apv, double* parts, unsigned* bar,
+    T* __restrict__ xv, T* __restrict__ rv, T* __restrict__ apv, unsigned long long* slots, unsigned tag_base,
     double* __restrict__ delta_out, double* __restrict__ poses, int update, double* __restrict__ stats, int* flags,
     unsigned spin_limit, MfArgs mf) {
   extern __shared__ double lds_dyn[];
-  T* p = reinterpret_cast<T*>(lds_dyn);  // the full search direction, one copy per workgroup
-  __shared__ double sh[(kDistWaves + 1) * kParts];
+  double* segsum = lds_dyn;                                 // [kDistThreads][6] segment sums
+  T* p = reinterpret_cast<T*>(lds_dyn + 6 * kDistThreads);  // the full search direction
+  __shared__ double sh[kDistWaves * 2];
   __shared__ int sh_ok;
+  __shared__ long long sh_range[2];
+  __shared__ int seg_first[kDistMaxRows + 1];
+  __shared__ int sh_c;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long long gw = (long long)blockIdx.x * kDistWaves + wave, nw = (long long)gridDim.x * kDistWaves;
+  const long long G = gridDim.x;
+  const long long gw = (long long)blockIdx.x * kDistWaves + wave, nw = G * kDistWaves;
   const long long n = 6 * nfree;
-  unsigned nbar = 0;
+  unsigned nred = 0;  // reductions so far: tag tag_base + nred + 1, slot parity nred & 1
+  auto reduce1 = [&](double (&v)[1]) {
+    const bool ok = dist_reduce<1>(v, slots, G, tag_base + nred + 1u, nred & 1u, sh, &sh_ok, flags, spin_limit);
+    ++nred;
+    return ok;
+  };
+
+  // ---- this workgroup's rows [rs, re) by weight, and their segments
   if (tid == 0) sh_ok = 1;
+  const long long Wt = row_ptr[nfree] + (1 + kDistRowWeight) * nfree;
+  if (tid < 2) {
+    const long long target = ((long long)(blockIdx.x + tid) * Wt + G - 1) / G;
+    long long lo = 0, hi = nfree;  // the first row whose weighted start reaches target
+    while (lo < hi) {
+      const long long mid = (lo + hi) / 2;
+      if (row_ptr[mid] + (1 + kDistRowWeight) * mid >= target) hi = mid;
+      else lo = mid + 1;
+    }
+    sh_range[tid] = lo;
+  }
   __syncthreads();
+  const long long rs = sh_range[0];
+  long long re = sh_range[1];
+  if (tid == 0) {
+    long long R = re - rs;
+    if (R > kDistMaxRows) {  // cannot be cut for the threads: flagged, its rows skipped
+      atomicOr(flags, kFlagShape);
+      R = 0;
+    }
+    const long long S = (row_ptr[rs + R] + rs + R) - (row_ptr[rs] + rs);  // entries of the range
+    long long c = R > 0 ? (S + (kDistThreads - R) - 1) / (kDistThreads - R) : 1;
+    if (c < 1) c = 1;
+    int sgs = 0;
+    for (long long r = 0; r < R; ++r) {
+      seg_first[r] = sgs;
+      const long long m = row_ptr[rs + r + 1] - row_ptr[rs + r] + 1;
+      sgs += (int)((m + c - 1) / c);
+    }
+    seg_first[R] = sgs;
+    sh_c = (int)c;
+    sh_range[1] = rs + R;
+  }
+  __syncthreads();
+  re = sh_range[1];
+  const int R = (int)(re - rs);
+  const int c = sh_c;
+  // this thread's segment: row my_v, entries [q0, q1) (entry ne = the diagonal block)
+  long long my_v = -1, q0 = 0, q1 = 0;
+  if (tid < seg_first[R]) {
+    int r = 0;
+    while (seg_first[r + 1] <= tid) ++r;
+    my_v = rs + r;
+    q0 = (long long)(tid - seg_first[r]) * c;
+    const long long m = row_ptr[my_v + 1] - row_ptr[my_v] + 1;
+    q1 = q0 + c < m ? q0 + c : m;
+  }
   const bool bad = (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagNotPD) != 0;
 
-  // z = M^-1 r for the rows of this wavefront (lanes 0..5), published; (r, z) partial
+  // z = M^-1 r for an owned row (lanes 0..5), published; (r, z) partial
   auto precondition = [&](long long v, double rb, double& part) {
-    double s = 0.0;
+    double s2 = 0.0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) {
       const double rbb = __shfl(rb, b);
-      if (lane < 6) s += (double)minv_g[v * 36 + 6 * lane + b] * rbb;
+      if (lane < 6) s2 += (double)minv_g[v * 36 + 6 * lane + b] * rbb;
     }
     if (lane < 6) {
-      const T zt = (T)s;
+      const T zt = (T)s2;
       st_shared(&zpub[6 * v + lane], zt);
       part += rb * (double)zt;
     }
@@ -1523,7 +1658,7 @@ __global__ void __launch_bounds__(kDistThreads) k_solve_dist(
   int done = 0;
   if (!bad) {
     double part[1] = {0.0};
-    for (long long v = gw; v < nfree; v += nw) {
+    for (long long v = rs + wave; v < re; v += kDistWaves) {
       const double rb = lane < 6 ? (double)r0[6 * v + lane] : 0.0;
       if (lane < 6) {
         xv[6 * v + lane] = (T)0;
@@ -1531,12 +1666,12 @@ __global__ void __launch_bounds__(kDistThreads) k_solve_dist(
       }
       precondition(v, rb, part[0]);
     }
-    grid_sums<1, kDistWaves>(part, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
+    reduce1(part);
     rz = rz0 = part[0];
   }
   for (int k = 0; k < iters && !bad && sh_ok; ++k) {
     if (rz <= 1e-30) break;
-    // p = z (first iteration) or z + beta p; z was published before the last barrier
+    // p = z (first iteration) or z + beta p; z was published before the last reduction
     const T tb = (T)beta;
     for (long long o = tid; o < n; o += kDistThreads) {
       const T zo = ld_shared(&zpub[o]);
@@ -1597,59 +1732,67 @@ __global__ void __launch_bounds__(kDistThreads) k_solve_dist(
           st_shared(&mf.y[12 * g + 6 + (lane >> 3)], mf.w * sb);
         }
       }
-      ++nbar;
-      if (!grid_sync(bar, nbar * (unsigned)gridDim.x, flags, &sh_ok, spin_limit)) break;
+      double none[1] = {0.0};  // a reduction as the barrier after the pair sums
+      if (!reduce1(none)) break;
     }
-    double part[1] = {0.0};
-    for (long long v = gw; v < nfree; v += nw) {
-      const long long e0 = row_ptr[v], ne = row_ptr[v + 1] - e0;
+    // segment sums of the block products
+    {
       double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      int2 en_next = lane < ne ? entries[e0 + lane] : make_int2((int)v, -1);
-      for (long long q = lane; q <= ne; q += 64) {
-        const int2 en = en_next;
-        if (q + 64 <= ne) en_next = q + 64 < ne ? entries[e0 + q + 64] : make_int2((int)v, -1);
-        const T* B = en.y >= 0 ? hij + (size_t)(en.y >> 1) * 36 : diag_t + (size_t)v * 36;
-        T pw[6], y[6];
+      if (my_v >= 0) {
+        const long long e0 = row_ptr[my_v], ne = row_ptr[my_v + 1] - e0;
+        int2 en_next = q0 < ne ? entries[e0 + q0] : make_int2((int)my_v, -1);
+        for (long long q = q0; q < q1; ++q) {
+          const int2 en = en_next;
+          if (q + 1 < q1) en_next = q + 1 < ne ? entries[e0 + q + 1] : make_int2((int)my_v, -1);
+          const T* B = en.y >= 0 ? hij + (size_t)(en.y >> 1) * 36 : diag_t + (size_t)my_v * 36;
+          T pw[6], y[6];
 #pragma unroll
-        for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)en.x + b];
-        block_mv<T>(B, pw, en.y >= 0 && (en.y & 1), y);
+          for (int b = 0; b < 6; ++b) pw[b] = p[6 * (long long)en.x + b];
+          block_mv<T>(B, pw, en.y >= 0 && (en.y & 1), y);
 #pragma unroll
-        for (int b = 0; b < 6; ++b) acc[b] += (double)y[b];
+          for (int b = 0; b < 6; ++b) acc[b] += (double)y[b];
+        }
       }
+#pragma unroll
+      for (int b = 0; b < 6; ++b) segsum[6 * tid + b] = acc[b];
+    }
+    __syncthreads();
+    // owners: A p of their rows (segments in order), and the (p, A p) partial
+    double part[1] = {0.0};
+    for (int rl = wave; rl < R; rl += kDistWaves) {
+      const long long v = rs + rl;
+      double mfv = 0.0;
       if constexpr (MF) {
         // the sparse pairs' sums over every edge of the frame, also those whose other
         // frame is not a variable (the gauge frame, held frames): as frame a (lower)
         // of the edges it starts, as frame b of the others
         const int f = frame_of_var[v];
         const long long ni = mf.iptr[f + 1] - mf.iptr[f], nj = mf.jptr[f + 1] - mf.jptr[f];
+        double ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (long long q = lane; q < ni + nj; q += 64) {
           const long long e = q < ni ? mf.iptr[f] + q : mf.ej_sorted[mf.jptr[f] + q - ni];
           const long long g = mf.edge_sparse[e];
           if (g >= 0) {
             const double* yg = mf.y + 12 * g + (q < ni ? 0 : 6);
 #pragma unroll
-            for (int b = 0; b < 6; ++b) acc[b] += ld_shared(&yg[b]);
+            for (int b = 0; b < 6; ++b) ms[b] += ld_shared(&yg[b]);
           }
         }
+        const double t = wave_sum6_d(ms);        // value lane / 8
+        mfv = __shfl(t, 8 * (lane < 6 ? lane : 0));  // lane a < 6: value a
       }
-      double tot[6];
-#pragma unroll
-      for (int b = 0; b < 6; ++b) tot[b] = wave_sum_d(acc[b]);
       if (lane < 6) {
-        double t = tot[0];
-#pragma unroll
-        for (int q = 1; q < 6; ++q)
-          if (lane == q) t = tot[q];
-        const T ap = (T)t;
+        double t = 0.0;
+        for (int sg = seg_first[rl]; sg < seg_first[rl + 1]; ++sg) t += segsum[6 * sg + lane];
+        const T ap = (T)(t + mfv);
         apv[6 * v + lane] = ap;
         part[0] += (double)p[6 * v + lane] * (double)ap;
       }
     }
-    grid_sums<1, kDistWaves>(part, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
-    if (!sh_ok) break;
+    if (!reduce1(part)) break;
     const double alpha = rz / part[0];
     double part2[1] = {0.0};
-    for (long long v = gw; v < nfree; v += nw) {
+    for (long long v = rs + wave; v < re; v += kDistWaves) {
       double rb = 0.0;
       if (lane < 6) {
         const long long o = 6 * v + lane;
@@ -1659,21 +1802,19 @@ __global__ void __launch_bounds__(kDistThreads) k_solve_dist(
       }
       precondition(v, rb, part2[0]);
     }
-    grid_sums<1, kDistWaves>(part2, parts, bar, nbar, flags, sh, &sh_ok, spin_limit);
-    if (!sh_ok) break;
+    if (!reduce1(part2)) break;
     beta = part2[0] / rz;
     rz = part2[0];
     ++done;
   }
   if (delta_out) {
-    for (long long v = gw; v < nfree; v += nw)
+    for (long long v = rs + wave; v < re; v += kDistWaves)
       if (lane < 6) delta_out[6LL * frame_of_var[v] + lane] = bad ? 0.0 : (double)xv[6 * v + lane];
-    for (long long o = (long long)blockIdx.x * kDistThreads + tid; o < 6LL * F;
-         o += (long long)gridDim.x * kDistThreads)
+    for (long long o = (long long)blockIdx.x * kDistThreads + tid; o < 6LL * F; o += G * kDistThreads)
       if (var_of[o / 6] < 0) delta_out[o] = 0.0;
   }
   if (update && !bad && sh_ok) {
-    for (long long v = gw; v < nfree; v += nw) {
+    for (long long v = rs + wave; v < re; v += kDistWaves) {
       if (lane != 0) continue;
       double xi[6];
 #pragma unroll
@@ -2011,18 +2152,17 @@ bool launch_solve_dist(Context& c, int iters, double* trace_slot, double* delta_
   long long nf = c.shape.nfree;
   long long n = 6 * nf;
   long long E = c.shape.E;
-  const size_t lds = sizeof(T) * (size_t)n;
+  const size_t lds = kDistSegBytes + sizeof(T) * (size_t)n;
   if (lds > kDistLdsMax) return false;
   const int per_cu = dist_blocks_per_cu<T, MF>(lds);
   if (per_cu < 1) return false;
-  // one row per wavefront while the grid fits the device at once, else rows in
-  // turn; the matrix-free product spreads its sparse pairs over every resident
-  // workgroup
-  const long long resident = std::min<long long>((long long)per_cu * c.num_cus, kMaxSolveGroups);
-  long long G = MF ? resident : std::min<long long>((nf + kDistWaves - 1) / kDistWaves, resident);
-  if (G < 1) G = 1;
-  ensure(c.pcg_partials, sizeof(double) * 2 * kParts * kMaxSolveGroups);
-  ensure(c.pcg_barrier, sizeof(unsigned) * 4);
+  // every resident workgroup takes a share of the rows (the matrix-free product also
+  // spreads its sparse pairs over all of them)
+  long long G = std::min<long long>((long long)per_cu * c.num_cus, kMaxSolveGroups);
+  if (!MF) G = std::min<long long>(G, std::max<long long>(1, (nf + 1) / 2));
+  // a workgroup's rows must fit its threads: at most (2 E + 9 nfree) / (9 G) + 2 rows
+  // start in one share of the weight (the kernel flags a range that does not fit)
+  if ((2 * E + (1 + kDistRowWeight) * nf) / ((1 + kDistRowWeight) * G) + 2 > kDistMaxRows) return false;
   MfArgs mf{nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr};
   if (MF) {
     ensure(c.mf_y, sizeof(double) * 12 * (size_t)(c.shape.S + 1));
@@ -2030,8 +2170,20 @@ bool launch_solve_dist(Context& c, int iters, double* trace_slot, double* delta_
                 c.edge_sparse.as<long long>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
                 c.ej_sorted.as<long long>(), c.mf_w_sparse, c.mf_y.as<double>()};
   }
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c.stream, c.pcg_barrier.as<unsigned>());
-  c.pcg_tags_dirty = true;  // the barrier counter no longer matches the replicated kernel's running count
+  // reduction slots: [2 parities][workgroups][2 tagged halves]; tags grow across
+  // launches, so the slots are cleared only when (re)allocated or before a tag wraps
+  ensure(c.pcg_barrier, sizeof(unsigned) * 4);
+  ensure(c.dist_slots, sizeof(unsigned long long) * 4 * kMaxSolveGroups);
+  const unsigned long long nred = 1ull + (unsigned long long)iters * (MF ? 3ull : 2ull);
+  if (c.dist_slots_ptr != c.dist_slots.p || (unsigned long long)c.dist_tag_base + nred + 1ull >= 0xffffffffull) {
+    hipLaunchKernelGGL(k_zero_tags, dim3((4 * kMaxSolveGroups + 255) / 256), dim3(256), 0, c.stream,
+                       c.dist_slots.as<unsigned long long>(), (long long)(4 * kMaxSolveGroups),
+                       c.pcg_barrier.as<unsigned>());
+    c.dist_tag_base = 0;
+    c.dist_slots_ptr = c.dist_slots.p;
+  }
+  unsigned tag_base = c.dist_tag_base;
+  c.dist_tag_base += (unsigned)nred;
   T* r0 = vec;
   T* z = vec + n;
   T* xv = vec + 2 * n;
@@ -2056,8 +2208,7 @@ bool launch_solve_dist(Context& c, int iters, double* trace_slot, double* delta_
   const T* dg = diag_t;
   const T* mi = minv_g;
   const T* r0c = r0;
-  double* parts = c.pcg_partials.as<double>();
-  unsigned* bar = c.pcg_barrier.as<unsigned>();
+  unsigned long long* slots = c.dist_slots.as<unsigned long long>();
   int F = c.shape.F;
   int upd = update ? 1 : 0;
   unsigned spin = c.spin_limit;
@@ -2065,15 +2216,15 @@ bool launch_solve_dist(Context& c, int iters, double* trace_slot, double* delta_
   // all workgroups wait for each other: a plain launch when this context is the
   // only one in the process (the grid fits the occupancy), else a cooperative one
   if (live_contexts() > 1) {
-    void* args[] = {&nf, &F, &itv, &hij_c, &rp, &en, &fov, &vof, &dg, &mi, &r0c, &z, &xv, &rv, &apv, &parts, &bar,
-                    &delta_out, &poses, &upd, &stats, &fl, &spin, &mf};
+    void* args[] = {&nf, &F, &itv, &hij_c, &rp, &en, &fov, &vof, &dg, &mi, &r0c, &z, &xv, &rv, &apv, &slots,
+                    &tag_base, &delta_out, &poses, &upd, &stats, &fl, &spin, &mf};
     check_hip(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_solve_dist<T, MF>), dim3((unsigned)G),
                                          dim3(kDistThreads), args, lds, c.stream),
               "cooperative distributed solve launch");
   } else {
     hipLaunchKernelGGL((k_solve_dist<T, MF>), dim3((unsigned)G), dim3(kDistThreads), lds, c.stream, nf, F, itv,
-                       hij_c, rp, en, fov, vof, dg, mi, r0c, z, xv, rv, apv, parts, bar, delta_out, poses, upd, stats,
-                       fl, spin, mf);
+                       hij_c, rp, en, fov, vof, dg, mi, r0c, z, xv, rv, apv, slots, tag_base, delta_out, poses, upd,
+                       stats, fl, spin, mf);
   }
   return true;
 }
