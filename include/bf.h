@@ -98,7 +98,10 @@ typedef struct bf_params {
                                2 = FP64 values and sums (association decisions are FP32 in
                                every mode, so the masks do not depend on this choice) */
   int32_t pcg_storage;      /* PCG matrix and vectors: 0 = FP32 (dots and alpha/beta in FP64), 1 = FP64 */
-  int32_t timing;           /* 1: record HIP events per phase for bf_last_timings() */
+  int32_t timing;           /* HIP events for bf_last_timings(): 0 none, 1 every phase, 2 only the
+                               dense pair-job launches and the whole call (every event recorded
+                               on the stream leaves the GPU idle for a few microseconds: level 1
+                               costs about 6 % of a 200-keyframe solve) */
   int32_t solve_kernel;     /* PCG kernel: 0 = automatic, 1 = single workgroup (vectors in LDS),
                                2 = cooperative grid with owner-computed vectors (any size),
                                3 = replicated vectors (vectors in LDS of every workgroup; rows
@@ -448,8 +451,17 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* frames, const 
 /* Microseconds spent in each phase of the last bf_gauss_newton() call run with
  * params->timing = 1, measured with HIP events on the context's stream (host out,
  * [8]): setup, dense pair jobs (sum over iterations), edge blocks, assembly,
- * PCG + update, final energy, total, and the number of dense pair-job launches. */
+ * PCG + update, final energy, total, and the number of dense pair-job launches.
+ * With params->timing = 2 only the dense pair jobs, the total and the launch count
+ * are measured (the other phases read 0). */
 bf_status bf_last_timings(const bf_context* ctx, double* out_us);
+
+/* Launch shape of this context's last dense pair-job launch with Jacobians and of
+ * its last one without (the energy at the returned poses), as the caller fixed it
+ * (params->dense_threads, params->dense_tiles) or the timing chose it (host out,
+ * [4]): threads per workgroup, tiles per job, then the same for the energy-only
+ * launch; zeros before any launch. */
+bf_status bf_dense_shape(const bf_context* ctx, int32_t* out_shape);
 
 /* Number of times this context has captured the Gauss-Newton loop into a HIP
  * graph (params->graph = 1); a call that replays the captured loop leaves it

@@ -108,6 +108,7 @@ _SIGS = {
     "bf_system_matvec": (c_int, [c_void_p, c_void_p, POINTER(bf_corrs), c_void_p, c_void_p, c_int32,
                                  POINTER(c_double)]),
     "bf_last_timings": (c_int, [c_void_p, POINTER(c_double)]),
+    "bf_dense_shape": (c_int, [c_void_p, POINTER(c_int32)]),
     "bf_graph_captures": (ctypes.c_int64, [c_void_p]),
 }
 
@@ -224,6 +225,13 @@ class Context:
         keys = ["setup_us", "dense_us", "edges_us", "assemble_us", "pcg_us", "final_us", "total_us",
                 "dense_launches"]
         return dict(zip(keys, list(out)))
+
+    def dense_shape(self):
+        """(threads, tiles) of the last dense launch with Jacobians and of the last
+        energy-only one."""
+        out = (c_int32 * 4)()
+        self._check(self.lib.bf_dense_shape(self.h, out))
+        return {"jacobians": (out[0], out[1]), "energy": (out[2], out[3])}
 
     def graph_captures(self):
         """How often this context has captured the Gauss-Newton loop into a graph."""

@@ -220,6 +220,7 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
       !isfinite(prm->w_sparse) || !isfinite(prm->w_dense) || !isfinite(prm->w_geo) || !isfinite(prm->w_photo))
     fail(BF_ERR_INVALID_ARG, "weights must be finite and >= 0");
   if (prm->accumulate < 0 || prm->accumulate > 2) fail(BF_ERR_INVALID_ARG, "accumulate must be 0, 1 or 2");
+  if (prm->timing < 0 || prm->timing > 2) fail(BF_ERR_INVALID_ARG, "timing must be 0, 1 or 2");
   if (prm->pcg_storage != 0 && prm->pcg_storage != 1) fail(BF_ERR_INVALID_ARG, "pcg_storage must be 0 or 1");
   if (prm->solve_kernel < 0 || prm->solve_kernel > 5) fail(BF_ERR_INVALID_ARG, "solve_kernel must be 0..5");
   if (prm->preconditioner != 0 && prm->preconditioner != 1) fail(BF_ERR_INVALID_ARG, "preconditioner must be 0 or 1");
@@ -390,12 +391,18 @@ void raise_flags(int fl) {
   if (fl & kFlagNotPD) fail(BF_ERR_NOT_PD, "a diagonal block of J^T J is not positive definite");
 }
 
+// HIP events on the context's stream.  Level 1 marks every phase; level 2 only the
+// dense launches and the whole call (each recorded event leaves the GPU idle for a
+// few microseconds, about 6 % of a 200-keyframe solve at level 1).
 struct Timer {
   bf_context* ctx;
   bool on;
+  int level;
   std::vector<std::pair<int, int>> spans[6];
   int used = 0;
-  Timer(bf_context* c, bool enable) : ctx(c), on(enable) {}
+  Timer(bf_context* c, int lvl) : ctx(c), on(lvl != 0), level(lvl) {}
+  // a mark of the phases beyond the dense launches (level 1 only)
+  int mark_phase() { return level == 1 ? mark() : -1; }
   int mark() {
     if (!on) return -1;
     if (used >= (int)ctx->pool.size()) {
@@ -407,7 +414,7 @@ struct Timer {
     return used++;
   }
   void span(int slot, int a, int b) {
-    if (on) spans[slot].push_back({a, b});
+    if (on && a >= 0 && b >= 0) spans[slot].push_back({a, b});
   }
   void finish(double* out) {
     for (int k = 0; k < 8; ++k) out[k] = 0.0;
@@ -514,7 +521,7 @@ void bf_destroy(bf_context* c) {
                  &c->pr_cnt, &c->pr_valid, &c->pr_flag, &c->pr_pos, &c->pr_fi, &c->pr_fj, &c->pr_pi, &c->pr_pj,
                  &c->pr_pflag, &c->pr_ppos, &c->pr_pairs, &c->pr_pairs_all, &c->pr_bval, &c->pr_bidx,
                  &c->pr_poses, &c->row_cnt, &c->row_ptr, &c->row_entries, &c->mf_pts, &c->mf_y,
-                 &c->ediag_dense, &c->dist_slots};
+                 &c->ediag_dense, &c->dist_slots, &c->energy_parts};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->rb_small) (void)hipHostFree(c->rb_small);
@@ -766,6 +773,7 @@ void enqueue_loop(Context& c, const bf_intrinsics* in, const bf_params* prm, con
   const int nseg = c.shape.nseg;
   double* poses = c.poses_work.as<double>();
   auto mark = [&] { return tm ? tm->mark() : -1; };
+  auto mark_phase = [&] { return tm ? tm->mark_phase() : -1; };
   hipLaunchKernelGGL(k_copy_d, dim3((16 * F + 255) / 256), dim3(256), 0, c.stream, init_poses, poses, 16 * F);
   for (int k = 0; k < prm->num_gn; ++k) {
     double wd = dense_weight(*prm, k);
@@ -774,24 +782,24 @@ void enqueue_loop(Context& c, const bf_intrinsics* in, const bf_params* prm, con
     launch_dense(c, *in, poses, *prm, wd, true);
     int b = mark();
     launch_edge_blocks(c, poses, *prm, true);
-    int d = mark();
+    int d = mark_phase();
     if (c.shape.nfree > 0) launch_solve(c, prm->num_pcg, slot, nullptr, poses, nullptr, true, prm->sparse_matrix_free);
     else launch_energy(c, slot);
-    int f = mark();
+    int f = mark_phase();
     if (tm) {
       tm->span(1, a, b);
       tm->span(2, b, d);
       tm->span(4, d, f);
     }
   }
-  int g0 = mark();
+  int g0 = mark_phase();
   double wd = dense_weight(*prm, prm->num_gn > 0 ? prm->num_gn - 1 : 0);
   launch_dense(c, *in, poses, *prm, wd, false);
   launch_edge_blocks(c, poses, *prm, false);
   launch_energy(c, c.energy.as<double>());
   hipLaunchKernelGGL(k_copy_if_ok, dim3((16 * F + 255) / 256), dim3(256), 0, c.stream, poses, out_poses, 16 * F,
                      c.flags.as<int>());
-  int g1 = mark();
+  int g1 = mark_phase();
   if (tm) tm->span(5, g0, g1);
 }
 
@@ -880,7 +888,7 @@ void run_gauss_newton(bf_context* ctx, const bf_intrinsics* in, const bf_params*
   const int F = c.shape.F;
   const int nseg = c.shape.nseg;
   ensure(c.poses_work, sizeof(double) * 16 * F);
-  int t_setup = tm.mark();
+  int t_setup = tm.mark_phase();
   tm.span(0, t_start, t_setup);
   if (allow_graph && prm->graph) launch_loop_graph(c, in, prm, init_poses, out_poses);
   else enqueue_loop(c, in, prm, init_poses, out_poses, &tm);
@@ -922,7 +930,7 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* fr, const bf_intrins
     validate_problem(co, pairs, init_poses);
     if (!out_poses || !out_energy) fail(BF_ERR_INVALID_ARG, "null out_poses or out_energy");
     Context& c = *ctx;
-    Timer tm(ctx, prm->timing != 0);
+    Timer tm(ctx, prm->timing);
     int t_start = tm.mark();
     ensure(c.flags, sizeof(int));
     check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
@@ -986,7 +994,7 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* fr, const bf_i
       fail(BF_ERR_UNSUPPORTED, "a batch is solved by the per-problem kernel (solve_kernel 0 or 4)");
     if (prm->sparse_matrix_free) fail(BF_ERR_UNSUPPORTED, "a batch uses assembled sparse blocks (sparse_matrix_free = 0)");
     Context& c = *ctx;
-    Timer tm(ctx, prm->timing != 0);
+    Timer tm(ctx, prm->timing);
     int t_start = tm.mark();
     ensure(c.flags, sizeof(int));
     check_hip(hipMemsetAsync(c.flags.p, 0, sizeof(int), c.stream), "memset flags");
@@ -1162,6 +1170,12 @@ int64_t bf_graph_captures(const bf_context* ctx) { return ctx ? ctx->gn_captures
 bf_status bf_last_timings(const bf_context* ctx, double* out_us) {
   if (!ctx || !out_us) return BF_ERR_INVALID_ARG;
   for (int k = 0; k < 8; ++k) out_us[k] = ctx->timings[k];
+  return BF_OK;
+}
+
+bf_status bf_dense_shape(const bf_context* ctx, int32_t* out_shape) {
+  if (!ctx || !out_shape) return BF_ERR_INVALID_ARG;
+  for (int k = 0; k < 4; ++k) out_shape[k] = ctx->dense_shape_last[k];
   return BF_OK;
 }
 

@@ -506,6 +506,8 @@ void launch_any(Context& c, const bf_intrinsics& in, const double* poses, const 
                 bool jac, int nt, int tiles, unsigned* masks = nullptr) {
   ensure_records(c, tiles);
   c.dense_tiles = tiles;
+  c.dense_shape_last[jac ? 0 : 2] = nt;  // the launch shape for bf_dense_shape
+  c.dense_shape_last[jac ? 1 : 3] = tiles;
   const int mode = prm.accumulate;
   if (jac) {
     if (mode == 2) launch_mode<2, true>(c, in, poses, prm, wd, nt, tiles, masks);

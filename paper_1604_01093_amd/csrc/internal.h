@@ -51,6 +51,7 @@ struct Context {
   unsigned spin_limit = 1u << 26;  // polls before a PCG kernel's wait for other workgroups gives up
   int dense_tiles = 1;      // tiles per dense pair job of the last dense launch (records per job)
   double mf_w_sparse = 0.0; // sparse weight of the matrix-free sparse PCG product
+  int dense_shape_last[4] = {0, 0, 0, 0};  // threads, tiles of the last dense launch with / without Jacobians
   double timings[8] = {0};
 
   // frames
@@ -74,6 +75,7 @@ struct Context {
   // matrix-free sparse PCG: sorted correspondence points, per-pair sums, dense diagonal parts
   Buf mf_pts, mf_y, ediag_dense;
   Buf dist_slots;  // reduction slots of the distributed-vector PCG
+  Buf energy_parts;  // partial energy sums of a large problem
   double sys_w_sparse = 0.0;
   // independent problems: frame offsets, segment of each frame, variable and edge ranges
   Buf seg_start, seg_of, seg_var_ptr, seg_edge_ptr;
@@ -159,6 +161,8 @@ void launch_mf_points(Context& c, const bf_corrs* co);
 void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
                   bool update_poses, bool sparse_matrix_free = false);
 void launch_energy(Context& c, double* dst8);
+// The energy words of one problem with many edges, summed on several workgroups.
+void launch_energy_split(Context& c, double* dst8);
 // Whether the PCG of the current structure runs in the per-problem kernel (no state
 // carried between launches, so it can be captured in a graph); prepare_solve()
 // makes the one-time kernel attribute settings that capture must not make.

@@ -1877,6 +1877,53 @@ __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ eb,
   }
 }
 
+// Energy sums of a large single problem on several workgroups: workgroup q sums a
+// contiguous range of edges with the tree of k_energy into parts[8q ..], then one
+// workgroup adds the parts (one per thread, the same tree).  A fixed order for a
+// given edge count; one workgroup over 225k edges took 0.6 ms.
+constexpr long long kEnergySplit = 32768;  // edges above which the split is used
+constexpr int kEnergyMaxParts = 256;
+
+__global__ void __launch_bounds__(256) k_energy_parts(const double* __restrict__ eb, long long E, long long chunk,
+                                                      double* __restrict__ parts) {
+  __shared__ double sh6[6][256];
+  const int tid = threadIdx.x;
+  const long long e0 = (long long)blockIdx.x * chunk, e1 = e0 + chunk < E ? e0 + chunk : E;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long long e = e0 + tid; e < e1; e += 256)
+    for (int k = 0; k < 6; ++k) acc[k] += eb[(size_t)e * kEdgeWords + kEEs + k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sh6[k][tid] = acc[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sh6[k][tid] += sh6[k][tid + o];
+    __syncthreads();
+  }
+  if (tid < 6) parts[8 * (size_t)blockIdx.x + tid] = sh6[tid][0];
+}
+
+__global__ void __launch_bounds__(256) k_energy_final(const double* __restrict__ parts, int nparts,
+                                                      double* __restrict__ dst) {
+  __shared__ double sh6[6][256];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sh6[k][tid] = tid < nparts ? parts[8 * (size_t)tid + k] : 0.0;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sh6[k][tid] += sh6[k][tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    dst[0] = sh6[0][0] + sh6[1][0] + sh6[2][0];
+    for (int k = 0; k < 6; ++k) dst[1 + k] = sh6[k][0];
+    dst[7] = 0.0;
+  }
+}
+
 // Full H and g for export: every frame's diagonal block and gradient, every edge's
 // off-diagonal block and its transpose.
 __global__ void k_export_diag(const double* __restrict__ eb, const long long* __restrict__ iptr,
@@ -2085,6 +2132,10 @@ bool launch_solve_rep(Context& c, int iters, double* trace_slot, double* delta_o
   T* r0 = vec;
   const int F = c.shape.F;
   int* fl = c.flags.as<int>();
+  if (trace_slot && E > kEnergySplit) {  // the trace energy on several workgroups
+    launch_energy_split(c, trace_slot);
+    trace_slot = nullptr;
+  }
   hipLaunchKernelGGL(k_row_assemble<T>, dim3((unsigned)(nf + 1)), dim3(kAsmThreads), 0, c.stream, nf, E,
                      c.eblocks.as<double>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
                      c.ej_sorted.as<long long>(), c.frame_of_var.as<int>(), c.precond, diag_t, minv_g, r0, trace_slot,
@@ -2190,6 +2241,10 @@ bool launch_solve_dist(Context& c, int iters, double* trace_slot, double* delta_
   T* rv = vec + 3 * n;
   T* apv = vec + 4 * n;
   int* fl = c.flags.as<int>();
+  if (trace_slot && E > kEnergySplit) {  // the trace energy on several workgroups
+    launch_energy_split(c, trace_slot);
+    trace_slot = nullptr;
+  }
   hipLaunchKernelGGL(k_row_assemble<T>, dim3((unsigned)(nf + 1)), dim3(kAsmThreads), 0, c.stream, nf, E,
                      c.eblocks.as<double>(), c.iptr.as<long long>(), c.jptr.as<long long>(),
                      c.ej_sorted.as<long long>(), c.frame_of_var.as<int>(), c.precond, diag_t, minv_g, r0, trace_slot,
@@ -2328,7 +2383,23 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
                              c.minv32.as<float>(), c.hij32.as<float>(), c.pcg_vec.as<float>());
 }
 
+// The eight energy words of a single problem with more than kEnergySplit edges.
+void launch_energy_split(Context& c, double* dst8) {
+  const long long E = c.shape.E;
+  long long chunk = (E + kEnergyMaxParts - 1) / kEnergyMaxParts;
+  if (chunk < 2048) chunk = 2048;
+  const int nparts = (int)((E + chunk - 1) / chunk);
+  ensure(c.energy_parts, sizeof(double) * 8 * kEnergyMaxParts);
+  hipLaunchKernelGGL(k_energy_parts, dim3((unsigned)nparts), dim3(256), 0, c.stream, c.eblocks.as<double>(), E, chunk,
+                     c.energy_parts.as<double>());
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, c.stream, c.energy_parts.as<double>(), nparts, dst8);
+}
+
 void launch_energy(Context& c, double* dst8) {
+  if (c.shape.nseg == 1 && c.shape.E > kEnergySplit) {
+    launch_energy_split(c, dst8);
+    return;
+  }
   hipLaunchKernelGGL(k_energy, dim3(c.shape.nseg), dim3(256), 0, c.stream, c.eblocks.as<double>(),
                      c.seg_edge_ptr.as<long long>(), dst8);
 }

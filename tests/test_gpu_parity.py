@@ -365,6 +365,27 @@ def test_matrix_free_sparse_refusals(ctx, chunk):
     assert e.value.status == bf.BF_ERR_INVALID_ARG
 
 
+def test_timing_levels(ctx, chunk):
+    """Timing events change no result: levels 0, 1 and 2 give bitwise the same
+    poses; level 1 fills every phase, level 2 only the dense launches and the total."""
+    prm = Params(num_gn=chunk.n_gn, num_pcg=chunk.n_pcg)
+    dp = device_problem(chunk)
+    init = poses_cuda(chunk.init_poses)
+    outs, tms = [], []
+    for level in (0, 1, 2):
+        outs.append(bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, timing=level, dense_threads=256))["poses"])
+        tms.append(ctx.last_timings())
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    t1, t2 = tms[1], tms[2]
+    assert all(t1[k] > 0 for k in ("setup_us", "dense_us", "edges_us", "pcg_us", "final_us", "total_us"))
+    assert t1["dense_launches"] == t2["dense_launches"] == chunk.n_gn
+    assert t2["dense_us"] > 0 and t2["total_us"] > 0
+    assert t2["setup_us"] == t2["edges_us"] == t2["pcg_us"] == t2["final_us"] == 0
+    with pytest.raises(bf.BFError) as e:
+        bf.bf_gauss_newton(ctx, dp, init, bf_params_from(prm, timing=3))
+    assert e.value.status == bf.BF_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("W,H", [(3, 3), (7, 5), (37, 23)])
 @pytest.mark.parametrize("dense_threads", [64, 256, 512])
 def test_small_and_ragged_images(ctx, W, H, dense_threads):
@@ -506,6 +527,7 @@ def test_dense_tiles(ctx, W, H, nt, tiles, accumulate):
                                 records=True, masks=True)
     tl = bf.bf_eval_residuals(ctx, dp, poses_cuda(pr.init_poses), bf_params_from(prm, dense_tiles=tiles, **kw),
                               gn_iter=1, records=True, masks=True)
+    assert ctx.dense_shape()["jacobians"] == (nt, tiles)
     assert torch.equal(base["masks"], tl["masks"])
     r0, r1 = base["records"].cpu().numpy(), tl["records"].cpu().numpy()
     assert np.array_equal(r0[:, 29:31], r1[:, 29:31])
