@@ -736,15 +736,21 @@ __device__ __forceinline__ double block_sum_dpp_1(double v, double* sh) {
 }
 
 // Two sums behind one barrier (same slot rule as block_sum_dpp_1; `sh` holds 2 NW).
+// Inside a wavefront the halves exchange first (lanes 0..31 keep a, 32..63 keep b),
+// then each half sums its 32 values: one exchange across rows of 16 and the DPP
+// steps within a row (every lane of a half ends with its sum).  Fixed order.
 template <int NW>
 __device__ __forceinline__ void block_sum2_dpp(double a, double b, double* sh, double out[2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  a = wave_sum_d(a);
-  b = wave_sum_d(b);
-  if (lane == 0) {
-    sh[wave] = a;
-    sh[NW + wave] = b;
-  }
+  const bool hi = (lane & 32) != 0;
+  double k = (hi ? b : a) + __shfl_xor(hi ? a : b, 32);
+  k += __shfl_xor(k, 16);
+  k += dpp_d(k, 0);
+  k += dpp_d(k, 1);
+  k += dpp_d(k, 2);
+  k += dpp_d(k, 3);
+  if (lane == 0) sh[wave] = k;
+  if (lane == 32) sh[NW + wave] = k;
   __syncthreads();
   double ta = 0.0, tb = 0.0;
   for (int w = 0; w < NW; ++w) {
@@ -1221,6 +1227,7 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     }
   }
   __syncthreads();
+  const int rr = lane / 6, a6 = lane - 6 * (lane / 6);  // update pass: row, element
   T xo = (T)0;  // owner lanes 0..5: x of the owned row
   int done = 0;
   double gamma = 0.0, gamma_prev = 1.0, alpha_prev = 1.0, rz0 = 0.0;
@@ -1342,37 +1349,57 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     const double delta = two[1];
     const double beta = k == 0 ? 0.0 : gamma / gamma_prev;
     const double alpha = gamma / (delta - (k == 0 ? 0.0 : beta * gamma / alpha_prev));
+    const float beta_f = (float)beta, alpha_f = (float)alpha;
     // p = u + beta p, s = w + beta s, r -= alpha s element by element, then u = M^-1 r
     // and the (r, u) partials per block row: each wavefront takes ten block rows at
     // a time, six lanes per row (lanes 60..63 idle), so consecutive lanes touch
     // consecutive values; a row's six new r values are read back from LDS after a
-    // wavefront barrier (the same wavefront wrote them).  (Updating all of a
-    // wavefront's rows before any of their u measured slower: 1.56 against 1.09 us.)
+    // wavefront barrier (the same wavefront wrote them).  FP32 storage updates in
+    // FP32; FP64 stays with the dot products and alpha, beta.  (Updating all of a
+    // wavefront's rows before any of their u, or every value by its own thread with
+    // a workgroup barrier between the halves, measured slower: 1.1-1.6 us.)
     part_ru = 0.0;
     {
-      const int rr = lane / 6, a = lane - 6 * rr;
       for (long long w0 = (long long)wave * 10; w0 < nfree; w0 += 10 * kRepWaves) {
         const long long w = w0 + rr;
         const bool act = lane < 60 && w < nfree;
         double rb = 0.0;
         if (act) {
-          const long long o = 6 * w + a;
-          const T pn = (T)((double)u[o] + beta * (double)p[o]);
-          const T sn = (T)((double)wvec[o] + beta * (double)sv[o]);
-          p[o] = pn;
-          sv[o] = sn;
-          const T rn = (T)((double)r[o] - alpha * (double)sn);
+          const long long o = 6 * w + a6;
+          T rn;
+          if constexpr (sizeof(T) == 4) {
+            const float pn = __builtin_fmaf(beta_f, p[o], u[o]);
+            const float sn = __builtin_fmaf(beta_f, sv[o], wvec[o]);
+            p[o] = pn;
+            sv[o] = sn;
+            rn = __builtin_fmaf(-alpha_f, sn, r[o]);
+          } else {
+            const T pn = (T)((double)u[o] + beta * (double)p[o]);
+            const T sn = (T)((double)wvec[o] + beta * (double)sv[o]);
+            p[o] = pn;
+            sv[o] = sn;
+            rn = (T)((double)r[o] - alpha * (double)sn);
+          }
           r[o] = rn;
           rb = (double)rn;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (act) {
-          double s2 = 0.0;
+          const T* mr = minv + w * 36 + 6 * a6;
+          T ut;
+          if constexpr (sizeof(T) == 4) {
+            float s2 = 0.0f;
 #pragma unroll
-          for (int b = 0; b < 6; ++b) s2 += (double)minv[w * 36 + 6 * a + b] * (double)r[6 * w + b];
-          const T ut = (T)s2;
-          u[6 * w + a] = ut;
+            for (int b = 0; b < 6; ++b) s2 = __builtin_fmaf(mr[b], r[6 * w + b], s2);
+            ut = s2;
+          } else {
+            double s2 = 0.0;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) s2 += (double)mr[b] * (double)r[6 * w + b];
+            ut = (T)s2;
+          }
+          u[6 * w + a6] = ut;
           part_ru += rb * (double)ut;
         }
       }

@@ -142,20 +142,26 @@ def test_sampled_masks_and_records(ctx, prob, golden, dp):
 SETTINGS = [(0, 0), (1, 1), (2, 1)]
 
 
-def test_one_step_parity_fixed_association(ctx, prob, golden, dp):
-    """At the oracle's first two iterates, with the oracle's association of that
-    iterate given to the kernels (all 220k jobs, computed in worker processes): the
+@pytest.mark.parametrize("steps", [(0, 1), (2, 3), (4, 5), (6, 7)])
+def test_one_step_parity_fixed_association(ctx, prob, golden, dp, steps):
+    """At each of the oracle's 8 iterates (two per test), with the oracle's
+    association of that iterate given to the kernels (all 220k jobs, computed in
+    worker processes): the
     increment within 1e-5 (rad, m) of the oracle's in the mixed-precision setting
-    and with FP64 values; on the all-FP32 path within twice the error that binary32
-    storage of the PCG matrix and vectors alone causes on the oracle's own system
-    (stored by make_golden.py, about 5e-5: this system is ill-conditioned), plus 1e-5."""
+    and with FP64 values.  The all-FP32 path is held at the first two iterates to
+    twice the error that binary32 storage of the PCG matrix and vectors alone
+    causes on the oracle's own system (stored by make_golden.py: 5.8e-5 and 3.3e-6,
+    this system is ill-conditioned), plus 1e-5; at the later iterates that storage
+    error falls to 3e-7..1e-5, the same size as the FP32 lane sums' own error,
+    which the storage model leaves out, so there the all-FP32 error is reported
+    and not bounded."""
     from assoc_pool import oracle_association
     from gpu_helpers import fix_association
     prm = Params(num_gn=prob.n_gn, num_pcg=prob.n_pcg)
     free = golden["free"]
     idx = (6 * free[:, None] + np.arange(6)[None, :]).ravel()
     dpp = device_problem(prob, pairs=golden["pairs"])
-    for k in range(2):
+    for k in steps:
         fixed = oracle_association(prob, golden["pairs"], golden["traj"][k], prm)
         for accumulate, pcg_storage in SETTINGS:
             p = fix_association(bf_params_from(prm, accumulate=accumulate, pcg_storage=pcg_storage), fixed)
@@ -167,7 +173,8 @@ def test_one_step_parity_fixed_association(ctx, prob, golden, dp):
             print(f"global2000 step {k} accumulate={accumulate} storage={pcg_storage}, oracle's association: "
                   f"max |d increment| {err:.2e} (bound {bound:.1e}, max |increment| "
                   f"{np.abs(golden['steps'][k]).max():.3f})", flush=True)
-            assert err < bound
+            if pcg_storage == 1 or k < 2:
+                assert err < bound
         del fixed
         torch.cuda.empty_cache()
 
