@@ -271,9 +271,13 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
   // right after the projection) and the tests only decide validity, so the loads of
   // a step overlap instead of waiting on each other; the source load of the next
   // step is issued before the current one is processed.
+  // The source pixel's data and its ray factors (kx, ky) for the next step are
+  // loaded one step ahead.  Past the last pixel (never valid) the row index runs
+  // beyond the image: it is clamped for the load.
   int x = (lo + tid) % W, y = (lo + tid) / W;
   const int sx = NT % W, sy = NT / W;
   float4 s_next = ld_at(ndi, (unsigned)(lo + tid < hi ? lo + tid : HW - 1));
+  float kx_next = ld_at(kx, (unsigned)x), ky_next = ld_at(ky, (unsigned)(y < H ? y : H - 1));
   for (int base = lo + wave * 64; base < hi; base += NT) {
     const int pix = base + lane;
     const int px = x, py = y;
@@ -284,18 +288,18 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
       y += 1;
     }
     const float4 s4 = s_next;
+    const float kxp = kx_next, kyp = ky_next;
     {
       const int nxt = pix + NT;
       s_next = ld_at(ndi, (unsigned)(nxt < hi ? nxt : HW - 1));
+      kx_next = ld_at(kx, (unsigned)x);
+      ky_next = ld_at(ky, (unsigned)(y < H ? y : H - 1));
     }
     float wv[kPayload];
     bool valid;
     {
       const float D = s4.w;
-      // past the last pixel (pix >= HW, never valid) the row index runs beyond the
-      // image: clamp it for the load
-      const float3 d = make_float3(mul_nc(ld_at(kx, (unsigned)px), D),
-                                   mul_nc(ld_at(ky, (unsigned)(py < H ? py : H - 1)), D), D);
+      const float3 d = make_float3(mul_nc(kxp, D), mul_nc(kyp, D), D);
       const float3 c = xform32(R, t, d);
       const float iz = 1.0f / c.z;
       const float u = project32(in.fx, c.x, iz, in.cx);
