@@ -313,11 +313,13 @@ __global__ void __launch_bounds__(NT) k_dense(const int* __restrict__ pairs, lon
         const float xf = floorf(u + 0.5f), yf = floorf(v + 0.5f);
         x0f = floorf(u);
         y0f = floorf(v);
-        // clamped copies for addressing (fminf/fmaxf also map NaN to the bound)
-        xh = (int)fminf(fmaxf(xf, 0.0f), fWm1);
-        yh = (int)fminf(fmaxf(yf, 0.0f), fHm1);
-        xt = (int)fminf(fmaxf(x0f, 0.0f), fWm2);
-        yt = (int)fminf(fmaxf(y0f, 0.0f), fHm2);
+        // clamped copies for addressing: the median of (value, 0, bound), one
+        // instruction; a NaN value gives 0 (the hardware's median of three with a
+        // NaN operand is the minimum of the other two)
+        xh = (int)__builtin_amdgcn_fmed3f(xf, 0.0f, fWm1);
+        yh = (int)__builtin_amdgcn_fmed3f(yf, 0.0f, fHm1);
+        xt = (int)__builtin_amdgcn_fmed3f(x0f, 0.0f, fWm2);
+        yt = (int)__builtin_amdgcn_fmed3f(y0f, 0.0f, fHm2);
         in_img = c.z > 0.0f && xf >= 0.0f && xf <= fWm1 && yf >= 0.0f && yf <= fHm1;
       } else {
         const size_t o = 2 * ((size_t)p * HW + (size_t)(pix < hi ? pix : HW - 1));

@@ -23,324 +23,292 @@ namespace bf {
 
 namespace {
 
-__device__ __forceinline__ int eps3(int a, int b, int c) {
-  // Levi-Civita symbol for indices in {0,1,2}
-  return ((a - b) * (b - c) * (c - a)) / 2;
+// Edge blocks: one wavefront per edge, four edges per workgroup.  The lanes load
+// the pair job's records (tiles summed in order) and the sparse moments into LDS;
+// then every 6x6 product and output entry is one lane's (entry (a, b) = lane
+// 6a + b), with wavefront barriers between the stages.
+constexpr int kEdgeThreads = 256;
+constexpr int kEdgeScratch = 32 + 32 + 36 * 10 + 24;  // doubles of LDS per wavefront
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ void skew(const double* v, double* S) {
-  S[0] = 0;
-  S[1] = -v[2];
-  S[2] = v[1];
-  S[3] = v[2];
-  S[4] = 0;
-  S[5] = -v[0];
-  S[6] = -v[1];
-  S[7] = v[0];
-  S[8] = 0;
+// position of (a, b), a <= b, in a record's packed upper triangle (row by row)
+__device__ __forceinline__ int packed_upper(int a, int b) { return a * (11 - a) / 2 + b; }
+
+// entry (r, c) of the cross-product matrix [v]x
+__device__ __forceinline__ double skew_at(const double* v, int r, int c) {
+  if (r == c) return 0.0;
+  const int k = 3 - r - c;  // the third index
+  const double x = v[k];
+  // [v]x = [[0, -v2, v1], [v2, 0, -v0], [-v1, v0, 0]]: +v_k where (r, c, k) is cyclic
+  return ((c - r + 3) % 3 == 1) ? -x : x;
 }
 
 template <class T>
-__global__ void __launch_bounds__(64) k_edge_blocks(const int* __restrict__ eij, long long E,
-                                                    const long long* __restrict__ edense,
-                                                    const long long* __restrict__ esparse,
-                                                    const double* __restrict__ mom, const double* __restrict__ rec,
-                                                    long long P, int bidir, int tiles,
-                                                    const double* __restrict__ poses, double w_sparse, int jac,
-                                                    double* __restrict__ eb, T* __restrict__ hij_store,
-                                                    double* __restrict__ ediag_dense) {
-  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
+__global__ void __launch_bounds__(kEdgeThreads) k_edge_blocks(const int* __restrict__ eij, long long E,
+                                                              const long long* __restrict__ edense,
+                                                              const long long* __restrict__ esparse,
+                                                              const double* __restrict__ mom,
+                                                              const double* __restrict__ rec, long long P, int bidir,
+                                                              int tiles, const double* __restrict__ poses,
+                                                              double w_sparse, int jac, double* __restrict__ eb,
+                                                              T* __restrict__ hij_store,
+                                                              double* __restrict__ ediag_dense) {
+  __shared__ double smem[kEdgeThreads / 64][kEdgeScratch];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long e = (long long)blockIdx.x * (kEdgeThreads / 64) + wave;
+  if (e >= E) return;  // whole wavefronts only: nothing below synchronises the workgroup
+  double* Fw = smem[wave];     // forward job record, tiles summed [32]
+  double* Rw = Fw + 32;        // reverse job record [32]
+  double* Mw = Rw + 32;        // sparse moments [36]
+  double* Hd = Mw + 36;        // forward job's frame-j block H_jj (full 6x6)
+  double* Hr = Hd + 36;        // reverse job's frame-i block
+  double* AD = Hr + 36;        // Ad(T_ji)
+  double* AD2 = AD + 36;       // Ad(T_ij)
+  double* Yw = AD2 + 36;       // Ad^T H_jj
+  double* Y2w = Yw + 36;       // H_ii_r Ad2
+  double* Pw = Y2w + 36;       // H_ii before symmetrising
+  double* Dw = Pw + 36;        // the dense term's H_ii before symmetrising
+  double* Zw = Dw + 36;        // Ad2^T H_ii_r Ad2
+  double* Gw = Zw + 36;        // R (row-major) [9], t [3], R^T [9], t2 = -R^T t [3]
   const int i = eij[2 * e], j = eij[2 * e + 1];
+  const long long s = esparse[e];
+  const long long d = edense[e];
+  const bool has_rev = bidir && d >= 0;
   double R[9], t[3];
   relative_pose_nc(poses + (size_t)i * 16, poses + (size_t)j * 16, R, t);
   double* out = eb + (size_t)e * kEdgeWords;
-  const long long s = esparse[e];
-  const long long d = edense[e];
 
-  double Hjj_d[36];
-  double gj_d[6];
-  for (int k = 0; k < 36; ++k) Hjj_d[k] = 0.0;
-  for (int k = 0; k < 6; ++k) gj_d[k] = 0.0;
-  double Eg = 0, Ep = 0, ng = 0, np = 0;
-  // a pair job's record is the sum of its `tiles` partial records, in tile order
-  if (d >= 0) {
-    for (int tl = 0; tl < tiles; ++tl) {
-      const double* r = rec + ((size_t)d * tiles + tl) * kRecWords;
-      if (jac) {
-        int k = 0;
-        for (int a = 0; a < 6; ++a)
-          for (int b = a; b < 6; ++b) {
-            Hjj_d[6 * a + b] += r[k];
-            ++k;
-          }
-        for (int a = 0; a < 6; ++a) gj_d[a] += r[kRecG + a];
-      }
-      Eg += r[kRecEg];
-      Ep += r[kRecEp];
-      ng += r[kRecNg];
-      np += r[kRecNp];
-    }
-    for (int a = 0; a < 6; ++a)
-      for (int b = 0; b < a; ++b) Hjj_d[6 * a + b] = Hjj_d[6 * b + a];
+  // stage 1: records (a pair job's record is the sum of its `tiles` partial
+  // records, in tile order) and moments
+  if (lane < 32) {
+    double v = 0.0;
+    if (d >= 0)
+      for (int tl = 0; tl < tiles; ++tl) v += rec[((size_t)d * tiles + tl) * kRecWords + lane];
+    Fw[lane] = v;
+  } else {
+    double v = 0.0;
+    if (has_rev)
+      for (int tl = 0; tl < tiles; ++tl) v += rec[((size_t)(P + d) * tiles + tl) * kRecWords + lane - 32];
+    Rw[lane - 32] = v;
   }
-  // the reverse job (j -> i, record P + d): its block is the one of frame i
-  double Hii_r[36], gi_r[6];
-  const bool has_rev = bidir && d >= 0;
-  for (int k = 0; k < 36; ++k) Hii_r[k] = 0.0;
-  for (int k = 0; k < 6; ++k) gi_r[k] = 0.0;
-  if (has_rev) {
-    for (int tl = 0; tl < tiles; ++tl) {
-      const double* r = rec + ((size_t)(P + d) * tiles + tl) * kRecWords;
-      if (jac) {
-        int k = 0;
-        for (int a = 0; a < 6; ++a)
-          for (int b = a; b < 6; ++b) {
-            Hii_r[6 * a + b] += r[k];
-            ++k;
-          }
-        for (int a = 0; a < 6; ++a) gi_r[a] += r[kRecG + a];
-      }
-      Eg += r[kRecEg];
-      Ep += r[kRecEp];
-      ng += r[kRecNg];
-      np += r[kRecNp];
-    }
-    for (int a = 0; a < 6; ++a)
-      for (int b = 0; b < a; ++b) Hii_r[6 * a + b] = Hii_r[6 * b + a];
+  if (lane < 36) Mw[lane] = s >= 0 ? mom[(size_t)s * kMomWords + lane] : 0.0;
+  if (lane == 0) {
+    for (int q = 0; q < 9; ++q) Gw[q] = R[q];
+    for (int q = 0; q < 3; ++q) Gw[9 + q] = t[q];
+    for (int q = 0; q < 3; ++q)
+      for (int r2 = 0; r2 < 3; ++r2) Gw[12 + 3 * q + r2] = R[3 * r2 + q];
+    for (int q = 0; q < 3; ++q) Gw[21 + q] = -(R[q] * t[0] + R[3 + q] * t[1] + R[6 + q] * t[2]);
   }
-  double Es = 0, ns = 0;
-  // sparse moments
-  double n = 0, sp[3] = {0, 0, 0}, sq[3] = {0, 0, 0}, Spp[9], Sqq[9], Spq[9];
-  for (int k = 0; k < 9; ++k) Spp[k] = Sqq[k] = Spq[k] = 0.0;
-  if (s >= 0) {
-    const double* m = mom + (size_t)s * kMomWords;
-    n = m[kMN];
-    for (int a = 0; a < 3; ++a) {
-      sp[a] = m[kMP + a];
-      sq[a] = m[kMQ + a];
+  wave_sync();
+  // energies and counts (the forward job's, then the reverse job's; the sparse
+  // term's from the moments)
+  if (lane == 63) {
+    double Es = 0, ns = 0;
+    if (s >= 0) {
+      const double* m = Mw;
+      const double n = m[kMN];
+      ns = n;
+      // E = w [tr Spp + tr Sqq + n |t|^2 + 2 t^T R sp - 2 t^T sq - 2 sum_cd R_cd Spq[d][c]]
+      double Rsp[3];
+      for (int a2 = 0; a2 < 3; ++a2)
+        Rsp[a2] = R[3 * a2] * m[kMP] + R[3 * a2 + 1] * m[kMP + 1] + R[3 * a2 + 2] * m[kMP + 2];
+      double qRp = 0.0;
+      for (int c2 = 0; c2 < 3; ++c2)
+        for (int d2 = 0; d2 < 3; ++d2) qRp += R[3 * c2 + d2] * m[kMPQ + 3 * d2 + c2];
+      const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+      const double tRsp = t[0] * Rsp[0] + t[1] * Rsp[1] + t[2] * Rsp[2];
+      const double tsq = t[0] * m[kMQ] + t[1] * m[kMQ + 1] + t[2] * m[kMQ + 2];
+      Es = w_sparse * ((m[kMPP] + m[kMPP + 4] + m[kMPP + 8]) + (m[kMQQ] + m[kMQQ + 4] + m[kMQQ + 8]) + n * tt +
+                       2.0 * tRsp - 2.0 * tsq - 2.0 * qRp);
     }
-    for (int k = 0; k < 9; ++k) {
-      Spp[k] = m[kMPP + k];
-      Sqq[k] = m[kMQQ + k];
-      Spq[k] = m[kMPQ + k];
-    }
-    ns = n;
-    // E = w [tr Spp + tr Sqq + n |t|^2 + 2 t^T R sp - 2 t^T sq - 2 sum_cd R_cd Spq[d][c]]
-    double Rsp[3];
-    for (int a = 0; a < 3; ++a) Rsp[a] = R[3 * a] * sp[0] + R[3 * a + 1] * sp[1] + R[3 * a + 2] * sp[2];
-    double qRp = 0.0;
-    for (int c2 = 0; c2 < 3; ++c2)
-      for (int d2 = 0; d2 < 3; ++d2) qRp += R[3 * c2 + d2] * Spq[3 * d2 + c2];
-    double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-    double tRsp = t[0] * Rsp[0] + t[1] * Rsp[1] + t[2] * Rsp[2];
-    double tsq = t[0] * sq[0] + t[1] * sq[1] + t[2] * sq[2];
-    Es = w_sparse * ((Spp[0] + Spp[4] + Spp[8]) + (Sqq[0] + Sqq[4] + Sqq[8]) + n * tt + 2.0 * tRsp - 2.0 * tsq -
-                     2.0 * qRp);
+    out[kEEs] = Es;
+    out[kEEg] = Fw[kRecEg] + Rw[kRecEg];
+    out[kEEp] = Fw[kRecEp] + Rw[kRecEp];
+    out[kENs] = ns;
+    out[kENg] = Fw[kRecNg] + Rw[kRecNg];
+    out[kENp] = Fw[kRecNp] + Rw[kRecNp];
   }
-  if (jac) {
-    const double w = w_sparse;
-    // H_jj
+  if (!jac) return;
+
+  const double w = w_sparse;
+  const int a = lane / 6, b = lane - 6 * (lane / 6);  // entry of lanes 0..35
+  // stage 2: full blocks from the packed records; the two adjoints
+  //   Ad(T_ji) = [[R, 0], [[t]x R, R]],  Ad(T_ij) = [[R^T, 0], [[t2]x R^T, R^T]], t2 = -R^T t
+  if (lane < 36) {
+    const int k = a <= b ? packed_upper(a, b) : packed_upper(b, a);
+    Hd[lane] = Fw[k];
+    Hr[lane] = Rw[k];
+    const double* Rg = Gw;        // R
+    const double* tg = Gw + 9;    // t
+    const double* R2g = Gw + 12;  // R^T
+    const double* t2g = Gw + 21;  // -R^T t
+    const int ra = a % 3, cb = b % 3;
+    double adv, ad2v;
+    if (a < 3) {
+      adv = b < 3 ? Rg[3 * ra + cb] : 0.0;
+      ad2v = b < 3 ? R2g[3 * ra + cb] : 0.0;
+    } else if (b < 3) {
+      adv = skew_at(tg, ra, 0) * Rg[cb] + skew_at(tg, ra, 1) * Rg[3 + cb] + skew_at(tg, ra, 2) * Rg[6 + cb];
+      ad2v = skew_at(t2g, ra, 0) * R2g[cb] + skew_at(t2g, ra, 1) * R2g[3 + cb] + skew_at(t2g, ra, 2) * R2g[6 + cb];
+    } else {
+      adv = Rg[3 * ra + cb];
+      ad2v = R2g[3 * ra + cb];
+    }
+    AD[lane] = adv;
+    AD2[lane] = ad2v;
+  }
+  wave_sync();
+  // stage 3: Y = Ad^T H_jj, Y2 = H_ii_r Ad2
+  if (lane < 36) {
+    double v = 0.0;
+    for (int k = 0; k < 6; ++k) v += AD[6 * k + a] * Hd[6 * k + b];
+    Yw[lane] = v;
+    double v2 = 0.0;
+    if (has_rev)
+      for (int k = 0; k < 6; ++k) v2 += Hr[6 * a + k] * AD2[6 * k + b];
+    Y2w[lane] = v2;
+  }
+  wave_sync();
+  // stage 4: the dense term's H_ii = Y Ad + H_ii_r and Z2 = Ad2^T Y2; the sparse
+  // H_ii (the moments: H_ii = sum A_p^T A_p with A_p = [-[p]x | I])
+  const double n = Mw[kMN];
+  if (lane < 36) {
+    double v = 0.0;
+    for (int k = 0; k < 6; ++k) v += Yw[6 * a + k] * AD[6 * k + b];
+    double z = 0.0;
+    if (has_rev)
+      for (int k = 0; k < 6; ++k) z += AD2[6 * k + a] * Y2w[6 * k + b];
+    Zw[lane] = z;
+    const double* sp = Mw + kMP;
+    const double* Spp = Mw + kMPP;
+    const int ra = a % 3, cb = b % 3;
+    const double trp = Spp[0] + Spp[4] + Spp[8];
+    double hs;
+    if (a < 3) hs = b < 3 ? w * ((a == b ? trp : 0.0) - Spp[3 * a + b]) : w * skew_at(sp, ra, cb);
+    else hs = b < 3 ? -w * skew_at(sp, ra, cb) : (ra == cb ? w * n : 0.0);
+    const double dv = v + Hr[lane];
+    Pw[lane] = hs + dv;
+    Dw[lane] = dv;
+  }
+  wave_sync();
+  // stage 5: outputs
+  if (lane < 36) {
+    const int ra = a % 3, cb = b % 3;
+    const double* sp = Mw + kMP;
+    const double* sq = Mw + kMQ;
+    const double* Sqq = Mw + kMQQ;
+    const double* Spq = Mw + kMPQ;
+    // H_jj: the forward job's block, the sparse part, then the reverse job's lifted
+    // block (symmetrised)
     {
-      double S[9];
-      skew(sq, S);
-      double trq = Sqq[0] + Sqq[4] + Sqq[8];
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-          double top = (a == b ? trq : 0.0) - Sqq[3 * a + b];
-          out[kEHjj + 6 * a + b] = Hjj_d[6 * a + b] + w * top;
-          out[kEHjj + 6 * a + (b + 3)] = Hjj_d[6 * a + b + 3] + w * S[3 * a + b];
-          out[kEHjj + 6 * (a + 3) + b] = Hjj_d[6 * (a + 3) + b] - w * S[3 * a + b];
-          out[kEHjj + 6 * (a + 3) + (b + 3)] = Hjj_d[6 * (a + 3) + b + 3] + (a == b ? w * n : 0.0);
-        }
+      const double trq = Sqq[0] + Sqq[4] + Sqq[8];
+      double v;
+      if (a < 3)
+        v = b < 3 ? Hd[lane] + w * ((a == b ? trq : 0.0) - Sqq[3 * a + b]) : Hd[lane] + w * skew_at(sq, ra, cb);
+      else v = b < 3 ? Hd[lane] - w * skew_at(sq, ra, cb) : Hd[lane] + (ra == cb ? w * n : 0.0);
+      if (has_rev) v += 0.5 * (Zw[6 * a + b] + Zw[6 * b + a]);
+      out[kEHjj + lane] = v;
     }
-    // reverse job: Ad(T_ij) = [[R^T, 0], [[t2]x R^T, R^T]] with t2 = -R^T t;
-    // H_jj += Ad2^T Hii_r Ad2 (symmetrised), H_ij -= Hii_r Ad2, g_j -= Ad2^T gi_r
-    double Y2[36], R2[9], TR2[9];
-    if (has_rev) {
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) R2[3 * a + b] = R[3 * b + a];
-      double t2[3], Tx2[9];
-      for (int a = 0; a < 3; ++a) t2[a] = -(R2[3 * a] * t[0] + R2[3 * a + 1] * t[1] + R2[3 * a + 2] * t[2]);
-      skew(t2, Tx2);
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-          TR2[3 * a + b] = Tx2[3 * a] * R2[b] + Tx2[3 * a + 1] * R2[3 + b] + Tx2[3 * a + 2] * R2[6 + b];
-    }
-    auto ad2 = [&](int r, int c) -> double {
-      if (r < 3) return c < 3 ? R2[3 * r + c] : 0.0;
-      return c < 3 ? TR2[3 * (r - 3) + c] : R2[3 * (r - 3) + (c - 3)];
-    };
-    double Z2[36];
-    if (has_rev) {
-      // Y2 = Hii_r Ad2
-      for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) {
-          double v = 0.0;
-          for (int k = 0; k < 6; ++k) v += Hii_r[6 * a + k] * ad2(k, b);
-          Y2[6 * a + b] = v;
-        }
-      for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) {
-          double v = 0.0;
-          for (int k = 0; k < 6; ++k) v += ad2(k, a) * Y2[6 * k + b];
-          Z2[6 * a + b] = v;
-        }
-      for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) out[kEHjj + 6 * a + b] += 0.5 * (Z2[6 * a + b] + Z2[6 * b + a]);
-    }
-    // H_ii sparse part
-    double Hii[36];
-    {
-      double S[9];
-      skew(sp, S);
-      double trp = Spp[0] + Spp[4] + Spp[8];
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-          Hii[6 * a + b] = w * ((a == b ? trp : 0.0) - Spp[3 * a + b]);
-          Hii[6 * a + b + 3] = w * S[3 * a + b];
-          Hii[6 * (a + 3) + b] = -w * S[3 * a + b];
-          Hii[6 * (a + 3) + b + 3] = (a == b ? w * n : 0.0);
-        }
-    }
-    // Ad(T_ji) = [[R, 0], [[t]x R, R]];  Y = Ad^T Hjj_d;  H_ii += Y Ad;  H_ij = -Y (+ sparse)
-    double TR[9];
-    {
-      double Tx[9];
-      skew(t, Tx);
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) TR[3 * a + b] = Tx[3 * a] * R[b] + Tx[3 * a + 1] * R[3 + b] + Tx[3 * a + 2] * R[6 + b];
-    }
-    auto ad = [&](int r, int c) -> double {
-      if (r < 3) return c < 3 ? R[3 * r + c] : 0.0;
-      return c < 3 ? TR[3 * (r - 3) + c] : R[3 * (r - 3) + (c - 3)];
-    };
-    double Y[36];
-    for (int a = 0; a < 6; ++a)
-      for (int b = 0; b < 6; ++b) {
-        double v = 0.0;
-        for (int k = 0; k < 6; ++k) v += ad(k, a) * Hjj_d[6 * k + b];
-        Y[6 * a + b] = v;
-      }
-    for (int a = 0; a < 6; ++a)
-      for (int b = 0; b < 6; ++b) {
-        double v = 0.0;
-        for (int k = 0; k < 6; ++k) v += Y[6 * a + k] * ad(k, b);
-        Hii[6 * a + b] += v + Hii_r[6 * a + b];
-        // the dense term's part alone (matrix-free sparse mode: the product takes the
-        // sparse part per correspondence)
-        if (ediag_dense) ediag_dense[(size_t)e * 72 + 6 * a + b] = v + Hii_r[6 * a + b];
-      }
+    // H_ii, symmetrised: both triangles from the same sums
+    out[kEHii + lane] = a == b ? Pw[lane] : 0.5 * (Pw[6 * a + b] + Pw[6 * b + a]);
     if (ediag_dense) {
       double* dd = ediag_dense + (size_t)e * 72;
-      for (int a = 0; a < 6; ++a)
-        for (int b = a + 1; b < 6; ++b) {
-          const double v = 0.5 * (dd[6 * a + b] + dd[6 * b + a]);
-          dd[6 * a + b] = v;
-          dd[6 * b + a] = v;
-        }
-      // H_jj of the dense term: the forward job's block and the reverse job's, as above
-      for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) {
-          double v = Hjj_d[6 * a + b];
-          if (has_rev) v += 0.5 * (Z2[6 * a + b] + Z2[6 * b + a]);
-          dd[36 + 6 * a + b] = v;
-        }
+      dd[lane] = a == b ? Dw[lane] : 0.5 * (Dw[6 * a + b] + Dw[6 * b + a]);
+      double v = Hd[lane];
+      if (has_rev) v += 0.5 * (Zw[6 * a + b] + Zw[6 * b + a]);
+      dd[36 + lane] = v;
     }
-    // symmetrise: both triangles from the same sums
-    for (int a = 0; a < 6; ++a)
-      for (int b = a + 1; b < 6; ++b) {
-        double v = 0.5 * (Hii[6 * a + b] + Hii[6 * b + a]);
-        Hii[6 * a + b] = v;
-        Hii[6 * b + a] = v;
-      }
-    for (int k = 0; k < 36; ++k) out[kEHii + k] = Hii[k];
-    // H_ij: sparse = -sum A_p^T R^T A_q = [[sum [p]x R^T [q]x, -[sp]x R^T], [R^T [sq]x, -n R^T]]
-    double Hij[36];
+    // H_ij: sparse = -sum A_p^T R^T A_q = [[sum [p]x R^T [q]x, -[sp]x R^T], [R^T [sq]x, -n R^T]];
+    // dense = -Y (and -Y2 for the reverse job)
+    double hs;
     {
-      double Rt[9];
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) Rt[3 * a + b] = R[3 * b + a];
-      double Sp[9], Sq[9];
-      skew(sp, Sp);
-      skew(sq, Sq);
-      for (int r = 0; r < 3; ++r)
-        for (int c2 = 0; c2 < 3; ++c2) {
-          // sum_k [p_k]x Rt [q_k]x = sum eps(r,k,m) eps(l,c,n) Rt[k][l] Spq[m][n]
-          double tl = 0.0;
-          for (int k = 0; k < 3; ++k)
-            for (int m = 0; m < 3; ++m) {
-              int e1 = eps3(r, k, m);
-              if (!e1) continue;
-              for (int l = 0; l < 3; ++l)
-                for (int nn = 0; nn < 3; ++nn) {
-                  int e2 = eps3(l, c2, nn);
-                  if (!e2) continue;
-                  tl += (double)(e1 * e2) * Rt[3 * k + l] * Spq[3 * m + nn];
-                }
-            }
-          double tr = 0.0, bl = 0.0;
-          for (int k = 0; k < 3; ++k) {
-            tr -= Sp[3 * r + k] * Rt[3 * k + c2];
-            bl += Rt[3 * r + k] * Sq[3 * k + c2];
-          }
-          Hij[6 * r + c2] = w * tl;
-          Hij[6 * r + c2 + 3] = w * tr;
-          Hij[6 * (r + 3) + c2] = w * bl;
-          Hij[6 * (r + 3) + c2 + 3] = -w * n * Rt[3 * r + c2];
-        }
+      const double* Rt = Gw + 12;  // R^T
+      const int r = ra, c2 = cb;
+      if (a < 3 && b < 3) {
+        // sum_k [p_k]x Rt [q_k]x = sum eps(r,k,m) eps(l,c,n) Rt[k][l] Spq[m][n]: four
+        // nonzero terms, (k, m) and (l, n) the two orders of the indices other than
+        // r and c; summed with k, then l ascending
+        const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;    // eps(r, r1, r2) = +1
+        const int c1 = (c2 + 1) % 3, c3 = (c2 + 2) % 3;  // eps(c3, c, c1) = +1
+        const int kA = r1 < r2 ? r1 : r2, kB = r1 < r2 ? r2 : r1;
+        const int lA = c1 < c3 ? c1 : c3, lB = c1 < c3 ? c3 : c1;
+        const double sk[2] = {kA == r1 ? 1.0 : -1.0, kB == r1 ? 1.0 : -1.0};  // eps(r, k, m)
+        const double sl[2] = {lA == c3 ? 1.0 : -1.0, lB == c3 ? 1.0 : -1.0};  // eps(l, c, n)
+        const int mk[2] = {kA == r1 ? r2 : r1, kB == r1 ? r2 : r1};
+        const int nl[2] = {lA == c3 ? c1 : c3, lB == c3 ? c1 : c3};
+        const int kk[2] = {kA, kB}, ll[2] = {lA, lB};
+        double tl = 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) tl += (sk[u] * sl[q]) * Rt[3 * kk[u] + ll[q]] * Spq[3 * mk[u] + nl[q]];
+        hs = w * tl;
+      } else if (a < 3) {
+        double tr = 0.0;
+        for (int k = 0; k < 3; ++k) tr -= skew_at(sp, r, k) * Rt[3 * k + c2];
+        hs = w * tr;
+      } else if (b < 3) {
+        double bl = 0.0;
+        for (int k = 0; k < 3; ++k) bl += Rt[3 * r + k] * skew_at(sq, k, c2);
+        hs = w * bl;
+      } else {
+        hs = -w * n * Rt[3 * r + c2];
+      }
     }
-    for (int k = 0; k < 36; ++k) {
-      const double vd = -Y[k] - (has_rev ? Y2[k] : 0.0);
-      double v = Hij[k] - Y[k] - (has_rev ? Y2[k] : 0.0);
-      out[kEHij + k] = v;
-      // the PCG's copy: the dense term's block alone in matrix-free sparse mode
-      hij_store[(size_t)e * 36 + k] = (T)(ediag_dense ? vd : v);
-    }
-    // gradients.  g_i sparse = w [sp x (R^T t) - sum p x (R^T q); sp + n R^T t - R^T sq]
-    //             g_j sparse = -w [sum q x (R p) + sq x t; R sp + n t - sq]
-    double Rtt[3], Rtsq[3], Rsp[3];
-    for (int a = 0; a < 3; ++a) {
-      Rtt[a] = R[a] * t[0] + R[3 + a] * t[1] + R[6 + a] * t[2];
-      Rtsq[a] = R[a] * sq[0] + R[3 + a] * sq[1] + R[6 + a] * sq[2];
-      Rsp[a] = R[3 * a] * sp[0] + R[3 * a + 1] * sp[1] + R[3 * a + 2] * sp[2];
-    }
-    double gi[6], gj[6];
-    for (int a = 0; a < 3; ++a) {
-      int b = (a + 1) % 3, c2 = (a + 2) % 3;
-      double sx = sp[b] * Rtt[c2] - sp[c2] * Rtt[b];
+    const double y2 = has_rev ? Y2w[lane] : 0.0;
+    const double vd = -Yw[lane] - y2;
+    const double v = hs - Yw[lane] - y2;
+    out[kEHij + lane] = v;
+    // the PCG's copy: the dense term's block alone in matrix-free sparse mode
+    hij_store[(size_t)e * 36 + lane] = (T)(ediag_dense ? vd : v);
+  } else if (lane < 42) {
+    // gradients, lane 36 + a2 for a2 = 0..5: g_i sparse = w [sp x (R^T t) - sum p x (R^T q);
+    // sp + n R^T t - R^T sq], g_j sparse = -w [sum q x (R p) + sq x t; R sp + n t - sq];
+    // dense: g_j += gj_d, g_i -= Ad^T gj_d (and the reverse job's, lifted with Ad2)
+    const int a2 = lane - 36;
+    const double* sp = Mw + kMP;
+    const double* sq = Mw + kMQ;
+    const double* Spq = Mw + kMPQ;
+    const double* Rg = Gw;      // R
+    const double* tg = Gw + 9;  // t
+    double gi, gj;
+    const int c3 = a2 % 3;
+    auto Rtt = [&](int q) { return Rg[q] * tg[0] + Rg[3 + q] * tg[1] + Rg[6 + q] * tg[2]; };
+    if (a2 < 3) {
+      const int bb0 = (c3 + 1) % 3, cc0 = (c3 + 2) % 3;
+      const double sx = sp[bb0] * Rtt(cc0) - sp[cc0] * Rtt(bb0);
+      // the two nonzero eps(c3, bb, cc), bb ascending
+      const int bA = bb0 < cc0 ? bb0 : cc0, bB = bb0 < cc0 ? cc0 : bb0;
+      const int bbs[2] = {bA, bB}, ccs[2] = {bA == bb0 ? cc0 : bb0, bB == bb0 ? cc0 : bb0};
+      const double eps[2] = {bA == bb0 ? 1.0 : -1.0, bB == bb0 ? 1.0 : -1.0};
       double pxRq = 0.0, qxRp = 0.0;
-      for (int bb = 0; bb < 3; ++bb)
-        for (int cc = 0; cc < 3; ++cc) {
-          int ep = eps3(a, bb, cc);
-          if (!ep) continue;
-          for (int dd = 0; dd < 3; ++dd) {
-            pxRq += ep * R[3 * dd + cc] * Spq[3 * bb + dd];   // sum p_b (R^T q)_c
-            qxRp += ep * R[3 * cc + dd] * Spq[3 * dd + bb];   // sum q_b (R p)_c
-          }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) {
+          pxRq += eps[u] * Rg[3 * dd + ccs[u]] * Spq[3 * bbs[u] + dd];  // sum p_b (R^T q)_c
+          qxRp += eps[u] * Rg[3 * ccs[u] + dd] * Spq[3 * dd + bbs[u]];  // sum q_b (R p)_c
         }
-      double sqxt = sq[b] * t[c2] - sq[c2] * t[b];
-      gi[a] = w * (sx - pxRq);
-      gi[a + 3] = w * (sp[a] + n * Rtt[a] - Rtsq[a]);
-      gj[a] = -w * (qxRp + sqxt);
-      gj[a + 3] = -w * (Rsp[a] + n * t[a] - sq[a]);
+      const double sqxt = sq[bb0] * tg[cc0] - sq[cc0] * tg[bb0];
+      gi = w * (sx - pxRq);
+      gj = -w * (qxRp + sqxt);
+    } else {
+      const double Rtsq = Rg[c3] * sq[0] + Rg[3 + c3] * sq[1] + Rg[6 + c3] * sq[2];
+      const double Rsp = Rg[3 * c3] * sp[0] + Rg[3 * c3 + 1] * sp[1] + Rg[3 * c3 + 2] * sp[2];
+      gi = w * (sp[c3] + n * Rtt(c3) - Rtsq);
+      gj = -w * (Rsp + n * tg[c3] - sq[c3]);
     }
-    // dense: g_j += gj_d, g_i -= Ad^T gj_d
-    for (int a = 0; a < 6; ++a) {
-      double v = 0.0, v2 = 0.0;
-      for (int k = 0; k < 6; ++k) v += ad(k, a) * gj_d[k];
-      if (has_rev)
-        for (int k = 0; k < 6; ++k) v2 += ad2(k, a) * gi_r[k];
-      out[kEGi + a] = gi[a] - v + gi_r[a];
-      out[kEGj + a] = gj[a] + gj_d[a] - v2;
-    }
+    double v = 0.0, v2 = 0.0;
+    for (int k = 0; k < 6; ++k) v += AD[6 * k + a2] * Fw[kRecG + k];
+    if (has_rev)
+      for (int k = 0; k < 6; ++k) v2 += AD2[6 * k + a2] * Rw[kRecG + k];
+    out[kEGi + a2] = gi - v + Rw[kRecG + a2];
+    out[kEGj + a2] = gj + Fw[kRecG + a2] - v2;
   }
-  out[kEEs] = Es;
-  out[kEEg] = Eg;
-  out[kEEp] = Ep;
-  out[kENs] = ns;
-  out[kENg] = ng;
-  out[kENp] = np;
 }
 
 // Deterministic block reduction of one double per thread (blockDim.x = 1024).
@@ -1997,15 +1965,16 @@ void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, b
   }
   const long long E = c.shape.E;
   if (E == 0) return;
-  unsigned grid = (unsigned)((E + 63) / 64);
+  constexpr int per = kEdgeThreads / 64;
+  unsigned grid = (unsigned)((E + per - 1) / per);
   if (c.pcg_storage == 1)
-    hipLaunchKernelGGL(k_edge_blocks<double>, dim3(grid), dim3(64), 0, c.stream, c.edge_ij.as<int>(), E,
+    hipLaunchKernelGGL(k_edge_blocks<double>, dim3(grid), dim3(kEdgeThreads), 0, c.stream, c.edge_ij.as<int>(), E,
                        c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.moments.as<double>(),
                        c.records.as<double>(), (long long)c.shape.P, c.bidir, c.dense_tiles, poses,
                        prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
                        c.eblocks.as<double>(), c.hij64.as<double>(), ed);
   else
-    hipLaunchKernelGGL(k_edge_blocks<float>, dim3(grid), dim3(64), 0, c.stream, c.edge_ij.as<int>(), E,
+    hipLaunchKernelGGL(k_edge_blocks<float>, dim3(grid), dim3(kEdgeThreads), 0, c.stream, c.edge_ij.as<int>(), E,
                        c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.moments.as<double>(),
                        c.records.as<double>(), (long long)c.shape.P, c.bidir, c.dense_tiles, poses,
                        prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
