@@ -1101,8 +1101,10 @@ __global__ void __launch_bounds__(kAsmThreads) k_row_assemble(
 //   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k,
 // the same iterates as the two-reduction form in exact arithmetic.  Per iteration
 // one product w = A u crosses workgroups (the owners publish their rows as tagged
-// words; every workgroup polls until it holds all of w) and both dot products
-// reduce behind one barrier; the vector updates need one more.
+// words; every workgroup polls until it holds all of w).  beta needs gamma alone,
+// so p = u + beta p runs while the words travel and s = w + beta s as they arrive;
+// delta = (w, u) then reduces behind one barrier, and gamma of the next iterate
+// behind the barrier that ends the r and u updates.
 constexpr int kRepThreads = 512;
 constexpr int kRepWaves = kRepThreads / 64;
 
@@ -1117,7 +1119,6 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
     double* __restrict__ stats, int* flags, unsigned tag_base, unsigned spin_limit) {
   extern __shared__ double lds_dyn[];
   __shared__ double sh[(kRepWaves + 1) * kParts];
-  __shared__ double red1024[kRepThreads];
   __shared__ double blk[kRepWaves][36];
   __shared__ int sh_ok;
   const long long n = 6 * nfree;
@@ -1194,191 +1195,193 @@ __global__ void __launch_bounds__(kRepThreads) k_solve_rep(
       part_ru += (double)r[6 * w + a] * (double)ut;
     }
   }
-  __syncthreads();
+  // gamma_0 = (r_0, u_0); its barrier also completes u.  The two sums of an
+  // iteration use their own slots (delta at sh[0..], gamma at sh[2 NW..]): a slot is
+  // written again only after the barrier of the other sum, which every thread
+  // passes after its reads.
+  double* const sh_delta = sh;
+  double* const sh_gamma = sh + 2 * kRepWaves;
+  double gamma = block_sum_dpp_1<kRepWaves>(part_ru, sh_gamma);
   const int rr = lane / 6, a6 = lane - 6 * (lane / 6);  // update pass: row, element
   T xo = (T)0;  // owner lanes 0..5: x of the owned row
   int done = 0;
-  double gamma = 0.0, gamma_prev = 1.0, alpha_prev = 1.0, rz0 = 0.0;
+  const double rz0 = bad ? 0.0 : gamma;
+  double gamma_prev = 1.0, alpha_prev = 1.0;
   constexpr int WPV = sizeof(T) / 4;  // 32-bit halves per value, each published with the tag
-  for (int k = 0; k <= iters && !bad && sh_ok; ++k) {
-    // ---- w = A u (exchange k), then (r, u) and (w, u) in one reduction; the last
-    // pass after the final update only reduces (r, u) for the statistics
-    double part_wu = 0.0;
-    if (k < iters) {
-      const unsigned tag = tag_base + (unsigned)k + 1u;
-      unsigned long long* apw = ap_words + (size_t)(k & 1) * n * WPV;
-      // owners compute (A u)_v from register blocks and the LDS copy of u, publish it
-      if (owner) {
-        T acc[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+  for (int k = 0; k < iters && !bad && sh_ok && gamma > 1e-30; ++k) {
+    const double beta = k == 0 ? 0.0 : gamma / gamma_prev;
+    const float beta_f = (float)beta;
+    const unsigned tag = tag_base + (unsigned)k + 1u;
+    unsigned long long* apw = ap_words + (size_t)(k & 1) * n * WPV;
+    // ---- w = A u (exchange k): owners compute (A u)_v from register blocks and
+    // the LDS copy of u, and publish it
+    if (owner) {
+      T acc[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-        for (int s = 0; s < NB; ++s) {
-          if (partner[s] >= 0) {
-            T uw[6];
+      for (int s = 0; s < NB; ++s) {
+        if (partner[s] >= 0) {
+          T uw[6];
 #pragma unroll
-            for (int b = 0; b < 6; ++b) uw[b] = u[6 * (long long)partner[s] + b];
+          for (int b = 0; b < 6; ++b) uw[b] = u[6 * (long long)partner[s] + b];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) {
-              T s2 = (T)0;
+          for (int i = 0; i < 6; ++i) {
+            T s2 = (T)0;
 #pragma unroll
-              for (int j = 0; j < 6; ++j)
-                s2 += (tr[s] ? blockreg[s][6 * j + i] : blockreg[s][6 * i + j]) * uw[j];
-              acc[i] += s2;
-            }
+            for (int j = 0; j < 6; ++j) s2 += (tr[s] ? blockreg[s][6 * j + i] : blockreg[s][6 * i + j]) * uw[j];
+            acc[i] += s2;
           }
-        }
-        // rows with more entries than the registers hold take the rest from memory
-        for (long long q = 64 * NB + lane; q <= ne; q += 64) {
-          T uw[6], y[6];
-          if (q < ne) {
-            const int2 en = entries[row_ptr[v] + q];
-#pragma unroll
-            for (int b = 0; b < 6; ++b) uw[b] = u[6 * (long long)en.x + b];
-            block_mv<T>(hij + (size_t)(en.y >> 1) * 36, uw, en.y & 1, y);
-          } else {
-            T dg[36];
-#pragma unroll
-            for (int q2 = 0; q2 < 36; ++q2) dg[q2] = (T)blk[wave][q2];
-#pragma unroll
-            for (int b = 0; b < 6; ++b) uw[b] = u[6 * v + b];
-            block_mv<T>(dg, uw, false, y);
-          }
-#pragma unroll
-          for (int b = 0; b < 6; ++b) acc[b] += y[b];
-        }
-        double accd[6];
-#pragma unroll
-        for (int b = 0; b < 6; ++b) accd[b] = (double)acc[b];
-        const double tb = wave_sum6_d(accd);  // value lane / 8
-        if ((lane >> 3) < 6 && (lane & 7) < WPV) {
-          // lane 8b + h publishes half h of value b: (tag << 32) | bits
-          const int b = lane >> 3, h = lane & 7;
-          unsigned bits;
-          if constexpr (WPV == 1) {
-            bits = __float_as_uint((float)tb);
-          } else {
-            const unsigned long long d = (unsigned long long)__double_as_longlong(tb);
-            bits = h ? (unsigned)(d >> 32) : (unsigned)(d & 0xffffffffull);
-          }
-          st_shared(&apw[(6 * v + b) * WPV + h], ((unsigned long long)tag << 32) | bits);
         }
       }
-      // every workgroup gathers all of w (polling the tagged words) and forms the
-      // (w, u) partials of the values it gathered
-      constexpr int kMaxPer = 8;                 // values per thread gathered at once
-      const long long nw = n * WPV;
-      for (long long o0 = tid; o0 < nw; o0 += (long long)kRepThreads * kMaxPer) {
-        unsigned long long wv[kMaxPer];
-        const unsigned long long filler = (unsigned long long)tag << 32;  // past the end: ready
-        unsigned spins = 0;
-        for (;;) {
-          // all loads of a poll are issued before any is tested
+      // rows with more entries than the registers hold take the rest from memory
+      for (long long q = 64 * NB + lane; q <= ne; q += 64) {
+        T uw[6], y[6];
+        if (q < ne) {
+          const int2 en = entries[row_ptr[v] + q];
 #pragma unroll
-          for (int q = 0; q < kMaxPer; ++q) {
-            const long long o = o0 + (long long)q * kRepThreads;
-            wv[q] = o < nw ? ld_shared(&apw[o]) : filler;
-          }
-          bool ready = true;
+          for (int b = 0; b < 6; ++b) uw[b] = u[6 * (long long)en.x + b];
+          block_mv<T>(hij + (size_t)(en.y >> 1) * 36, uw, en.y & 1, y);
+        } else {
+          T dg[36];
 #pragma unroll
-          for (int q = 0; q < kMaxPer; ++q) ready = ready & ((unsigned)(wv[q] >> 32) == tag);
-          if (ready) break;
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins > spin_limit) {
-            atomicOr(flags, kFlagTimeout);
-            sh_ok = 0;
-            break;
+          for (int q2 = 0; q2 < 36; ++q2) dg[q2] = (T)blk[wave][q2];
+#pragma unroll
+          for (int b = 0; b < 6; ++b) uw[b] = u[6 * v + b];
+          block_mv<T>(dg, uw, false, y);
+        }
+#pragma unroll
+        for (int b = 0; b < 6; ++b) acc[b] += y[b];
+      }
+      double accd[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) accd[b] = (double)acc[b];
+      const double tb = wave_sum6_d(accd);  // value lane / 8
+      if ((lane >> 3) < 6 && (lane & 7) < WPV) {
+        // lane 8b + h publishes half h of value b: (tag << 32) | bits
+        const int b = lane >> 3, h = lane & 7;
+        unsigned bits;
+        if constexpr (WPV == 1) {
+          bits = __float_as_uint((float)tb);
+        } else {
+          const unsigned long long d = (unsigned long long)__double_as_longlong(tb);
+          bits = h ? (unsigned)(d >> 32) : (unsigned)(d & 0xffffffffull);
+        }
+        st_shared(&apw[(6 * v + b) * WPV + h], ((unsigned long long)tag << 32) | bits);
+      }
+    }
+    // ---- p = u + beta p over the whole vector (beta needs gamma only), while the
+    // other owners' words are on their way
+    for (long long o = tid; o < n; o += kRepThreads) {
+      if constexpr (sizeof(T) == 4)
+        p[o] = __builtin_fmaf(beta_f, p[o], u[o]);
+      else
+        p[o] = (T)((double)u[o] + beta * (double)p[o]);
+    }
+    // ---- every workgroup gathers all of w (polling the tagged words); the thread
+    // that gathers a value forms s = w + beta s and the (w, u) partial of it
+    double part_wu = 0.0;
+    constexpr int kMaxPer = 8;  // values per thread gathered at once
+    const long long nw = n * WPV;
+    for (long long o0 = tid; o0 < nw; o0 += (long long)kRepThreads * kMaxPer) {
+      unsigned long long wv[kMaxPer];
+      const unsigned long long filler = (unsigned long long)tag << 32;  // past the end: ready
+      unsigned spins = 0;
+      for (;;) {
+        // all loads of a poll are issued before any is tested
+#pragma unroll
+        for (int q = 0; q < kMaxPer; ++q) {
+          const long long o = o0 + (long long)q * kRepThreads;
+          wv[q] = o < nw ? ld_shared(&apw[o]) : filler;
+        }
+        bool ready = true;
+#pragma unroll
+        for (int q = 0; q < kMaxPer; ++q) ready = ready & ((unsigned)(wv[q] >> 32) == tag);
+        if (ready) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > spin_limit) {
+          atomicOr(flags, kFlagTimeout);
+          sh_ok = 0;
+          break;
+        }
+      }
+      if constexpr (WPV == 1) {
+#pragma unroll
+        for (int q = 0; q < kMaxPer; ++q) {
+          const long long o = o0 + (long long)q * kRepThreads;
+          if (o < nw) {
+            const float wq = __uint_as_float((unsigned)(wv[q] & 0xffffffffull));
+            sv[o] = __builtin_fmaf(beta_f, sv[o], wq);
+            part_wu += (double)wq * (double)u[o];
           }
         }
+      } else {
 #pragma unroll
         for (int q = 0; q < kMaxPer; ++q) {
           const long long o = o0 + (long long)q * kRepThreads;
           if (o < nw) reinterpret_cast<unsigned*>(wvec)[o] = (unsigned)(wv[q] & 0xffffffffull);
         }
-        if constexpr (WPV == 1) {
-#pragma unroll
-          for (int q = 0; q < kMaxPer; ++q) {
-            const long long o = o0 + (long long)q * kRepThreads;
-            if (o < nw) part_wu += (double)__uint_as_float((unsigned)(wv[q] & 0xffffffffull)) * (double)u[o];
-          }
-        }
-      }
-      if constexpr (WPV == 2) {
-        __syncthreads();  // both halves of a value gathered
-        for (long long o = tid; o < n; o += kRepThreads) part_wu += (double)wvec[o] * (double)u[o];
       }
     }
-    // (r, u) and (w, u) reduce behind one barrier (slots alternate with k, so a slot
-    // is written again only after the barriers that follow its reads)
-    double two[2];
-    block_sum2_dpp<kRepWaves>(part_ru, part_wu, sh + (k & 1) * 2 * kRepWaves, two);
+    if constexpr (WPV == 2) {
+      __syncthreads();  // both halves of a value gathered
+      for (long long o = tid; o < n; o += kRepThreads) {
+        sv[o] = (T)((double)wvec[o] + beta * (double)sv[o]);
+        part_wu += (double)wvec[o] * (double)u[o];
+      }
+    }
+    // ---- delta = (w, u) behind one barrier (which also completes p and s)
+    const double delta = block_sum_dpp_1<kRepWaves>(part_wu, sh_delta);
     if (!sh_ok) break;
-    gamma = two[0];
-    if (k == 0) rz0 = gamma;
-    if (k == iters || gamma <= 1e-30) break;
-    const double delta = two[1];
-    const double beta = k == 0 ? 0.0 : gamma / gamma_prev;
     const double alpha = gamma / (delta - (k == 0 ? 0.0 : beta * gamma / alpha_prev));
-    const float beta_f = (float)beta, alpha_f = (float)alpha;
-    // p = u + beta p, s = w + beta s, r -= alpha s element by element, then u = M^-1 r
-    // and the (r, u) partials per block row: each wavefront takes ten block rows at
-    // a time, six lanes per row (lanes 60..63 idle), so consecutive lanes touch
-    // consecutive values; a row's six new r values are read back from LDS after a
-    // wavefront barrier (the same wavefront wrote them).  FP32 storage updates in
-    // FP32; FP64 stays with the dot products and alpha, beta.  (Updating all of a
-    // wavefront's rows before any of their u, or every value by its own thread with
-    // a workgroup barrier between the halves, measured slower: 1.1-1.6 us.)
+    const float alpha_f = (float)alpha;
+    if (owner && lane < 6) xo = (T)((double)xo + alpha * (double)p[6 * v + lane]);
+    // ---- r -= alpha s element by element, then u = M^-1 r and the (r, u) partials
+    // per block row: each wavefront takes ten block rows at a time, six lanes per
+    // row (lanes 60..63 idle), so consecutive lanes touch consecutive values; a
+    // row's six new r values are read back from LDS after a wavefront barrier (the
+    // same wavefront wrote them).  FP32 storage updates in FP32; FP64 stays with the
+    // dot products and alpha, beta.
     part_ru = 0.0;
-    {
-      for (long long w0 = (long long)wave * 10; w0 < nfree; w0 += 10 * kRepWaves) {
-        const long long w = w0 + rr;
-        const bool act = lane < 60 && w < nfree;
-        double rb = 0.0;
-        if (act) {
-          const long long o = 6 * w + a6;
-          T rn;
-          if constexpr (sizeof(T) == 4) {
-            const float pn = __builtin_fmaf(beta_f, p[o], u[o]);
-            const float sn = __builtin_fmaf(beta_f, sv[o], wvec[o]);
-            p[o] = pn;
-            sv[o] = sn;
-            rn = __builtin_fmaf(-alpha_f, sn, r[o]);
-          } else {
-            const T pn = (T)((double)u[o] + beta * (double)p[o]);
-            const T sn = (T)((double)wvec[o] + beta * (double)sv[o]);
-            p[o] = pn;
-            sv[o] = sn;
-            rn = (T)((double)r[o] - alpha * (double)sn);
-          }
-          r[o] = rn;
-          rb = (double)rn;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (act) {
-          const T* mr = minv + w * 36 + 6 * a6;
-          T ut;
-          if constexpr (sizeof(T) == 4) {
-            float s2 = 0.0f;
+    for (long long w0 = (long long)wave * 10; w0 < nfree; w0 += 10 * kRepWaves) {
+      const long long w = w0 + rr;
+      const bool act = lane < 60 && w < nfree;
+      double rb = 0.0;
+      if (act) {
+        const long long o = 6 * w + a6;
+        T rn;
+        if constexpr (sizeof(T) == 4)
+          rn = __builtin_fmaf(-alpha_f, sv[o], r[o]);
+        else
+          rn = (T)((double)r[o] - alpha * (double)sv[o]);
+        r[o] = rn;
+        rb = (double)rn;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (act) {
+        const T* mr = minv + w * 36 + 6 * a6;
+        T ut;
+        if constexpr (sizeof(T) == 4) {
+          float s2 = 0.0f;
 #pragma unroll
-            for (int b = 0; b < 6; ++b) s2 = __builtin_fmaf(mr[b], r[6 * w + b], s2);
-            ut = s2;
-          } else {
-            double s2 = 0.0;
+          for (int b = 0; b < 6; ++b) s2 = __builtin_fmaf(mr[b], r[6 * w + b], s2);
+          ut = s2;
+        } else {
+          double s2 = 0.0;
 #pragma unroll
-            for (int b = 0; b < 6; ++b) s2 += (double)mr[b] * (double)r[6 * w + b];
-            ut = (T)s2;
-          }
-          u[6 * w + a6] = ut;
-          part_ru += rb * (double)ut;
+          for (int b = 0; b < 6; ++b) s2 += (double)mr[b] * (double)r[6 * w + b];
+          ut = (T)s2;
         }
+        u[6 * w + a6] = ut;
+        part_ru += rb * (double)ut;
       }
     }
-    __syncthreads();
-    if (owner && lane < 6) xo = (T)((double)xo + alpha * (double)p[6 * v + lane]);
     gamma_prev = gamma;
     alpha_prev = alpha;
+    // ---- gamma = (r, u) of the new iterate; its barrier also completes u
+    gamma = block_sum_dpp_1<kRepWaves>(part_ru, sh_gamma);
     ++done;
   }
-  const double rz = gamma;
+  const double rz = bad ? 0.0 : gamma;
   // epilogue: owners publish dx and update their poses
   if (owner && lane < 6 && delta_out) delta_out[6LL * frame_of_var[v] + lane] = bad ? 0.0 : (double)xo;
   if (delta_out)
