@@ -513,8 +513,8 @@ def batched(bf, ctx, chunks, steps):
     import torch
 
     n_gn, n_pcg = chunks[0].n_gn, chunks[0].n_pcg
-    params = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0)
-    gparams = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0, graph=1)
+    params = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0, pcg_threads=-1)
+    gparams = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0, pcg_threads=-1, graph=1)
     dp, offs, init = bf.device_batch(chunks)
     out = torch.empty_like(init)
     gout = torch.empty_like(init)
@@ -542,13 +542,14 @@ def batched(bf, ctx, chunks, steps):
     t_batch = (time.perf_counter() - t0) / steps
     graph_same = bool(torch.equal(out, gout)) and gres["energy"] == res["energy"]
     first = gout[:offs[4]].cpu().numpy()
-    tparams = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0, timing=1)
+    tparams = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=0, pcg_threads=-1, timing=1)
     bf.bf_gauss_newton_batch(ctx, dp, offs, init, tparams, out_poses=out)
     phases = {k: round(v, 1) for k, v in ctx.last_timings().items()}
     log(f"batched phases (us, eager, timed call): {phases}")
     log(f"batched: graph replays {t_batch * 1e3:.3f} ms, eager launches {t_eager * 1e3:.3f} ms per batch; "
         f"captures during the timed replays {ctx.graph_captures() - n_cap}; graph result == eager: {graph_same}")
     batch_shape = ctx.dense_shape()["jacobians"]
+    batch_pcg = ctx.pcg_threads()
     t0 = time.perf_counter()
     for (d, i), o in zip(singles, singles_out):
         bf.bf_gauss_newton(ctx, d, i, params, out_poses=o)
@@ -568,7 +569,8 @@ def batched(bf, ctx, chunks, steps):
     own = worst_diff(singles_out)
     # the same problems one at a time with the batch's dense launch shape (not timed):
     # the per-problem kernels then sum in the same order, so the results are the batch's
-    fixed = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=batch_shape[0], dense_tiles=batch_shape[1])
+    fixed = bf.bf_params_default(num_gn=n_gn, num_pcg=n_pcg, dense_threads=batch_shape[0], dense_tiles=batch_shape[1],
+                                 pcg_threads=batch_pcg)
     for (d, i), o in zip(singles, singles_out):
         bf.bf_gauss_newton(ctx, d, i, fixed, out_poses=o)
     same = worst_diff(singles_out)
@@ -587,7 +589,8 @@ def batched(bf, ctx, chunks, steps):
                         "to this size"},
             "config": {"workload": f"{nb} chunk problems, 4-11 frames (sum {offs[-1]}), 160x120, "
                                    f"{n_gn} GN x {n_pcg} PCG, dense launch {batch_shape[0]} threads x "
-                                   f"{batch_shape[1]} tiles per pair job (timed per shape), "
+                                   f"{batch_shape[1]} tiles per pair job, per-problem PCG {batch_pcg} threads "
+                                   f"(both timed per shape), "
                                    f"Gauss-Newton loop replayed as one HIP graph"}}
 
 

@@ -169,6 +169,13 @@ typedef struct bf_params {
                                PCG kernel (solve_kernel 0 or 5; BF_ERR_UNSUPPORTED where the
                                search direction does not fit one workgroup's LDS) and only in
                                bf_gauss_newton and bf_gauss_newton_noalloc. */
+  int32_t pcg_threads;      /* threads per problem of the per-problem PCG kernel (batches, and
+                               problems of at most 64 free frames): 64, 128, 256 or 1024; 0
+                               (default) = 256; -1 = the fastest of the four, timed once per
+                               (storage, problem count range, largest problem) in the context (the
+                               timing runs solve the current system without writing any result; in
+                               graph mode a choice not yet timed by an eager call is 256).  Each
+                               size sums in its own fixed order: results agree within rounding. */
 } bf_params;
 
 void bf_params_default(bf_params* out);
@@ -455,6 +462,16 @@ bf_status bf_gauss_newton_batch(bf_context* ctx, const bf_frames* frames, const 
  * With params->timing = 2 only the dense pair jobs, the total and the launch count
  * are measured (the other phases read 0). */
 bf_status bf_last_timings(const bf_context* ctx, double* out_us);
+
+/* Workgroup size of this context's last per-problem PCG launch (params->pcg_threads
+ * fixed, or the timed choice); 0 before any (host out, [1]). */
+bf_status bf_pcg_threads(const bf_context* ctx, int32_t* out_threads);
+
+/* Device memory held by this context's workspace, in bytes (host out, [1]): the sum
+ * of its buffers' capacities.  They grow on demand (by a quarter more than asked)
+ * and are kept until bf_destroy; inputs the caller owns are not counted.  A
+ * caller that admits work by memory footprint can check its estimate against it. */
+bf_status bf_workspace_bytes(const bf_context* ctx, int64_t* out_bytes);
 
 /* Launch shape of this context's last dense pair-job launch with Jacobians and of
  * its last one without (the energy at the returned poses), as the caller fixed it

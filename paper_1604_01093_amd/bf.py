@@ -58,7 +58,7 @@ class bf_params(ctypes.Structure):
                 ("depth_min", c_double), ("depth_max", c_double), ("preconditioner", c_int32),
                 ("graph", c_int32), ("bidirectional", c_int32), ("dense_tiles", c_int32),
                 ("pcg_spin_limit", c_int32), ("fixed_association", c_void_p),
-                ("sparse_matrix_free", c_int32)]
+                ("sparse_matrix_free", c_int32), ("pcg_threads", c_int32)]
 
 
 class bf_structure(ctypes.Structure):
@@ -109,6 +109,8 @@ _SIGS = {
                                  POINTER(c_double)]),
     "bf_last_timings": (c_int, [c_void_p, POINTER(c_double)]),
     "bf_dense_shape": (c_int, [c_void_p, POINTER(c_int32)]),
+    "bf_workspace_bytes": (c_int, [c_void_p, POINTER(c_int64)]),
+    "bf_pcg_threads": (c_int, [c_void_p, POINTER(c_int32)]),
     "bf_graph_captures": (ctypes.c_int64, [c_void_p]),
 }
 
@@ -232,6 +234,18 @@ class Context:
         out = (c_int32 * 4)()
         self._check(self.lib.bf_dense_shape(self.h, out))
         return {"jacobians": (out[0], out[1]), "energy": (out[2], out[3])}
+
+    def pcg_threads(self):
+        """Workgroup size of the last per-problem PCG launch (0 before any)."""
+        out = c_int32(0)
+        self._check(self.lib.bf_pcg_threads(self.h, ctypes.byref(out)))
+        return int(out.value)
+
+    def workspace_bytes(self):
+        """Device bytes held by this context's workspace buffers."""
+        out = c_int64(0)
+        self._check(self.lib.bf_workspace_bytes(self.h, ctypes.byref(out)))
+        return int(out.value)
 
     def graph_captures(self):
         """How often this context has captured the Gauss-Newton loop into a graph."""

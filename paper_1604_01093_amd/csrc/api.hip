@@ -26,7 +26,7 @@ struct bf_system {
   hipStream_t stream = nullptr;  // the owner's stream, synchronised before the buffers are freed
   bool built = false;
   bf::Shape shape;
-  int pcg_storage = 0, precond = 0, solve_mode = 0, bidir = 0;
+  int pcg_storage = 0, precond = 0, solve_mode = 0, bidir = 0, pcg_threads = 0;
   unsigned spin_limit = 1u << 26;
   double w_sparse = 0.0;
   bf::Buf eblocks, hij32, hij64, edge_ij, iptr, jptr, ej_sorted, row_ptr, row_entries, frame_of_var, var_of,
@@ -234,6 +234,9 @@ void validate_common(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* 
   if (prm->sparse_matrix_free && prm->graph)
     fail(BF_ERR_UNSUPPORTED, "the matrix-free sparse term is not replayed as a graph");
   if (prm->dense_tiles < 0 || prm->dense_tiles > 16) fail(BF_ERR_INVALID_ARG, "dense_tiles must be within [0, 16]");
+  if (prm->pcg_threads != -1 && prm->pcg_threads != 0 && prm->pcg_threads != 64 && prm->pcg_threads != 128 &&
+      prm->pcg_threads != 256 && prm->pcg_threads != 1024)
+    fail(BF_ERR_INVALID_ARG, "pcg_threads must be -1, 0, 64, 128, 256 or 1024");
   if (prm->dense_threads != 0 && prm->dense_threads != 64 && prm->dense_threads != 128 &&
       prm->dense_threads != 256 && prm->dense_threads != 512)
     fail(BF_ERR_INVALID_ARG, "dense_threads must be 0, 64, 128, 256 or 512");
@@ -282,6 +285,7 @@ void setup(bf_context* ctx, const bf_frames* fr, const bf_intrinsics* in, const 
   c.precond = prm->preconditioner;
   c.bidir = prm->bidirectional;
   c.spin_limit = prm->pcg_spin_limit > 0 ? (unsigned)prm->pcg_spin_limit : (1u << 26);
+  c.pcg_threads = prm->pcg_threads;
   ensure(c.counts, 8 * sizeof(long long));
   ensure(c.flags, sizeof(int));
   set_segments(c, fr->num_frames, offsets, nseg);
@@ -345,6 +349,7 @@ void swap_system(Context& c, bf_system& y) {
   std::swap(c.solve_mode, y.solve_mode);
   std::swap(c.bidir, y.bidir);
   std::swap(c.spin_limit, y.spin_limit);
+  std::swap(c.pcg_threads, y.pcg_threads);
   std::swap(c.sys_w_sparse, y.w_sparse);
   c.seg_host.clear();  // the segment arrays on the device changed hands
   bump_alloc_generation();
@@ -505,23 +510,28 @@ bf_status bf_create(bf_context** out, void* hip_stream) {
   return BF_OK;
 }
 
+// Every device buffer a context owns (grown on demand, freed by bf_destroy).
+static std::vector<Buf*> context_buffers(bf_context* c) {
+  return {&c->nd, &c->grad, &c->kx, &c->ky, &c->kx64, &c->ky64, &c->pair_flags, &c->row_count, &c->row_off, &c->pairs,
+          &c->pair_keys, &c->corr_key, &c->corr_idx, &c->corr_key_sorted, &c->corr_perm, &c->corr_head,
+          &c->corr_group, &c->sparse_ij, &c->sparse_keys, &c->sparse_ptr, &c->moments, &c->in_b,
+          &c->common_scan, &c->edge_ij, &c->edge_keys, &c->edge_dense, &c->edge_sparse, &c->ej_key,
+          &c->ej_idx, &c->ej_key_sorted, &c->ej_sorted, &c->iptr, &c->jptr, &c->free_flag, &c->var_of,
+          &c->frame_of_var, &c->records, &c->eblocks, &c->hij32, &c->hij64, &c->diag32, &c->diag64,
+          &c->minv32, &c->minv64, &c->rhs, &c->poses_work, &c->pcg_vec, &c->stats, &c->trace,
+          &c->cub_tmp, &c->counts, &c->flags, &c->energy,
+          &c->pcg_partials, &c->pcg_barrier, &c->pcg_tags, &c->seg_start, &c->seg_of,
+          &c->seg_var_ptr, &c->seg_edge_ptr, &c->sys_poses, &c->mf_u, &c->pr_active, &c->pr_cnt0,
+          &c->pr_cnt, &c->pr_valid, &c->pr_flag, &c->pr_pos, &c->pr_fi, &c->pr_fj, &c->pr_pi, &c->pr_pj,
+          &c->pr_pflag, &c->pr_ppos, &c->pr_pairs, &c->pr_pairs_all, &c->pr_bval, &c->pr_bidx,
+          &c->pr_poses, &c->row_cnt, &c->row_ptr, &c->row_entries, &c->mf_pts, &c->mf_y,
+          &c->ediag_dense, &c->dist_slots, &c->energy_parts};
+}
+
 void bf_destroy(bf_context* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  Buf* bufs[] = {&c->nd, &c->grad, &c->kx, &c->ky, &c->kx64, &c->ky64, &c->pair_flags, &c->row_count, &c->row_off, &c->pairs,
-                 &c->pair_keys, &c->corr_key, &c->corr_idx, &c->corr_key_sorted, &c->corr_perm, &c->corr_head,
-                 &c->corr_group, &c->sparse_ij, &c->sparse_keys, &c->sparse_ptr, &c->moments, &c->in_b,
-                 &c->common_scan, &c->edge_ij, &c->edge_keys, &c->edge_dense, &c->edge_sparse, &c->ej_key,
-                 &c->ej_idx, &c->ej_key_sorted, &c->ej_sorted, &c->iptr, &c->jptr, &c->free_flag, &c->var_of,
-                 &c->frame_of_var, &c->records, &c->eblocks, &c->hij32, &c->hij64, &c->diag32, &c->diag64,
-                 &c->minv32, &c->minv64, &c->rhs, &c->poses_work, &c->pcg_vec, &c->stats, &c->trace,
-                 &c->cub_tmp, &c->counts, &c->flags, &c->energy,
-                 &c->pcg_partials, &c->pcg_barrier, &c->pcg_tags, &c->seg_start, &c->seg_of,
-                 &c->seg_var_ptr, &c->seg_edge_ptr, &c->sys_poses, &c->mf_u, &c->pr_active, &c->pr_cnt0,
-                 &c->pr_cnt, &c->pr_valid, &c->pr_flag, &c->pr_pos, &c->pr_fi, &c->pr_fj, &c->pr_pi, &c->pr_pj,
-                 &c->pr_pflag, &c->pr_ppos, &c->pr_pairs, &c->pr_pairs_all, &c->pr_bval, &c->pr_bidx,
-                 &c->pr_poses, &c->row_cnt, &c->row_ptr, &c->row_entries, &c->mf_pts, &c->mf_y,
-                 &c->ediag_dense, &c->dist_slots, &c->energy_parts};
+  const std::vector<Buf*> bufs = context_buffers(c);
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->rb_small) (void)hipHostFree(c->rb_small);
@@ -532,6 +542,20 @@ void bf_destroy(bf_context* c) {
   delete c->noalloc;  // its buffers lie in the static scratch array: nothing to free
   delete c;
   --g_live_contexts;
+}
+
+bf_status bf_pcg_threads(const bf_context* ctx, int32_t* out_threads) {
+  if (!ctx || !out_threads) return BF_ERR_INVALID_ARG;
+  *out_threads = ctx->pcg_threads_last;
+  return BF_OK;
+}
+
+bf_status bf_workspace_bytes(const bf_context* ctx, int64_t* out_bytes) {
+  if (!ctx || !out_bytes) return BF_ERR_INVALID_ARG;
+  int64_t total = 0;
+  for (const Buf* b : context_buffers(const_cast<bf_context*>(ctx))) total += (int64_t)b->cap;
+  *out_bytes = total;
+  return BF_OK;
 }
 
 const char* bf_status_string(bf_status s) {
@@ -825,7 +849,7 @@ std::vector<unsigned char> graph_key(const Context& c, const bf_intrinsics* in, 
   add(&gen, sizeof gen);
   add(&init_poses, sizeof init_poses);
   add(&out_poses, sizeof out_poses);
-  const int other[] = {nt_jac, nt_eval, c.pcg_storage, c.precond, c.solve_mode};
+  const int other[] = {nt_jac, nt_eval, c.pcg_storage, c.precond, c.solve_mode, per_problem_pcg_threads(const_cast<Context&>(c), false)};
   add(other, sizeof other);
   return k;
 }
@@ -856,14 +880,17 @@ void launch_loop_graph(Context& c, const bf_intrinsics* in, const bf_params* prm
     c.stream = c.capture_stream;
     hipGraph_t g = nullptr;
     check_hip(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    c.in_capture = true;
     try {
       enqueue_loop(c, in, prm, init_poses, out_poses, nullptr);
     } catch (...) {
       (void)hipStreamEndCapture(c.stream, &g);
       if (g) (void)hipGraphDestroy(g);
       c.stream = user;
+      c.in_capture = false;
       throw;
     }
+    c.in_capture = false;
     hipError_t e = hipStreamEndCapture(c.stream, &g);
     c.stream = user;
     check_hip(e, "end capture");

@@ -90,6 +90,10 @@ struct Context {
   size_t rb_big_cap = 0;
   // threads per dense pair job chosen by timing, per (pixels per frame, precision mode, Jacobians)
   std::map<long long, int> dense_threads;
+  int pcg_threads = 0;                   // per-problem PCG workgroup size: 0 = 256, -1 = timed, else fixed
+  bool in_capture = false;               // the Gauss-Newton loop is being captured into a graph
+  int pcg_threads_last = 0;              // workgroup size of the last per-problem PCG launch
+  std::map<long long, int> pcg_threads_timed;  // timed choices by (storage, problem count range, largest problem)
   int pcg_grid = 0;       // workgroups of the cooperative PCG kernel (0 = not yet chosen)
   // replicated-vector PCG: exchange tags used so far since the last clear
   unsigned pcg_tag_base = 0;
@@ -149,6 +153,9 @@ void launch_dense(Context& c, const bf_intrinsics& in, const double* poses, cons
 // Launch shape launch_dense() will use, threads * 16 + tiles per job (timing the
 // candidates first when params.dense_threads is 0 and the shape is new in this
 // context); also sizes the records for it.
+// Workgroup size of the per-problem PCG kernel for the current system (timed when
+// asked for and allowed and not yet known).
+int per_problem_pcg_threads(Context& c, bool may_time, int iters = 0);
 int dense_threads_for(Context& c, const bf_intrinsics& in, const double* poses, const bf_params& prm, double wd,
                       bool with_jacobians);
 // Whole-job records [jobs][kRecWords] of the last dense launch (its tiles summed).

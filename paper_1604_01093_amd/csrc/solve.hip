@@ -17,6 +17,8 @@
 #include <atomic>
 #include <mutex>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace bf {
@@ -2310,8 +2312,78 @@ bool solve_per_problem(const Context& c) {
 }
 
 void prepare_solve(Context& c) {
-  if (c.pcg_storage == 1) set_single_lds_limit<double, 256>();
-  else set_single_lds_limit<float, 256>();
+  if (c.pcg_storage == 1) {
+    set_single_lds_limit<double, 64>();
+    set_single_lds_limit<double, 128>();
+    set_single_lds_limit<double, 256>();
+    set_single_lds_limit<double, 1024>();
+  } else {
+    set_single_lds_limit<float, 64>();
+    set_single_lds_limit<float, 128>();
+    set_single_lds_limit<float, 256>();
+    set_single_lds_limit<float, 1024>();
+  }
+}
+
+namespace {
+
+// The per-problem kernel with workgroups of nt threads (64, 128, 256 or 1024).
+bool launch_per_problem(Context& c, int nt, int iters, double* trace_slot, double* delta_out, double* poses,
+                        double* stats, bool update) {
+  auto go = [&](auto ntc) {
+    constexpr int NT = decltype(ntc)::value;
+    return c.pcg_storage == 1
+               ? launch_solve_single<double, NT>(c, iters, trace_slot, delta_out, poses, stats, update,
+                                                 c.diag64.as<double>(), c.minv64.as<double>(), c.hij64.as<double>())
+               : launch_solve_single<float, NT>(c, iters, trace_slot, delta_out, poses, stats, update,
+                                                c.diag32.as<float>(), c.minv32.as<float>(), c.hij32.as<float>());
+  };
+  switch (nt) {
+    case 64: return go(std::integral_constant<int, 64>{});
+    case 128: return go(std::integral_constant<int, 128>{});
+    case 1024: return go(std::integral_constant<int, 1024>{});
+    default: return go(std::integral_constant<int, 256>{});
+  }
+}
+
+}  // namespace
+
+// params.pcg_threads: 0 = 256, a size, or -1 = the fastest size for this (storage,
+// problem count range, largest problem), timed once on the current system: each
+// candidate launched once, then three times between two events, with no pose
+// update, increment, statistics or trace written (only the flags the real solve
+// would raise as well).  No timing while a graph is being captured.
+int per_problem_pcg_threads(Context& c, bool may_time, int iters) {
+  if (c.pcg_threads > 0) return c.pcg_threads;
+  if (c.pcg_threads == 0) return 256;
+  int bucket = 0;
+  while (bucket < 40 && (1LL << bucket) < c.shape.nseg) ++bucket;
+  const long long key = ((long long)c.shape.max_seg_free * 64 + bucket) * 2 + c.pcg_storage;
+  auto it = c.pcg_threads_timed.find(key);
+  if (it != c.pcg_threads_timed.end()) return it->second;
+  if (!may_time || c.in_capture || iters <= 0) return 256;
+  hipEvent_t e0, e1;
+  check_hip(hipEventCreate(&e0), "hipEventCreate");
+  check_hip(hipEventCreate(&e1), "hipEventCreate");
+  int best = 256;
+  float best_ms = 1e30f;
+  for (int nt : {64, 128, 256, 1024}) {
+    if (!launch_per_problem(c, nt, iters, nullptr, nullptr, nullptr, nullptr, false)) continue;  // warm-up
+    check_hip(hipEventRecord(e0, c.stream), "hipEventRecord");
+    for (int r = 0; r < 3; ++r) launch_per_problem(c, nt, iters, nullptr, nullptr, nullptr, nullptr, false);
+    check_hip(hipEventRecord(e1, c.stream), "hipEventRecord");
+    check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = nt;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.pcg_threads_timed[key] = best;
+  return best;
 }
 
 void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, double* poses_inout, double* stats,
@@ -2337,14 +2409,11 @@ void launch_solve(Context& c, int iters, double* trace_slot, double* delta_out, 
   if (many && c.solve_mode != 0 && c.solve_mode != 4)
     fail(BF_ERR_UNSUPPORTED, "several problems are solved by the per-problem kernel (solve_kernel 0 or 4)");
   if (solve_per_problem(c)) {
-    bool ok = c.pcg_storage == 1
-                  ? launch_solve_single<double, 256>(c, iters, trace_slot, delta_out, poses_inout, stats,
-                                                     update_poses, c.diag64.as<double>(), c.minv64.as<double>(),
-                                                     c.hij64.as<double>())
-                  : launch_solve_single<float, 256>(c, iters, trace_slot, delta_out, poses_inout, stats,
-                                                    update_poses, c.diag32.as<float>(), c.minv32.as<float>(),
-                                                    c.hij32.as<float>());
-    if (ok) return;
+    const int nt = per_problem_pcg_threads(c, true, iters);
+    if (launch_per_problem(c, nt, iters, trace_slot, delta_out, poses_inout, stats, update_poses)) {
+      c.pcg_threads_last = nt;
+      return;
+    }
     fail(BF_ERR_UNSUPPORTED, "a problem's PCG vectors do not fit in one workgroup's LDS");
   }
   if (c.solve_mode == 0 || c.solve_mode == 3) {

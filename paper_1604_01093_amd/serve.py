@@ -22,6 +22,16 @@ interrupted (it is one launch sequence over all members), the other members
 complete as usual and the cancelled one completes with a `Cancelled` error and
 no result.
 
+Warm start (paper Sec. 4.4: each solve starts from the result of the last one):
+a request that names a problem (`key`) leaves its result poses resident under
+that key; a later request with the same key and `warm_start=True` starts from
+them instead of its own initial poses, for as many leading frames as the stored
+result has (a grown problem, one with new frames appended, keeps its own initial
+poses for the new frames).  The stored result is the one of the last request of
+that key completed when the warm request starts running; if none has completed,
+the request starts from its own initial poses (`Request.warm_frames` says how many
+frames were warm-started).
+
 Every computation of a solve runs in libbf's kernels; this module only
 queues, groups, concatenates device tensors and records times.
 """
@@ -37,17 +47,25 @@ from . import bf
 
 
 def footprint_bytes(num_frames, width, height, num_corrs, num_pairs=None, directions=1):
-    """Estimated device bytes of one solve: inputs, prepared frames, pair search
-    flags, pair records (one per pair job: `directions` per pair), edge blocks and
-    correspondence indexing (upper bound on the pair count when it is not known)."""
+    """Estimated device bytes of one solve: the inputs (depth and intensity, the
+    correspondences' frame indices and points) and the context's workspace --
+    prepared frames, pair search flags, pair records (one per pair job: `directions`
+    per pair, up to four partial records each when the dense launch splits jobs into
+    tiles), edge blocks, correspondence indexing and sorting -- with the workspace
+    taken a quarter larger (its buffers grow by a quarter more than asked) plus 1 MiB
+    for the small fixed buffers.  The pair count is bounded by F (F - 1) / 2 when it
+    is not known."""
     F, HW = int(num_frames), int(width) * int(height)
     P = int(num_pairs) if num_pairs is not None else F * (F - 1) // 2
-    frames = F * HW * (8 + 20)
+    M = int(num_corrs)
+    inputs = F * HW * 8 + M * 32
+    frames = F * HW * 20
     pair_search = F * F + 24 * (F + 1)
-    records = P * (256 * int(directions) + 16)
+    records = P * (4 * 256 * int(directions) + 16)
     edges = (P + F) * (1024 + 144 + 64)
-    corr = int(num_corrs) * (24 + 8 + 96)
-    return frames + pair_search + records + edges + corr + 64 * F * 16
+    corr = M * 96
+    work = frames + pair_search + records + edges + corr + 64 * F * 16
+    return inputs + work + work // 4 + (1 << 20)
 
 
 class Cancelled(RuntimeError):
@@ -59,13 +77,17 @@ class Request:
 
     _next_id = 0
 
-    def __init__(self, problem: "bf.DeviceProblem", init_poses: torch.Tensor, params, tag=None):
+    def __init__(self, problem: "bf.DeviceProblem", init_poses: torch.Tensor, params, tag=None, key=None,
+                 warm_start=False):
         self.id = Request._next_id
         Request._next_id += 1
         self.problem = problem
         self.init_poses = init_poses
         self.params = params
         self.tag = tag
+        self.key = key
+        self.warm_start = bool(warm_start) and key is not None
+        self.warm_frames = 0
         self.num_frames = problem.num_frames
         intr = problem.intr
         self.intr_key = (intr.fx, intr.fy, intr.cx, intr.cy, intr.width, intr.height)
@@ -103,6 +125,7 @@ class Server:
         self.stop = False
         self.lanes = []
         self.batches = []  # (number of requests, seconds) of every batch-lane call
+        self.resident = {}  # key -> result poses (device) of the last completed request of that key
         for name, fn in (("batch", self._batch_lane), ("large", self._large_lane)):
             stream = torch.cuda.Stream()
             ctx = bf.Context(stream=stream)
@@ -206,7 +229,30 @@ class Server:
                 if r.cancelled and err is None:
                     r.error = Cancelled(f"request {r.id} cancelled while running")
                     r.poses = r.energy = None
+                if r.key is not None and r.error is None:
+                    self.resident[r.key] = r.poses
                 r.done.set()
+
+    def _initial_poses(self, r):
+        """The poses a request starts from (on the current stream): its own, or with
+        warm start the leading frames from the resident result of its key."""
+        if not r.warm_start:
+            return r.init_poses
+        with self.cv:
+            prev = self.resident.get(r.key)
+        if prev is None:
+            return r.init_poses
+        n = min(prev.shape[0], r.num_frames)
+        init = r.init_poses.clone()
+        init[:n].copy_(prev[:n])
+        r.warm_frames = n
+        return init
+
+    def forget(self, key):
+        """Drop the resident result of `key` (its device memory is freed when no
+        request holds it)."""
+        with self.cv:
+            self.resident.pop(key, None)
 
     def _batch_lane(self, ctx, stream):
         while True:
@@ -218,12 +264,13 @@ class Server:
                 with torch.cuda.stream(stream):
                     for r in reqs:
                         stream.wait_event(r.ready_event)
+                    inits = [self._initial_poses(r) for r in reqs]
                     if len(reqs) == 1:
                         r = reqs[0]
-                        res = bf.bf_gauss_newton(ctx, r.problem, r.init_poses, r.params)
+                        res = bf.bf_gauss_newton(ctx, r.problem, inits[0], r.params)
                         r.poses, r.energy = res["poses"], res["energy"]
                     else:
-                        dp, offs, init = concat_device(reqs)
+                        dp, offs, init = concat_device(reqs, inits)
                         res = bf.bf_gauss_newton_batch(ctx, dp, offs, init, reqs[0].params)
                         for b, r in enumerate(reqs):
                             r.poses = res["poses"][offs[b]:offs[b + 1]].clone()
@@ -246,7 +293,7 @@ class Server:
             try:
                 with torch.cuda.stream(stream):
                     stream.wait_event(r.ready_event)
-                    res = bf.bf_gauss_newton(ctx, r.problem, r.init_poses, r.params)
+                    res = bf.bf_gauss_newton(ctx, r.problem, self._initial_poses(r), r.params)
                     r.poses, r.energy = res["poses"], res["energy"]
                     stream.synchronize()
                 self._finish(reqs, "large", t0)
@@ -256,16 +303,17 @@ class Server:
                 self._release(reqs)
 
 
-def concat_device(reqs):
+def concat_device(reqs, inits=None):
     """One DeviceProblem over the requests' frames (device copies on the current
-    stream), their frame offsets and initial poses."""
+    stream), their frame offsets and initial poses (`inits`, else the requests'
+    own)."""
     offs = [0]
     for r in reqs:
         offs.append(offs[-1] + r.num_frames)
     P = [r.problem for r in reqs]
     depth = torch.cat([p.depth for p in P])
     inten = torch.cat([p.intensity for p in P])
-    init = torch.cat([r.init_poses for r in reqs])
+    init = torch.cat(inits if inits is not None else [r.init_poses for r in reqs])
     with_c = [p for p in P if p.num_corrs > 0]
     if with_c:
         ci = torch.cat([p.keep[0] + o for p, o in zip(P, offs) if p.num_corrs > 0])

@@ -161,3 +161,39 @@ def test_batch_rejects_cross_problem_data(ctx, chunks):
     with pytest.raises(bf.BFError) as ei:
         bf.bf_gauss_newton_batch(ctx, dp, offs, init, bf_params_from(prm, solve_kernel=3))
     assert ei.value.status == bf.BF_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("nt", [64, 128, 1024])
+def test_per_problem_pcg_threads(ctx, chunks, nt):
+    """The per-problem PCG at other workgroup sizes (params.pcg_threads): each size
+    sums in its own fixed order, so the batch's poses stay within the 1e-5 (rad, m)
+    the FP32 path is held to (as for the timed dense shape: an association decision
+    within rounding of a threshold may go the other way) and its energies within
+    1e-5 relative of the 256-thread solve, and a second call is bitwise the first.  With pcg_threads = -1 the size is timed once and kept: two
+    calls agree bitwise and with the fixed size they chose."""
+    prm = Params(num_gn=chunks[0].n_gn, num_pcg=chunks[0].n_pcg)
+    dp, offs, init = bf.device_batch(chunks)
+    ref = bf.bf_gauss_newton_batch(ctx, dp, offs, init, bf_params_from(prm, dense_threads=256))
+    got = bf.bf_gauss_newton_batch(ctx, dp, offs, init, bf_params_from(prm, dense_threads=256, pcg_threads=nt))
+    again = bf.bf_gauss_newton_batch(ctx, dp, offs, init, bf_params_from(prm, dense_threads=256, pcg_threads=nt))
+    assert torch.equal(got["poses"], again["poses"])
+    rot, tr = pose_errors(got["poses"].cpu().numpy(), ref["poses"].cpu().numpy())
+    print(f"per-problem PCG with {nt} threads: {rot:.1e} rad {tr:.1e} m from 256 threads", flush=True)
+    assert rot < 1e-5 and tr < 1e-5
+    for b in range(len(chunks)):
+        assert abs(got["energy"][b]["total"] - ref["energy"][b]["total"]) <= 1e-5 * ref["energy"][b]["total"]
+    timed = bf.bf_gauss_newton_batch(ctx, dp, offs, init, bf_params_from(prm, dense_threads=256, pcg_threads=-1))
+    timed2 = bf.bf_gauss_newton_batch(ctx, dp, offs, init, bf_params_from(prm, dense_threads=256, pcg_threads=-1))
+    assert torch.equal(timed["poses"], timed2["poses"])
+    matches = [k for k in (64, 128, 256, 1024)
+               if torch.equal(timed["poses"], bf.bf_gauss_newton_batch(
+                   ctx, dp, offs, init, bf_params_from(prm, dense_threads=256, pcg_threads=k))["poses"])]
+    assert matches, "the timed choice equals none of the fixed sizes"
+
+
+def test_pcg_threads_rejects_other_sizes(ctx, chunks):
+    prm = Params(num_gn=1, num_pcg=2)
+    dp, offs, init = bf.device_batch(chunks)
+    with pytest.raises(bf.BFError) as ei:
+        bf.bf_gauss_newton_batch(ctx, dp, offs, init, bf_params_from(prm, pcg_threads=512))
+    assert ei.value.status == bf.BF_ERR_INVALID_ARG

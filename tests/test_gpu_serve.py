@@ -27,10 +27,15 @@ def ctx():
 
 
 @pytest.fixture(scope="module")
-def pool(ctx):
+def g120():
+    return make_global(120, "floor3", config=3, outlier_rate=0.10, corr_range=(200, 200), name="g120",
+                       per_pair_streams=True)
+
+
+@pytest.fixture(scope="module")
+def pool(ctx, g120):
     chunks = make_batch_chunks(count=10, config=3)
-    g = make_global(120, "floor3", config=3, outlier_rate=0.10, corr_range=(200, 200), name="g120",
-                    per_pair_streams=True)
+    g = g120
     wins = [window(g, 5, 40), window(g, 20, 90)]
     p_chunk = bf.bf_params_default(num_gn=5, num_pcg=10, dense_threads=256)
     p_glob = bf.bf_params_default(num_gn=4, num_pcg=20, dense_threads=256)
@@ -125,3 +130,87 @@ def test_cancellation(pool):
         assert server.inflight == 0
     finally:
         server.close()
+
+
+def test_warm_start(ctx, g120):
+    """Warm start (paper Sec. 4.4: a solve starts from the last one's result): a
+    request naming a problem key starts from the resident result of the last
+    completed request of that key -- the same problem solved again, and then a grown
+    problem (15 frames appended) whose 40 leading frames start from that result and
+    the new ones from its own initial poses; a key with no resident result starts
+    cold.  Each result equals bf_gauss_newton called alone with those initial
+    poses, bit for bit."""
+    prm = bf.bf_params_default(num_gn=4, num_pcg=20, dense_threads=256)
+
+    def dev(pr):
+        return (bf.DeviceProblem.from_numpy(pr.depth, pr.intensity, pr.intrinsics, pr.corr_i, pr.corr_j, pr.corr_p,
+                                            pr.corr_q), torch.as_tensor(pr.init_poses).cuda())
+    small, grown = dev(window(g120, 5, 40)), dev(window(g120, 5, 55))
+    server = serve.Server()
+    try:
+        def run(d, key, warm):
+            r = server.submit(serve.Request(d[0], d[1], prm, key=key, warm_start=warm))
+            r.done.wait()
+            assert r.error is None, r.error
+            return r
+        first = run(small, "w", False)
+        assert first.warm_frames == 0
+        again = run(small, "w", True)
+        assert again.warm_frames == 40
+        ref = bf.bf_gauss_newton(ctx, small[0], first.poses, prm)
+        assert torch.equal(again.poses, ref["poses"]) and again.energy == ref["energy"]
+        big = run(grown, "w", True)
+        assert big.warm_frames == 40
+        init = grown[1].clone()
+        init[:40] = again.poses
+        ref = bf.bf_gauss_newton(ctx, grown[0], init, prm)
+        assert torch.equal(big.poses, ref["poses"]) and big.energy == ref["energy"]
+        cold = run(small, "other", True)
+        assert cold.warm_frames == 0
+        ref = bf.bf_gauss_newton(ctx, small[0], small[1], prm)
+        assert torch.equal(cold.poses, ref["poses"])
+        print(f"warm start: energy {first.energy['total']:.6g} cold, {again.energy['total']:.6g} warm; grown problem "
+              f"{big.energy['total']:.6g}", flush=True)
+        server.forget("w")
+        assert "w" not in server.resident
+    finally:
+        server.close()
+
+
+def _input_bytes(d, init):
+    ts = [d.depth, d.intensity, init] + (list(d.keep) if d.num_corrs > 0 else [])
+    return sum(t.numel() * t.element_size() for t in ts)
+
+
+def test_footprint_estimate_covers_workspace(pool):
+    """The admission estimate (serve.footprint_bytes) of every request is at least
+    the device memory its solve holds: the workspace of a fresh context after the
+    solve (bf_workspace_bytes) plus the request's own input tensors; and for a
+    batch of all the chunk requests, the sum of their estimates covers the batch
+    context's workspace plus the concatenated inputs."""
+    dev, _ = pool
+    ratios = []
+    for d, i, prm in dev:
+        c = bf.Context()
+        try:
+            bf.bf_gauss_newton(c, d, i, prm)
+            torch.cuda.synchronize()
+            used = c.workspace_bytes() + _input_bytes(d, i)
+        finally:
+            c.close()
+        est = serve.Request(d, i, prm).footprint
+        ratios.append(est / used)
+        assert est >= used, (d.num_frames, est, used)
+    reqs = [serve.Request(d, i, prm) for d, i, prm in dev if prm is dev[0][2]]  # the chunks
+    c = bf.Context()
+    try:
+        dp, offs, init = serve.concat_device(reqs)
+        bf.bf_gauss_newton_batch(c, dp, offs, init, reqs[0].params)
+        torch.cuda.synchronize()
+        used = c.workspace_bytes() + _input_bytes(dp, init)
+    finally:
+        c.close()
+    est = sum(r.footprint for r in reqs)
+    print(f"footprint estimate / device bytes held: {min(ratios):.2f}..{max(ratios):.2f} per request, "
+          f"{est / used:.2f} for a batch of {len(reqs)}", flush=True)
+    assert est >= used
