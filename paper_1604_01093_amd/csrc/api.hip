@@ -397,8 +397,10 @@ void raise_flags(int fl) {
 }
 
 // HIP events on the context's stream.  Level 1 marks every phase; level 2 only the
-// dense launches and the whole call (each recorded event leaves the GPU idle for a
-// few microseconds, about 6 % of a 200-keyframe solve at level 1).
+// dense launches and the whole call.  The events only time (their elapsed times are
+// read after the call's final synchronisation), so they are recorded without the
+// system-scope fence a default event carries: that fence's cache write-back and
+// invalidation left the GPU idle for about 5 us per event.
 struct Timer {
   bf_context* ctx;
   bool on;
@@ -412,7 +414,7 @@ struct Timer {
     if (!on) return -1;
     if (used >= (int)ctx->pool.size()) {
       hipEvent_t e;
-      check_hip(hipEventCreate(&e), "hipEventCreate");
+      check_hip(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreateWithFlags");
       ctx->pool.push_back(e);
     }
     check_hip(hipEventRecord(ctx->pool[used], ctx->stream), "hipEventRecord");
