@@ -422,7 +422,8 @@ def main():
                    "gn_iters": prob.n_gn, "pcg_iters": prob.n_pcg,
                    "pcg_storage": "fp64" if args.pcg_storage else "fp32",
                    "accumulate": ["fp32", "fp32-two-sum", "fp64"][args.accumulate],
-                   "solve_kernel": ["auto", "single", "coop", "replicated", "per-problem"][args.solve_kernel],
+                   "solve_kernel": ["auto", "single", "coop", "replicated", "per-problem",
+                                    "distributed"][args.solve_kernel],
                    "dense_launch": f"{shape[0]} threads x {shape[1]} tiles per pair job" +
                                    ("" if args.dense_threads else " (the timed choice)"),
                    "preconditioner": ["block-jacobi", "jacobi"][args.preconditioner]},
