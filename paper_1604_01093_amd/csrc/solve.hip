@@ -25,11 +25,339 @@ namespace bf {
 
 namespace {
 
+// Edge blocks, one lane per edge (used when there are enough edges to fill the
+// GPU one lane each; the wavefront-per-edge kernel below serves fewer edges):
+// the same quantities, each lane reading its edge's records and moments and
+// forming the 6x6 products in registers.
+__device__ __forceinline__ int eps3(int a, int b, int c) {
+  // Levi-Civita symbol for indices in {0,1,2}
+  return ((a - b) * (b - c) * (c - a)) / 2;
+}
+
+__device__ __forceinline__ void skew(const double* v, double* S) {
+  S[0] = 0;
+  S[1] = -v[2];
+  S[2] = v[1];
+  S[3] = v[2];
+  S[4] = 0;
+  S[5] = -v[0];
+  S[6] = -v[1];
+  S[7] = v[0];
+  S[8] = 0;
+}
+
+template <class T>
+__global__ void __launch_bounds__(64) k_edge_blocks_lane(const int* __restrict__ eij, long long E,
+                                                    const long long* __restrict__ edense,
+                                                    const long long* __restrict__ esparse,
+                                                    const double* __restrict__ mom, const double* __restrict__ rec,
+                                                    long long P, int bidir, int tiles,
+                                                    const double* __restrict__ poses, double w_sparse, int jac,
+                                                    double* __restrict__ eb, T* __restrict__ hij_store,
+                                                    double* __restrict__ ediag_dense) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int i = eij[2 * e], j = eij[2 * e + 1];
+  double R[9], t[3];
+  relative_pose_nc(poses + (size_t)i * 16, poses + (size_t)j * 16, R, t);
+  double* out = eb + (size_t)e * kEdgeWords;
+  const long long s = esparse[e];
+  const long long d = edense[e];
+
+  double Hjj_d[36];
+  double gj_d[6];
+  for (int k = 0; k < 36; ++k) Hjj_d[k] = 0.0;
+  for (int k = 0; k < 6; ++k) gj_d[k] = 0.0;
+  double Eg = 0, Ep = 0, ng = 0, np = 0;
+  // a pair job's record is the sum of its `tiles` partial records, in tile order
+  if (d >= 0) {
+    for (int tl = 0; tl < tiles; ++tl) {
+      const double* r = rec + ((size_t)d * tiles + tl) * kRecWords;
+      if (jac) {
+        int k = 0;
+        for (int a = 0; a < 6; ++a)
+          for (int b = a; b < 6; ++b) {
+            Hjj_d[6 * a + b] += r[k];
+            ++k;
+          }
+        for (int a = 0; a < 6; ++a) gj_d[a] += r[kRecG + a];
+      }
+      Eg += r[kRecEg];
+      Ep += r[kRecEp];
+      ng += r[kRecNg];
+      np += r[kRecNp];
+    }
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < a; ++b) Hjj_d[6 * a + b] = Hjj_d[6 * b + a];
+  }
+  // the reverse job (j -> i, record P + d): its block is the one of frame i
+  double Hii_r[36], gi_r[6];
+  const bool has_rev = bidir && d >= 0;
+  for (int k = 0; k < 36; ++k) Hii_r[k] = 0.0;
+  for (int k = 0; k < 6; ++k) gi_r[k] = 0.0;
+  if (has_rev) {
+    for (int tl = 0; tl < tiles; ++tl) {
+      const double* r = rec + ((size_t)(P + d) * tiles + tl) * kRecWords;
+      if (jac) {
+        int k = 0;
+        for (int a = 0; a < 6; ++a)
+          for (int b = a; b < 6; ++b) {
+            Hii_r[6 * a + b] += r[k];
+            ++k;
+          }
+        for (int a = 0; a < 6; ++a) gi_r[a] += r[kRecG + a];
+      }
+      Eg += r[kRecEg];
+      Ep += r[kRecEp];
+      ng += r[kRecNg];
+      np += r[kRecNp];
+    }
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < a; ++b) Hii_r[6 * a + b] = Hii_r[6 * b + a];
+  }
+  double Es = 0, ns = 0;
+  // sparse moments
+  double n = 0, sp[3] = {0, 0, 0}, sq[3] = {0, 0, 0}, Spp[9], Sqq[9], Spq[9];
+  for (int k = 0; k < 9; ++k) Spp[k] = Sqq[k] = Spq[k] = 0.0;
+  if (s >= 0) {
+    const double* m = mom + (size_t)s * kMomWords;
+    n = m[kMN];
+    for (int a = 0; a < 3; ++a) {
+      sp[a] = m[kMP + a];
+      sq[a] = m[kMQ + a];
+    }
+    for (int k = 0; k < 9; ++k) {
+      Spp[k] = m[kMPP + k];
+      Sqq[k] = m[kMQQ + k];
+      Spq[k] = m[kMPQ + k];
+    }
+    ns = n;
+    // E = w [tr Spp + tr Sqq + n |t|^2 + 2 t^T R sp - 2 t^T sq - 2 sum_cd R_cd Spq[d][c]]
+    double Rsp[3];
+    for (int a = 0; a < 3; ++a) Rsp[a] = R[3 * a] * sp[0] + R[3 * a + 1] * sp[1] + R[3 * a + 2] * sp[2];
+    double qRp = 0.0;
+    for (int c2 = 0; c2 < 3; ++c2)
+      for (int d2 = 0; d2 < 3; ++d2) qRp += R[3 * c2 + d2] * Spq[3 * d2 + c2];
+    double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    double tRsp = t[0] * Rsp[0] + t[1] * Rsp[1] + t[2] * Rsp[2];
+    double tsq = t[0] * sq[0] + t[1] * sq[1] + t[2] * sq[2];
+    Es = w_sparse * ((Spp[0] + Spp[4] + Spp[8]) + (Sqq[0] + Sqq[4] + Sqq[8]) + n * tt + 2.0 * tRsp - 2.0 * tsq -
+                     2.0 * qRp);
+  }
+  if (jac) {
+    const double w = w_sparse;
+    // H_jj
+    {
+      double S[9];
+      skew(sq, S);
+      double trq = Sqq[0] + Sqq[4] + Sqq[8];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double top = (a == b ? trq : 0.0) - Sqq[3 * a + b];
+          out[kEHjj + 6 * a + b] = Hjj_d[6 * a + b] + w * top;
+          out[kEHjj + 6 * a + (b + 3)] = Hjj_d[6 * a + b + 3] + w * S[3 * a + b];
+          out[kEHjj + 6 * (a + 3) + b] = Hjj_d[6 * (a + 3) + b] - w * S[3 * a + b];
+          out[kEHjj + 6 * (a + 3) + (b + 3)] = Hjj_d[6 * (a + 3) + b + 3] + (a == b ? w * n : 0.0);
+        }
+    }
+    // reverse job: Ad(T_ij) = [[R^T, 0], [[t2]x R^T, R^T]] with t2 = -R^T t;
+    // H_jj += Ad2^T Hii_r Ad2 (symmetrised), H_ij -= Hii_r Ad2, g_j -= Ad2^T gi_r
+    double Y2[36], R2[9], TR2[9];
+    if (has_rev) {
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) R2[3 * a + b] = R[3 * b + a];
+      double t2[3], Tx2[9];
+      for (int a = 0; a < 3; ++a) t2[a] = -(R2[3 * a] * t[0] + R2[3 * a + 1] * t[1] + R2[3 * a + 2] * t[2]);
+      skew(t2, Tx2);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          TR2[3 * a + b] = Tx2[3 * a] * R2[b] + Tx2[3 * a + 1] * R2[3 + b] + Tx2[3 * a + 2] * R2[6 + b];
+    }
+    auto ad2 = [&](int r, int c) -> double {
+      if (r < 3) return c < 3 ? R2[3 * r + c] : 0.0;
+      return c < 3 ? TR2[3 * (r - 3) + c] : R2[3 * (r - 3) + (c - 3)];
+    };
+    double Z2[36];
+    if (has_rev) {
+      // Y2 = Hii_r Ad2
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          double v = 0.0;
+          for (int k = 0; k < 6; ++k) v += Hii_r[6 * a + k] * ad2(k, b);
+          Y2[6 * a + b] = v;
+        }
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          double v = 0.0;
+          for (int k = 0; k < 6; ++k) v += ad2(k, a) * Y2[6 * k + b];
+          Z2[6 * a + b] = v;
+        }
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) out[kEHjj + 6 * a + b] += 0.5 * (Z2[6 * a + b] + Z2[6 * b + a]);
+    }
+    // H_ii sparse part
+    double Hii[36];
+    {
+      double S[9];
+      skew(sp, S);
+      double trp = Spp[0] + Spp[4] + Spp[8];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          Hii[6 * a + b] = w * ((a == b ? trp : 0.0) - Spp[3 * a + b]);
+          Hii[6 * a + b + 3] = w * S[3 * a + b];
+          Hii[6 * (a + 3) + b] = -w * S[3 * a + b];
+          Hii[6 * (a + 3) + b + 3] = (a == b ? w * n : 0.0);
+        }
+    }
+    // Ad(T_ji) = [[R, 0], [[t]x R, R]];  Y = Ad^T Hjj_d;  H_ii += Y Ad;  H_ij = -Y (+ sparse)
+    double TR[9];
+    {
+      double Tx[9];
+      skew(t, Tx);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) TR[3 * a + b] = Tx[3 * a] * R[b] + Tx[3 * a + 1] * R[3 + b] + Tx[3 * a + 2] * R[6 + b];
+    }
+    auto ad = [&](int r, int c) -> double {
+      if (r < 3) return c < 3 ? R[3 * r + c] : 0.0;
+      return c < 3 ? TR[3 * (r - 3) + c] : R[3 * (r - 3) + (c - 3)];
+    };
+    double Y[36];
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) {
+        double v = 0.0;
+        for (int k = 0; k < 6; ++k) v += ad(k, a) * Hjj_d[6 * k + b];
+        Y[6 * a + b] = v;
+      }
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) {
+        double v = 0.0;
+        for (int k = 0; k < 6; ++k) v += Y[6 * a + k] * ad(k, b);
+        Hii[6 * a + b] += v + Hii_r[6 * a + b];
+        // the dense term's part alone (matrix-free sparse mode: the product takes the
+        // sparse part per correspondence)
+        if (ediag_dense) ediag_dense[(size_t)e * 72 + 6 * a + b] = v + Hii_r[6 * a + b];
+      }
+    if (ediag_dense) {
+      double* dd = ediag_dense + (size_t)e * 72;
+      for (int a = 0; a < 6; ++a)
+        for (int b = a + 1; b < 6; ++b) {
+          const double v = 0.5 * (dd[6 * a + b] + dd[6 * b + a]);
+          dd[6 * a + b] = v;
+          dd[6 * b + a] = v;
+        }
+      // H_jj of the dense term: the forward job's block and the reverse job's, as above
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          double v = Hjj_d[6 * a + b];
+          if (has_rev) v += 0.5 * (Z2[6 * a + b] + Z2[6 * b + a]);
+          dd[36 + 6 * a + b] = v;
+        }
+    }
+    // symmetrise: both triangles from the same sums
+    for (int a = 0; a < 6; ++a)
+      for (int b = a + 1; b < 6; ++b) {
+        double v = 0.5 * (Hii[6 * a + b] + Hii[6 * b + a]);
+        Hii[6 * a + b] = v;
+        Hii[6 * b + a] = v;
+      }
+    for (int k = 0; k < 36; ++k) out[kEHii + k] = Hii[k];
+    // H_ij: sparse = -sum A_p^T R^T A_q = [[sum [p]x R^T [q]x, -[sp]x R^T], [R^T [sq]x, -n R^T]]
+    double Hij[36];
+    {
+      double Rt[9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Rt[3 * a + b] = R[3 * b + a];
+      double Sp[9], Sq[9];
+      skew(sp, Sp);
+      skew(sq, Sq);
+      for (int r = 0; r < 3; ++r)
+        for (int c2 = 0; c2 < 3; ++c2) {
+          // sum_k [p_k]x Rt [q_k]x = sum eps(r,k,m) eps(l,c,n) Rt[k][l] Spq[m][n]
+          double tl = 0.0;
+          for (int k = 0; k < 3; ++k)
+            for (int m = 0; m < 3; ++m) {
+              int e1 = eps3(r, k, m);
+              if (!e1) continue;
+              for (int l = 0; l < 3; ++l)
+                for (int nn = 0; nn < 3; ++nn) {
+                  int e2 = eps3(l, c2, nn);
+                  if (!e2) continue;
+                  tl += (double)(e1 * e2) * Rt[3 * k + l] * Spq[3 * m + nn];
+                }
+            }
+          double tr = 0.0, bl = 0.0;
+          for (int k = 0; k < 3; ++k) {
+            tr -= Sp[3 * r + k] * Rt[3 * k + c2];
+            bl += Rt[3 * r + k] * Sq[3 * k + c2];
+          }
+          Hij[6 * r + c2] = w * tl;
+          Hij[6 * r + c2 + 3] = w * tr;
+          Hij[6 * (r + 3) + c2] = w * bl;
+          Hij[6 * (r + 3) + c2 + 3] = -w * n * Rt[3 * r + c2];
+        }
+    }
+    for (int k = 0; k < 36; ++k) {
+      const double vd = -Y[k] - (has_rev ? Y2[k] : 0.0);
+      double v = Hij[k] - Y[k] - (has_rev ? Y2[k] : 0.0);
+      out[kEHij + k] = v;
+      // the PCG's copy: the dense term's block alone in matrix-free sparse mode
+      hij_store[(size_t)e * 36 + k] = (T)(ediag_dense ? vd : v);
+    }
+    // gradients.  g_i sparse = w [sp x (R^T t) - sum p x (R^T q); sp + n R^T t - R^T sq]
+    //             g_j sparse = -w [sum q x (R p) + sq x t; R sp + n t - sq]
+    double Rtt[3], Rtsq[3], Rsp[3];
+    for (int a = 0; a < 3; ++a) {
+      Rtt[a] = R[a] * t[0] + R[3 + a] * t[1] + R[6 + a] * t[2];
+      Rtsq[a] = R[a] * sq[0] + R[3 + a] * sq[1] + R[6 + a] * sq[2];
+      Rsp[a] = R[3 * a] * sp[0] + R[3 * a + 1] * sp[1] + R[3 * a + 2] * sp[2];
+    }
+    double gi[6], gj[6];
+    for (int a = 0; a < 3; ++a) {
+      int b = (a + 1) % 3, c2 = (a + 2) % 3;
+      double sx = sp[b] * Rtt[c2] - sp[c2] * Rtt[b];
+      double pxRq = 0.0, qxRp = 0.0;
+      for (int bb = 0; bb < 3; ++bb)
+        for (int cc = 0; cc < 3; ++cc) {
+          int ep = eps3(a, bb, cc);
+          if (!ep) continue;
+          for (int dd = 0; dd < 3; ++dd) {
+            pxRq += ep * R[3 * dd + cc] * Spq[3 * bb + dd];   // sum p_b (R^T q)_c
+            qxRp += ep * R[3 * cc + dd] * Spq[3 * dd + bb];   // sum q_b (R p)_c
+          }
+        }
+      double sqxt = sq[b] * t[c2] - sq[c2] * t[b];
+      gi[a] = w * (sx - pxRq);
+      gi[a + 3] = w * (sp[a] + n * Rtt[a] - Rtsq[a]);
+      gj[a] = -w * (qxRp + sqxt);
+      gj[a + 3] = -w * (Rsp[a] + n * t[a] - sq[a]);
+    }
+    // dense: g_j += gj_d, g_i -= Ad^T gj_d
+    for (int a = 0; a < 6; ++a) {
+      double v = 0.0, v2 = 0.0;
+      for (int k = 0; k < 6; ++k) v += ad(k, a) * gj_d[k];
+      if (has_rev)
+        for (int k = 0; k < 6; ++k) v2 += ad2(k, a) * gi_r[k];
+      out[kEGi + a] = gi[a] - v + gi_r[a];
+      out[kEGj + a] = gj[a] + gj_d[a] - v2;
+    }
+  }
+  out[kEEs] = Es;
+  out[kEEg] = Eg;
+  out[kEEp] = Ep;
+  out[kENs] = ns;
+  out[kENg] = ng;
+  out[kENp] = np;
+}
+
 // Edge blocks: one wavefront per edge, four edges per workgroup.  The lanes load
 // the pair job's records (tiles summed in order) and the sparse moments into LDS;
 // then every 6x6 product and output entry is one lane's (entry (a, b) = lane
 // 6a + b), with wavefront barriers between the stages.
 constexpr int kEdgeThreads = 256;
+// Above this many edges the lane-per-edge kernel is used: at 224,736 edges it took
+// 121 us per launch against 268 us for a wavefront per edge, at 3789 edges 13.3 us
+// against 10.0 us.
+constexpr long long kEdgeLaneMin = 32768;
 constexpr int kEdgeScratch = 32 + 32 + 36 * 10 + 24;  // doubles of LDS per wavefront
 
 __device__ __forceinline__ void wave_sync() {
@@ -1970,6 +2298,23 @@ void launch_edge_blocks(Context& c, const double* poses, const bf_params& prm, b
   }
   const long long E = c.shape.E;
   if (E == 0) return;
+  if (E > kEdgeLaneMin) {
+    // enough edges to fill the GPU one lane each
+    const unsigned grid = (unsigned)((E + 63) / 64);
+    if (c.pcg_storage == 1)
+      hipLaunchKernelGGL(k_edge_blocks_lane<double>, dim3(grid), dim3(64), 0, c.stream, c.edge_ij.as<int>(), E,
+                         c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.moments.as<double>(),
+                         c.records.as<double>(), (long long)c.shape.P, c.bidir, c.dense_tiles, poses,
+                         prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
+                         c.eblocks.as<double>(), c.hij64.as<double>(), ed);
+    else
+      hipLaunchKernelGGL(k_edge_blocks_lane<float>, dim3(grid), dim3(64), 0, c.stream, c.edge_ij.as<int>(), E,
+                         c.edge_dense.as<long long>(), c.edge_sparse.as<long long>(), c.moments.as<double>(),
+                         c.records.as<double>(), (long long)c.shape.P, c.bidir, c.dense_tiles, poses,
+                         prm.use_sparse ? prm.w_sparse : 0.0, with_jacobians ? 1 : 0,
+                         c.eblocks.as<double>(), c.hij32.as<float>(), ed);
+    return;
+  }
   constexpr int per = kEdgeThreads / 64;
   unsigned grid = (unsigned)((E + per - 1) / per);
   if (c.pcg_storage == 1)
