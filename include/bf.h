@@ -343,7 +343,8 @@ bf_status bf_gauss_newton(bf_context* ctx, const bf_frames* frames, const bf_int
  * 300k correspondences fit, or any chunk of up to 11 frames at 160x120).  The call
  * makes no hipMalloc, hipFree, hipHostMalloc or hipEventCreate; host readbacks go
  * through a static host buffer.  params->dense_threads must be fixed (64, 128, 256
- * or 512) and params->timing and params->graph 0 (else BF_ERR_UNSUPPORTED).
+ * or 512), params->pcg_threads not -1, and params->timing and params->graph 0
+ * (else BF_ERR_UNSUPPORTED).
  *
  * Every call on a GPU uses that GPU's one array: calls are serialised by a
  * process-wide lock and each call finishes its device work before releasing it;

@@ -980,6 +980,8 @@ bf_status bf_gauss_newton_noalloc(bf_context* ctx, const bf_frames* fr, const bf
       fail(BF_ERR_UNSUPPORTED, "the allocation-free entry point runs without timing events or graph capture");
     if (prm->dense_threads == 0)
       fail(BF_ERR_UNSUPPORTED, "the allocation-free entry point needs a fixed params->dense_threads");
+    if (prm->pcg_threads < 0)
+      fail(BF_ERR_UNSUPPORTED, "the allocation-free entry point needs params->pcg_threads fixed (not -1)");
     if (!ctx->noalloc) fail(BF_ERR_DEVICE, "context has no allocation-free state");
     char* base = static_cast<char*>(scratch_address(ctx->device));
     std::lock_guard<std::mutex> lk(g_noalloc_mu);

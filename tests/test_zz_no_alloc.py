@@ -63,4 +63,8 @@ def test_noalloc_refuses_beyond_scratch(ctx):
     with pytest.raises(bf.BFError) as e:
         bf.bf_gauss_newton_noalloc(ctx, dp, init, p0, out_poses=torch.empty_like(init))
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    p1 = bf.bf_params_default(dense_threads=256, pcg_threads=-1)  # timing would create events
+    with pytest.raises(bf.BFError) as e:
+        bf.bf_gauss_newton_noalloc(ctx, dp, init, p1, out_poses=torch.empty_like(init))
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
     _same(ctx, make_chunk(num_frames=5, seed_offset=32), "5-frame chunk after a refusal")
