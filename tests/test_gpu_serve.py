@@ -214,3 +214,34 @@ def test_footprint_estimate_covers_workspace(pool):
     print(f"footprint estimate / device bytes held: {min(ratios):.2f}..{max(ratios):.2f} per request, "
           f"{est / used:.2f} for a batch of {len(reqs)}", flush=True)
     assert est >= used
+
+
+def test_warm_start_in_a_batch(ctx, pool):
+    """Warm-started small requests batched together (their initial poses are the
+    resident results, concatenated on the device with the members' frames): all
+    eight submitted while the server's lock is held, so the batch lane takes them
+    in one call; each result equals bf_gauss_newton alone from its resident
+    result, bit for bit."""
+    dev, _ = pool
+    chunks = [(d, i, p) for d, i, p in dev if p is dev[0][2]][:8]
+    server = serve.Server()
+    try:
+        firsts = [server.submit(serve.Request(d, i, p, key=f"chunk{k}")) for k, (d, i, p) in enumerate(chunks)]
+        for r in firsts:
+            r.done.wait()
+            assert r.error is None, r.error
+        warm = [serve.Request(d, i, p, key=f"chunk{k}", warm_start=True) for k, (d, i, p) in enumerate(chunks)]
+        with server.cv:  # the lanes wait for the lock: every request is queued before one is taken
+            for r in warm:
+                server.submit(r)
+        for r in warm:
+            r.done.wait()
+            assert r.error is None, r.error
+        assert max(r.batch_size for r in warm) == len(warm)
+        for k, r in enumerate(warm):
+            d, _, p = chunks[k]
+            assert r.warm_frames == d.num_frames
+            ref = bf.bf_gauss_newton(ctx, d, firsts[k].poses, p)
+            assert torch.equal(r.poses, ref["poses"]) and r.energy == ref["energy"], k
+    finally:
+        server.close()
