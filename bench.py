@@ -676,6 +676,11 @@ def serving(bf, ctx, pool, n_requests):
             reqs = make_reqs()
             wall = serve.run_stream(server, reqs, arr)
             st = serve.latency_stats(reqs, wall)
+            for cls in ("chunk", "global"):
+                sub = [r for r in reqs if items[r.tag][0] == cls]
+                lat = np.array([r.latency for r in sub if r.error is None]) * 1e3
+                st[f"{cls}_p50_ms"] = round(float(np.percentile(lat, 50)), 3)
+                st[f"{cls}_p99_ms"] = round(float(np.percentile(lat, 99)), 3)
             for r in reqs:
                 same = same and r.error is None and torch.equal(r.poses, alone[r.tag])
             batches = [n for n, _ in server.batches[-200:]]
